@@ -1,0 +1,141 @@
+/*
+ * sfd.h -- C ABI of the MI355X (gfx950) Sparse Frequent Directions library.
+ *
+ * Method: Ghashami, Liberty & Phillips, "Efficient Frequent Directions Algorithm for Sparse
+ * Matrices" (arXiv:1602.00412).  Rows of a sparse matrix A (n x d) arrive one at a time; the
+ * library keeps an ell x d sketch B with the covariance guarantee of Theorem 3.1.  Each call
+ * below cites the passage that defines the operation it performs.
+ *
+ * Conventions for every call:
+ *  - Ownership: the caller owns every pointer it passes.  Input arrays are consumed (copied
+ *    or fully read) before the call returns; output arrays are written before it returns.
+ *  - Memory kind: `mem` is SFD_MEM_HOST for host pointers and SFD_MEM_DEVICE for pointers to
+ *    device memory of the handle's device (e.g. torch CUDA tensors).
+ *  - Synchronisation: work runs on the handle's HIP stream (sfd_set_stream); every call
+ *    returns after that work has completed.
+ *  - Errors: functions return SFD_OK (0) or a negative SFD_E_* code; sfd_strerror() names it.
+ *    Argument and input-validation errors leave the handle unchanged.  A device error or an
+ *    exhausted retry loop (SFD_E_NOCONVERGE) leaves the handle in an error state in which
+ *    every call but sfd_reset/sfd_destroy/sfd_get_stats returns SFD_E_STATE.
+ *  - Threads: a handle must not be used by two threads at once.  Different handles are
+ *    independent.
+ *  - Sizes: 1 <= ell <= min(d, 64) in this build; ell*d + d < 2^31 (int32 buffer indices).
+ */
+#ifndef SFD_H
+#define SFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfd_s sfd_t;
+
+enum {
+  SFD_OK = 0,
+  SFD_E_ARG = -1,        /* bad argument (size, null pointer, option value) */
+  SFD_E_INDEX = -2,      /* a column index outside [0, d) */
+  SFD_E_SHAPE = -3,      /* merge of handles with different (d, ell) */
+  SFD_E_NOMEM = -4,      /* device allocation failed */
+  SFD_E_DEVICE = -5,     /* a HIP runtime call failed */
+  SFD_E_NOCONVERGE = -6, /* BoostedSparseShrink exhausted its attempts */
+  SFD_E_STATE = -7       /* handle is in an error state (see above) */
+};
+
+enum { SFD_MEM_HOST = 0, SFD_MEM_DEVICE = 1 };
+
+/* Option keys for sfd_set_option. */
+enum {
+  SFD_OPT_DELTA = 1,        /* failure probability delta of Alg 2 / Alg 6, in (0,1); default 0.01 */
+  SFD_OPT_Q = 2,            /* power count q of Alg 1; <= 0 restores q = ceil(ln(m/eps)/eps) */
+  SFD_OPT_MAX_ATTEMPTS = 3, /* cap on the BoostedSparseShrink loop (Alg 4); default 16 */
+  SFD_OPT_VERIFY = 4,       /* 1: BoostedSparseShrink (Alg 4); 0: SparseShrink alone (Sec. 4) */
+  SFD_OPT_STREAM_ID = 5     /* second word of the random key; default 0 */
+};
+
+/* Per-handle counters and the last buffer step's figures. */
+typedef struct {
+  int64_t rows_seen;      /* rows appended so far */
+  int64_t nnz_seen;       /* stored entries appended so far */
+  int64_t flushes;        /* completed buffer steps (b) */
+  int64_t vs_calls;       /* persistent VerifySpectral counter i (Alg 6) */
+  int64_t attempts;       /* SparseShrink runs in total (Alg 4 loop iterations) */
+  int64_t vs_rejects;     /* VerifySpectral calls that returned False */
+  int32_t live_rows;      /* structural count of rows of B that may be non-zero */
+  int32_t pending_rows;   /* rows in the buffer A' */
+  int64_t pending_nnz;    /* stored entries in the buffer A' */
+  int32_t last_q;         /* q of the last SparseShrink */
+  int32_t last_t;         /* power steps of the last VerifySpectral */
+  double last_ln_norm;    /* ln ||C^t x|| of the last VerifySpectral */
+  double last_delta;      /* Delta of the last BoostedSparseShrink attempt */
+  double last_fro2_buffer;/* ||A'||_F^2 of the last buffer */
+  double last_lambda_ell2;/* lambda_ell^2 of the last SparseShrink */
+} sfd_stats_t;
+
+/* Create a stream sketch of width d and ell rows on the current HIP device (Alg 2 inputs).
+ * eps is the accuracy of SimultaneousIteration (Alg 1; SparseShrink uses 1/4) and sets the
+ * power count q = ceil(ln(m/eps)/eps) for an m-row buffer; seed is the first word of the
+ * random key.  B starts at 0 (Alg 2).  Allocates all device memory the handle uses.
+ * Errors: SFD_E_ARG (ell < 1, ell > min(d, 64), ell*d + d >= 2^31, eps not in (0,1),
+ * out == NULL), SFD_E_NOMEM, SFD_E_DEVICE. */
+int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t **out);
+
+/* Free the handle and its device memory.  NULL is a no-op. */
+int sfd_destroy(sfd_t *h);
+
+/* Return the handle to its just-created state (B = 0, empty buffer, counters 0), keeping its
+ * options and memory; clears an error state. */
+int sfd_reset(sfd_t *h);
+
+/* Set an option (keys above).  Errors: SFD_E_ARG for an unknown key or a value out of range. */
+int sfd_set_option(sfd_t *h, int key, double value);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for this
+ * handle's work; NULL selects the handle's own stream. */
+int sfd_set_stream(sfd_t *h, void *hip_stream);
+
+/* Append nrows rows in CSR form (Alg 2, the loop over rows a of A).  Row r holds the entries
+ * indices[k], values[k] for indptr[r] <= k < indptr[r+1]; indptr has nrows+1 entries and
+ * indptr[0] may be non-zero.  Repeated column ids in a row add up; every stored entry counts
+ * towards nnz(A').  After each row the buffer is flushed when nnz(A') >= ell*d or
+ * rows(A') = d: B' = BoostedSparseShrink(A', ell, delta) (Alg 4), B = DenseShrink([B; B'], ell)
+ * (Alg 5).  indptr/indices/values live in memory of kind `mem`.
+ * Errors (state unchanged): SFD_E_ARG (nrows < 0, null pointer with nrows > 0, decreasing
+ * indptr, a row with more than d entries), SFD_E_INDEX (column id outside [0, d)).
+ * SFD_E_NOCONVERGE / SFD_E_DEVICE put the handle in its error state. */
+int sfd_append_csr(sfd_t *h, int64_t nrows, const int64_t *indptr, const int32_t *indices,
+                   const float *values, int mem);
+
+/* Write the sketch of everything appended so far into B_out: ell x d, row-major, FP32, memory
+ * of kind `mem`.  Rows still in the buffer are folded into a copy of the state (Alg 2 returns
+ * B; folding the pending rows keeps them), so the stream is unchanged and a repeated query
+ * returns the same B.  *live_rows (may be NULL) receives the structural count of rows of
+ * B_out that may be non-zero.  Errors: SFD_E_ARG (B_out == NULL), SFD_E_NOCONVERGE. */
+int sfd_sketch(sfd_t *h, float *B_out, int mem, int32_t *live_rows);
+
+/* Merge src into dst (mergeability of Frequent Directions sketches, Sec. 2.1):
+ * dst.B = DenseShrink([sketch(dst); sketch(src)], ell); dst's buffer is consumed; src is
+ * unchanged.  Both handles must be on the same device.  Errors: SFD_E_SHAPE (different d or
+ * ell), SFD_E_ARG (NULL or dst == src). */
+int sfd_merge(sfd_t *dst, sfd_t *src);
+
+/* Copy the handle's counters into *out. */
+int sfd_get_stats(const sfd_t *h, sfd_stats_t *out);
+
+/* The start block G ~ N(0,1)^{d x ell} of SimultaneousIteration (Alg 1) that the handle
+ * scheme draws for (seed, stream_id, buffer, attempt, purpose), written FP32 row-major
+ * (d x ell) to the device array G_out; purpose 0 = flush, 2 = query.  With purpose 1 or 3 and
+ * ell = 1 it writes the Gaussian vector whose normalisation is VerifySpectral's x (Alg 6).
+ * Runs on the null stream.  Errors: SFD_E_ARG. */
+int sfd_start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint64_t attempt,
+                    uint64_t purpose, int64_t d, int32_t ell, float *G_out);
+
+/* Static text for an SFD_E_* code. */
+const char *sfd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFD_H */

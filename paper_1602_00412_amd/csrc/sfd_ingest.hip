@@ -1,0 +1,297 @@
+// Ingest of streamed CSR rows (Alg 2: append rows to the buffer A' and flush when
+// nnz(A') >= ell*d or rows(A') = d) and the per-buffer CSR -> CSC conversion that turns the
+// transposed products A'^T Y into gathers.
+#include "sfd_internal.h"
+
+namespace sfd {
+
+namespace {
+
+inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+__global__ void k_validate_rows(const int64_t* indptr, int64_t nrows, int64_t d, int* err) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; r < nrows; r += stride) {
+    int64_t len = indptr[r + 1] - indptr[r];
+    if (len < 0 || len > d) bad = 1;
+  }
+  if (bad) atomicOr(err, 1);
+}
+
+__global__ void k_validate_indices(const int32_t* idx, int64_t lo, int64_t hi, int64_t d, int* err) {
+  int64_t k = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; k < hi; k += stride) {
+    int32_t c = idx[k];
+    if (c < 0 || (int64_t)c >= d) bad = 1;
+  }
+  if (bad) atomicOr(err, 2);
+}
+
+// One thread walks the block: each cut is one binary search over indptr (Alg 2's test
+// nnz(A') >= ell*d or rows(A') = d after appending a row).
+__global__ void k_find_cuts(const int64_t* indptr, int64_t nrows, int64_t buf_rows, int64_t buf_nnz, int64_t budget,
+                            int64_t d, int64_t max_cuts, int64_t* cuts, int64_t* cut_ptr, int64_t* ncuts) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t r = 0, m = buf_rows, z = buf_nnz, count = 0;
+  while (r < nrows && count < max_cuts) {
+    // smallest k >= r with z + indptr[k+1] - indptr[r] >= budget
+    int64_t target = budget - z + indptr[r];
+    int64_t lo = r + 1, hi = nrows + 1;  // search indptr[lo..hi) for the first value >= target
+    while (lo < hi) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (indptr[mid] >= target) hi = mid; else lo = mid + 1;
+    }
+    int64_t by_nnz = lo - 1;            // == nrows when no row reaches the budget
+    int64_t by_rows = r + (d - m) - 1;  // row at which rows(A') reaches d
+    int64_t cut = by_nnz < by_rows ? by_nnz : by_rows;
+    if (cut >= nrows) break;
+    cuts[count] = cut;
+    cut_ptr[count] = indptr[cut + 1];
+    ++count;
+    r = cut + 1;
+    m = 0;
+    z = 0;
+  }
+  *ncuts = count;
+}
+
+__global__ void k_append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* rowptr, int m0, int nnz0) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t base = indptr[r0];
+  for (; i < cnt; i += stride) rowptr[m0 + 1 + i] = (int)(indptr[r0 + 1 + i] - base) + nnz0;
+}
+
+__global__ void k_col_count(const int* colidx, int nnz, int* counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (; i < nnz; i += stride) atomicAdd(&counts[colidx[i]], 1);
+}
+
+__global__ void k_expand_rowid(const int* rowptr, int m, int* rowid) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (; r < m; r += stride) {
+    int a = rowptr[r], b = rowptr[r + 1];
+    for (int k = a; k < b; ++k) rowid[k] = r;
+  }
+}
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void k_radix_hist(const int* keys, int n, int shift, int ntiles,
+                                                           int* hist) {
+  __shared__ int cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int base = blockIdx.x * kRsTile;
+#pragma unroll
+  for (int it = 0; it < kRsItems; ++it) {
+    int e = base + it * kRsThreads + threadIdx.x;
+    if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter of one radix pass: an element's destination is its digit's offset for this
+// tile plus the number of earlier elements of the tile with the same digit.  Elements are
+// taken 256 at a time in index order; inside a wave, lanes with equal digits are found with
+// eight ballots (one per digit bit).
+__global__ __launch_bounds__(kRsThreads) void k_radix_scatter(const int* keys_in, const int* vals_in, int* keys_out,
+                                                              int* vals_out, int n, int shift, int ntiles,
+                                                              const int* offs) {
+  __shared__ int run[256];
+  __shared__ int wcnt[kRsThreads / 64][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  run[tid] = offs[tid * ntiles + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kRsThreads / 64; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  int base = blockIdx.x * kRsTile;
+  for (int it = 0; it < kRsItems; ++it) {
+    int e = base + it * kRsThreads + tid;
+    bool valid = e < n;
+    int k = valid ? keys_in[e] : 0;
+    int v = valid ? (vals_in ? vals_in[e] : e) : 0;
+    int digit = (k >> shift) & 255;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (digit >> b) & 1;
+      unsigned long long bal = __ballot(valid && bit);
+      peers &= bit ? bal : ~bal;
+    }
+    int rank = __popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[wave][digit] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = run[digit] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
+      keys_out[pos] = k;
+      vals_out[pos] = v;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < kRsThreads / 64; ++w) {
+      add += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void k_csc_gather(const int* perm, const int* rowid, const float* val, int nnz, int* cscrow,
+                             float* cscval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (; i < nnz; i += stride) {
+    int e = perm[i];
+    cscrow[i] = rowid[e];
+    cscval[i] = val[e];
+  }
+}
+
+// ||A'||_F^2 with repeated (row, col) entries summed: each run of equal (col, row) in the
+// sorted order contributes (sum of its values)^2, accumulated in FP64.
+__global__ __launch_bounds__(256) void k_fro2_runs(const int* keys, const int* cscrow, const float* cscval, int nnz,
+                                                   double* part) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (; i < nnz; i += stride) {
+    bool start = (i == 0) || keys[i - 1] != keys[i] || cscrow[i - 1] != cscrow[i];
+    if (!start) continue;
+    double v = cscval[i];
+    for (int j = i + 1; j < nnz && keys[j] == keys[i] && cscrow[j] == cscrow[i]; ++j) v += cscval[j];
+    acc += v * v;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_to_scalar(const double* part, int nb, double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
+                                 int ld, int L) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < d; j += stride) {
+    float* o = out + j * ld;
+    for (int c = 0; c < L; ++c) o[c] = 0.f;
+    for (int k = cscptr[j]; k < cscptr[j + 1]; ++k) o[cscrow[k]] += cscval[k];
+  }
+}
+
+constexpr int kFroBlocks = 512;
+
+}  // namespace
+
+hipError_t validate_rows(const int64_t* indptr, int64_t nrows, int64_t d, int* err, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  k_validate_rows<<<grid_for(nrows, 256, 4096), 256, 0, st>>>(indptr, nrows, d, err);
+  return hipGetLastError();
+}
+
+hipError_t validate_indices(const int32_t* idx, int64_t lo, int64_t hi, int64_t d, int* err, hipStream_t st) {
+  if (hi <= lo) return hipSuccess;
+  k_validate_indices<<<grid_for(hi - lo, 256, 8192), 256, 0, st>>>(idx, lo, hi, d, err);
+  return hipGetLastError();
+}
+
+hipError_t find_cuts(const int64_t* indptr, int64_t nrows, int64_t buf_rows, int64_t buf_nnz, int64_t budget,
+                     int64_t d, int64_t max_cuts, int64_t* cuts, int64_t* cut_ptr, int64_t* ncuts, hipStream_t st) {
+  k_find_cuts<<<1, 64, 0, st>>>(indptr, nrows, buf_rows, buf_nnz, budget, d, max_cuts, cuts, cut_ptr, ncuts);
+  return hipGetLastError();
+}
+
+hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* rowptr, int m0, int nnz0,
+                         hipStream_t st) {
+  if (cnt <= 0) return hipSuccess;
+  k_append_rowptr<<<grid_for(cnt, 256, 4096), 256, 0, st>>>(indptr, r0, cnt, rowptr, m0, nnz0);
+  return hipGetLastError();
+}
+
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
+                     int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st) {
+  hipError_t e;
+  // column pointers: counts then exclusive scan
+  if ((e = fill_i32(w.counts, d + 1, 0, st)) != hipSuccess) return e;
+  if (nnz > 0) {
+    k_col_count<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(colidx, nnz, w.counts);
+  }
+  if ((e = scan_exclusive(w.counts, cscptr, d, w.scan_tmp, st)) != hipSuccess) return e;
+  if (nnz == 0) {
+    return fill_i32(reinterpret_cast<int*>(&sc->fro2A), 2, 0, st);  // fro2A = +0.0
+  }
+  k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid);
+  // stable LSD radix sort of the column ids, payload = entry index
+  int bits = 1;
+  while ((int64_t(1) << bits) < d) ++bits;
+  int passes = (bits + 7) / 8;
+  int ntiles = (nnz + kRsTile - 1) / kRsTile;
+  const int* kin = colidx;
+  const int* vin = nullptr;
+  int* kout = w.keys0;
+  int* vout = w.vals0;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    k_radix_hist<<<ntiles, kRsThreads, 0, st>>>(kin, nnz, shift, ntiles, w.hist);
+    if ((e = scan_exclusive(w.hist, w.hist, (int64_t)256 * ntiles, w.scan_tmp, st)) != hipSuccess) return e;
+    k_radix_scatter<<<ntiles, kRsThreads, 0, st>>>(kin, vin, kout, vout, nnz, shift, ntiles, w.hist);
+    kin = kout;
+    vin = vout;
+    if (kout == w.keys0) {
+      kout = w.keys1;
+      vout = w.vals1;
+    } else {
+      kout = w.keys0;
+      vout = w.vals0;
+    }
+  }
+  k_csc_gather<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(vin, w.rowid, val, nnz, cscrow, cscval);
+  k_fro2_runs<<<kFroBlocks, 256, 0, st>>>(kin, cscrow, cscval, nnz, w.part);
+  k_sum_to_scalar<<<1, 256, 0, st>>>(w.part, kFroBlocks, &sc->fro2A);
+  return hipGetLastError();
+}
+
+hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
+                          int ld, int L, hipStream_t st) {
+  k_dense_from_csc<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, cscval, d, out, ld, L);
+  return hipGetLastError();
+}
+
+}  // namespace sfd

@@ -1,0 +1,135 @@
+// Internal interface between the host orchestrator (sfd_api.cpp) and the HIP kernels.
+// Every launcher enqueues on `st` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfd {
+
+constexpr int kMaxEll = 56;      // 2*ell <= 112 keeps the FP64 eigensolver in one CU's LDS
+constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
+
+// Small device-resident scalars of one buffer step.
+struct DevScalars {
+  double fro2A;       // ||A'||_F^2 (repeated entries summed)
+  double fro2Bp;      // ||B'||_F^2 = sum_i (lambda_i^2 - lambda_ell^2)_+
+  double S;           // fro2A - fro2Bp = trace(A'^T A' - B'^T B')
+  double half_delta;  // Delta / 2, Delta = S / (alpha ell)
+  double lam_ell2;    // lambda_ell^2
+  double ln_norm;     // running ln ||C^s x|| of VerifySpectral
+  double inv_norm;    // 1 / ||w|| of the last power step (scales the next input)
+  double mu_ell;      // DenseShrink pivot mu_ell (0 when the stack is kept exactly)
+  int zero_flag;      // a power step vector was exactly 0
+  int dropped;        // directions dropped by the last pivoted Cholesky
+  int pad[2];
+};
+
+// ---------------------------------------------------------------- utilities (sfd_util.hip)
+hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t fill_i32(int* p, int64_t n, int v, hipStream_t st);
+// exclusive prefix sum of n int32 values; out[n] = total (out has n + 1 entries; may alias in)
+hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t st);
+int64_t scan_tmp_ints(int64_t n);
+// copy a d x w block between panels with pitches (elements)
+hipError_t copy_panel(const float* src, int lds, float* dst, int ldd, int64_t rows, int w, hipStream_t st);
+// out (ell x d, row-major) = panel^T restricted to the first ell columns
+hipError_t transpose_out(const float* panel, int ld, int64_t d, int ell, float* out, hipStream_t st);
+
+// ---------------------------------------------------------------- ingest / CSC (sfd_ingest.hip)
+// validation of a device CSR block: err |= 1 for a decreasing or over-long row, 2 for a bad index
+hipError_t validate_rows(const int64_t* indptr, int64_t nrows, int64_t d, int* err, hipStream_t st);
+hipError_t validate_indices(const int32_t* idx, int64_t lo, int64_t hi, int64_t d, int* err, hipStream_t st);
+// flush cut rows of a device block (single thread): cuts[k] = last row of the k-th full buffer,
+// cut_ptr[k] = indptr[cuts[k] + 1]; *ncuts = count
+hipError_t find_cuts(const int64_t* indptr, int64_t nrows, int64_t buf_rows, int64_t buf_nnz, int64_t budget,
+                     int64_t d, int64_t max_cuts, int64_t* cuts, int64_t* cut_ptr, int64_t* ncuts, hipStream_t st);
+// rowptr[m0 + 1 + i] = indptr[r0 + 1 + i] - indptr[r0] + nnz0 for i < cnt
+hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* rowptr, int m0, int nnz0,
+                         hipStream_t st);
+// CSR -> CSC by a stable LSD radix sort of the column ids; also ||A'||_F^2 with repeated (row, col)
+// entries summed, into sc->fro2A
+struct CscWork {
+  int* counts;    // d + 1
+  int* scan_tmp;
+  int* rowid;     // cap
+  int* keys0; int* keys1; int* vals0; int* vals1;  // cap each
+  int* hist;      // 256 * tiles
+  double* part;   // reduction partials
+};
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
+                     int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st);
+// dense transpose of a small buffer (m <= L rows): out[j][r] = sum of A'[r][j], pitch ld, width L
+hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
+                          int ld, int L, hipStream_t st);
+
+// ---------------------------------------------------------------- sparse products (sfd_spmm.hip)
+struct Schedule {
+  int* nch;          // rows + 1 : chunks per row -> scanned chunk start
+  int* pslot;        // rows + 1 : partial slots per long row -> scanned slot start
+  int* chunk_row;    // nchunks
+  int* long_rows;    // rows
+  int* counters;     // [0] = number of long rows
+  int nchunks;
+  int nslots;
+  int nlong;
+};
+// first half: per-row counts (device); the caller scans nch/pslot, reads totals, then calls finish
+hipError_t schedule_counts(const int* ptr, int rows, Schedule& s, hipStream_t st);
+hipError_t schedule_finish(const int* ptr, int rows, Schedule& s, hipStream_t st);
+// Y[r, :] = sum_k val[k] X[idx[k], :]  (rows of width L, pitches ldx / ldy)
+hipError_t spmm(const int* ptr, const int* idx, const float* val, int rows, const Schedule& s, const float* X,
+                int ldx, float* Y, int ldy, int L, float* partial, hipStream_t st);
+// z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)
+hipError_t spmv(const int* ptr, const int* idx, const float* val, int rows, const Schedule& s, const float* y,
+                const double* scale_ptr, float* z, float* partial, hipStream_t st);
+
+// ---------------------------------------------------------------- dense panels (sfd_dense.hip)
+// Gram W = P^T P of a rows x w panel (w in {32, 64, 128}) into FP64 W (w x w); partials
+// hold at most gram_max_blocks() blocks of w*w floats
+int gram_max_blocks();
+hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st);
+// in-place / out-of-place row transform: out[j, 0:wout] = in[j, 0:win] * T (T: win x wout, f32)
+hipError_t panel_xform(const float* in, int ldi, int win, const float* T, float* out, int ldo, int wout,
+                       int64_t rows, hipStream_t st);
+// partial sums of P^T y over row blocks: part[b][k] = sum_{j in block} P[j][k] * y[j] * scale
+int gemv_blocks(int64_t rows);
+hipError_t panel_gemv_t(const float* P, int ld, int L, int64_t rows, const float* y, const double* scale_ptr,
+                        float* part, hipStream_t st);
+// Philox4x64-10 start block: out[row][col] for row < d, col < ell (pitch ld); pads untouched
+hipError_t start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint64_t attempt, uint64_t purpose,
+                       int64_t d, int ell, float* out, int ld, hipStream_t st);
+
+// ---------------------------------------------------------------- small FP64 solvers (sfd_small.hip)
+// pivoted Cholesky of the ell x ell Gram W (pitch ldw) and the inverse of its factor, T (L x L,
+// f32, zero-padded); columns whose residual falls to tau * (their norm^2) are dropped
+hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
+                    hipStream_t st);
+// symmetric eigensolver (cyclic Jacobi, FP64) of the n x n matrix A (pitch lda), n <= 2*kMaxEll:
+// evals descending, evecs column i <-> evals[i], pitch n
+hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, hipStream_t st);
+// SparseShrink tail: from the eigenpairs of P P^T: M = H D (ell x ell, FP64 and f32 L x L),
+// ||B'||^2, S, Delta/2, lambda_ell^2
+hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
+                    DevScalars* sc, hipStream_t st);
+// exact buffer: M = I
+hipError_t ssh_identity(int ell, int L, double* M64, float* M32, DevScalars* sc, hipStream_t st);
+// DenseShrink stack Gram: SS = diag(I, M^T) W2 diag(I, M) (2 ell x 2 ell) from W2 (2L x 2L)
+hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, double* SS, hipStream_t st);
+// DenseShrink factors: T2 (2L x L, f32) = diag(I, M) U_ell D; lossless: no shift
+hipError_t dsh_post(const double* evals, const double* U, int ell, int L, const double* M64, int lossless,
+                    float* T2, DevScalars* sc, hipStream_t st);
+
+// ---------------------------------------------------------------- VerifySpectral (sfd_vs.hip)
+// x: gaussian vector already in w; sets sc->inv_norm = 1/||w||, ln_norm = 0, zero_flag = 0
+hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st);
+// c2 = M M^T c with c = sum of gemv partials (nb blocks)
+hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st);
+// w = w_raw - P c2; partial ||w||^2 per block
+int vs_finish_blocks(int64_t d);
+hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
+                     float* w, double* part, hipStream_t st);
+// reduce ||w||^2, ln_norm += ln||w|| - ln(Delta/2), inv_norm = 1/||w||
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st);
+
+}  // namespace sfd

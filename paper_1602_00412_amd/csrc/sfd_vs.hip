@@ -1,0 +1,155 @@
+// VerifySpectral (Alg 6) on C = (A'^T A' - B'^T B') / (Delta/2): power steps
+//   w = A'^T (A' y) - B'^T (B' y),  y <- w / ||w||,  ln||C^t x|| = sum (ln||w|| - ln(Delta/2)).
+// B'^T = P^T M is never formed: B'^T (B' y) = P^T (M (M^T (P y))).  The sparse products use the
+// chunked SpMV of the SimultaneousIteration schedule; the scalars live in DevScalars.
+#include <math.h>
+
+#include "sfd_internal.h"
+
+namespace sfd {
+
+namespace {
+
+constexpr int kNormBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double v = x[i];
+    acc += v * v;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__device__ double block_sum(const double* part, int nb, double* s) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  return s[0];
+}
+
+__global__ __launch_bounds__(256) void k_vs_init(const double* __restrict__ part, int nb, DevScalars* sc) {
+  __shared__ double s[256];
+  double tot = block_sum(part, nb, s);
+  if (threadIdx.x == 0) {
+    double nrm = sqrt(tot);
+    sc->ln_norm = 0.0;
+    sc->zero_flag = nrm > 0.0 ? 0 : 1;
+    sc->inv_norm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+}
+
+// c = sum of the P y partials (FP64); c2 = M (M^T c)
+__global__ __launch_bounds__(256) void k_vs_small(const float* __restrict__ part, int nb,
+                                                  const double* __restrict__ M, int ell, int L,
+                                                  float* __restrict__ c2) {
+  __shared__ double c[kMaxEll];
+  __shared__ double u[kMaxEll];
+  const int tid = threadIdx.x;
+  if (tid < ell) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * L + tid];
+    c[tid] = s;
+  }
+  __syncthreads();
+  if (tid < ell) {
+    double s = 0.0;
+    for (int k = 0; k < ell; ++k) s += M[k * ell + tid] * c[k];
+    u[tid] = s;
+  }
+  __syncthreads();
+  if (tid < L) {
+    double s = 0.0;
+    if (tid < ell)
+      for (int k = 0; k < ell; ++k) s += M[tid * ell + k] * u[k];
+    c2[tid] = (float)s;
+  }
+}
+
+// w[j] = w_raw[j] - P[j, :] . c2, one wave per row, and the block's sum of w^2 in FP64.
+__global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_raw, const float* __restrict__ P,
+                                                   int ld, int L, const float* __restrict__ c2, int64_t d,
+                                                   float* __restrict__ w, double* __restrict__ part) {
+  __shared__ double s[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float cA = lane < L ? c2[lane] : 0.f;
+  const float cB = 64 + lane < L ? c2[64 + lane] : 0.f;
+  double acc = 0.0;
+  for (int64_t j = ((int64_t)blockIdx.x * 4 + wave); j < d; j += (int64_t)gridDim.x * 4) {
+    const float* pr = P + j * ld;
+    float v = (lane < L ? pr[lane] * cA : 0.f) + (64 + lane < L ? pr[64 + lane] * cB : 0.f);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) {
+      float r = w_raw[j] - v;
+      w[j] = r;
+      acc += (double)r * (double)r;
+    }
+  }
+  if (lane == 0) s[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part, int nb, DevScalars* sc) {
+  __shared__ double s[256];
+  double tot = block_sum(part, nb, s);
+  if (threadIdx.x == 0) {
+    double nrm = sqrt(tot);
+    if (sc->zero_flag || !(nrm > 0.0)) {
+      sc->zero_flag = 1;
+      sc->ln_norm = -HUGE_VAL;
+      sc->inv_norm = 0.0;
+    } else {
+      sc->ln_norm += log(nrm) - log(sc->half_delta);
+      sc->inv_norm = 1.0 / nrm;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st) {
+  k_sumsq<<<kNormBlocks, 256, 0, st>>>(w, d, part);
+  k_vs_init<<<1, 256, 0, st>>>(part, kNormBlocks, sc);
+  return hipGetLastError();
+}
+
+hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st) {
+  k_vs_small<<<1, 256, 0, st>>>(part, nb, M64, ell, L, c2);
+  return hipGetLastError();
+}
+
+int vs_finish_blocks(int64_t d) {
+  int64_t nb = (d + 63) / 64;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
+                     float* w, double* part, hipStream_t st) {
+  (void)ell;
+  k_vs_finish<<<vs_finish_blocks(d), 256, 0, st>>>(w_raw, P, ld, L, c2, d, w, part);
+  return hipGetLastError();
+}
+
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st) {
+  k_vs_norm<<<1, 256, 0, st>>>(part, nb, sc);
+  return hipGetLastError();
+}
+
+}  // namespace sfd

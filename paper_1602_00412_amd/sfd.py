@@ -1,0 +1,225 @@
+"""ctypes binding of libsfd.so (include/sfd.h): argument marshalling only.
+
+Every step of the sketch runs in the HIP library; this module converts torch tensors / numpy
+arrays to pointers and memory kinds, and error codes to exceptions.  It raises if the library
+is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfd.so")
+
+SFD_OK = 0
+SFD_E_ARG = -1
+SFD_E_INDEX = -2
+SFD_E_SHAPE = -3
+SFD_E_NOMEM = -4
+SFD_E_DEVICE = -5
+SFD_E_NOCONVERGE = -6
+SFD_E_STATE = -7
+MEM_HOST = 0
+MEM_DEVICE = 1
+OPT_DELTA = 1
+OPT_Q = 2
+OPT_MAX_ATTEMPTS = 3
+OPT_VERIFY = 4
+OPT_STREAM_ID = 5
+
+EXPORTS = [
+    "sfd_create",
+    "sfd_destroy",
+    "sfd_reset",
+    "sfd_set_option",
+    "sfd_set_stream",
+    "sfd_append_csr",
+    "sfd_sketch",
+    "sfd_merge",
+    "sfd_get_stats",
+    "sfd_start_block",
+    "sfd_strerror",
+]
+
+
+class SfdError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("rows_seen", ctypes.c_int64),
+        ("nnz_seen", ctypes.c_int64),
+        ("flushes", ctypes.c_int64),
+        ("vs_calls", ctypes.c_int64),
+        ("attempts", ctypes.c_int64),
+        ("vs_rejects", ctypes.c_int64),
+        ("live_rows", ctypes.c_int32),
+        ("pending_rows", ctypes.c_int32),
+        ("pending_nnz", ctypes.c_int64),
+        ("last_q", ctypes.c_int32),
+        ("last_t", ctypes.c_int32),
+        ("last_ln_norm", ctypes.c_double),
+        ("last_delta", ctypes.c_double),
+        ("last_fro2_buffer", ctypes.c_double),
+        ("last_lambda_ell2", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsfd.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built (python -m paper_1602_00412_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u64, dbl, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "sfd_create": (i, [i64, i32, dbl, u64, ctypes.POINTER(vp)]),
+        "sfd_destroy": (i, [vp]),
+        "sfd_reset": (i, [vp]),
+        "sfd_set_option": (i, [vp, i, dbl]),
+        "sfd_set_stream": (i, [vp, vp]),
+        "sfd_append_csr": (i, [vp, i64, vp, vp, vp, i]),
+        "sfd_sketch": (i, [vp, vp, i, ctypes.POINTER(i32)]),
+        "sfd_merge": (i, [vp, vp]),
+        "sfd_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
+        "sfd_start_block": (i, [u64, u64, u64, u64, u64, i64, i32, vp]),
+        "sfd_strerror": (ctypes.c_char_p, [i]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().sfd_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != SFD_OK:
+        raise SfdError(code, what)
+
+
+def _ptr_kind(x, dtype):
+    """(pointer, memory kind, keep-alive) of a torch tensor or numpy array of ``dtype``."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(x, torch.Tensor):
+        want = {np.int64: torch.int64, np.int32: torch.int32, np.float32: torch.float32}[dtype]
+        if x.dtype != want:
+            raise TypeError(f"expected {want}, got {x.dtype}")
+        if not x.is_contiguous():
+            x = x.contiguous()
+        return x.data_ptr(), (MEM_DEVICE if x.is_cuda else MEM_HOST), x
+    a = np.ascontiguousarray(x)
+    if a.dtype != dtype:
+        raise TypeError(f"expected {np.dtype(dtype)}, got {a.dtype}")
+    return a.ctypes.data, MEM_HOST, a
+
+
+def _torch_stream_handle():
+    import torch
+
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+class Sketch:
+    """A Sparse Frequent Directions stream (sfd_create ... sfd_destroy)."""
+
+    def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
+                 max_attempts=None, verify=None, stream_id=None, use_torch_stream: bool = True):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
+        self._h = h
+        self.d, self.ell = int(d), int(ell)
+        for key, val in ((OPT_DELTA, delta), (OPT_Q, q), (OPT_MAX_ATTEMPTS, max_attempts),
+                         (OPT_VERIFY, None if verify is None else float(bool(verify))), (OPT_STREAM_ID, stream_id)):
+            if val is not None:
+                self.set_option(key, val)
+        if use_torch_stream:
+            s = _torch_stream_handle()
+            if s is not None:
+                _check(lib.sfd_set_stream(self._h, ctypes.c_void_p(s)), "sfd_set_stream")
+
+    def set_option(self, key: int, value: float):
+        _check(load().sfd_set_option(self._h, int(key), float(value)), "sfd_set_option")
+
+    def append_csr(self, indptr, indices, values):
+        """Append rows in CSR form; torch CUDA tensors are read in device memory."""
+        p_ptr, p_kind, k1 = _ptr_kind(indptr, np.int64)
+        i_ptr, i_kind, k2 = _ptr_kind(indices, np.int32)
+        v_ptr, v_kind, k3 = _ptr_kind(values, np.float32)
+        if not (p_kind == i_kind == v_kind):
+            raise ValueError("indptr, indices and values must live in the same kind of memory")
+        nrows = (k1.numel() if hasattr(k1, "numel") else k1.size) - 1
+        _check(load().sfd_append_csr(self._h, nrows, p_ptr, i_ptr, v_ptr, p_kind), "sfd_append_csr")
+        del k1, k2, k3
+
+    def sketch(self, out=None, device: bool = True):
+        """B (ell x d, FP32): a torch CUDA tensor (device=True) or a numpy array."""
+        live = ctypes.c_int32()
+        if device:
+            import torch
+
+            if out is None:
+                out = torch.empty((self.ell, self.d), dtype=torch.float32, device="cuda")
+            _check(load().sfd_sketch(self._h, out.data_ptr(), MEM_DEVICE, ctypes.byref(live)), "sfd_sketch")
+        else:
+            if out is None:
+                out = np.empty((self.ell, self.d), dtype=np.float32)
+            _check(load().sfd_sketch(self._h, out.ctypes.data, MEM_HOST, ctypes.byref(live)), "sfd_sketch")
+        self.last_live = live.value
+        return out
+
+    def merge(self, other: "Sketch"):
+        _check(load().sfd_merge(self._h, other._h), "sfd_merge")
+
+    def reset(self):
+        _check(load().sfd_reset(self._h), "sfd_reset")
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().sfd_get_stats(self._h, ctypes.byref(s)), "sfd_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().sfd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def start_block(seed: int, stream_id: int, buffer: int, attempt: int, purpose: int, d: int, ell: int):
+    """The FP32 start block G (d x ell) the library draws, as a torch CUDA tensor (sfd_start_block)."""
+    import torch
+
+    out = torch.empty((d, ell), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    _check(load().sfd_start_block(seed, stream_id, buffer, attempt, purpose, d, ell, out.data_ptr()), "sfd_start_block")
+    return out

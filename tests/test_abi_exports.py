@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every function include/sfd.h declares (no compute calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+pytestmark = pytest.mark.cpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "sfd.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1602_00412_amd import sfd
+
+    if not os.path.exists(sfd.LIB_PATH):
+        from paper_1602_00412_amd.build import build
+
+        build()
+    lib = ctypes.CDLL(sfd.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(sfd.EXPORTS)
+
+
+def test_strerror_and_argument_errors_without_a_gpu():
+    from paper_1602_00412_amd import sfd
+
+    lib = sfd.load()
+    assert lib.sfd_strerror(sfd.SFD_E_INDEX) == b"column index out of range"
+    h = ctypes.c_void_p()
+    # argument checks run before any device call
+    assert lib.sfd_create(10, 0, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_create(10, 11, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_create(100, 5, 1.5, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_create(1 << 30, 5, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_destroy(None) == sfd.SFD_OK
+    assert lib.sfd_merge(None, None) == sfd.SFD_E_ARG

@@ -1,0 +1,197 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar (fixed for the FP32 path): relative Frobenius distance of B^T B between the GPU sketch and
+the oracle's, ||B_g^T B_g - B_o^T B_o||_F / ||B_o^T B_o||_F <= 1e-4, with the oracle fed the
+same Philox start blocks and the same q, and taking its lossless-accept decision at the
+panels' unit roundoff (2^-24) so both sides decide the same way.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import SFDOracle, evaluate
+from oracle.rng import start_block as oracle_start_block
+from workloads import config1_fp64_reference, small_random_csr
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+U32 = 2.0 ** -24
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dev(st):
+    torch = _torch()
+    return (torch.from_numpy(np.ascontiguousarray(st.indptr)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(st.indices)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(st.values)).cuda())
+
+
+def _gpu_sketch(sfd, st, ell, *, blocks=None, host=False, **opts):
+    sk = sfd.Sketch(st.d, ell, opts.pop("eps", 0.25), opts.pop("seed", 0), **opts)
+    bounds = blocks or [(0, st.n)]
+    for lo, hi in bounds:
+        sub = st.rows(lo, hi)
+        if host:
+            sk.append_csr(sub.indptr, sub.indices, sub.values)
+        else:
+            sk.append_csr(*_dev(sub))
+    B = sk.sketch().cpu().numpy().astype(np.float64)
+    return sk, B
+
+
+def _oracle(st, ell, **kw):
+    o = SFDOracle(st.d, ell, kw.pop("eps", 0.25), kw.pop("seed", 0), unit_roundoff=U32, **kw)
+    o.append_csr(st.indptr, st.indices, st.values)
+    return o
+
+
+def test_start_block_matches_oracle(gpu_lib):
+    for (seed, sid, b, a, p, d, ell) in [(0, 0, 0, 0, 0, 1000, 20), (7, 3, 5, 2, 1, 333, 1), (2**40, 9, 1, 0, 2, 97, 13)]:
+        g = gpu_lib.start_block(seed, sid, b, a, p, d, ell).cpu().numpy()
+        want = oracle_start_block(seed, sid, b, a, p, d, ell)
+        np.testing.assert_allclose(g, want, rtol=2e-7, atol=2e-7)
+
+
+@pytest.mark.parametrize("n,d,ell,lam,seed", [
+    (400, 60, 5, 6, 0),      # several flushes by the rows rule, ragged tail
+    (900, 80, 20, 9, 1),     # ell = 20 (L = 32), nnz budget reached
+    (700, 150, 33, 12, 2),   # ell = 33 -> L = 64 padding
+    (1500, 90, 50, 20, 3),   # ell = 50
+])
+def test_small_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
+    st = small_random_csr(n, d, lam, seed, dist="lognormal")
+    o = _oracle(st, ell)
+    sk, B = _gpu_sketch(gpu_lib, st, ell)
+    assert sk.stats()["flushes"] == o.flushes
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+    assert sk.last_live == o.query()[1]
+
+
+def test_config1_matches_oracle_and_fd_bound(gpu_lib):
+    st = config1_fp64_reference()
+    o = _oracle(st, 20)
+    sk, B = _gpu_sketch(gpu_lib, st, 20)
+    stats = sk.stats()
+    assert stats["flushes"] == 10 and stats["vs_calls"] == o.vs_calls == 10 and stats["vs_rejects"] == 0
+    dist = evaluate.gram_distance(B, o.sketch())
+    assert dist <= TOL, dist
+    A = st.to_scipy()
+    assert evaluate.cov_err(A, B) <= evaluate.fd_bound(A, 20, 10) / evaluate.fro2(A)
+    # the last buffer's VerifySpectral log norm agrees with the oracle's
+    want = o.log[-1]["attempts"][-1]["ln_norm"]
+    assert abs(stats["last_ln_norm"] - want) <= 1e-3 * abs(want)
+
+
+def test_block_boundaries_do_not_change_the_result(gpu_lib):
+    st = small_random_csr(600, 70, 8, 4)
+    _, B1 = _gpu_sketch(gpu_lib, st, 10)
+    _, B2 = _gpu_sketch(gpu_lib, st, 10, blocks=[(0, 1), (1, 69), (69, 70), (70, 333), (333, 600)])
+    np.testing.assert_array_equal(B1, B2)
+
+
+def test_host_and_device_inputs_agree(gpu_lib):
+    st = small_random_csr(500, 64, 7, 5)
+    _, Bd = _gpu_sketch(gpu_lib, st, 12)
+    _, Bh = _gpu_sketch(gpu_lib, st, 12, host=True, blocks=[(0, 250), (250, 500)])
+    np.testing.assert_array_equal(Bd, Bh)
+
+
+def test_query_is_non_destructive(gpu_lib):
+    st = small_random_csr(800, 60, 6, 6)
+    torch = _torch()
+    a = gpu_lib.Sketch(st.d, 8)
+    b = gpu_lib.Sketch(st.d, 8)
+    for lo, hi in [(0, 170), (170, 555), (555, 800)]:
+        sub = st.rows(lo, hi)
+        a.append_csr(*_dev(sub))
+        b.append_csr(*_dev(sub))
+        q1 = a.sketch().clone()
+        q2 = a.sketch()
+        assert torch.equal(q1, q2)
+    assert torch.equal(a.sketch(), b.sketch())
+    o = _oracle(st, 8)
+    assert evaluate.gram_distance(a.sketch().cpu().numpy().astype(np.float64), o.sketch()) <= TOL
+
+
+def test_exact_when_rows_at_most_ell(gpu_lib):
+    st = small_random_csr(9, 50, 6, 7)
+    _, B = _gpu_sketch(gpu_lib, st, 12)
+    A = st.to_scipy().toarray()
+    G = A.T @ A
+    assert np.linalg.norm(B.T @ B - G) <= TOL * np.linalg.norm(G)
+
+
+def test_empty_stream_and_empty_rows(gpu_lib):
+    torch = _torch()
+    sk = gpu_lib.Sketch(40, 6)
+    assert torch.count_nonzero(sk.sketch()) == 0
+    st = small_random_csr(300, 40, 4, 8, empty_rate=0.3)
+    o = _oracle(st, 6)
+    _, B = _gpu_sketch(gpu_lib, st, 6)
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+def test_duplicate_column_ids(gpu_lib):
+    st = small_random_csr(400, 50, 5, 9, dup_rate=0.25)
+    o = _oracle(st, 7)
+    _, B = _gpu_sketch(gpu_lib, st, 7)
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+def test_verify_off_matches_oracle(gpu_lib):
+    st = small_random_csr(500, 60, 6, 10)
+    o = _oracle(st, 9, verify=False)
+    sk, B = _gpu_sketch(gpu_lib, st, 9, verify=False)
+    assert sk.stats()["vs_calls"] == 0
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+def test_merge_matches_oracle(gpu_lib):
+    st = small_random_csr(900, 60, 6, 11)
+    shards = [(0, 300), (300, 640), (640, 900)]
+    gs, os_ = [], []
+    for k, (lo, hi) in enumerate(shards):
+        sub = st.rows(lo, hi)
+        g = gpu_lib.Sketch(st.d, 10, stream_id=k)
+        g.append_csr(*_dev(sub))
+        gs.append(g)
+        o = SFDOracle(st.d, 10, 0.25, 0, stream_id=k, unit_roundoff=U32)
+        o.append_csr(sub.indptr, sub.indices, sub.values)
+        os_.append(o)
+    gs[0].merge(gs[1])
+    gs[0].merge(gs[2])
+    os_[0].merge(os_[1])
+    os_[0].merge(os_[2])
+    B = gs[0].sketch().cpu().numpy().astype(np.float64)
+    assert evaluate.gram_distance(B, os_[0].sketch()) <= TOL
+    with pytest.raises(gpu_lib.SfdError):
+        gs[0].merge(gpu_lib.Sketch(61, 10))
+
+
+def test_errors_leave_state_unchanged(gpu_lib):
+    torch = _torch()
+    sk = gpu_lib.Sketch(30, 4)
+    st = small_random_csr(50, 30, 4, 12)
+    sk.append_csr(*_dev(st))
+    before = sk.sketch().clone()
+    s0 = sk.stats()
+    bad_idx = torch.tensor([0, 2], dtype=torch.int64, device="cuda")
+    with pytest.raises(gpu_lib.SfdError) as e:
+        sk.append_csr(bad_idx, torch.tensor([1, 30], dtype=torch.int32, device="cuda"),
+                      torch.ones(2, dtype=torch.float32, device="cuda"))
+    assert e.value.code == gpu_lib.SFD_E_INDEX
+    with pytest.raises(gpu_lib.SfdError) as e:
+        sk.append_csr(torch.tensor([0, 2, 1], dtype=torch.int64, device="cuda"),
+                      torch.tensor([1, 2], dtype=torch.int32, device="cuda"),
+                      torch.ones(2, dtype=torch.float32, device="cuda"))
+    assert e.value.code == gpu_lib.SFD_E_ARG
+    assert sk.stats() == s0
+    assert torch.equal(sk.sketch(), before)
+    with pytest.raises(gpu_lib.SfdError):
+        gpu_lib.Sketch(10, 11)
