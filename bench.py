@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the Sparse Frequent Directions hot path on one MI355X.
+
+One step = one pass of the whole path over the workload: reset the handle, append every row
+(CSR already resident in HBM; each full buffer goes through the buffer step: CSC build,
+SimultaneousIteration, VerifySpectral, BoostedSparseShrink, DenseShrink) and query the sketch.
+
+Workload: n = 1,000,000 rows, d = 100,000, Poisson(50) entries per row from Zipf(1.0) columns,
+lognormal(0,1) values plus a planted rank-20 component with 30% of the energy, ell = 50,
+eps = 1/4, FP32 (workloads.config2_plain_fp32).
+
+Prints one JSON line (metric, value in nnz/s, roofline of the dominant kernel class measured
+with HIP events on the library's stream over the timed region, and the FP64 oracle's rate on
+a bounded sample of the same stream as cpu_baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "ingested nnz/s on 1 MI355X at fixed cov-err; BF16/batched vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFS = 157.3
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(st, ell: int, rows: int):
+    """The FP64 oracle on the first `rows` rows of the stream (query folds them in one buffer)."""
+    import numpy as np
+
+    from oracle import SFDOracle
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    sub = st.rows(0, rows)
+    t0 = time.perf_counter()
+    o = SFDOracle(st.d, ell, 0.25, 0)
+    o.append_csr(sub.indptr, sub.indices, sub.values)
+    B = o.sketch()
+    dt = time.perf_counter() - t0
+    return sub, B.astype(np.float64), {
+        "value": sub.nnz / dt,
+        "unit": "nnz/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {rows} rows ({sub.nnz} nnz) of the same stream, folded by one query "
+                  f"(m={rows}, q={o.log[-1]['attempts'][0]['q'] if o.log else 'n/a'}); {dt:.1f} s; "
+                  f"BLAS threads={threads}, scipy sparse products single-threaded",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sample-rows", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without the per-class HIP events")
+    ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
+              f"one merge at the end, which this build does not run across GPUs", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1602_00412_amd import sfd
+    from workloads import config2_plain_fp32
+
+    sfd.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    t0 = time.perf_counter()
+    st = config2_plain_fp32(seed=0, n=args.rows)
+    ell = 50
+    log(f"generated n={st.n} d={st.d} nnz={st.nnz} in {time.perf_counter() - t0:.1f} s")
+    indptr = torch.from_numpy(st.indptr).cuda()
+    indices = torch.from_numpy(st.indices).cuda()
+    values = torch.from_numpy(st.values).cuda()
+    out = torch.empty((ell, st.d), dtype=torch.float32, device="cuda")
+    sk = sfd.Sketch(st.d, ell, 0.25, 0)
+
+    def step():
+        sk.reset()
+        sk.append_csr(indptr, indices, values)
+        sk.sketch(out=out)
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
+    if not args.no_profile:
+        sk.set_option(sfd.OPT_PROFILE, 1)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    stats = sk.stats()
+    prof = sk.profile() if not args.no_profile else {}
+    value = st.nnz / (elapsed / args.steps)
+    log(f"{ms_per_step:.1f} ms/step, {value:.3e} nnz/s, flushes/step={stats['flushes']}")
+
+    # roofline of the dominant kernel class (largest device time)
+    roof = None
+    phases = {}
+    if prof:
+        for name, p in prof.items():
+            if p["launches"]:
+                phases[name] = {"ms_per_step": p["ms"] / args.steps, "launches_per_step": p["launches"] / args.steps,
+                                "avg_us": 1e3 * p["ms"] / p["launches"]}
+        dom = max(prof, key=lambda k: prof[k]["ms"])
+        p = prof[dom]
+        avg_s = p["ms"] / 1e3 / p["launches"]
+        if dom in ("gram",):
+            achieved = p["flops"] / p["launches"] / avg_s / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_MFMA_PEAK_TFS, "traffic": None}
+        else:
+            achieved = p["bytes"] / p["launches"] / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+        roof["kernel"] = dom
+        roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["launches"]
+        roof["avg_launch_us"] = avg_s * 1e6
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        sub, B_oracle, cpu = cpu_baseline(st, ell, min(args.cpu_sample_rows, st.n))
+        log(f"cpu baseline: {cpu['value']:.3e} nnz/s in {time.perf_counter() - t:.1f} s")
+        # the GPU on the same sample, compared with the oracle (relative Frobenius of B^T B)
+        from oracle import evaluate
+
+        sk2 = sfd.Sketch(st.d, ell, 0.25, 0)
+        sk2.append_csr(torch.from_numpy(sub.indptr).cuda(), torch.from_numpy(sub.indices).cuda(),
+                       torch.from_numpy(sub.values).cuda())
+        Bg = sk2.sketch().cpu().numpy().astype(np.float64)
+        parity = evaluate.gram_distance(Bg, B_oracle)
+        log(f"sample parity (rel. Frobenius of B^T B vs oracle): {parity:.2e}")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"zipf-poisson stream n={st.n} d={st.d} lambda=50 s=1.0 lognormal+planted rank-20 (30%), "
+                        f"ell={ell} eps=1/4 fp32",
+            "nnz": st.nnz,
+            "ell": ell,
+            "buffers_per_step": stats["flushes"],
+            "q_last": stats["last_q"],
+            "parallelism": "1 GPU",
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "sample_parity_rel_frobenius": parity,
+        "phases": phases,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -19,7 +19,7 @@
  *    every call but sfd_reset/sfd_destroy/sfd_get_stats returns SFD_E_STATE.
  *  - Threads: a handle must not be used by two threads at once.  Different handles are
  *    independent.
- *  - Sizes: 1 <= ell <= min(d, 64) in this build; ell*d + d < 2^31 (int32 buffer indices).
+ *  - Sizes: 1 <= ell <= min(d, 56) in this build; ell*d + d < 2^31 (int32 buffer indices).
  */
 #ifndef SFD_H
 #define SFD_H
@@ -51,8 +51,34 @@ enum {
   SFD_OPT_Q = 2,            /* power count q of Alg 1; <= 0 restores q = ceil(ln(m/eps)/eps) */
   SFD_OPT_MAX_ATTEMPTS = 3, /* cap on the BoostedSparseShrink loop (Alg 4); default 16 */
   SFD_OPT_VERIFY = 4,       /* 1: BoostedSparseShrink (Alg 4); 0: SparseShrink alone (Sec. 4) */
-  SFD_OPT_STREAM_ID = 5     /* second word of the random key; default 0 */
+  SFD_OPT_STREAM_ID = 5,    /* second word of the random key; default 0 */
+  SFD_OPT_PROFILE = 6       /* 1: time every kernel class with HIP events and clear the
+                               counters; 0: stop timing.  Default 0. */
 };
+
+/* Kernel classes of the per-phase profile (sfd_get_profile). */
+enum {
+  SFD_PROF_CSC_BUILD = 0, /* CSR -> CSC of a buffer */
+  SFD_PROF_SPMM_CSR = 1,  /* Y = A' X (Alg 1 products with A') */
+  SFD_PROF_SPMM_CSC = 2,  /* X = A'^T Y and P^T = A'^T Z (Alg 1, Alg 3) */
+  SFD_PROF_GRAM = 3,      /* panel Gram matrices on MFMA */
+  SFD_PROF_CHOL = 4,      /* ell x ell FP64 Cholesky + inverse */
+  SFD_PROF_XFORM = 5,     /* panel x small-matrix row transforms */
+  SFD_PROF_EIG = 6,       /* FP64 symmetric eigensolves */
+  SFD_PROF_VS = 7,        /* VerifySpectral power steps (Alg 6) */
+  SFD_PROF_OTHER = 8,     /* start blocks, shrink factors, copies */
+  SFD_PROF_COUNT = 9
+};
+
+/* Accumulated per-class figures since profiling was switched on: kernel launches, device time
+ * between HIP events recorded around the class's launches on the handle's stream, and the
+ * class's algorithmic bytes and flops (what the method must read/write once, and compute). */
+typedef struct {
+  int64_t launches[16];
+  double ms[16];
+  double bytes[16];
+  double flops[16];
+} sfd_profile_t;
 
 /* Per-handle counters and the last buffer step's figures. */
 typedef struct {
@@ -77,7 +103,7 @@ typedef struct {
  * eps is the accuracy of SimultaneousIteration (Alg 1; SparseShrink uses 1/4) and sets the
  * power count q = ceil(ln(m/eps)/eps) for an m-row buffer; seed is the first word of the
  * random key.  B starts at 0 (Alg 2).  Allocates all device memory the handle uses.
- * Errors: SFD_E_ARG (ell < 1, ell > min(d, 64), ell*d + d >= 2^31, eps not in (0,1),
+ * Errors: SFD_E_ARG (ell < 1, ell > min(d, 56), ell*d + d >= 2^31, eps not in (0,1),
  * out == NULL), SFD_E_NOMEM, SFD_E_DEVICE. */
 int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t **out);
 
@@ -122,6 +148,9 @@ int sfd_merge(sfd_t *dst, sfd_t *src);
 
 /* Copy the handle's counters into *out. */
 int sfd_get_stats(const sfd_t *h, sfd_stats_t *out);
+
+/* Copy the handle's per-class profile (SFD_OPT_PROFILE) into *out.  Errors: SFD_E_ARG. */
+int sfd_get_profile(const sfd_t *h, sfd_profile_t *out);
 
 /* The start block G ~ N(0,1)^{d x ell} of SimultaneousIteration (Alg 1) that the handle
  * scheme draws for (seed, stream_id, buffer, attempt, purpose), written FP32 row-major

@@ -76,6 +76,17 @@ struct sfd_s {
   int64_t cut_cap = 0;
   int* scan_tmp = nullptr;
   std::vector<void*> allocs;
+  // per-class profile (SFD_OPT_PROFILE)
+  int prof = 0;
+  sfd_profile_t profile{};
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+    int launches;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
   // pinned host staging
   DevScalars* sc_host = nullptr;
   int64_t* i64_host = nullptr;  // small readbacks
@@ -106,6 +117,13 @@ bool dalloc(sfd_t* h, T** p, int64_t count) {
 }
 
 void free_all(sfd_t* h) {
+  for (auto& p : h->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  h->pending.clear();
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  h->ev_pool.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->sc_host) (void)hipHostFree(h->sc_host);
@@ -127,8 +145,60 @@ int fail(sfd_t* h, int code) {
     if (_e != hipSuccess) return fail(h, SFD_E_DEVICE); \
   } while (0)
 
+// Events bracketing the launches of one kernel class on the handle's stream.
+struct ProfScope {
+  sfd_t* h;
+  int cls;
+  double bytes, flops;
+  int launches;
+  hipEvent_t a = nullptr;
+  static hipEvent_t take(sfd_t* h) {
+    if (!h->ev_pool.empty()) {
+      hipEvent_t e = h->ev_pool.back();
+      h->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ProfScope(sfd_t* h_, int cls_, double bytes_, double flops_ = 0.0, int launches_ = 1)
+      : h(h_), cls(cls_), bytes(bytes_), flops(flops_), launches(launches_) {
+    if (h->prof) {
+      a = take(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!h->prof || !a) return;
+    hipEvent_t b = take(h);
+    if (!b) {
+      h->ev_pool.push_back(a);
+      return;
+    }
+    (void)hipEventRecord(b, h->stream);
+    h->pending.push_back({cls, a, b, bytes, flops, launches});
+  }
+};
+
+void prof_resolve(sfd_t* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      h->profile.ms[p.cls] += ms;
+      h->profile.launches[p.cls] += p.launches;
+      h->profile.bytes[p.cls] += p.bytes;
+      h->profile.flops[p.cls] += p.flops;
+    }
+    h->ev_pool.push_back(p.a);
+    h->ev_pool.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
 int sync(sfd_t* h) {
   CK(hipStreamSynchronize(h->stream));
+  if (!h->pending.empty()) prof_resolve(h);
   return SFD_OK;
 }
 
@@ -219,9 +289,38 @@ int build_schedule(sfd_t* h, const int* ptr, int rows, Schedule& s) {
 int orth(sfd_t* h, float* panel, int64_t rows) {
   hipStream_t st = h->stream;
   const int L = h->L;
-  CK(gram(panel, L, rows, L, h->gram_part, h->W, st));
-  CK(chol_inv(h->W, L, h->ell, L, kCholDropTol, h->T, h->sc, st));
-  CK(panel_xform(panel, L, L, h->T, panel, L, L, rows, st));
+  const double ell = h->ell;
+  {
+    ProfScope ps(h, SFD_PROF_GRAM, 4.0 * rows * ell, 2.0 * rows * ell * ell, 2);
+    CK(gram(panel, L, rows, L, h->gram_part, h->W, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
+    CK(chol_inv(h->W, L, h->ell, L, kCholDropTol, h->T, h->sc, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_XFORM, 8.0 * rows * ell, 2.0 * rows * ell * ell, 1);
+    CK(panel_xform(panel, L, L, h->T, panel, L, L, rows, st));
+  }
+  return SFD_OK;
+}
+
+// algorithmic bytes of one sparse product over the buffer: the stored entries (id + value)
+// and row pointers once, the input panel read once, the output panel written once
+double spmm_bytes(const sfd_t* h, bool transposed) {
+  const double N = h->nnz, m = h->m, d = (double)h->d, ell = h->ell;
+  return 8.0 * N + 4.0 * ((transposed ? d : m) + 1) + 4.0 * ell * (m + d);
+}
+
+int spmm_csr(sfd_t* h, const float* X, int ldx, float* Y, int ldy) {
+  ProfScope ps(h, SFD_PROF_SPMM_CSR, spmm_bytes(h, false), 2.0 * h->nnz * h->ell, 1);
+  CK(spmm(h->rowptr, h->colidx, h->val, h->m, h->sr, X, ldx, Y, ldy, h->L, h->partial, h->stream));
+  return SFD_OK;
+}
+
+int spmm_csc(sfd_t* h, const float* Y, int ldy, float* X, int ldx) {
+  ProfScope ps(h, SFD_PROF_SPMM_CSC, spmm_bytes(h, true), 2.0 * h->nnz * h->ell, 1);
+  CK(spmm(h->cscptr, h->cscrow, h->cscval, (int)h->d, h->sc_sched, Y, ldy, X, ldx, h->L, h->partial, h->stream));
   return SFD_OK;
 }
 
@@ -233,21 +332,34 @@ int sparse_shrink(sfd_t* h, int purpose, int64_t buffer, int attempt, int q) {
   const int64_t d = h->d;
   const int m = h->m;
   int rc;
-  CK(fill_f32(h->X, d * L, 0.f, st));
-  CK(start_block(h->seed, h->stream_id, (uint64_t)buffer, (uint64_t)attempt, (uint64_t)purpose, d, ell, h->X, L, st));
+  {
+    ProfScope ps(h, SFD_PROF_OTHER, 4.0 * d * ell, 0.0, 2);
+    CK(fill_f32(h->X, d * L, 0.f, st));
+    CK(start_block(h->seed, h->stream_id, (uint64_t)buffer, (uint64_t)attempt, (uint64_t)purpose, d, ell, h->X, L,
+                   st));
+  }
   if ((rc = orth(h, h->X, d))) return rc;
   for (int it = 0; it < q; ++it) {
-    CK(spmm(h->rowptr, h->colidx, h->val, m, h->sr, h->X, L, h->Y, L, L, h->partial, st));
+    if ((rc = spmm_csr(h, h->X, L, h->Y, L))) return rc;
     if ((rc = orth(h, h->Y, m))) return rc;
-    CK(spmm(h->cscptr, h->cscrow, h->cscval, (int)d, h->sc_sched, h->Y, L, h->X, L, L, h->partial, st));
+    if ((rc = spmm_csc(h, h->Y, L, h->X, L))) return rc;
     if ((rc = orth(h, h->X, d))) return rc;
   }
-  CK(spmm(h->rowptr, h->colidx, h->val, m, h->sr, h->X, L, h->Y, L, L, h->partial, st));
+  if ((rc = spmm_csr(h, h->X, L, h->Y, L))) return rc;
   if ((rc = orth(h, h->Y, m))) return rc;
-  CK(spmm(h->cscptr, h->cscrow, h->cscval, (int)d, h->sc_sched, h->Y, L, h->C + L, 2 * L, L, h->partial, st));
-  CK(gram(h->C, 2 * L, d, 2 * L, h->gram_part, h->W, st));
-  CK(eig_sym(h->W + (int64_t)L * 2 * L + L, 2 * L, ell, h->evals, h->evecs, st));
-  CK(ssh_post(h->evals, h->evecs, ell, L, kAlpha, h->M64, h->M32, h->sc, st));
+  if ((rc = spmm_csc(h, h->Y, L, h->C + L, 2 * L))) return rc;
+  {
+    ProfScope ps(h, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
+    CK(gram(h->C, 2 * L, d, 2 * L, h->gram_part, h->W, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
+    CK(eig_sym(h->W + (int64_t)L * 2 * L + L, 2 * L, ell, h->evals, h->evecs, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(ssh_post(h->evals, h->evecs, ell, L, kAlpha, h->M64, h->M32, h->sc, st));
+  }
   return SFD_OK;
 }
 
@@ -259,6 +371,8 @@ int verify_spectral(sfd_t* h, int purpose, int64_t buffer, int attempt, int t, d
   const int64_t d = h->d;
   const int m = h->m;
   const float* Pt = h->C + L;
+  ProfScope ps(h, SFD_PROF_VS, t * (16.0 * h->nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
+               t * (4.0 * h->nnz + 4.0 * d * ell), 6 * t + 3);
   CK(start_block(h->seed, h->stream_id, (uint64_t)buffer, (uint64_t)attempt, (uint64_t)purpose, d, 1, h->vs_w, 1, st));
   CK(vs_init(h->vs_w, d, h->vs_npart, h->sc, st));
   for (int s = 0; s < t; ++s) {
@@ -269,9 +383,6 @@ int verify_spectral(sfd_t* h, int purpose, int64_t buffer, int attempt, int t, d
     CK(vs_finish(h->vs_wraw, Pt, 2 * L, L, ell, h->vs_c2, d, h->vs_w, h->vs_npart, st));
     CK(vs_norm(h->vs_npart, vs_finish_blocks(d), h->sc, st));
   }
-  int rc = read_scalars(h);
-  if (rc) return rc;
-  *ln_norm = h->sc_host->ln_norm;
   return SFD_OK;
 }
 
@@ -285,7 +396,10 @@ int fold(sfd_t* h, int purpose_g, int purpose_x, int64_t buffer, int64_t vs_base
   const int m = h->m;
   int rc;
   *calls_out = 0;
-  CK(build_csc(h->rowptr, h->colidx, h->val, m, h->nnz, d, h->cscptr, h->cscrow, h->cscval, h->csc, h->sc, st));
+  {
+    ProfScope ps(h, SFD_PROF_CSC_BUILD, 16.0 * h->nnz + 4.0 * (m + d), 0.0, 1);
+    CK(build_csc(h->rowptr, h->colidx, h->val, m, h->nnz, d, h->cscptr, h->cscrow, h->cscval, h->csc, h->sc, st));
+  }
   int r_add;
   if (m <= ell) {
     // exact buffer (SparseShrink needs ell <= m): P^T = A'^T, M = I
@@ -316,6 +430,8 @@ int fold(sfd_t* h, int purpose_g, int purpose_x, int64_t buffer, int64_t vs_base
       const int t = vs_steps(h, vs_base + calls);
       double ln_norm = 0.0;
       if ((rc = verify_spectral(h, purpose_x, buffer, a, t, &ln_norm))) return rc;
+      if ((rc = read_scalars(h))) return rc;
+      ln_norm = h->sc_host->ln_norm;
       h->stats.last_t = t;
       h->stats.last_ln_norm = ln_norm;
       if (ln_norm <= 0.0)
@@ -328,10 +444,22 @@ int fold(sfd_t* h, int purpose_g, int purpose_x, int64_t buffer, int64_t vs_base
     r_add = ell - 1;
   }
   const int lossless = (h->live + r_add <= ell) ? 1 : 0;
-  CK(dsh_assemble(h->W, L, ell, h->M64, h->SS, st));
-  CK(eig_sym(h->SS, 2 * ell, 2 * ell, h->evals, h->evecs, st));
-  CK(dsh_post(h->evals, h->evecs, ell, L, h->M64, lossless, h->T2, h->sc, st));
-  CK(panel_xform(h->C, 2 * L, 2 * L, h->T2, out, out_ld, L, d, st));
+  {
+    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(dsh_assemble(h->W, L, ell, h->M64, h->SS, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
+    CK(eig_sym(h->SS, 2 * ell, 2 * ell, h->evals, h->evecs, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(dsh_post(h->evals, h->evecs, ell, L, h->M64, lossless, h->T2, h->sc, st));
+  }
+  {
+    ProfScope ps(h, SFD_PROF_XFORM, 12.0 * d * ell, 4.0 * d * ell * ell, 1);
+    CK(panel_xform(h->C, 2 * L, 2 * L, h->T2, out, out_ld, L, d, st));
+  }
   *live_out = lossless ? h->live + r_add : ell - 1;
   return sync(h);
 }
@@ -510,6 +638,11 @@ int sfd_set_option(sfd_t* h, int key, double value) {
       if (value != 0.0 && value != 1.0) return SFD_E_ARG;
       h->verify = (int)value;
       return SFD_OK;
+    case SFD_OPT_PROFILE:
+      if (value != 0.0 && value != 1.0) return SFD_E_ARG;
+      h->prof = (int)value;
+      if (h->prof) std::memset(&h->profile, 0, sizeof(h->profile));
+      return SFD_OK;
     case SFD_OPT_STREAM_ID:
       if (!(value >= 0) || value > 9.0e15 || value != std::floor(value)) return SFD_E_ARG;
       h->stream_id = (uint64_t)value;
@@ -535,6 +668,12 @@ int sfd_get_stats(const sfd_t* h, sfd_stats_t* out) {
   out->live_rows = h->live;
   out->pending_rows = h->m;
   out->pending_nnz = h->nnz;
+  return SFD_OK;
+}
+
+int sfd_get_profile(const sfd_t* h, sfd_profile_t* out) {
+  if (!h || !out) return SFD_E_ARG;
+  *out = h->profile;
   return SFD_OK;
 }
 

@@ -29,6 +29,8 @@ OPT_Q = 2
 OPT_MAX_ATTEMPTS = 3
 OPT_VERIFY = 4
 OPT_STREAM_ID = 5
+OPT_PROFILE = 6
+PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other"]
 
 EXPORTS = [
     "sfd_create",
@@ -40,6 +42,7 @@ EXPORTS = [
     "sfd_sketch",
     "sfd_merge",
     "sfd_get_stats",
+    "sfd_get_profile",
     "sfd_start_block",
     "sfd_strerror",
 ]
@@ -74,6 +77,19 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_int64 * 16),
+        ("ms", ctypes.c_double * 16),
+        ("bytes", ctypes.c_double * 16),
+        ("flops", ctypes.c_double * 16),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: {"launches": int(self.launches[i]), "ms": float(self.ms[i]), "bytes": float(self.bytes[i]),
+                       "flops": float(self.flops[i])} for i, name in enumerate(PROF_CLASSES)}
+
+
 _lib = None
 
 
@@ -96,6 +112,7 @@ def load(path: str = LIB_PATH):
         "sfd_sketch": (i, [vp, vp, i, ctypes.POINTER(i32)]),
         "sfd_merge": (i, [vp, vp]),
         "sfd_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
+        "sfd_get_profile": (i, [vp, ctypes.POINTER(Profile)]),
         "sfd_start_block": (i, [u64, u64, u64, u64, u64, i64, i32, vp]),
         "sfd_strerror": (ctypes.c_char_p, [i]),
     }
@@ -202,6 +219,11 @@ class Sketch:
         s = Stats()
         _check(load().sfd_get_stats(self._h, ctypes.byref(s)), "sfd_get_stats")
         return s.as_dict()
+
+    def profile(self) -> dict:
+        p = Profile()
+        _check(load().sfd_get_profile(self._h, ctypes.byref(p)), "sfd_get_profile")
+        return p.as_dict()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
