@@ -1,14 +1,19 @@
 // Host orchestrator and C ABI of the Sparse Frequent Directions library (declarations and
 // conventions in include/sfd.h).
 //
-// Per handle the device holds: the buffer A' as CSR (and, per buffer step, its CSC copy), the
-// panel C = [B^T | P^T] (d x 2L, row-major, L = ell rounded up to 32) whose left half is the
-// sketch B stored transposed, the SimultaneousIteration panels X (d x L) and Y (m x L), and
-// the small FP64 work of the shrink steps.  The buffer step (Alg 2's flush) runs:
-//   CSC build -> G (Philox) -> q x { Y = orth(A' X); X = orth(A'^T Y) } -> Y = orth(A' X)
-//   -> P^T = A'^T Y -> Gram of C -> eig(P P^T) -> M = H D (so B'^T = P^T M)
-//   -> VerifySpectral (Alg 6) -> on reject retry with the next attempt's G (Alg 4)
-//   -> DenseShrink (Alg 5) of [B; B'] through the Gram of C -> B^T = C T2.
+// Device state of a handle: the sketch B stored transposed as a d x L panel (row-major,
+// L = ell rounded up to 32, zero-padded), the pending buffer A' as CSR, and kLanes "lanes".
+// A lane is the workspace of one buffer step with its own HIP stream: a CSR view of the buffer,
+// its CSC copy and chunk schedules, the SimultaneousIteration panels X (d x L) and Y (m x L),
+// P^T (d x L) and the small FP64 work.  The buffer step (Alg 2's flush) is:
+//   CSC build -> G (Philox) -> q x { Y = A' X T_x; X = A'^T Y T_y } -> Y = A' X T_x
+//   -> P^T = A'^T Y T_y   (T_* = inverse Cholesky factor of the previous panel's Gram)
+//   -> eig(P P^T) -> M = H D (so B'^T = P^T M)                     [SparseShrink, Alg 3]
+//   -> VerifySpectral on the lane (Alg 6), retry with the next attempt's G on reject [Alg 4]
+//   -> DenseShrink (Alg 5) of [B; B'] through the Gram of [B^T | P^T] -> B^T = [B^T | P^T] T2.
+// SparseShrink never reads B, so the lanes run the SimultaneousIteration of successive full
+// buffers concurrently; VerifySpectral and DenseShrink are issued in buffer order, so the
+// persistent VerifySpectral counter and the random draws follow the stream order exactly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,17 +30,47 @@ using namespace sfd;
 
 namespace {
 
-constexpr double kAlpha = 6.0 / 41.0;          // alpha of Alg 4 / Theorem 3.1
+constexpr double kAlpha = 6.0 / 41.0;                 // alpha of Alg 4 / Theorem 3.1
 constexpr double kUnitRoundoff32 = 1.0 / 16777216.0;  // 2^-24: the panels' arithmetic
-constexpr double kCholDropTol = 1e-5;          // relative residual^2 below which a column is dependent
+constexpr double kCholDropTol = 1e-5;                 // relative residual^2 below which a column is dependent
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
+constexpr int kLanes = 4;
+
+struct Lane {
+  hipStream_t st = nullptr;
+  // the buffer: CSR view (rowptr may be the lane's own array or the handle's pending buffer)
+  int* own_rowptr = nullptr;
+  const int* rowptr = nullptr;
+  const int* colidx = nullptr;
+  const float* val = nullptr;
+  int m = 0, nnz = 0;
+  int64_t buffer = 0;
+  int pg = 0, px = 0;  // purposes of the start block and of the VerifySpectral vector
+  int q = 0;
+  // CSC and schedules
+  int *cscptr = nullptr, *cscrow = nullptr;
+  float* cscval = nullptr;
+  CscWork csc{};
+  int* scan_tmp = nullptr;
+  Schedule sr{}, scs{};
+  float* partial = nullptr;
+  // panels and small work
+  float *X = nullptr, *Y = nullptr, *Pt = nullptr;
+  float* gram_part = nullptr;
+  double *W = nullptr, *W2 = nullptr;
+  double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
+  float *M32 = nullptr, *T = nullptr, *T2 = nullptr;
+  float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
+  double* vs_npart = nullptr;
+  DevScalars* sc = nullptr;
+  DevScalars* sc_host = nullptr;  // pinned
+};
 
 }  // namespace
 
 struct sfd_s {
   int device = 0;
-  hipStream_t own_stream = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t user_stream = nullptr;  // the caller's stream (inputs are ordered on it), or null
   int64_t d = 0;
   int ell = 0;
   int L = 0;
@@ -48,33 +83,23 @@ struct sfd_s {
   // stream state
   int live = 0;
   int64_t flushes = 0, vs_calls = 0;
-  int m = 0;    // pending rows
-  int nnz = 0;  // pending stored entries
   int error = 0;
   sfd_stats_t stats{};
   int64_t cap = 0;
   // device memory
-  int* rowptr = nullptr;
-  int* colidx = nullptr;
-  float* val = nullptr;
-  int* cscptr = nullptr;
-  int* cscrow = nullptr;
-  float* cscval = nullptr;
-  CscWork csc{};
-  Schedule sr{}, sc_sched{};
-  float* partial = nullptr;
-  float *X = nullptr, *Y = nullptr, *C = nullptr, *Bq = nullptr;
-  float* gram_part = nullptr;
-  double* W = nullptr;
-  double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
-  float *M32 = nullptr, *T = nullptr, *T2 = nullptr;
-  float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
-  double* vs_npart = nullptr;
-  DevScalars* sc = nullptr;
+  float* B = nullptr;   // d x L: the sketch, transposed
+  float* Bq = nullptr;  // d x L: a query's copy of B with the pending rows folded in
+  int* prow = nullptr;  // pending buffer (CSR): rows, entries
+  int* pcol = nullptr;
+  float* pval = nullptr;
+  int pm = 0, pnnz = 0;
+  Lane lanes[kLanes];
   int* err_dev = nullptr;
-  int64_t* cut_dev = nullptr;  // [0] count, then cuts, then cut_ptr
+  int64_t* cut_dev = nullptr;
   int64_t cut_cap = 0;
-  int* scan_tmp = nullptr;
+  int64_t* i64_host = nullptr;  // pinned small readbacks
+  hipEvent_t ev_in = nullptr;   // caller's stream -> lanes
+  hipEvent_t ev_dsh = nullptr;  // the last DenseShrink (B is current after it)
   std::vector<void*> allocs;
   // per-class profile (SFD_OPT_PROFILE)
   int prof = 0;
@@ -87,9 +112,6 @@ struct sfd_s {
   };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
-  // pinned host staging
-  DevScalars* sc_host = nullptr;
-  int64_t* i64_host = nullptr;  // small readbacks
 };
 
 namespace {
@@ -126,12 +148,17 @@ void free_all(sfd_t* h) {
   h->ev_pool.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
-  if (h->sc_host) (void)hipHostFree(h->sc_host);
+  for (Lane& ln : h->lanes) {
+    if (ln.sc_host) (void)hipHostFree(ln.sc_host);
+    ln.sc_host = nullptr;
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+    ln.st = nullptr;
+  }
   if (h->i64_host) (void)hipHostFree(h->i64_host);
-  h->sc_host = nullptr;
   h->i64_host = nullptr;
-  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
-  h->own_stream = nullptr;
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_dsh) (void)hipEventDestroy(h->ev_dsh);
+  h->ev_in = h->ev_dsh = nullptr;
 }
 
 int fail(sfd_t* h, int code) {
@@ -145,9 +172,10 @@ int fail(sfd_t* h, int code) {
     if (_e != hipSuccess) return fail(h, SFD_E_DEVICE); \
   } while (0)
 
-// Events bracketing the launches of one kernel class on the handle's stream.
+// HIP events bracketing the launches of one kernel class on a lane's stream.
 struct ProfScope {
   sfd_t* h;
+  hipStream_t st;
   int cls;
   double bytes, flops;
   int launches;
@@ -162,11 +190,11 @@ struct ProfScope {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
-  ProfScope(sfd_t* h_, int cls_, double bytes_, double flops_ = 0.0, int launches_ = 1)
-      : h(h_), cls(cls_), bytes(bytes_), flops(flops_), launches(launches_) {
+  ProfScope(sfd_t* h_, hipStream_t st_, int cls_, double bytes_, double flops_ = 0.0, int launches_ = 1)
+      : h(h_), st(st_), cls(cls_), bytes(bytes_), flops(flops_), launches(launches_) {
     if (h->prof) {
       a = take(h);
-      if (a) (void)hipEventRecord(a, h->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~ProfScope() {
@@ -176,7 +204,7 @@ struct ProfScope {
       h->ev_pool.push_back(a);
       return;
     }
-    (void)hipEventRecord(b, h->stream);
+    (void)hipEventRecord(b, st);
     h->pending.push_back({cls, a, b, bytes, flops, launches});
   }
 };
@@ -196,15 +224,28 @@ void prof_resolve(sfd_t* h) {
   h->pending.clear();
 }
 
-int sync(sfd_t* h) {
-  CK(hipStreamSynchronize(h->stream));
+int sync_lane(sfd_t* h, Lane& ln) {
+  CK(hipStreamSynchronize(ln.st));
+  return SFD_OK;
+}
+
+int sync_all(sfd_t* h) {
+  for (Lane& ln : h->lanes) CK(hipStreamSynchronize(ln.st));
   if (!h->pending.empty()) prof_resolve(h);
   return SFD_OK;
 }
 
-int read_scalars(sfd_t* h) {
-  CK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
-  return sync(h);
+// the caller's stream must have produced its inputs before any lane reads them
+int order_after_caller(sfd_t* h) {
+  if (!h->user_stream) return SFD_OK;
+  CK(hipEventRecord(h->ev_in, h->user_stream));
+  for (Lane& ln : h->lanes) CK(hipStreamWaitEvent(ln.st, h->ev_in, 0));
+  return SFD_OK;
+}
+
+int read_scalars(sfd_t* h, Lane& ln) {
+  CK(hipMemcpyAsync(ln.sc_host, ln.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ln.st));
+  return sync_lane(h, ln);
 }
 
 int alloc_state(sfd_t* h) {
@@ -215,32 +256,42 @@ int alloc_state(sfd_t* h) {
   const int64_t max_chunks = d + cap / kSpmmChunk + 2;
   const int64_t slots = 2 * cap / kSpmmChunk + 16;
   bool ok = true;
-  ok = ok && dalloc(h, &h->rowptr, d + 1) && dalloc(h, &h->colidx, cap) && dalloc(h, &h->val, cap);
-  ok = ok && dalloc(h, &h->cscptr, d + 1) && dalloc(h, &h->cscrow, cap) && dalloc(h, &h->cscval, cap);
-  ok = ok && dalloc(h, &h->csc.counts, d + 1) && dalloc(h, &h->csc.rowid, cap);
-  ok = ok && dalloc(h, &h->csc.keys0, cap) && dalloc(h, &h->csc.keys1, cap);
-  ok = ok && dalloc(h, &h->csc.vals0, cap) && dalloc(h, &h->csc.vals1, cap);
-  ok = ok && dalloc(h, &h->csc.hist, 256 * tiles + 1) && dalloc(h, &h->csc.part, 1024);
-  ok = ok && dalloc(h, &h->scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, d + 1)) + 16);
-  h->csc.scan_tmp = h->scan_tmp;
-  for (Schedule* s : {&h->sr, &h->sc_sched}) {
-    ok = ok && dalloc(h, &s->nch, d + 1) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->chunk_row, max_chunks) &&
-         dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4);
+  ok = ok && dalloc(h, &h->B, d * L) && dalloc(h, &h->Bq, d * L);
+  ok = ok && dalloc(h, &h->prow, d + 1) && dalloc(h, &h->pcol, cap) && dalloc(h, &h->pval, cap);
+  ok = ok && dalloc(h, &h->err_dev, 4);
+  for (Lane& ln : h->lanes) {
+    ok = ok && dalloc(h, &ln.own_rowptr, d + 1);
+    ok = ok && dalloc(h, &ln.cscptr, d + 1) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
+    ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
+    ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
+    ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
+    ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
+    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, d + 1)) + 16);
+    ln.csc.scan_tmp = ln.scan_tmp;
+    for (Schedule* s : {&ln.sr, &ln.scs}) {
+      ok = ok && dalloc(h, &s->nch, d + 1) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->chunk_row, max_chunks) &&
+           dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4);
+      s->max_chunks = max_chunks;
+    }
+    ok = ok && dalloc(h, &ln.partial, slots * L);
+    ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
+    ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
+         dalloc(h, &ln.W2, 4 * L * L);
+    ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
+    ok = ok && dalloc(h, &ln.M64, L * L) && dalloc(h, &ln.M32, L * L) && dalloc(h, &ln.T, L * L) &&
+         dalloc(h, &ln.T2, 2 * L * L);
+    ok = ok && dalloc(h, &ln.vs_w, d) && dalloc(h, &ln.vs_wraw, d) && dalloc(h, &ln.vs_z, d) &&
+         dalloc(h, &ln.vs_c2, 2 * L) && dalloc(h, &ln.vs_gpart, (int64_t)gemv_blocks(d) * L) &&
+         dalloc(h, &ln.vs_npart, 2048);
+    ok = ok && dalloc(h, &ln.sc, 1);
+    if (!ok) return SFD_E_NOMEM;
+    if (hipHostMalloc((void**)&ln.sc_host, sizeof(DevScalars)) != hipSuccess) return SFD_E_NOMEM;
+    if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess) return SFD_E_DEVICE;
   }
-  ok = ok && dalloc(h, &h->partial, slots * L);
-  ok = ok && dalloc(h, &h->X, d * L) && dalloc(h, &h->Y, d * L) && dalloc(h, &h->C, d * 2 * L) &&
-       dalloc(h, &h->Bq, d * L);
-  ok = ok && dalloc(h, &h->gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &h->W, 4 * L * L);
-  ok = ok && dalloc(h, &h->evals, 2 * L) && dalloc(h, &h->evecs, 4 * L * L) && dalloc(h, &h->SS, 4 * L * L);
-  ok = ok && dalloc(h, &h->M64, L * L) && dalloc(h, &h->M32, L * L) && dalloc(h, &h->T, L * L) &&
-       dalloc(h, &h->T2, 2 * L * L);
-  ok = ok && dalloc(h, &h->vs_w, d) && dalloc(h, &h->vs_wraw, d) && dalloc(h, &h->vs_z, d) &&
-       dalloc(h, &h->vs_c2, 2 * L) && dalloc(h, &h->vs_gpart, (int64_t)gemv_blocks(d) * L) &&
-       dalloc(h, &h->vs_npart, 2048);
-  ok = ok && dalloc(h, &h->sc, 1) && dalloc(h, &h->err_dev, 4);
   if (!ok) return SFD_E_NOMEM;
-  if (hipHostMalloc((void**)&h->sc_host, sizeof(DevScalars)) != hipSuccess) return SFD_E_NOMEM;
   if (hipHostMalloc((void**)&h->i64_host, sizeof(int64_t) * 16) != hipSuccess) return SFD_E_NOMEM;
+  if (hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
+  if (hipEventCreateWithFlags(&h->ev_dsh, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   return SFD_OK;
 }
 
@@ -248,13 +299,17 @@ int reset_state(sfd_t* h) {
   h->live = 0;
   h->flushes = 0;
   h->vs_calls = 0;
-  h->m = 0;
-  h->nnz = 0;
+  h->pm = 0;
+  h->pnnz = 0;
   h->error = 0;
   std::memset(&h->stats, 0, sizeof(h->stats));
-  CK(fill_f32(h->C, h->d * 2 * h->L, 0.f, h->stream));
-  CK(fill_i32(h->rowptr, 1, 0, h->stream));
-  return sync(h);
+  Lane& l0 = h->lanes[0];
+  int rc = sync_all(h);
+  if (rc) return rc;
+  CK(fill_f32(h->B, h->d * h->L, 0.f, l0.st));
+  CK(fill_i32(h->prow, 1, 0, l0.st));
+  CK(hipEventRecord(h->ev_dsh, l0.st));
+  return sync_all(h);
 }
 
 int si_iterations(const sfd_t* h, int m) {
@@ -267,158 +322,184 @@ int vs_steps(const sfd_t* h, int64_t i) {
   return (int)std::ceil(std::log2((double)h->d / di));
 }
 
-int build_schedule(sfd_t* h, const int* ptr, int rows, Schedule& s) {
-  hipStream_t st = h->stream;
-  CK(schedule_counts(ptr, rows, s, st));
-  CK(scan_exclusive(s.nch, s.nch, rows, h->scan_tmp, st));
-  CK(scan_exclusive(s.pslot, s.pslot, rows, h->scan_tmp, st));
-  CK(schedule_finish(ptr, rows, s, st));
-  int* hv = reinterpret_cast<int*>(h->i64_host);
-  CK(hipMemcpyAsync(hv + 0, s.nch + rows, sizeof(int), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(hv + 1, s.pslot + rows, sizeof(int), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(hv + 2, s.counters, sizeof(int), hipMemcpyDeviceToHost, st));
-  int rc = sync(h);
-  if (rc) return rc;
-  s.nchunks = hv[0];
-  s.nslots = hv[1];
-  s.nlong = hv[2];
-  return SFD_OK;
-}
-
-// panel <- panel * R^{-1} with R the (pivoted) Cholesky factor of panel^T panel
-int orth(sfd_t* h, float* panel, int64_t rows) {
-  hipStream_t st = h->stream;
-  const int L = h->L;
-  const double ell = h->ell;
-  {
-    ProfScope ps(h, SFD_PROF_GRAM, 4.0 * rows * ell, 2.0 * rows * ell * ell, 2);
-    CK(gram(panel, L, rows, L, h->gram_part, h->W, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
-    CK(chol_inv(h->W, L, h->ell, L, kCholDropTol, h->T, h->sc, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_XFORM, 8.0 * rows * ell, 2.0 * rows * ell * ell, 1);
-    CK(panel_xform(panel, L, L, h->T, panel, L, L, rows, st));
-  }
-  return SFD_OK;
-}
-
 // algorithmic bytes of one sparse product over the buffer: the stored entries (id + value)
 // and row pointers once, the input panel read once, the output panel written once
-double spmm_bytes(const sfd_t* h, bool transposed) {
-  const double N = h->nnz, m = h->m, d = (double)h->d, ell = h->ell;
+double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed) {
+  const double N = ln.nnz, m = ln.m, d = (double)h->d, ell = h->ell;
   return 8.0 * N + 4.0 * ((transposed ? d : m) + 1) + 4.0 * ell * (m + d);
 }
 
-int spmm_csr(sfd_t* h, const float* X, int ldx, float* Y, int ldy) {
-  ProfScope ps(h, SFD_PROF_SPMM_CSR, spmm_bytes(h, false), 2.0 * h->nnz * h->ell, 1);
-  CK(spmm(h->rowptr, h->colidx, h->val, h->m, h->sr, X, ldx, Y, ldy, h->L, h->partial, h->stream));
+// T <- R^{-1}, R the (pivoted) Cholesky factor of panel^T panel: panel * T has orthonormal
+// columns (the GramSchmidt of Alg 1 as CholeskyQR; the next sparse product applies T)
+int orth(sfd_t* h, Lane& ln, const float* panel, int64_t rows) {
+  const int L = h->L;
+  const double ell = h->ell;
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 4.0 * rows * ell, 2.0 * rows * ell * ell, 2);
+    CK(gram(panel, L, rows, L, ln.gram_part, ln.W, ln.st));
+  }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
+    CK(chol_inv(ln.W, L, h->ell, L, kCholDropTol, ln.T, ln.sc, ln.st));
+  }
   return SFD_OK;
 }
 
-int spmm_csc(sfd_t* h, const float* Y, int ldy, float* X, int ldx) {
-  ProfScope ps(h, SFD_PROF_SPMM_CSC, spmm_bytes(h, true), 2.0 * h->nnz * h->ell, 1);
-  CK(spmm(h->cscptr, h->cscrow, h->cscval, (int)h->d, h->sc_sched, Y, ldy, X, ldx, h->L, h->partial, h->stream));
+int spmm_csr(sfd_t* h, Lane& ln, const float* X, float* Y) {
+  ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false),
+               2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 2);
+  CK(spmm(ln.rowptr, ln.colidx, ln.val, ln.sr, X, h->L, Y, h->L, h->L, ln.partial, ln.T, ln.st));
   return SFD_OK;
 }
 
-// SparseShrink (Alg 3) of the buffer with start block (buffer, attempt, purpose): leaves P^T in
-// the right half of C, the Gram of C in W, M = H D and the scalars of Alg 4 on the device.
-int sparse_shrink(sfd_t* h, int purpose, int64_t buffer, int attempt, int q) {
-  hipStream_t st = h->stream;
+int spmm_csc(sfd_t* h, Lane& ln, const float* Y, float* X) {
+  ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true),
+               2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 2);
+  CK(spmm(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, Y, h->L, X, h->L, h->L, ln.partial, ln.T, ln.st));
+  return SFD_OK;
+}
+
+// Buffer set-up on the lane: CSC (with ||A'||_F^2) and, for m > ell, the chunk schedules.
+int prepare(sfd_t* h, Lane& ln) {
+  const int64_t d = h->d;
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_CSC_BUILD, 16.0 * ln.nnz + 4.0 * (ln.m + d), 0.0, 1);
+    CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, ln.cscptr, ln.cscrow, ln.cscval, ln.csc, ln.sc,
+                 ln.st));
+  }
+  if (ln.m > h->ell) {
+    ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 2);
+    ln.sr.max_chunks = std::min<int64_t>(d + h->cap / kSpmmChunk + 2, (int64_t)ln.m + ln.nnz / kSpmmChunk + 2);
+    ln.scs.max_chunks = std::min<int64_t>(d + h->cap / kSpmmChunk + 2, d + ln.nnz / kSpmmChunk + 2);
+    CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
+    CK(schedule_build(ln.cscptr, (int)d, ln.scs, ln.scan_tmp, ln.st));
+  }
+  return SFD_OK;
+}
+
+// SparseShrink (Alg 3) of the lane's buffer with the start block of `attempt`: leaves P^T in
+// ln.Pt, M = H D and the scalars of Alg 4 (S, Delta/2) on the device.  Asynchronous.
+int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   const int L = h->L, ell = h->ell;
   const int64_t d = h->d;
-  const int m = h->m;
+  const int m = ln.m;
   int rc;
   {
-    ProfScope ps(h, SFD_PROF_OTHER, 4.0 * d * ell, 0.0, 2);
-    CK(fill_f32(h->X, d * L, 0.f, st));
-    CK(start_block(h->seed, h->stream_id, (uint64_t)buffer, (uint64_t)attempt, (uint64_t)purpose, d, ell, h->X, L,
-                   st));
+    ProfScope ps(h, ln.st, SFD_PROF_OTHER, 4.0 * d * ell, 0.0, 2);
+    CK(fill_f32(ln.X, d * L, 0.f, ln.st));
+    CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.pg, d, ell, ln.X, L,
+                   ln.st));
   }
-  if ((rc = orth(h, h->X, d))) return rc;
-  for (int it = 0; it < q; ++it) {
-    if ((rc = spmm_csr(h, h->X, L, h->Y, L))) return rc;
-    if ((rc = orth(h, h->Y, m))) return rc;
-    if ((rc = spmm_csc(h, h->Y, L, h->X, L))) return rc;
-    if ((rc = orth(h, h->X, d))) return rc;
+  if ((rc = orth(h, ln, ln.X, d))) return rc;
+  for (int it = 0; it < ln.q; ++it) {
+    if ((rc = spmm_csr(h, ln, ln.X, ln.Y))) return rc;
+    if ((rc = orth(h, ln, ln.Y, m))) return rc;
+    if ((rc = spmm_csc(h, ln, ln.Y, ln.X))) return rc;
+    if ((rc = orth(h, ln, ln.X, d))) return rc;
   }
-  if ((rc = spmm_csr(h, h->X, L, h->Y, L))) return rc;
-  if ((rc = orth(h, h->Y, m))) return rc;
-  if ((rc = spmm_csc(h, h->Y, L, h->C + L, 2 * L))) return rc;
+  if ((rc = spmm_csr(h, ln, ln.X, ln.Y))) return rc;
+  if ((rc = orth(h, ln, ln.Y, m))) return rc;
+  if ((rc = spmm_csc(h, ln, ln.Y, ln.Pt))) return rc;
   {
-    ProfScope ps(h, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
-    CK(gram(h->C, 2 * L, d, 2 * L, h->gram_part, h->W, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(h->W + (int64_t)L * 2 * L + L, 2 * L, ell, h->evals, h->evecs, st));
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 4.0 * d * ell, 2.0 * d * ell * ell, 2);
+    CK(gram(ln.Pt, L, d, L, ln.gram_part, ln.W, ln.st));
   }
   {
-    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(ssh_post(h->evals, h->evecs, ell, L, kAlpha, h->M64, h->M32, h->sc, st));
+    ProfScope ps(h, ln.st, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
+    CK(eig_sym(ln.W, L, ell, ln.evals, ln.evecs, ln.st));
+  }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(ssh_post(ln.evals, ln.evecs, ell, L, kAlpha, ln.M64, ln.M32, ln.sc, ln.st));
   }
   return SFD_OK;
 }
 
-// VerifySpectral (Alg 6): t power steps from the sphere vector of (buffer, attempt, purpose);
-// returns ln ||C^t x|| in *ln_norm.
-int verify_spectral(sfd_t* h, int purpose, int64_t buffer, int attempt, int t, double* ln_norm) {
-  hipStream_t st = h->stream;
+// VerifySpectral (Alg 6): t power steps from the sphere vector of (buffer, attempt); leaves
+// ln ||C^t x|| in ln.sc.  Asynchronous.
+int verify_spectral(sfd_t* h, Lane& ln, int attempt, int t) {
   const int L = h->L, ell = h->ell;
   const int64_t d = h->d;
-  const int m = h->m;
-  const float* Pt = h->C + L;
-  ProfScope ps(h, SFD_PROF_VS, t * (16.0 * h->nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
-               t * (4.0 * h->nnz + 4.0 * d * ell), 6 * t + 3);
-  CK(start_block(h->seed, h->stream_id, (uint64_t)buffer, (uint64_t)attempt, (uint64_t)purpose, d, 1, h->vs_w, 1, st));
-  CK(vs_init(h->vs_w, d, h->vs_npart, h->sc, st));
+  const int m = ln.m;
+  ProfScope ps(h, ln.st, SFD_PROF_VS, t * (16.0 * ln.nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
+               t * (4.0 * ln.nnz + 4.0 * d * ell), 8 * t + 3);
+  CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w, 1,
+                 ln.st));
+  CK(vs_init(ln.vs_w, d, ln.vs_npart, ln.sc, ln.st));
   for (int s = 0; s < t; ++s) {
-    CK(spmv(h->rowptr, h->colidx, h->val, m, h->sr, h->vs_w, &h->sc->inv_norm, h->vs_z, h->partial, st));
-    CK(panel_gemv_t(Pt, 2 * L, L, d, h->vs_w, &h->sc->inv_norm, h->vs_gpart, st));
-    CK(spmv(h->cscptr, h->cscrow, h->cscval, (int)d, h->sc_sched, h->vs_z, nullptr, h->vs_wraw, h->partial, st));
-    CK(vs_small(h->vs_gpart, gemv_blocks(d), h->M64, ell, L, h->vs_c2, st));
-    CK(vs_finish(h->vs_wraw, Pt, 2 * L, L, ell, h->vs_c2, d, h->vs_w, h->vs_npart, st));
-    CK(vs_norm(h->vs_npart, vs_finish_blocks(d), h->sc, st));
+    CK(spmv(ln.rowptr, ln.colidx, ln.val, ln.sr, ln.vs_w, &ln.sc->inv_norm, ln.vs_z, ln.partial, ln.st));
+    CK(panel_gemv_t(ln.Pt, L, L, d, ln.vs_w, &ln.sc->inv_norm, ln.vs_gpart, ln.st));
+    CK(spmv(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, ln.vs_z, nullptr, ln.vs_wraw, ln.partial, ln.st));
+    CK(vs_small(ln.vs_gpart, gemv_blocks(d), ln.M64, ell, L, ln.vs_c2, ln.st));
+    CK(vs_finish(ln.vs_wraw, ln.Pt, L, L, ell, ln.vs_c2, d, ln.vs_w, ln.vs_npart, ln.st));
+    CK(vs_norm(ln.vs_npart, vs_finish_blocks(d), ln.sc, ln.st));
   }
   return SFD_OK;
 }
 
-// Fold the pending buffer into B (Alg 2's flush, or a query's copy of it).  B is read from the
-// left half of C; the result goes to `out` (pitch out_ld).  live/calls: results for the caller.
-int fold(sfd_t* h, int purpose_g, int purpose_x, int64_t buffer, int64_t vs_base, float* out, int out_ld,
-         int* live_out, int64_t* calls_out) {
-  hipStream_t st = h->stream;
+// Issue everything of a buffer step that does not depend on B or on the VerifySpectral counter.
+int issue_shrink(sfd_t* h, Lane& ln) {
+  int rc = prepare(h, ln);
+  if (rc) return rc;
+  if (ln.m <= h->ell) {
+    // exact buffer (SparseShrink needs ell <= m): P^T = A'^T, M = I
+    CK(dense_from_csc(ln.cscptr, ln.cscrow, ln.cscval, h->d, ln.Pt, h->L, h->L, ln.st));
+    CK(ssh_identity(h->ell, h->L, ln.M64, ln.M32, ln.sc, ln.st));
+    return SFD_OK;
+  }
+  ln.q = si_iterations(h, ln.m);
+  return sparse_shrink(h, ln, 0);
+}
+
+// DenseShrink (Alg 5) of [B; B'] with B'^T = P^T M (M = I for an exact block); the stack is
+// kept exactly when it has at most ell live rows.  B is read from `Bin`, the result goes to
+// `out` (both d x L).  Waits for the previous DenseShrink and records its own completion.
+int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int lossless, float* out) {
   const int L = h->L, ell = h->ell;
   const int64_t d = h->d;
-  const int m = h->m;
-  int rc;
-  *calls_out = 0;
+  CK(hipStreamWaitEvent(ln.st, h->ev_dsh, 0));
   {
-    ProfScope ps(h, SFD_PROF_CSC_BUILD, 16.0 * h->nnz + 4.0 * (m + d), 0.0, 1);
-    CK(build_csc(h->rowptr, h->colidx, h->val, m, h->nnz, d, h->cscptr, h->cscrow, h->cscval, h->csc, h->sc, st));
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
+    CK(gram2(Bin, L, Pt, L, d, L, ln.gram_part, ln.W2, ln.st));
   }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(dsh_assemble(ln.W2, L, ell, ln.M64, ln.SS, ln.st));
+  }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
+    CK(eig_sym(ln.SS, 2 * ell, 2 * ell, ln.evals, ln.evecs, ln.st));
+  }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
+    CK(dsh_post(ln.evals, ln.evecs, ell, L, ln.M64, lossless, ln.T2, ln.sc, ln.st));
+  }
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_XFORM, 12.0 * d * ell, 4.0 * d * ell * ell, 1);
+    CK(panel_xform2(Bin, L, Pt, L, L, ln.T2, out, L, d, ln.st));
+  }
+  CK(hipEventRecord(h->ev_dsh, ln.st));
+  return SFD_OK;
+}
+
+// The in-order part of a buffer step: BoostedSparseShrink's acceptance (Alg 4, with the
+// VerifySpectral counter continued from vs_base) and the DenseShrink into `out`.
+// *live = structural live rows of the result, *calls = VerifySpectral calls made.
+int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* Bin, float* out, int* live,
+                int64_t* calls) {
+  const int ell = h->ell;
+  int rc;
+  *calls = 0;
   int r_add;
-  if (m <= ell) {
-    // exact buffer (SparseShrink needs ell <= m): P^T = A'^T, M = I
-    CK(dense_from_csc(h->cscptr, h->cscrow, h->cscval, d, h->C + L, 2 * L, L, st));
-    CK(ssh_identity(ell, L, h->M64, h->M32, h->sc, st));
-    CK(gram(h->C, 2 * L, d, 2 * L, h->gram_part, h->W, st));
-    r_add = m;
+  if (ln.m <= ell) {
+    r_add = ln.m;
   } else {
-    if ((rc = build_schedule(h, h->rowptr, m, h->sr))) return rc;
-    if ((rc = build_schedule(h, h->cscptr, (int)d, h->sc_sched))) return rc;
-    const int q = si_iterations(h, m);
     bool accepted = false;
-    int64_t calls = 0;
-    for (int a = 0; a < h->max_attempts && !accepted; ++a) {
-      if ((rc = sparse_shrink(h, purpose_g, buffer, a, q))) return rc;
-      if ((rc = read_scalars(h))) return rc;
-      const DevScalars s = *h->sc_host;
+    for (int a = 0;; ++a) {
+      if ((rc = read_scalars(h, ln))) return rc;
+      const DevScalars s = *ln.sc_host;
       h->stats.attempts += 1;
-      h->stats.last_q = q;
+      h->stats.last_q = ln.q;
       h->stats.last_fro2_buffer = s.fro2A;
       h->stats.last_lambda_ell2 = s.lam_ell2;
       h->stats.last_delta = 2.0 * s.half_delta;
@@ -426,70 +507,102 @@ int fold(sfd_t* h, int purpose_g, int purpose_x, int64_t buffer, int64_t vs_base
         accepted = true;
         break;
       }
-      ++calls;
-      const int t = vs_steps(h, vs_base + calls);
-      double ln_norm = 0.0;
-      if ((rc = verify_spectral(h, purpose_x, buffer, a, t, &ln_norm))) return rc;
-      if ((rc = read_scalars(h))) return rc;
-      ln_norm = h->sc_host->ln_norm;
+      *calls += 1;
+      const int t = vs_steps(h, vs_base + *calls);
+      if ((rc = verify_spectral(h, ln, a, t))) return rc;
+      if ((rc = read_scalars(h, ln))) return rc;
+      const double ln_norm = ln.sc_host->ln_norm;
       h->stats.last_t = t;
       h->stats.last_ln_norm = ln_norm;
-      if (ln_norm <= 0.0)
+      if (ln_norm <= 0.0) {
         accepted = true;
-      else
-        h->stats.vs_rejects += 1;
+        break;
+      }
+      h->stats.vs_rejects += 1;
+      if (a + 1 >= h->max_attempts) break;
+      if ((rc = sparse_shrink(h, ln, a + 1))) return rc;
     }
-    *calls_out = calls;
     if (!accepted) return fail(h, SFD_E_NOCONVERGE);
     r_add = ell - 1;
   }
-  const int lossless = (h->live + r_add <= ell) ? 1 : 0;
-  {
-    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(dsh_assemble(h->W, L, ell, h->M64, h->SS, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(h->SS, 2 * ell, 2 * ell, h->evals, h->evecs, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(dsh_post(h->evals, h->evecs, ell, L, h->M64, lossless, h->T2, h->sc, st));
-  }
-  {
-    ProfScope ps(h, SFD_PROF_XFORM, 12.0 * d * ell, 4.0 * d * ell * ell, 1);
-    CK(panel_xform(h->C, 2 * L, 2 * L, h->T2, out, out_ld, L, d, st));
-  }
-  *live_out = lossless ? h->live + r_add : ell - 1;
-  return sync(h);
-}
-
-int flush(sfd_t* h) {
-  int live = 0;
-  int64_t calls = 0;
-  int rc = fold(h, kPurposeSI, kPurposeVS, h->flushes, h->vs_calls, h->C, 2 * h->L, &live, &calls);
-  if (rc) return rc;
-  h->live = live;
-  h->vs_calls += calls;
-  h->flushes += 1;
-  h->m = 0;
-  h->nnz = 0;
+  const int lossless = (live_in + r_add <= ell) ? 1 : 0;
+  if ((rc = dense_shrink(h, ln, Bin, ln.Pt, lossless, out))) return rc;
+  *live = lossless ? live_in + r_add : ell - 1;
   return SFD_OK;
 }
 
-// Query: fold the pending rows into a copy of B (left in Bq, pitch L), or point at B itself.
-int query(sfd_t* h, const float** panel, int* ld, int* live, int64_t* calls) {
+// A buffer of the stream: a CSR view plus where its rows come from.
+struct BufferView {
+  const int* rowptr;      // int32 row pointers (if already rebased), else nullptr
+  const int64_t* indptr;  // caller's int64 row pointers to rebase from (device), or nullptr
+  int64_t r0;             // first row in indptr
+  const int* colidx;
+  const float* val;
+  int m, nnz;
+};
+
+int bind(sfd_t* h, Lane& ln, const BufferView& v, int64_t buffer, int pg, int px) {
+  ln.m = v.m;
+  ln.nnz = v.nnz;
+  ln.colidx = v.colidx;
+  ln.val = v.val;
+  ln.buffer = buffer;
+  ln.pg = pg;
+  ln.px = px;
+  if (v.rowptr) {
+    ln.rowptr = v.rowptr;
+  } else {
+    CK(fill_i32(ln.own_rowptr, 1, 0, ln.st));
+    CK(append_rowptr(v.indptr, v.r0, v.m, ln.own_rowptr, 0, 0, ln.st));
+    ln.rowptr = ln.own_rowptr;
+  }
+  return SFD_OK;
+}
+
+// Run the buffer steps of `views` (consecutive flushes of the stream) through the lanes.
+int run_flushes(sfd_t* h, const std::vector<BufferView>& views) {
+  const int nbuf = (int)views.size();
+  int rc;
+  for (int b = 0; b < nbuf && b < kLanes; ++b) {
+    Lane& ln = h->lanes[b % kLanes];
+    if ((rc = bind(h, ln, views[b], h->flushes + b, kPurposeSI, kPurposeVS))) return rc;
+    if ((rc = issue_shrink(h, ln))) return rc;
+  }
+  for (int b = 0; b < nbuf; ++b) {
+    Lane& ln = h->lanes[b % kLanes];
+    int live = 0;
+    int64_t calls = 0;
+    if ((rc = finish_step(h, ln, h->vs_calls, h->live, h->B, h->B, &live, &calls))) return rc;
+    h->live = live;
+    h->vs_calls += calls;
+    h->flushes += 1;
+    if (b + kLanes < nbuf) {
+      // same lane: ordered after this buffer's DenseShrink by the stream
+      if ((rc = bind(h, ln, views[b + kLanes], h->flushes - 1 + kLanes, kPurposeSI, kPurposeVS))) return rc;
+      if ((rc = issue_shrink(h, ln))) return rc;
+    }
+  }
+  return SFD_OK;
+}
+
+// Query: B with the pending rows folded into a copy (purposes 2/3, counter from vs_calls + 1,
+// nothing stored).  Returns the panel holding the result.
+int query(sfd_t* h, const float** panel, int* live, int64_t* calls) {
   *calls = 0;
-  if (h->m == 0) {
-    *panel = h->C;
-    *ld = 2 * h->L;
+  int rc = sync_all(h);
+  if (rc) return rc;
+  if (h->pm == 0) {
+    *panel = h->B;
     *live = h->live;
     return SFD_OK;
   }
-  int rc = fold(h, kPurposeQuerySI, kPurposeQueryVS, h->flushes, h->vs_calls, h->Bq, h->L, live, calls);
-  if (rc) return rc;
+  Lane& ln = h->lanes[0];
+  BufferView v{h->prow, nullptr, 0, h->pcol, h->pval, h->pm, h->pnnz};
+  if ((rc = bind(h, ln, v, h->flushes, kPurposeQuerySI, kPurposeQueryVS))) return rc;
+  if ((rc = issue_shrink(h, ln))) return rc;
+  if ((rc = finish_step(h, ln, h->vs_calls, h->live, h->B, h->Bq, live, calls))) return rc;
+  if ((rc = sync_all(h))) return rc;
   *panel = h->Bq;
-  *ld = h->L;
   return SFD_OK;
 }
 
@@ -499,46 +612,39 @@ int check_handle(sfd_t* h) {
   return SFD_OK;
 }
 
-// Append rows [r0, r1) of a block whose entries [p0, p1) are known on the host.
-int copy_rows_device(sfd_t* h, const int64_t* indptr, const int32_t* indices, const float* values, int64_t r0,
-                     int64_t r1, int64_t p0, int64_t p1) {
-  hipStream_t st = h->stream;
+// Rows [r0, r1) (entries [p0, p1)) of a block appended to the pending buffer.
+int to_pending(sfd_t* h, bool host, const int64_t* indptr, const int32_t* indices, const float* values, int64_t r0,
+               int64_t r1, int64_t p0, int64_t p1) {
+  Lane& l0 = h->lanes[0];
   const int64_t cnt = r1 - r0, nz = p1 - p0;
   if (cnt <= 0) return SFD_OK;
-  CK(append_rowptr(indptr, r0, cnt, h->rowptr, h->m, h->nnz, st));
-  if (nz > 0) {
-    CK(hipMemcpyAsync(h->colidx + h->nnz, indices + p0, sizeof(int32_t) * nz, hipMemcpyDeviceToDevice, st));
-    CK(hipMemcpyAsync(h->val + h->nnz, values + p0, sizeof(float) * nz, hipMemcpyDeviceToDevice, st));
+  const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  if (host) {
+    std::vector<int> rp((size_t)cnt);
+    for (int64_t i = 0; i < cnt; ++i) rp[(size_t)i] = (int)(indptr[r0 + 1 + i] - p0) + h->pnnz;
+    CK(hipMemcpyAsync(h->prow + h->pm + 1, rp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, l0.st));
+    if (nz > 0) {
+      CK(hipMemcpyAsync(h->pcol + h->pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(h->pval + h->pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
+    }
+    int rc = sync_lane(h, l0);  // the staging vector goes out of scope
+    if (rc) return rc;
+  } else {
+    CK(append_rowptr(indptr, r0, cnt, h->prow, h->pm, h->pnnz, l0.st));
+    if (nz > 0) {
+      CK(hipMemcpyAsync(h->pcol + h->pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(h->pval + h->pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
+    }
   }
-  h->m += (int)cnt;
-  h->nnz += (int)nz;
+  h->pm += (int)cnt;
+  h->pnnz += (int)nz;
   return SFD_OK;
 }
 
-int copy_rows_host(sfd_t* h, const int64_t* indptr, const int32_t* indices, const float* values, int64_t r0,
-                   int64_t r1) {
-  hipStream_t st = h->stream;
-  const int64_t cnt = r1 - r0;
-  if (cnt <= 0) return SFD_OK;
-  const int64_t p0 = indptr[r0], p1 = indptr[r1], nz = p1 - p0;
-  std::vector<int> rp((size_t)cnt);
-  for (int64_t i = 0; i < cnt; ++i) rp[(size_t)i] = (int)(indptr[r0 + 1 + i] - p0) + h->nnz;
-  CK(hipMemcpyAsync(h->rowptr + h->m + 1, rp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, st));
-  if (nz > 0) {
-    CK(hipMemcpyAsync(h->colidx + h->nnz, indices + p0, sizeof(int32_t) * nz, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->val + h->nnz, values + p0, sizeof(float) * nz, hipMemcpyHostToDevice, st));
-  }
-  int rc = sync(h);  // the staging vector goes out of scope
-  if (rc) return rc;
-  h->m += (int)cnt;
-  h->nnz += (int)nz;
-  return SFD_OK;
-}
-
-// Alg 2's rule, on the host: rows after which a flush happens.
+// Alg 2's rule on host row pointers: rows after which a flush happens.
 void host_cuts(const sfd_t* h, const int64_t* indptr, int64_t nrows, std::vector<int64_t>& cuts) {
   const int64_t budget = (int64_t)h->ell * h->d;
-  int64_t r = 0, m = h->m, z = h->nnz;
+  int64_t r = 0, m = h->pm, z = h->pnnz;
   while (r < nrows) {
     const int64_t target = budget - z + indptr[r];
     const int64_t* it = std::lower_bound(indptr + r + 1, indptr + nrows + 1, target);
@@ -588,11 +694,6 @@ int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t** out) {
     delete h;
     return SFD_E_DEVICE;
   }
-  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess) {
-    delete h;
-    return SFD_E_DEVICE;
-  }
-  h->stream = h->own_stream;
   int rc = alloc_state(h);
   if (rc == SFD_OK) rc = reset_state(h);
   if (rc != SFD_OK) {
@@ -607,7 +708,8 @@ int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t** out) {
 int sfd_destroy(sfd_t* h) {
   if (!h) return SFD_OK;
   DeviceGuard g(h->device);
-  (void)hipStreamSynchronize(h->stream);
+  for (Lane& ln : h->lanes)
+    if (ln.st) (void)hipStreamSynchronize(ln.st);
   free_all(h);
   delete h;
   return SFD_OK;
@@ -655,8 +757,9 @@ int sfd_set_option(sfd_t* h, int key, double value) {
 int sfd_set_stream(sfd_t* h, void* hip_stream) {
   if (!h) return SFD_E_ARG;
   DeviceGuard g(h->device);
-  (void)hipStreamSynchronize(h->stream);
-  h->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->own_stream;
+  int rc = sync_all(h);
+  if (rc) return rc;
+  h->user_stream = static_cast<hipStream_t>(hip_stream);
   return SFD_OK;
 }
 
@@ -666,8 +769,8 @@ int sfd_get_stats(const sfd_t* h, sfd_stats_t* out) {
   out->flushes = h->flushes;
   out->vs_calls = h->vs_calls;
   out->live_rows = h->live;
-  out->pending_rows = h->m;
-  out->pending_nnz = h->nnz;
+  out->pending_rows = h->pm;
+  out->pending_nnz = h->pnnz;
   return SFD_OK;
 }
 
@@ -685,9 +788,14 @@ int sfd_append_csr(sfd_t* h, int64_t nrows, const int64_t* indptr, const int32_t
   if (nrows == 0) return SFD_OK;
   if (!indptr) return SFD_E_ARG;
   DeviceGuard g(h->device);
-  hipStream_t st = h->stream;
-  if (mem == SFD_MEM_HOST) {
-    const int64_t lo = indptr[0], hi = indptr[nrows];
+  if ((rc = order_after_caller(h))) return rc;
+  Lane& l0 = h->lanes[0];
+  const bool host = mem == SFD_MEM_HOST;
+  int64_t lo, hi;
+  std::vector<int64_t> cuts, cut_ptr;
+  if (host) {
+    lo = indptr[0];
+    hi = indptr[nrows];
     if (hi < lo || lo < 0) return SFD_E_ARG;
     if (hi > lo && (!indices || !values)) return SFD_E_ARG;
     for (int64_t r = 0; r < nrows; ++r) {
@@ -696,61 +804,73 @@ int sfd_append_csr(sfd_t* h, int64_t nrows, const int64_t* indptr, const int32_t
     }
     for (int64_t k = lo; k < hi; ++k)
       if (indices[k] < 0 || (int64_t)indices[k] >= h->d) return SFD_E_INDEX;
-    std::vector<int64_t> cuts;
     host_cuts(h, indptr, nrows, cuts);
-    int64_t r = 0;
-    for (int64_t c : cuts) {
-      if ((rc = copy_rows_host(h, indptr, indices, values, r, c + 1))) return rc;
-      if ((rc = flush(h))) return rc;
-      r = c + 1;
+    for (int64_t c : cuts) cut_ptr.push_back(indptr[c + 1]);
+  } else {
+    int64_t* hv = h->i64_host;
+    CK(hipMemcpyAsync(hv + 0, indptr, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+    CK(hipMemcpyAsync(hv + 1, indptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+    if ((rc = sync_lane(h, l0))) return rc;
+    lo = hv[0];
+    hi = hv[1];
+    if (hi < lo || lo < 0) return SFD_E_ARG;
+    if (hi > lo && (!indices || !values)) return SFD_E_ARG;
+    CK(fill_i32(h->err_dev, 1, 0, l0.st));
+    CK(validate_rows(indptr, nrows, h->d, h->err_dev, l0.st));
+    CK(validate_indices(indices, lo, hi, h->d, h->err_dev, l0.st));
+    int* e32 = reinterpret_cast<int*>(hv + 2);
+    CK(hipMemcpyAsync(e32, h->err_dev, sizeof(int), hipMemcpyDeviceToHost, l0.st));
+    if ((rc = sync_lane(h, l0))) return rc;
+    if (*e32 & 1) return SFD_E_ARG;
+    if (*e32 & 2) return SFD_E_INDEX;
+    const int64_t max_cuts = (nrows + h->pm) / h->ell + 2;
+    if (max_cuts > h->cut_cap) {
+      int64_t* p = nullptr;
+      if (!dalloc(h, &p, 1 + 2 * max_cuts)) return SFD_E_NOMEM;
+      h->cut_dev = p;
+      h->cut_cap = max_cuts;
     }
-    if ((rc = copy_rows_host(h, indptr, indices, values, r, nrows))) return rc;
-    h->stats.rows_seen += nrows;
-    h->stats.nnz_seen += hi - lo;
-    return SFD_OK;
+    CK(find_cuts(indptr, nrows, h->pm, h->pnnz, (int64_t)h->ell * h->d, h->d, max_cuts, h->cut_dev + 1,
+                 h->cut_dev + 1 + h->cut_cap, h->cut_dev, l0.st));
+    CK(hipMemcpyAsync(hv + 3, h->cut_dev, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+    if ((rc = sync_lane(h, l0))) return rc;
+    const int64_t ncuts = hv[3];
+    cuts.resize((size_t)ncuts);
+    cut_ptr.resize((size_t)ncuts);
+    if (ncuts > 0) {
+      CK(hipMemcpy(cuts.data(), h->cut_dev + 1, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
+      CK(hipMemcpy(cut_ptr.data(), h->cut_dev + 1 + h->cut_cap, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
+    }
   }
-  // device block: read the ends, validate on the device, then find the cuts on the device
-  int64_t* hv = h->i64_host;
-  CK(hipMemcpyAsync(hv + 0, indptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(hv + 1, indptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  if ((rc = sync(h))) return rc;
-  const int64_t lo = hv[0], hi = hv[1];
-  if (hi < lo || lo < 0) return SFD_E_ARG;
-  if (hi > lo && (!indices || !values)) return SFD_E_ARG;
-  CK(fill_i32(h->err_dev, 1, 0, st));
-  CK(validate_rows(indptr, nrows, h->d, h->err_dev, st));
-  CK(validate_indices(indices, lo, hi, h->d, h->err_dev, st));
-  int* hi32 = reinterpret_cast<int*>(hv + 2);
-  CK(hipMemcpyAsync(hi32, h->err_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-  if ((rc = sync(h))) return rc;
-  if (*hi32 & 1) return SFD_E_ARG;
-  if (*hi32 & 2) return SFD_E_INDEX;
-  const int64_t max_cuts = (nrows + h->m) / h->ell + 2;
-  if (max_cuts > h->cut_cap) {
-    int64_t* p = nullptr;
-    if (!dalloc(h, &p, 1 + 2 * max_cuts)) return SFD_E_NOMEM;
-    h->cut_dev = p;
-    h->cut_cap = max_cuts;
-  }
-  CK(find_cuts(indptr, nrows, h->m, h->nnz, (int64_t)h->ell * h->d, h->d, max_cuts, h->cut_dev + 1,
-               h->cut_dev + 1 + max_cuts, h->cut_dev, st));
-  CK(hipMemcpyAsync(hv + 3, h->cut_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  if ((rc = sync(h))) return rc;
-  const int64_t ncuts = hv[3];
-  std::vector<int64_t> cuts((size_t)ncuts), cut_ptr((size_t)ncuts);
-  if (ncuts > 0) {
-    CK(hipMemcpy(cuts.data(), h->cut_dev + 1, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
-    CK(hipMemcpy(cut_ptr.data(), h->cut_dev + 1 + max_cuts, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
-  }
+  // the full buffers of this block: the first one continues the pending rows (copied), the
+  // others are read in place from the caller's device arrays; host blocks are staged one
+  // buffer at a time through the pending buffer
+  std::vector<BufferView> views;
   int64_t r = 0, p = lo;
-  for (int64_t k = 0; k < ncuts; ++k) {
-    if ((rc = copy_rows_device(h, indptr, indices, values, r, cuts[(size_t)k] + 1, p, cut_ptr[(size_t)k]))) return rc;
-    if ((rc = flush(h))) return rc;
-    r = cuts[(size_t)k] + 1;
-    p = cut_ptr[(size_t)k];
+  for (size_t k = 0; k < cuts.size(); ++k) {
+    const int64_t r1 = cuts[k] + 1, p1 = cut_ptr[k];
+    if (host && !views.empty()) {
+      if ((rc = run_flushes(h, views))) return rc;
+      views.clear();
+      if ((rc = sync_all(h))) return rc;
+      h->pm = h->pnnz = 0;
+    }
+    if (host || (k == 0 && h->pm > 0)) {
+      if ((rc = to_pending(h, host, indptr, indices, values, r, r1, p, p1))) return rc;
+      views.push_back({h->prow, nullptr, 0, h->pcol, h->pval, h->pm, h->pnnz});
+    } else {
+      views.push_back({nullptr, indptr, r, indices + p, values + p, (int)(r1 - r), (int)(p1 - p)});
+    }
+    r = r1;
+    p = p1;
   }
-  if ((rc = copy_rows_device(h, indptr, indices, values, r, nrows, p, hi))) return rc;
-  if ((rc = sync(h))) return rc;
+  if (!views.empty()) {
+    if ((rc = run_flushes(h, views))) return rc;
+    if ((rc = sync_all(h))) return rc;
+    h->pm = h->pnnz = 0;
+  }
+  if ((rc = to_pending(h, host, indptr, indices, values, r, nrows, p, hi))) return rc;
+  if ((rc = sync_all(h))) return rc;
   h->stats.rows_seen += nrows;
   h->stats.nnz_seen += hi - lo;
   return SFD_OK;
@@ -761,17 +881,19 @@ int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
   if (rc) return rc;
   if (!B_out || (mem != SFD_MEM_HOST && mem != SFD_MEM_DEVICE)) return SFD_E_ARG;
   DeviceGuard g(h->device);
+  if ((rc = order_after_caller(h))) return rc;
   const float* panel;
-  int ld, live;
+  int live;
   int64_t calls;
-  if ((rc = query(h, &panel, &ld, &live, &calls))) return rc;
+  if ((rc = query(h, &panel, &live, &calls))) return rc;
+  Lane& l0 = h->lanes[0];
   if (mem == SFD_MEM_DEVICE) {
-    CK(transpose_out(panel, ld, h->d, h->ell, B_out, h->stream));
+    CK(transpose_out(panel, h->L, h->d, h->ell, B_out, l0.st));
   } else {
-    CK(transpose_out(panel, ld, h->d, h->ell, h->X, h->stream));
-    CK(hipMemcpyAsync(B_out, h->X, sizeof(float) * h->d * h->ell, hipMemcpyDeviceToHost, h->stream));
+    CK(transpose_out(panel, h->L, h->d, h->ell, l0.X, l0.st));
+    CK(hipMemcpyAsync(B_out, l0.X, sizeof(float) * h->d * h->ell, hipMemcpyDeviceToHost, l0.st));
   }
-  if ((rc = sync(h))) return rc;
+  if ((rc = sync_all(h))) return rc;
   if (live_rows) *live_rows = live;
   return SFD_OK;
 }
@@ -785,30 +907,23 @@ int sfd_merge(sfd_t* dst, sfd_t* src) {
   if (dst->device != src->device) return SFD_E_ARG;
   DeviceGuard g(dst->device);
   sfd_t* h = dst;
+  if ((rc = order_after_caller(dst))) return rc;
+  if ((rc = order_after_caller(src))) return rc;
   const float *ps, *pd;
-  int lds, ldd, live_s, live_d;
+  int live_s, live_d;
   int64_t calls_s, calls_d;
-  if ((rc = query(src, &ps, &lds, &live_s, &calls_s))) return rc;
-  if ((rc = query(dst, &pd, &ldd, &live_d, &calls_d))) return rc;
-  const int L = h->L, ell = h->ell;
-  const int64_t d = h->d;
-  hipStream_t st = h->stream;
-  // C = [query(dst)^T | query(src)^T]; DenseShrink with M = I
-  if (pd != h->C) CK(copy_panel(pd, ldd, h->C, 2 * L, d, L, st));
-  CK(copy_panel(ps, lds, h->C + L, 2 * L, d, L, st));
-  CK(ssh_identity(ell, L, h->M64, h->M32, h->sc, st));
-  CK(gram(h->C, 2 * L, d, 2 * L, h->gram_part, h->W, st));
-  const int lossless = (live_d + live_s <= ell) ? 1 : 0;
-  CK(dsh_assemble(h->W, L, ell, h->M64, h->SS, st));
-  CK(eig_sym(h->SS, 2 * ell, 2 * ell, h->evals, h->evecs, st));
-  CK(dsh_post(h->evals, h->evecs, ell, L, h->M64, lossless, h->T2, h->sc, st));
-  CK(panel_xform(h->C, 2 * L, 2 * L, h->T2, h->C, 2 * L, L, d, st));
-  if ((rc = sync(h))) return rc;
-  h->live = lossless ? live_d + live_s : ell - 1;
+  if ((rc = query(src, &ps, &live_s, &calls_s))) return rc;
+  if ((rc = query(dst, &pd, &live_d, &calls_d))) return rc;
+  // stack [query(dst); query(src)], DenseShrink with M = I
+  Lane& ln = h->lanes[0];
+  CK(ssh_identity(h->ell, h->L, ln.M64, ln.M32, ln.sc, ln.st));
+  const int lossless = (live_d + live_s <= h->ell) ? 1 : 0;
+  if ((rc = dense_shrink(h, ln, pd, ps, lossless, h->B))) return rc;
+  if ((rc = sync_all(h))) return rc;
+  h->live = lossless ? live_d + live_s : h->ell - 1;
   h->vs_calls += calls_d;
   h->flushes += 1;
-  h->m = 0;
-  h->nnz = 0;
+  h->pm = h->pnnz = 0;
   return SFD_OK;
 }
 

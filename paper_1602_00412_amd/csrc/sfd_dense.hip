@@ -13,21 +13,27 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGramMaxBlocks = 512;
+constexpr int kGramMaxBlocks = 256;
 
 // Gram partial of a row block.  MFMA v_mfma_f32_16x16x4f32: A (16 x 4) and B (4 x 16) come one
 // float per lane, lane l holding row-of-A / column-of-B (l % 16) at k = l / 16; the 16 x 16
 // accumulator leaves 4 floats per lane, lane l holding column l % 16, rows 4*(l/16) .. +3.
 // For W = P^T P both operands are the same 4-row slab of the panel: lane l loads
-// P[k0 + l/16][16*s + l%16] for each 16-column strip s.
-template <int W>
-__global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ P, int ld, int64_t rows, int rpb,
-                                                      float* __restrict__ partials) {
-  constexpr int S = W / 16;          // strips
-  constexpr int NT = S * S;          // 16 x 16 tiles
-  constexpr int TG = NT >= 64 ? 4 : 1;  // tile groups (waves split tiles)
-  constexpr int KG = 4 / TG;            // k groups (waves split rows)
-  constexpr int TPW = NT / TG;          // tiles per wave
+// P[k0 + l/16][16*s + l%16] for each 16-column strip s.  Eight waves per block split the rows
+// (and, for W = 128, the tiles); the next slab is loaded while the current one is multiplied.
+constexpr int kGramThreads = 512;
+constexpr int kGramWaves = kGramThreads / 64;
+
+// TWO: the panel is [P | P2] side by side, each W/2 wide (strips of the right half from P2).
+template <int W, bool TWO>
+__global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __restrict__ P, int ld,
+                                                               const float* __restrict__ P2, int ld2, int64_t rows,
+                                                               int rpb, float* __restrict__ partials) {
+  constexpr int S = W / 16;                // strips
+  constexpr int NT = S * S;                // 16 x 16 tiles
+  constexpr int TG = NT >= 64 ? 4 : 1;     // tile groups (waves split tiles)
+  constexpr int KG = kGramWaves / TG;      // k groups (waves split rows)
+  constexpr int TPW = NT / TG;             // tiles per wave
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tg = wave % TG;
@@ -39,94 +45,119 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
   for (int t = 0; t < TPW; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lrow = lane >> 4;
   const int lcol = lane & 15;
-  for (int64_t k0 = r0 + 4 * kg; k0 < r1; k0 += 4 * KG) {
+  constexpr int SPLIT = TWO ? S / 2 : S;  // strips read from P; the rest from P2
+  float f[S], g[S];
+  int64_t k0 = r0 + 4 * kg;
+  {
     const int64_t row = k0 + lrow;
-    float f[S];
-    if (row < r1) {
-      const float* pr = P + row * ld + lcol;
+    const bool ok = row < r1;
+    const float* pr = P + (ok ? row : 0) * ld + lcol;
+    const float* pr2 = P2 + (ok ? row : 0) * ld2 + lcol;
 #pragma unroll
-      for (int s = 0; s < S; ++s) f[s] = pr[16 * s];
-    } else {
+    for (int s = 0; s < S; ++s) f[s] = ok ? (s < SPLIT ? pr[16 * s] : pr2[16 * (s - SPLIT)]) : 0.f;
+  }
+  for (; k0 < r1; k0 += 4 * KG) {
+    const int64_t nrow = k0 + 4 * KG + lrow;
+    const bool ok = nrow < r1;
+    const float* pr = P + (ok ? nrow : 0) * ld + lcol;
+    const float* pr2 = P2 + (ok ? nrow : 0) * ld2 + lcol;
 #pragma unroll
-      for (int s = 0; s < S; ++s) f[s] = 0.f;
-    }
+    for (int s = 0; s < S; ++s) g[s] = ok ? (s < SPLIT ? pr[16 * s] : pr2[16 * (s - SPLIT)]) : 0.f;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = tg * TPW + t;
       const int ti = tile / S, tj = tile % S;
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[ti], f[tj], acc[t], 0, 0, 0);
     }
+#pragma unroll
+    for (int s = 0; s < S; ++s) f[s] = g[s];
   }
   float* out = partials + (int64_t)blockIdx.x * W * W;
-  if constexpr (KG == 1) {
+  // each k group writes its sums to its own LDS region; then all threads add the regions in
+  // k-group order (W = 64: 8 x 16 KiB, W = 128: 2 x 64 KiB)
+  __shared__ float red[KG][W * W];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = tg * TPW + t;
-      const int ti = tile / S, tj = tile % S;
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = tg * TPW + t;
+    const int ti = tile / S, tj = tile % S;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(16 * ti + 4 * lrow + v) * W + 16 * tj + lcol] = acc[t][v];
-    }
-  } else {
-    __shared__ float red[W * W];
-    for (int g = 0; g < KG; ++g) {
-      if (kg == g) {
+    for (int v = 0; v < 4; ++v) red[kg][(16 * ti + 4 * lrow + v) * W + 16 * tj + lcol] = acc[t][v];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < W * W; e += kGramThreads) {
+    float sum = red[0][e];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-          const int tile = tg * TPW + t;
-          const int ti = tile / S, tj = tile % S;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int e = (16 * ti + 4 * lrow + v) * W + 16 * tj + lcol;
-            red[e] = (g == 0) ? acc[t][v] : red[e] + acc[t][v];
-          }
-        }
-      }
-      __syncthreads();
-    }
-    for (int e = threadIdx.x; e < W * W; e += 256) out[e] = red[e];
+    for (int g2 = 1; g2 < KG; ++g2) sum += red[g2][e];
+    out[e] = sum;
   }
 }
 
-// W64[i][j] = sum over blocks (in block order, FP64) of the upper-triangle partial (i <= j),
-// mirrored, so W64 is exactly symmetric.
-__global__ void k_gram_reduce(const float* __restrict__ partials, int nb, int W, double* __restrict__ Wout) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= W * W) return;
-  int i = e / W, j = e % W;
-  int src = i <= j ? e : j * W + i;
+// W64[i][j] = sum over blocks of the upper-triangle partial (i <= j), mirrored, so W64 is exactly
+// symmetric.  A block owns 16 entries; sixteen thread groups sum interleaved sixteenths of the
+// partials (fixed order) and the group sums are added in group order.
+__global__ __launch_bounds__(256) void k_gram_reduce(const float* __restrict__ partials, int nb, int W,
+                                                     double* __restrict__ Wout) {
+  __shared__ double red[16][16];
+  const int q = threadIdx.x & 15;
+  const int grp = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + q;
+  const int WW = W * W;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += (double)partials[(int64_t)b * W * W + src];
-  Wout[e] = s;
+  if (e < WW) {
+    const int i = e / W, j = e % W;
+    const int src = i <= j ? e : j * W + i;
+    const float* p = partials + src;
+    int b = grp;
+    for (; b + 16 < nb; b += 32) {
+      const float v0 = p[(int64_t)b * WW], v1 = p[(int64_t)(b + 16) * WW];
+      s += (double)v0;
+      s += (double)v1;
+    }
+    for (; b < nb; b += 16) s += (double)p[(int64_t)b * WW];
+  }
+  red[grp][q] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && e < WW) {
+    double t = 0.0;
+#pragma unroll
+    for (int g2 = 0; g2 < 16; ++g2) t += red[g2][q];
+    Wout[e] = t;
+  }
 }
 
-// out[j, 0:WOUT] = in[j, 0:WIN] * T.  One wave per row; lane c keeps column c of T in
-// registers and gathers the input row through readlane broadcasts.
-template <int WIN, int WOUT>
-__global__ __launch_bounds__(256) void k_panel_xform(const float* in, int ldi, const float* __restrict__ T,
-                                                     float* out, int ldo, int64_t rows) {
-  static_assert((WIN == 32 || WIN == 64 || WIN == 128) && WOUT <= 64, "panel shape");
-  constexpr int KA = WIN < 64 ? WIN : 64;
+// out[j, 0:L] = [P1[j, 0:L] | P2[j, 0:L]] * T2 (T2: 2L x L).  One wave per row; lane c keeps
+// column c of T2 in registers and receives the row through readlane broadcasts.  The row is
+// read before it is written, so out may be P1.
+template <int L>
+__global__ __launch_bounds__(256) void k_panel_xform2(const float* P1, int ld1, const float* P2, int ld2,
+                                                      const float* __restrict__ T2, float* out, int ldo,
+                                                      int64_t rows) {
+  static_assert(L == 32 || L == 64, "panel width");
+  constexpr int WIN = 2 * L;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
   float t[WIN];
 #pragma unroll
-  for (int k = 0; k < WIN; ++k) t[k] = lane < WOUT ? T[k * WOUT + lane] : 0.f;
+  for (int k = 0; k < WIN; ++k) t[k] = lane < L ? T2[k * L + lane] : 0.f;
   for (int64_t r = wave; r < rows; r += nwaves) {
-    const float* ir = in + r * ldi;
-    const float a = lane < KA ? ir[lane] : 0.f;
-    float b = 0.f;
-    if constexpr (WIN > 64) b = ir[64 + lane];
+    float a, b = 0.f;
+    if constexpr (L == 64) {
+      a = P1[r * ld1 + lane];
+      b = P2[r * ld2 + lane];
+    } else {
+      a = lane < L ? P1[r * ld1 + lane] : P2[r * ld2 + (lane - L)];
+    }
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < KA; ++k)
+    for (int k = 0; k < 64 && k < WIN; ++k)
       acc = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), k)), t[k], acc);
-    if constexpr (WIN > 64) {
+    if constexpr (L == 64) {
 #pragma unroll
       for (int k = 0; k < 64; ++k)
         acc = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), k)), t[64 + k], acc);
     }
-    if (lane < WOUT) out[r * ldo + lane] = acc;
+    if (lane < L) out[r * ldo + lane] = acc;
   }
 }
 
@@ -139,11 +170,28 @@ __global__ __launch_bounds__(256) void k_panel_gemv_t(const float* __restrict__ 
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = min(rows, r0 + rpb);
   float a0 = 0.f, a1 = 0.f;
-  for (int64_t r = r0 + wave; r < r1; r += 4) {
-    float yv = y[r];
-    const float* pr = P + r * ld;
-    if (lane < L) a0 = fmaf(pr[lane], yv, a0);
-    if (64 + lane < L) a1 = fmaf(pr[64 + lane], yv, a1);
+  const int c0 = lane < L ? lane : 0;
+  const int c1 = 64 + lane < L ? 64 + lane : 0;
+  const float m0 = lane < L ? 1.f : 0.f, m1 = 64 + lane < L ? 1.f : 0.f;
+  int64_t r = r0 + wave;
+  for (; r + 12 < r1; r += 16) {
+    float yv[4], p0[4], p1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      yv[u] = y[r + 4 * u];
+      p0[u] = P[(r + 4 * u) * ld + c0];
+      p1[u] = P[(r + 4 * u) * ld + c1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0 = fmaf(p0[u] * m0, yv[u], a0);
+      a1 = fmaf(p1[u] * m1, yv[u], a1);
+    }
+  }
+  for (; r < r1; r += 4) {
+    const float yv = y[r];
+    a0 = fmaf(P[r * ld + c0] * m0, yv, a0);
+    a1 = fmaf(P[r * ld + c1] * m1, yv, a1);
   }
   red[wave][lane] = a0;
   red[wave][64 + lane] = a1;
@@ -217,35 +265,55 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
 
 int gram_max_blocks() { return kGramMaxBlocks; }
 
-hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st) {
-  int64_t nb = (rows + 63) / 64;
+static void gram_grid(int64_t rows, int64_t& nb, int& rpb) {
+  nb = (rows + 511) / 512;
   if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
   if (nb < 1) nb = 1;
-  int rpb = (int)((rows + nb - 1) / nb);
+  rpb = (int)((rows + nb - 1) / nb);
   rpb = (rpb + 3) & ~3;
   nb = rows > 0 ? (rows + rpb - 1) / rpb : 1;
+}
+
+hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st) {
+  int64_t nb;
+  int rpb;
+  gram_grid(rows, nb, rpb);
   switch (w) {
-    case 32: k_gram_partial<32><<<(unsigned)nb, 256, 0, st>>>(P, ld, rows, rpb, partials); break;
-    case 64: k_gram_partial<64><<<(unsigned)nb, 256, 0, st>>>(P, ld, rows, rpb, partials); break;
-    case 128: k_gram_partial<128><<<(unsigned)nb, 256, 0, st>>>(P, ld, rows, rpb, partials); break;
+    case 32: k_gram_partial<32, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials); break;
+    case 64: k_gram_partial<64, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials); break;
+    case 128:
+      k_gram_partial<128, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials);
+      break;
     default: return hipErrorInvalidValue;
   }
-  k_gram_reduce<<<(unsigned)((w * w + 255) / 256), 256, 0, st>>>(partials, (int)nb, w, W);
+  k_gram_reduce<<<(unsigned)((w * w + 15) / 16), 256, 0, st>>>(partials, (int)nb, w, W);
   return hipGetLastError();
 }
 
-hipError_t panel_xform(const float* in, int ldi, int win, const float* T, float* out, int ldo, int wout,
-                       int64_t rows, hipStream_t st) {
+hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t rows, int L, float* partials, double* W,
+                 hipStream_t st) {
+  int64_t nb;
+  int rpb;
+  gram_grid(rows, nb, rpb);
+  switch (L) {
+    case 32: k_gram_partial<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials); break;
+    case 64:
+      k_gram_partial<128, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W);
+  return hipGetLastError();
+}
+
+hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int L, const float* T2, float* out,
+                        int ldo, int64_t rows, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  unsigned grid = grid_for(rows, 4, 8192);
-  if (win == 32 && wout == 32)
-    k_panel_xform<32, 32><<<grid, 256, 0, st>>>(in, ldi, T, out, ldo, rows);
-  else if (win == 64 && wout == 64)
-    k_panel_xform<64, 64><<<grid, 256, 0, st>>>(in, ldi, T, out, ldo, rows);
-  else if (win == 64 && wout == 32)
-    k_panel_xform<64, 32><<<grid, 256, 0, st>>>(in, ldi, T, out, ldo, rows);
-  else if (win == 128 && wout == 64)
-    k_panel_xform<128, 64><<<grid, 256, 0, st>>>(in, ldi, T, out, ldo, rows);
+  const unsigned grid = grid_for(rows, 4, 8192);
+  if (L == 32)
+    k_panel_xform2<32><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
+  else if (L == 64)
+    k_panel_xform2<64><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -71,10 +71,16 @@ __global__ void k_append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, 
   for (; i < cnt; i += stride) rowptr[m0 + 1 + i] = (int)(indptr[r0 + 1 + i] - base) + nnz0;
 }
 
-__global__ void k_col_count(const int* colidx, int nnz, int* counts) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// cscptr[c] = first sorted position whose column id is >= c: the thread at a position where
+// the id changes fills the ids in between (empty columns), the last thread fills up to d.
+__global__ void k_colptr_from_sorted(const int* keys, int nnz, int64_t d, int* cscptr) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
   int stride = gridDim.x * blockDim.x;
-  for (; i < nnz; i += stride) atomicAdd(&counts[colidx[i]], 1);
+  for (; p <= nnz; p += stride) {
+    int64_t prev = p == 0 ? -1 : keys[p - 1];
+    int64_t cur = p == nnz ? d : keys[p];
+    for (int64_t c = prev + 1; c <= cur; ++c) cscptr[c] = p;
+  }
 }
 
 __global__ void k_expand_rowid(const int* rowptr, int m, int* rowid) {
@@ -248,13 +254,8 @@ hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* ro
 hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st) {
   hipError_t e;
-  // column pointers: counts then exclusive scan
-  if ((e = fill_i32(w.counts, d + 1, 0, st)) != hipSuccess) return e;
-  if (nnz > 0) {
-    k_col_count<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(colidx, nnz, w.counts);
-  }
-  if ((e = scan_exclusive(w.counts, cscptr, d, w.scan_tmp, st)) != hipSuccess) return e;
   if (nnz == 0) {
+    if ((e = fill_i32(cscptr, d + 1, 0, st)) != hipSuccess) return e;
     return fill_i32(reinterpret_cast<int*>(&sc->fro2A), 2, 0, st);  // fro2A = +0.0
   }
   k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid);
@@ -282,6 +283,7 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
       vout = w.vals0;
     }
   }
+  k_colptr_from_sorted<<<grid_for((int64_t)nnz + 1, 256, 8192), 256, 0, st>>>(kin, nnz, d, cscptr);
   k_csc_gather<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(vin, w.rowid, val, nnz, cscrow, cscval);
   k_fro2_runs<<<kFroBlocks, 256, 0, st>>>(kin, cscrow, cscval, nnz, w.part);
   k_sum_to_scalar<<<1, 256, 0, st>>>(w.part, kFroBlocks, &sc->fro2A);

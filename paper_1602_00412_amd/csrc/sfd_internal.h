@@ -65,23 +65,22 @@ hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* csc
 
 // ---------------------------------------------------------------- sparse products (sfd_spmm.hip)
 struct Schedule {
-  int* nch;          // rows + 1 : chunks per row -> scanned chunk start
+  int* nch;          // rows + 1 : chunks per row -> scanned chunk start; nch[rows] = number of chunks
   int* pslot;        // rows + 1 : partial slots per long row -> scanned slot start
-  int* chunk_row;    // nchunks
-  int* long_rows;    // rows
+  int* chunk_row;    // chunk -> row
+  int* long_rows;    // rows split into several chunks
   int* counters;     // [0] = number of long rows
-  int nchunks;
-  int nslots;
-  int nlong;
+  int rows;          // rows of the structure the schedule was built for
+  int64_t max_chunks;  // capacity of chunk_row (bounds the persistent grid)
 };
-// first half: per-row counts (device); the caller scans nch/pslot, reads totals, then calls finish
-hipError_t schedule_counts(const int* ptr, int rows, Schedule& s, hipStream_t st);
-hipError_t schedule_finish(const int* ptr, int rows, Schedule& s, hipStream_t st);
-// Y[r, :] = sum_k val[k] X[idx[k], :]  (rows of width L, pitches ldx / ldy)
-hipError_t spmm(const int* ptr, const int* idx, const float* val, int rows, const Schedule& s, const float* X,
-                int ldx, float* Y, int ldy, int L, float* partial, hipStream_t st);
+// builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
+hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
+// Y[r, :] = (sum_k val[k] X[idx[k], :]) * T  (rows of width L, pitches ldx / ldy; T: L x L f32,
+// nullptr for none; L <= 64 with T)
+hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* X, int ldx,
+                float* Y, int ldy, int L, float* partial, const float* T, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)
-hipError_t spmv(const int* ptr, const int* idx, const float* val, int rows, const Schedule& s, const float* y,
+hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* y,
                 const double* scale_ptr, float* z, float* partial, hipStream_t st);
 
 // ---------------------------------------------------------------- dense panels (sfd_dense.hip)
@@ -89,9 +88,12 @@ hipError_t spmv(const int* ptr, const int* idx, const float* val, int rows, cons
 // hold at most gram_max_blocks() blocks of w*w floats
 int gram_max_blocks();
 hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st);
-// in-place / out-of-place row transform: out[j, 0:wout] = in[j, 0:win] * T (T: win x wout, f32)
-hipError_t panel_xform(const float* in, int ldi, int win, const float* T, float* out, int ldo, int wout,
-                       int64_t rows, hipStream_t st);
+// Gram of the side-by-side panel [P1 | P2] (rows x 2L, each half L wide) into FP64 (2L x 2L)
+hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t rows, int L, float* partials, double* W,
+                 hipStream_t st);
+// out[j, 0:L] = [P1[j, 0:L] | P2[j, 0:L]] * T2 (T2: 2L x L, f32); out may be P1 (row-wise in place)
+hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int L, const float* T2, float* out,
+                        int ldo, int64_t rows, hipStream_t st);
 // partial sums of P^T y over row blocks: part[b][k] = sum_{j in block} P[j][k] * y[j] * scale
 int gemv_blocks(int64_t rows);
 hipError_t panel_gemv_t(const float* P, int ld, int L, int64_t rows, const float* y, const double* scale_ptr,

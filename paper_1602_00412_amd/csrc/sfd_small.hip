@@ -13,106 +13,216 @@ namespace {
 constexpr int kCholMax = 64;
 constexpr int kEigMax = 2 * kMaxEll;
 
-// Right-looking Cholesky W = R^T R on the ell x ell leading block, in LDS.  A pivot that has
-// fallen to tau * W_kk (the column's own squared norm) marks column k as dependent on the
-// earlier ones: its row of R is zeroed and it is skipped.  Then T = R^{-1} on the kept
-// columns (zero rows/columns for dropped ones), so panel * T has orthonormal kept columns
-// spanning the panel's numerical column space.
+// Blocked right-looking Cholesky W = R^T R of the ell x ell leading block, 4 columns per step,
+// with the matrix in registers: thread t owns column j = t % 64 and rows i = t / 64 + 4 s, so
+// the rows of block K are slot K of the four thread groups.  A step broadcasts the block's 4
+// rows through LDS, every thread factors the 4 x 4 diagonal block itself, the 64 threads of
+// group 0 solve the block row of R, and everyone applies the rank-4 update to the rows below.
+// A pivot that has fallen to tau * W_kk (the column's own squared norm) marks column k as
+// dependent on the earlier ones: it is skipped and its row of R is zero.  T = R^{-1} on the kept
+// columns follows by blocked back substitution, bottom-up (R_KK T_K = B_K, then the rows above
+// subtract R_{:,K} T_K), so panel * T has orthonormal kept columns spanning the panel's
+// numerical column space.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ W, int ldw, int n, int L, double tau,
                                                   float* __restrict__ T, DevScalars* sc) {
-  __shared__ double A[kCholMax][kCholMax + 1];
-  __shared__ double Ti[kCholMax][kCholMax + 1];
+  constexpr int S = kCholMax / 4;  // row slots per thread = block steps
+  __shared__ double rows[4][kCholMax];  // the current block's rows (factor) / rows of B (inverse)
+  __shared__ double rp[4][kCholMax];    // solved block row of R (factor) / column block of R (inverse)
   __shared__ double d0[kCholMax];
-  __shared__ int drop[kCholMax];
-  __shared__ int ndrop;
+  __shared__ double inv[kCholMax];
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += 256) {
-    int i = e / n, j = e % n;
-    A[i][j] = W[i * ldw + j];
+  const int j = tid & 63;
+  const int r0 = tid >> 6;
+  const bool jn = j < n;
+  double a[S], b[S];
+  {
+    // unconditional loads from clamped indices (all in flight together), then masked
+    const int jc = jn ? j : 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = r0 + 4 * s;
+      const double w = W[(i < n ? i : 0) * ldw + jc];
+      a[s] = (i < n && jn) ? w : 0.0;
+      b[s] = (i == j && i < n) ? 1.0 : 0.0;
+    }
+    const int tc = tid < n ? tid : 0;
+    const double dd = W[tc * ldw + tc];
+    if (tid < kCholMax) d0[tid] = tid < n ? dd : 0.0;
   }
-  if (tid < n) {
-    d0[tid] = W[tid * ldw + tid];
-    drop[tid] = 0;
-  }
-  if (tid == 0) ndrop = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double piv = A[k][k];
-    const bool dk = !(d0[k] > 0.0) || !(piv > tau * d0[k]);
-    if (dk) {
-      for (int j = k + tid; j < n; j += 256) A[k][j] = 0.0;
-      if (tid == 0) {
-        drop[k] = 1;
-        ++ndrop;
+  const int nblk = (n + 3) / 4;
+  for (int K = 0; K < nblk; ++K) {
+    const int k0 = 4 * K;
+    double mine = a[0];
+#pragma unroll
+    for (int s = 1; s < S; ++s) mine = (s == K) ? a[s] : mine;
+    rows[r0][j] = mine;  // row k0 + r0, column j
+    __syncthreads();
+    // 4 x 4 diagonal block, factored by every thread (upper factor U, inverse pivots iv)
+    double D[4][4], U[4][4], iv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) D[t][u] = (k0 + t < n && k0 + u < n) ? rows[t][k0 + u] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double p = D[t][t];
+      const double dk = k0 + t < n ? d0[k0 + t] : 0.0;
+      const bool keep = (dk > 0.0) && (p > tau * dk);
+      const double is = keep ? 1.0 / sqrt(p) : 0.0;
+      iv[t] = is;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) U[t][u] = u >= t ? D[t][u] * is : 0.0;
+#pragma unroll
+      for (int u = t + 1; u < 4; ++u)
+#pragma unroll
+        for (int v = u; v < 4; ++v) D[u][v] = fma(-U[t][u], U[t][v], D[u][v]);
+    }
+    if (tid < 4 && k0 + tid < n) inv[k0 + tid] = iv[tid];
+    if (r0 == 0) {
+      // block row of R for column j: U^T r = rows[:, j] (columns right of the block), U itself inside
+      double r[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double x = rows[t][j];
+#pragma unroll
+        for (int v = 0; v < t; ++v) x = fma(-U[v][t], r[v], x);
+        r[t] = x * iv[t];
       }
-    } else {
-      const double rkk = sqrt(piv);
-      for (int j = k + 1 + tid; j < n; j += 256) A[k][j] /= rkk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double val = 0.0;
+        if (jn && j >= k0 + 4) val = r[t];
+        if (j >= k0 && j < k0 + 4) val = U[t][j - k0];
+        rp[t][j] = val;
+      }
     }
     __syncthreads();
-    if (!dk) {
-      if (tid == 0) A[k][k] = sqrt(piv);
-      const int m = n - k - 1;
-      for (int e = tid; e < m * m; e += 256) {
-        int i = k + 1 + e / m, j = k + 1 + e % m;
-        if (i <= j) A[i][j] -= A[k][i] * A[k][j];
-      }
-    }
-    __syncthreads();
-  }
-  if (tid < n) {
-    const int j = tid;
-    for (int i = 0; i < n; ++i) Ti[i][j] = 0.0;
-    if (!drop[j]) {
-      Ti[j][j] = 1.0 / A[j][j];
-      for (int i = j - 1; i >= 0; --i) {
-        if (drop[i]) continue;
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) s += A[i][k] * Ti[k][j];
-        Ti[i][j] = -s / A[i][i];
+    const double rkj[4] = {rp[0][j], rp[1][j], rp[2][j], rp[3][j]};
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = r0 + 4 * s;
+      if (s == K) {
+        a[s] = rkj[r0];  // final row k0 + r0 of R
+      } else if (s > K) {
+        const double f = (i <= j) ? 1.0 : 0.0;
+        double x = a[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x = fma(-rp[t][i] * f, rkj[t], x);
+        a[s] = x;
       }
     }
   }
   __syncthreads();
-  for (int e = tid; e < L * L; e += 256) {
-    int i = e / L, j = e % L;
-    T[e] = (i < n && j < n) ? (float)Ti[i][j] : 0.f;
+  // T = R^{-1}, bottom-up by blocks
+  for (int K = nblk - 1; K >= 0; --K) {
+    const int k0 = 4 * K;
+    double mine = b[0];
+#pragma unroll
+    for (int s = 1; s < S; ++s) mine = (s == K) ? b[s] : mine;
+    rows[r0][j] = mine;  // row k0 + r0 of B
+    if (j >= k0 && j < k0 + 4) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) rp[j - k0][r0 + 4 * s] = a[s];  // R[i][j] for all i
+    }
+    __syncthreads();
+    // T rows of the block for column j: U t = B_block[:, j] (U = R_KK, back substitution)
+    double tk[4];
+#pragma unroll
+    for (int t = 3; t >= 0; --t) {
+      double x = rows[t][j];
+#pragma unroll
+      for (int v = t + 1; v < 4; ++v) x = fma(-rp[v][k0 + t], tk[v], x);
+      tk[t] = (k0 + t < n) ? x * inv[k0 + t] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = r0 + 4 * s;
+      if (s == K) {
+        b[s] = tk[r0];
+      } else if (s < K) {
+        double x = b[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x = fma(-rp[t][i], tk[t], x);
+        b[s] = x;
+      }
+    }
+    __syncthreads();
   }
-  if (tid == 0) sc->dropped = ndrop;
+  for (int e = tid; e < L * L; e += 256) T[e] = 0.f;
+  __syncthreads();
+  if (jn) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = r0 + 4 * s;
+      if (i < n) T[i * L + j] = (float)b[s];
+    }
+  }
+  if (tid == 0) {
+    int nd = 0;
+    for (int k = 0; k < n; ++k) nd += inv[k] == 0.0;
+    sc->dropped = nd;
+  }
 }
 
 __device__ inline int packed_index(int i, int j, int N) {
-  if (i > j) {
-    int t = i;
-    i = j;
-    j = t;
-  }
-  return i * N - (i * (i - 1)) / 2 + (j - i);
+  const int a = i < j ? i : j;
+  const int b = i < j ? j : i;
+  return a * N - ((a * (a - 1)) >> 1) + (b - a);
 }
 
+constexpr int kJacobiThreads = 1024;
+constexpr int kJacobiMaxBlocksPerThread = (kEigMax / 2) * (kEigMax / 2 + 1) / 2 / kJacobiThreads + 1;
+
 // Cyclic Jacobi with the round-robin ordering: in each round the N/2 index pairs are disjoint,
-// every workgroup thread updates whole 2 x 2 blocks of A (packed upper triangle in LDS) and
-// pairs of entries of V (N x N in LDS), so one round needs two barriers.  Sweeps repeat until
-// no off-diagonal entry is above 1e-15 sqrt(|a_pp a_qq|) (and above 1e-18 of the largest
-// diagonal).  An odd n is padded with a zero row and column, which is never rotated.
-__global__ __launch_bounds__(256) void k_eig_jacobi(const double* __restrict__ Ain, int lda, int n,
+// so every thread updates whole 2 x 2 blocks of A (packed upper triangle in LDS) and pairs of
+// entries of V (N x N in LDS) with two barriers per round.  The (pair, pair) blocks a thread
+// owns and the V entries it rotates are fixed for the whole solve.  Sweeps repeat until no
+// off-diagonal entry exceeds 1e-15 sqrt(|a_pp a_qq|) (and 1e-18 of the largest diagonal entry).
+// An odd n is padded with a zero row and column, which is never rotated.
+__global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __restrict__ Ain, int lda, int n,
                                                     double* __restrict__ evals, double* __restrict__ evecs) {
   extern __shared__ double lds[];
   const int N = n + (n & 1);
   const int P = N / 2;
-  double* A = lds;                                 // N (N + 1) / 2
-  double* V = A + (N * (N + 1)) / 2;               // N * N
-  double* rc = V + N * N;                          // P
-  double* rs = rc + P;                             // P
-  int* rp = reinterpret_cast<int*>(rs + P);        // P
-  int* rq = rp + P;                                // P
+  double* A = lds;                           // N (N + 1) / 2
+  double* V = A + (N * (N + 1)) / 2;         // N * N
+  double* rc = V + N * N;                    // P
+  double* rs = rc + P;                       // P
+  int* rp = reinterpret_cast<int*>(rs + P);  // P
+  int* rq = rp + P;                          // P
   __shared__ int flag;
   __shared__ double scale;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += 256) {
-    for (int j = i; j < N; ++j) A[packed_index(i, j, N)] = (i < n && j < n) ? Ain[i * lda + j] : 0.0;
+  for (int e = tid; e < N * N; e += kJacobiThreads) {
+    const int i = e / N, j = e - (e / N) * N;
+    if (i <= j) A[packed_index(i, j, N)] = (i < n && j < n) ? Ain[i * lda + j] : 0.0;
   }
-  for (int e = tid; e < N * N; e += 256) V[e] = (e / N == e % N) ? 1.0 : 0.0;
+  for (int e = tid; e < N * N; e += kJacobiThreads) V[e] = (e / N == e % N) ? 1.0 : 0.0;
+  // blocks (k1 <= k2) owned by this thread
+  int nblk = 0;
+  int bk1[kJacobiMaxBlocksPerThread], bk2[kJacobiMaxBlocksPerThread];
+  {
+    const int total = P * (P + 1) / 2;
+    int k1 = 0, base = 0;  // blocks of row k1 are [base, base + P - k1)
+    for (int b = tid; b < total; b += kJacobiThreads) {
+      while (b >= base + (P - k1)) {
+        base += P - k1;
+        ++k1;
+      }
+#pragma unroll
+      for (int r = 0; r < kJacobiMaxBlocksPerThread; ++r)
+        if (r == nblk) {
+          bk1[r] = k1;
+          bk2[r] = k1 + (b - base);
+        }
+      ++nblk;
+    }
+  }
+  // V entries: pair vk, rows vi0, vi0 + vstride, ...
+  const int vstride = kJacobiThreads / P;
+  const int vk = tid % P;
+  const int vi0 = tid / P;
+  const bool vactive = tid < vstride * P;
   __syncthreads();
   if (tid == 0) {
     double m = 0.0;
@@ -125,20 +235,21 @@ __global__ __launch_bounds__(256) void k_eig_jacobi(const double* __restrict__ A
     if (tid == 0) flag = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int k = tid; k < P; k += 256) {
-        int i0 = k, i1 = N - 1 - k;
-        int p = i0 == 0 ? 0 : 1 + (i0 - 1 + r) % (N - 1);
-        int q = 1 + (i1 - 1 + r) % (N - 1);
+      if (tid < P) {
+        const int k = tid;
+        int p = k == 0 ? 0 : 1 + (k - 1 + r) % (N - 1);
+        int q = 1 + (N - 2 - k + r) % (N - 1);
         if (p > q) {
-          int t = p;
+          const int t = p;
           p = q;
           q = t;
         }
-        double app = A[packed_index(p, p, N)], aqq = A[packed_index(q, q, N)], apq = A[packed_index(p, q, N)];
+        const double app = A[packed_index(p, p, N)], aqq = A[packed_index(q, q, N)];
+        const double apq = A[packed_index(p, q, N)];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-          double theta = (aqq - app) / (2.0 * apq);
-          double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          const double theta = (aqq - app) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
           flag = 1;
@@ -149,9 +260,10 @@ __global__ __launch_bounds__(256) void k_eig_jacobi(const double* __restrict__ A
         rq[k] = q;
       }
       __syncthreads();
-      for (int b = tid; b < P * P; b += 256) {
-        const int k1 = b / P, k2 = b % P;
-        if (k1 > k2) continue;
+#pragma unroll
+      for (int rr = 0; rr < kJacobiMaxBlocksPerThread; ++rr) {
+        if (rr >= nblk) break;
+        const int k1 = bk1[rr], k2 = bk2[rr];
         const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
         if (s1 == 0.0 && s2 == 0.0) continue;
         const int p1 = rp[k1], q1 = rq[k1], p2 = rp[k2], q2 = rq[k2];
@@ -174,23 +286,25 @@ __global__ __launch_bounds__(256) void k_eig_jacobi(const double* __restrict__ A
           A[i_qq] = s1 * uq + c1 * wq;
         }
       }
-      for (int e = tid; e < N * P; e += 256) {
-        const int i = e / P, k = e % P;
-        const double c = rc[k], s = rs[k];
-        if (s == 0.0) continue;
-        const int p = rp[k], q = rq[k];
-        const double vp = V[i * N + p], vq = V[i * N + q];
-        V[i * N + p] = c * vp - s * vq;
-        V[i * N + q] = s * vp + c * vq;
+      if (vactive) {
+        const double c = rc[vk], s = rs[vk];
+        if (s != 0.0) {
+          const int p = rp[vk], q = rq[vk];
+          for (int i = vi0; i < N; i += vstride) {
+            const double vp = V[i * N + p], vq = V[i * N + q];
+            V[i * N + p] = c * vp - s * vq;
+            V[i * N + q] = s * vp + c * vq;
+          }
+        }
       }
       __syncthreads();
     }
+    const int done = (flag == 0);
     __syncthreads();
-    if (flag == 0) break;
-    __syncthreads();
+    if (done) break;
   }
   // eigenvalues descending (ties by index), eigenvector columns follow
-  for (int i = tid; i < n; i += 256) {
+  for (int i = tid; i < n; i += kJacobiThreads) {
     const double li = A[packed_index(i, i, N)];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
@@ -331,7 +445,7 @@ hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr_set = true;
   }
-  k_eig_jacobi<<<1, 256, bytes, st>>>(A, lda, n, evals, evecs);
+  k_eig_jacobi<<<1, kJacobiThreads, bytes, st>>>(A, lda, n, evals, evecs);
   return hipGetLastError();
 }
 

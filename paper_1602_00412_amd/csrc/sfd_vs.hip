@@ -51,17 +51,38 @@ __global__ __launch_bounds__(256) void k_vs_init(const double* __restrict__ part
   }
 }
 
-// c = sum of the P y partials (FP64); c2 = M (M^T c)
-__global__ __launch_bounds__(256) void k_vs_small(const float* __restrict__ part, int nb,
-                                                  const double* __restrict__ M, int ell, int L,
-                                                  float* __restrict__ c2) {
+// c = sum of the P y partials (FP64; wave w adds partials w, w + 4, ..., then the waves in
+// order); c2 = M (M^T c)
+__global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ part, int nb,
+                                                   const double* __restrict__ M, int ell, int L,
+                                                   float* __restrict__ c2) {
+  __shared__ double red[16][64];
   __shared__ double c[kMaxEll];
   __shared__ double u[kMaxEll];
   const int tid = threadIdx.x;
-  if (tid < ell) {
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * L + tid];
-    c[tid] = s;
+    const int col = lane < L ? lane : 0;
+    int b = wave;
+    for (; b + 48 < nb; b += 64) {
+      const float v0 = part[(int64_t)b * L + col], v1 = part[(int64_t)(b + 16) * L + col];
+      const float v2 = part[(int64_t)(b + 32) * L + col], v3 = part[(int64_t)(b + 48) * L + col];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; b < nb; b += 16) s += part[(int64_t)b * L + col];
+    red[wave][lane] = s;
+  }
+  __syncthreads();
+  if (tid < ell) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += red[w][tid];
+    c[tid] = t;
   }
   __syncthreads();
   if (tid < ell) {
@@ -129,7 +150,7 @@ hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipS
 }
 
 hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st) {
-  k_vs_small<<<1, 256, 0, st>>>(part, nb, M64, ell, L, c2);
+  k_vs_small<<<1, 1024, 0, st>>>(part, nb, M64, ell, L, c2);
   return hipGetLastError();
 }
 
