@@ -272,6 +272,7 @@ int alloc_state(sfd_t* h) {
       ok = ok && dalloc(h, &s->nch, d + 1) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->chunk_row, max_chunks) &&
            dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4);
       s->max_chunks = max_chunks;
+      s->row_packed = (s == &ln.sr);  // the buffer's rows; the CSC keeps one chunk per wave
     }
     ok = ok && dalloc(h, &ln.partial, slots * L);
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);

@@ -71,6 +71,7 @@ struct Schedule {
   int* long_rows;    // rows split into several chunks
   int* counters;     // [0] = number of long rows
   int rows;          // rows of the structure the schedule was built for
+  bool row_packed;   // short, similar rows: one chunk per lane group (else one chunk per wave)
   int64_t max_chunks;  // capacity of chunk_row (bounds the persistent grid)
 };
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)

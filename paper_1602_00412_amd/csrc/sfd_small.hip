@@ -11,6 +11,24 @@ namespace sfd {
 namespace {
 
 constexpr int kCholMax = 64;
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by one Newton step (relative error
+// about one unit in the last place).
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  const double r = fma(-h, y, 0.5);
+  return fma(y, r, y);
+}
+
+// 1/x: the hardware estimate refined by two Newton steps.
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
 constexpr int kEigMax = 2 * kMaxEll;
 
 // Blocked right-looking Cholesky W = R^T R of the ell x ell leading block, 4 columns per step,
@@ -68,7 +86,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ W, 
       const double p = D[t][t];
       const double dk = k0 + t < n ? d0[k0 + t] : 0.0;
       const bool keep = (dk > 0.0) && (p > tau * dk);
-      const double is = keep ? 1.0 / sqrt(p) : 0.0;
+      const double is = keep ? rsqrt_nr(p) : 0.0;
       iv[t] = is;
 #pragma unroll
       for (int u = 0; u < 4; ++u) U[t][u] = u >= t ? D[t][u] * is : 0.0;
@@ -248,9 +266,10 @@ __global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __r
         const double apq = A[packed_index(p, q, N)];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
+          const double theta = (aqq - app) * rcp_nr(2.0 * apq);
+          const double h2 = fma(theta, theta, 1.0);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + h2 * rsqrt_nr(h2));
+          c = rsqrt_nr(fma(t, t, 1.0));
           s = t * c;
           flag = 1;
         }

@@ -131,6 +131,88 @@ __global__ __launch_bounds__(256) void k_spmm(const int* __restrict__ ptr, const
   }
 }
 
+// Row-packed variant for structures whose rows are short and of similar length (the CSR of a
+// buffer): each L/4-lane group of a wave owns one chunk, so a wave advances 64/(L/4) chunks at
+// once and needs no cross-group reduction.  Same output and transform as k_spmm.
+template <int L>
+__global__ __launch_bounds__(256) void k_spmm_rows(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                   const float* __restrict__ val,
+                                                   const int* __restrict__ chunk_start,
+                                                   const int* __restrict__ slot_start,
+                                                   const int* __restrict__ chunk_row,
+                                                   const int* __restrict__ nchunks_ptr, const float* __restrict__ X,
+                                                   int ldx, float* __restrict__ Y, int ldy,
+                                                   float* __restrict__ partial, const float* __restrict__ T) {
+  constexpr int LPR = L / 4;   // lanes per group
+  constexpr int G = 64 / LPR;  // chunks per wave
+  constexpr int TR = L <= 64 ? L : 4;
+  __shared__ float tl[TR * TR];
+  const int nchunks = *nchunks_ptr;
+  const int lane = threadIdx.x & 63;
+  const int sub = lane % LPR;
+  const int grp = lane / LPR;
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  const float4* X4 = reinterpret_cast<const float4*>(X);
+  const int ldx4 = ldx / 4;
+  const bool xf = (T != nullptr) && (L <= 64);
+  if (xf) {
+    for (int e = threadIdx.x; e < TR * TR; e += 256) tl[e] = T[e];
+  }
+  __syncthreads();
+  const int tc = lane < TR ? lane : 0;
+  for (int64_t base = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * G; base < nchunks; base += nwaves * G) {
+    const int64_t cc = base + grp;
+    const bool active = cc < nchunks;
+    int r = 0, k = 0, nch = 1, b = 0, e = 0;
+    if (active) {
+      r = chunk_row[cc];
+      const int cs = chunk_start[r];
+      k = (int)cc - cs;
+      nch = chunk_start[r + 1] - cs;
+      b = ptr[r] + k * kSpmmChunk;
+      e = min(ptr[r + 1], b + kSpmmChunk);
+    }
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int p = b;
+    for (; p + 3 < e; p += 4) {
+      const int c0 = idx[p], c1 = idx[p + 1], c2 = idx[p + 2], c3 = idx[p + 3];
+      const float v0 = val[p], v1 = val[p + 1], v2 = val[p + 2], v3 = val[p + 3];
+      const float4 x0 = X4[(int64_t)c0 * ldx4 + sub];
+      const float4 x1 = X4[(int64_t)c1 * ldx4 + sub];
+      const float4 x2 = X4[(int64_t)c2 * ldx4 + sub];
+      const float4 x3 = X4[(int64_t)c3 * ldx4 + sub];
+      acc = fma4(v0, x0, acc);
+      acc = fma4(v1, x1, acc);
+      acc = fma4(v2, x2, acc);
+      acc = fma4(v3, x3, acc);
+    }
+    for (; p < e; ++p) acc = fma4(val[p], X4[(int64_t)idx[p] * ldx4 + sub], acc);
+    float* dst = (nch == 1) ? Y + (int64_t)r * ldy : partial + (int64_t)(slot_start[(nch == 1) ? 0 : r] + k) * L;
+    if (xf) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int lead = g * LPR;
+        if (!__builtin_amdgcn_readlane((int)active, lead)) continue;
+        float o = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < TR; kk += 4) {
+          const int src = lead + kk / 4;
+          o = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc.x), src)), tl[kk * TR + tc], o);
+          o = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc.y), src)), tl[(kk + 1) * TR + tc], o);
+          o = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc.z), src)), tl[(kk + 2) * TR + tc], o);
+          o = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc.w), src)), tl[(kk + 3) * TR + tc], o);
+        }
+        const int64_t dlo = (int64_t)__builtin_amdgcn_readlane((int)(uintptr_t)dst, lead);
+        const int64_t dhi = (int64_t)__builtin_amdgcn_readlane((int)((uintptr_t)dst >> 32), lead);
+        float* dg = reinterpret_cast<float*>((uintptr_t)((dhi << 32) | (dlo & 0xffffffffll)));
+        if (lane < L) dg[lane] = o;
+      }
+    } else if (active) {
+      reinterpret_cast<float4*>(dst)[sub] = acc;
+    }
+  }
+}
+
 // One block per long row: wave w adds the row's partials w, w + 4, ... (in order), then the
 // four wave sums are added in wave order.
 template <int L>
@@ -274,6 +356,22 @@ hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule
   if (g < 1) g = 1;
   const unsigned grid = (unsigned)g;
   const unsigned gfix = 256;
+  if (s.row_packed && L <= 64) {
+    int64_t gp = ((int64_t)s.max_chunks + 4 * (256 / L) - 1) / (4 * (256 / L));
+    if (gp > kSpmmMaxBlocks) gp = kSpmmMaxBlocks;
+    if (gp < 1) gp = 1;
+    if (L == 32)
+      k_spmm_rows<32><<<(unsigned)gp, 256, 0, st>>>(ptr, idx, val, s.nch, s.pslot, s.chunk_row, nchunks, X, ldx, Y,
+                                                    ldy, partial, T);
+    else
+      k_spmm_rows<64><<<(unsigned)gp, 256, 0, st>>>(ptr, idx, val, s.nch, s.pslot, s.chunk_row, nchunks, X, ldx, Y,
+                                                    ldy, partial, T);
+    if (L == 32)
+      k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    else
+      k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    return hipGetLastError();
+  }
   switch (L) {
     case 32:
       k_spmm<32><<<grid, 256, 0, st>>>(ptr, idx, val, s.nch, s.pslot, s.chunk_row, nchunks, X, ldx, Y, ldy, partial, T);
