@@ -25,6 +25,29 @@ import time
 METRIC = "ingested nnz/s on 1 MI355X at fixed cov-err; BF16/batched vs plain FP32"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# HBM traffic of one product measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# per dispatch, the factors that make a plain 1 GiB copy read as 1 GiB each way), summed over the
+# product's kernels.  Valid only for the kernel source it was taken with (sha256 prefix).
+MEASURED_TRAFFIC = {
+    # class: (bytes per call, source file, sha256 prefix of that file, summary under profiles/)
+}
+
+
+def measured_traffic(cls: str):
+    import hashlib
+
+    ent = MEASURED_TRAFFIC.get(cls)
+    if not ent:
+        return None
+    nbytes, src, sha, _ = ent
+    try:
+        with open(os.path.join(HERE, src), "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return nbytes if cur.startswith(sha) else None
 
 
 def log(msg: str):
@@ -69,6 +92,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-class HIP events")
     ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
+    ap.add_argument("--csc-bands", type=int, default=0, help="row bands of the transposed products (0: default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -105,7 +129,7 @@ def main() -> int:
     indices = torch.from_numpy(st.indices).cuda()
     values = torch.from_numpy(st.values).cuda()
     out = torch.empty((ell, st.d), dtype=torch.float32, device="cuda")
-    sk = sfd.Sketch(st.d, ell, 0.25, 0)
+    sk = sfd.Sketch(st.d, ell, 0.25, 0, csc_bands=args.csc_bands or None)
 
     def step():
         sk.reset()
@@ -132,28 +156,31 @@ def main() -> int:
     value = st.nnz / (elapsed / args.steps)
     log(f"{ms_per_step:.1f} ms/step, {value:.3e} nnz/s, flushes/step={stats['flushes']}")
 
-    # roofline of the dominant kernel class (largest device time)
+    # roofline of the dominant kernel class (largest device time); its unit is one call of the
+    # class (a whole sparse product: main kernel + long-row fix-up [+ band reduction])
     roof = None
     phases = {}
     if prof:
         for name, p in prof.items():
-            if p["launches"]:
-                phases[name] = {"ms_per_step": p["ms"] / args.steps, "launches_per_step": p["launches"] / args.steps,
-                                "avg_us": 1e3 * p["ms"] / p["launches"]}
+            if p["calls"]:
+                phases[name] = {"ms_per_step": p["ms"] / args.steps, "calls_per_step": p["calls"] / args.steps,
+                                "launches_per_step": p["launches"] / args.steps,
+                                "avg_call_us": 1e3 * p["ms"] / p["calls"]}
         dom = max(prof, key=lambda k: prof[k]["ms"])
         p = prof[dom]
-        avg_s = p["ms"] / 1e3 / p["launches"]
+        avg_s = p["ms"] / 1e3 / p["calls"]
         if dom in ("gram",):
-            achieved = p["flops"] / p["launches"] / avg_s / 1e12
+            achieved = p["flops"] / p["calls"] / avg_s / 1e12
             roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_MFMA_PEAK_TFS, "traffic": None}
         else:
-            achieved = p["bytes"] / p["launches"] / avg_s / 1e9
+            achieved = p["bytes"] / p["calls"] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
         roof["kernel"] = dom
-        roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["launches"]
-        roof["avg_launch_us"] = avg_s * 1e6
+        roof["algorithmic_bytes_per_call"] = p["bytes"] / p["calls"]
+        roof["launches_per_call"] = p["launches"] / p["calls"]
+        roof["avg_call_us"] = avg_s * 1e6
 
     cpu = None
     parity = None

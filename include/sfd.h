@@ -52,8 +52,12 @@ enum {
   SFD_OPT_MAX_ATTEMPTS = 3, /* cap on the BoostedSparseShrink loop (Alg 4); default 16 */
   SFD_OPT_VERIFY = 4,       /* 1: BoostedSparseShrink (Alg 4); 0: SparseShrink alone (Sec. 4) */
   SFD_OPT_STREAM_ID = 5,    /* second word of the random key; default 0 */
-  SFD_OPT_PROFILE = 6       /* 1: time every kernel class with HIP events and clear the
+  SFD_OPT_PROFILE = 6,      /* 1: time every kernel class with HIP events and clear the
                                counters; 0: stop timing.  Default 0. */
+  SFD_OPT_CSC_BANDS = 7     /* row bands of the transposed products A'^T Y (0..8): with k > 1 the
+                               buffer's rows are cut into k bands gathered by different XCDs and
+                               the bands' sums added afterwards; 0 or 1 = one band (default).
+                               Results agree to rounding. */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */
@@ -74,10 +78,11 @@ enum {
  * between HIP events recorded around the class's launches on the handle's stream, and the
  * class's algorithmic bytes and flops (what the method must read/write once, and compute). */
 typedef struct {
-  int64_t launches[16];
+  int64_t launches[16]; /* kernel launches */
   double ms[16];
   double bytes[16];
   double flops[16];
+  int64_t calls[16];    /* timed calls (one product, one solve, ...), each of one or more launches */
 } sfd_profile_t;
 
 /* Per-handle counters and the last buffer step's figures. */

@@ -54,6 +54,7 @@ struct Lane {
   int* scan_tmp = nullptr;
   Schedule sr{}, scs{};
   float* partial = nullptr;
+  float* bandbuf = nullptr;  // per-band output rows of the banded CSC products (kMaxBands * d x L)
   // panels and small work
   float *X = nullptr, *Y = nullptr, *Pt = nullptr;
   float* gram_part = nullptr;
@@ -80,6 +81,7 @@ struct sfd_s {
   int q_override = 0;
   int max_attempts = 16;
   int verify = 1;
+  int bands_opt = 0;  // SFD_OPT_CSC_BANDS: 0 automatic
   // stream state
   int live = 0;
   int64_t flushes = 0, vs_calls = 0;
@@ -215,6 +217,7 @@ void prof_resolve(sfd_t* h) {
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       h->profile.ms[p.cls] += ms;
       h->profile.launches[p.cls] += p.launches;
+      h->profile.calls[p.cls] += 1;
       h->profile.bytes[p.cls] += p.bytes;
       h->profile.flops[p.cls] += p.flops;
     }
@@ -253,28 +256,32 @@ int alloc_state(sfd_t* h) {
   const int64_t cap = h->ell * d + d;
   h->cap = cap;
   const int64_t tiles = (cap + 2047) / 2048;
-  const int64_t max_chunks = d + cap / kSpmmChunk + 2;
+  // chunk capacity: one per row of the unbanded CSC (empty rows included), or one per
+  // non-empty row of the banded CSC, plus the extra chunks of long rows
+  const int64_t max_chunks = std::max<int64_t>(d, std::min<int64_t>(kMaxBands * d, cap)) + cap / kSpmmChunk + 2;
   const int64_t slots = 2 * cap / kSpmmChunk + 16;
+  const int64_t band_rows = kMaxBands * d + 1;
   bool ok = true;
   ok = ok && dalloc(h, &h->B, d * L) && dalloc(h, &h->Bq, d * L);
   ok = ok && dalloc(h, &h->prow, d + 1) && dalloc(h, &h->pcol, cap) && dalloc(h, &h->pval, cap);
   ok = ok && dalloc(h, &h->err_dev, 4);
   for (Lane& ln : h->lanes) {
     ok = ok && dalloc(h, &ln.own_rowptr, d + 1);
-    ok = ok && dalloc(h, &ln.cscptr, d + 1) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
+    ok = ok && dalloc(h, &ln.cscptr, band_rows) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
     ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
     ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
     ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
     ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
-    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, d + 1)) + 16);
+    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, band_rows)) + 16);
     ln.csc.scan_tmp = ln.scan_tmp;
     for (Schedule* s : {&ln.sr, &ln.scs}) {
-      ok = ok && dalloc(h, &s->nch, d + 1) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->chunk_row, max_chunks) &&
-           dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4);
+      const int64_t rows = (s == &ln.scs) ? band_rows : d + 1;
+      ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, rows) && dalloc(h, &s->desc, max_chunks) &&
+           dalloc(h, &s->long_rows, rows) && dalloc(h, &s->counters, 4);
       s->max_chunks = max_chunks;
-      s->row_packed = (s == &ln.sr);  // the buffer's rows; the CSC keeps one chunk per wave
     }
-    ok = ok && dalloc(h, &ln.partial, slots * L);
+    ok = ok && dalloc(h, &ln.partial, slots * L) && dalloc(h, &ln.bandbuf, kMaxBands * d * L);
+    ln.scs.bandbuf = ln.bandbuf;
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
     ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
          dalloc(h, &ln.W2, 4 * L * L);
@@ -355,25 +362,41 @@ int spmm_csr(sfd_t* h, Lane& ln, const float* X, float* Y) {
 
 int spmm_csc(sfd_t* h, Lane& ln, const float* Y, float* X) {
   ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true),
-               2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 2);
+               2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, ln.scs.bands > 1 ? 3 : 2);
   CK(spmm(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, Y, h->L, X, h->L, h->L, ln.partial, ln.T, ln.st));
   return SFD_OK;
 }
 
 // Buffer set-up on the lane: CSC (with ||A'||_F^2) and, for m > ell, the chunk schedules.
+// Row bands of the buffer's CSC (SFD_OPT_CSC_BANDS): the transposed products gather rows of the
+// m x L panel Y; with k bands, band b's rows are gathered by the blocks dispatched to XCD b
+// (mod 8) only, and the bands' sums are added afterwards.  Off unless asked for: on a 1e5-row
+// buffer it cuts the product's L2 misses about 4x, but the band reduction costs more than the
+// product saves.
+int csc_bands(const sfd_t* h, const Lane& ln) {
+  if (ln.m <= h->ell || ln.nnz == 0) return 1;
+  if ((int64_t)kMaxBands * h->d + 1 >= ((int64_t)1 << 31)) return 1;  // int32 keys and row ids
+  return h->bands_opt > 0 ? std::min(h->bands_opt, kMaxBands) : 1;
+}
+
 int prepare(sfd_t* h, Lane& ln) {
   const int64_t d = h->d;
+  const int bands = csc_bands(h, ln);
   {
     ProfScope ps(h, ln.st, SFD_PROF_CSC_BUILD, 16.0 * ln.nnz + 4.0 * (ln.m + d), 0.0, 1);
-    CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, ln.cscptr, ln.cscrow, ln.cscval, ln.csc, ln.sc,
-                 ln.st));
+    CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, bands, ln.cscptr, ln.cscrow, ln.cscval, ln.csc,
+                 ln.sc, ln.st));
   }
+  ln.scs.bands = bands;
+  ln.scs.band_rows = (int)d;
   if (ln.m > h->ell) {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 2);
-    ln.sr.max_chunks = std::min<int64_t>(d + h->cap / kSpmmChunk + 2, (int64_t)ln.m + ln.nnz / kSpmmChunk + 2);
-    ln.scs.max_chunks = std::min<int64_t>(d + h->cap / kSpmmChunk + 2, d + ln.nnz / kSpmmChunk + 2);
+    const int64_t cap_chunks = std::max<int64_t>(d, std::min<int64_t>(kMaxBands * d, h->cap)) + h->cap / kSpmmChunk + 2;
+    ln.sr.max_chunks = std::min<int64_t>(cap_chunks, (int64_t)ln.m + ln.nnz / kSpmmChunk + 2);
+    ln.scs.max_chunks = std::min<int64_t>(
+        cap_chunks, (bands > 1 ? std::min<int64_t>(bands * d, ln.nnz) : d) + ln.nnz / kSpmmChunk + 2);
     CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
-    CK(schedule_build(ln.cscptr, (int)d, ln.scs, ln.scan_tmp, ln.st));
+    CK(schedule_build(ln.cscptr, (int)(bands * d), ln.scs, ln.scan_tmp, ln.st));
   }
   return SFD_OK;
 }
@@ -423,7 +446,7 @@ int verify_spectral(sfd_t* h, Lane& ln, int attempt, int t) {
   const int64_t d = h->d;
   const int m = ln.m;
   ProfScope ps(h, ln.st, SFD_PROF_VS, t * (16.0 * ln.nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
-               t * (4.0 * ln.nnz + 4.0 * d * ell), 8 * t + 3);
+               t * (4.0 * ln.nnz + 4.0 * d * ell), (ln.scs.bands > 1 ? 9 : 8) * t + 3);
   CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w, 1,
                  ln.st));
   CK(vs_init(ln.vs_w, d, ln.vs_npart, ln.sc, ln.st));
@@ -749,6 +772,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_STREAM_ID:
       if (!(value >= 0) || value > 9.0e15 || value != std::floor(value)) return SFD_E_ARG;
       h->stream_id = (uint64_t)value;
+      return SFD_OK;
+    case SFD_OPT_CSC_BANDS:
+      if (!(value >= 0 && value <= kMaxBands) || value != std::floor(value)) return SFD_E_ARG;
+      h->bands_opt = (int)value;
       return SFD_OK;
     default:
       return SFD_E_ARG;

@@ -83,12 +83,20 @@ __global__ void k_colptr_from_sorted(const int* keys, int nnz, int64_t d, int* c
   }
 }
 
-__global__ void k_expand_rowid(const int* rowptr, int m, int* rowid) {
+// rowid[k] = row of entry k; with bands > 1 also keys[k] = band(row) * d + column, the band of
+// a row being floor(rowptr[row] * bands / nnz) (contiguous bands of about nnz / bands entries)
+__global__ void k_expand_rowid(const int* rowptr, int m, int* rowid, const int* colidx, int nnz, int bands, int d,
+                               int* keys) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   int stride = gridDim.x * blockDim.x;
   for (; r < m; r += stride) {
     int a = rowptr[r], b = rowptr[r + 1];
     for (int k = a; k < b; ++k) rowid[k] = r;
+    if (keys) {
+      int band = (int)(((int64_t)a * bands) / nnz);
+      if (band > bands - 1) band = bands - 1;
+      for (int k = a; k < b; ++k) keys[k] = band * d + colidx[k];
+    }
   }
 }
 
@@ -251,20 +259,22 @@ hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* ro
   return hipGetLastError();
 }
 
-hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st) {
   hipError_t e;
+  const int64_t rows = d * bands;
   if (nnz == 0) {
-    if ((e = fill_i32(cscptr, d + 1, 0, st)) != hipSuccess) return e;
+    if ((e = fill_i32(cscptr, rows + 1, 0, st)) != hipSuccess) return e;
     return fill_i32(reinterpret_cast<int*>(&sc->fro2A), 2, 0, st);  // fro2A = +0.0
   }
-  k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid);
-  // stable LSD radix sort of the column ids, payload = entry index
+  k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid, colidx, nnz, bands, (int)d,
+                                                         bands > 1 ? w.keys1 : nullptr);
+  // stable LSD radix sort of the (band, column) keys, payload = entry index
   int bits = 1;
-  while ((int64_t(1) << bits) < d) ++bits;
+  while ((int64_t(1) << bits) < rows) ++bits;
   int passes = (bits + 7) / 8;
   int ntiles = (nnz + kRsTile - 1) / kRsTile;
-  const int* kin = colidx;
+  const int* kin = bands > 1 ? w.keys1 : colidx;
   const int* vin = nullptr;
   int* kout = w.keys0;
   int* vout = w.vals0;
@@ -283,7 +293,7 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
       vout = w.vals0;
     }
   }
-  k_colptr_from_sorted<<<grid_for((int64_t)nnz + 1, 256, 8192), 256, 0, st>>>(kin, nnz, d, cscptr);
+  k_colptr_from_sorted<<<grid_for((int64_t)nnz + 1, 256, 8192), 256, 0, st>>>(kin, nnz, rows, cscptr);
   k_csc_gather<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(vin, w.rowid, val, nnz, cscrow, cscval);
   k_fro2_runs<<<kFroBlocks, 256, 0, st>>>(kin, cscrow, cscval, nnz, w.part);
   k_sum_to_scalar<<<1, 256, 0, st>>>(w.part, kFroBlocks, &sc->fro2A);

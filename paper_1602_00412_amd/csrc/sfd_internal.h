@@ -9,6 +9,7 @@ namespace sfd {
 
 constexpr int kMaxEll = 56;      // 2*ell <= 112 keeps the FP64 eigensolver in one CU's LDS
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
+constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
 
 // Small device-resident scalars of one buffer step.
 struct DevScalars {
@@ -57,7 +58,11 @@ struct CscWork {
   int* hist;      // 256 * tiles
   double* part;   // reduction partials
 };
-hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
+// With bands > 1 the buffer's rows are split into `bands` contiguous bands of about nnz/bands
+// entries (row r is in band floor(rowptr[r] * bands / nnz)) and the structure becomes the
+// concatenation of the bands' CSCs: "row" b*d + c of cscptr (bands*d + 1 entries) holds the
+// entries of column c in band b.  Rows stay ascending inside every column.
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st);
 // dense transpose of a small buffer (m <= L rows): out[j][r] = sum of A'[r][j], pitch ld, width L
 hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
@@ -67,17 +72,24 @@ hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* csc
 struct Schedule {
   int* nch;          // rows + 1 : chunks per row -> scanned chunk start; nch[rows] = number of chunks
   int* pslot;        // rows + 1 : partial slots per long row -> scanned slot start
-  int* chunk_row;    // chunk -> row
+  int4* desc;        // chunk -> {row, first entry, end entry, partial slot or -1 (whole row)}
   int* long_rows;    // rows split into several chunks
   int* counters;     // [0] = number of long rows
   int rows;          // rows of the structure the schedule was built for
-  bool row_packed;   // short, similar rows: one chunk per lane group (else one chunk per wave)
-  int64_t max_chunks;  // capacity of chunk_row (bounds the persistent grid)
+  int64_t max_chunks;  // capacity of desc (bounds the grid)
+  // banded CSC (build_csc with bands > 1): rows = bands * band_rows; empty rows get no chunk;
+  // products write raw per-band rows into bandbuf (rows x L floats) and a reduction adds the
+  // bands of each output row
+  int bands = 1;
+  int band_rows = 0;
+  float* bandbuf = nullptr;
 };
-// builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
+// builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation);
+// with s.bands > 1 the structure is a banded CSC of s.band_rows columns per band
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
 // Y[r, :] = (sum_k val[k] X[idx[k], :]) * T  (rows of width L, pitches ldx / ldy; T: L x L f32,
-// nullptr for none; L <= 64 with T)
+// nullptr for none; L <= 64 with T).  For a banded schedule r runs over the band_rows output
+// rows and the bands are added in band order.
 hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* X, int ldx,
                 float* Y, int ldy, int L, float* partial, const float* T, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)

@@ -30,6 +30,7 @@ OPT_MAX_ATTEMPTS = 3
 OPT_VERIFY = 4
 OPT_STREAM_ID = 5
 OPT_PROFILE = 6
+OPT_CSC_BANDS = 7
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other"]
 
 EXPORTS = [
@@ -83,11 +84,13 @@ class Profile(ctypes.Structure):
         ("ms", ctypes.c_double * 16),
         ("bytes", ctypes.c_double * 16),
         ("flops", ctypes.c_double * 16),
+        ("calls", ctypes.c_int64 * 16),
     ]
 
     def as_dict(self) -> dict:
-        return {name: {"launches": int(self.launches[i]), "ms": float(self.ms[i]), "bytes": float(self.bytes[i]),
-                       "flops": float(self.flops[i])} for i, name in enumerate(PROF_CLASSES)}
+        return {name: {"launches": int(self.launches[i]), "calls": int(self.calls[i]), "ms": float(self.ms[i]),
+                       "bytes": float(self.bytes[i]), "flops": float(self.flops[i])}
+                for i, name in enumerate(PROF_CLASSES)}
 
 
 _lib = None
@@ -164,14 +167,15 @@ class Sketch:
     """A Sparse Frequent Directions stream (sfd_create ... sfd_destroy)."""
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
-                 max_attempts=None, verify=None, stream_id=None, use_torch_stream: bool = True):
+                 max_attempts=None, verify=None, stream_id=None, csc_bands=None, use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
         self._h = h
         self.d, self.ell = int(d), int(ell)
         for key, val in ((OPT_DELTA, delta), (OPT_Q, q), (OPT_MAX_ATTEMPTS, max_attempts),
-                         (OPT_VERIFY, None if verify is None else float(bool(verify))), (OPT_STREAM_ID, stream_id)):
+                         (OPT_VERIFY, None if verify is None else float(bool(verify))), (OPT_STREAM_ID, stream_id),
+                         (OPT_CSC_BANDS, csc_bands)):
             if val is not None:
                 self.set_option(key, val)
         if use_torch_stream:

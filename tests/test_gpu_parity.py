@@ -73,6 +73,29 @@ def test_small_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
     assert sk.last_live == o.query()[1]
 
 
+@pytest.mark.parametrize("bands", [2, 8])
+def test_banded_csc_matches_oracle(gpu_lib, bands):
+    # transposed products through the row-banded CSC (forced on small buffers)
+    st = small_random_csr(1500, 90, 20, 3, dist="lognormal", dup_rate=0.05)
+    o = _oracle(st, 50)
+    sk, B = _gpu_sketch(gpu_lib, st, 50, csc_bands=bands)
+    assert sk.stats()["flushes"] == o.flushes
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+    _, B1 = _gpu_sketch(gpu_lib, st, 50, csc_bands=1)
+    assert evaluate.gram_distance(B, B1) <= 1e-5
+
+
+@pytest.mark.parametrize("bands", [1, 8])
+def test_large_buffer_matches_oracle(gpu_lib, bands):
+    # one 20,000-row buffer (flushed by the rows rule: 6e5 stored entries, long CSC columns)
+    # and a 4,000-row pending buffer folded by the query
+    st = small_random_csr(24000, 20000, 30, 5, dist="lognormal")
+    o = _oracle(st, 40)
+    sk, B = _gpu_sketch(gpu_lib, st, 40, csc_bands=bands)
+    assert sk.stats()["flushes"] == o.flushes == 1
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
 def test_config1_matches_oracle_and_fd_bound(gpu_lib):
     st = config1_fp64_reference()
     o = _oracle(st, 20)
