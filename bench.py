@@ -32,6 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # product's kernels.  Valid only for the kernel source it was taken with (sha256 prefix).
 MEASURED_TRAFFIC = {
     # class: (bytes per call, source file, sha256 prefix of that file, summary under profiles/)
+    "spmm_csc": (1.2201e+09, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "518854583c222958",
+                 "profiles/sfd_spmm_csc_2e5rows_hbm_traffic.txt"),
 }
 
 
@@ -90,7 +92,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample-rows", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="time without the per-class HIP events")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel-class pass (roofline, phases)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="warm-up and the per-kernel-class pass only (no timed steps; for rocprofv3 runs)")
     ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
     ap.add_argument("--csc-bands", type=int, default=0, help="row bands of the transposed products (0: default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -141,30 +145,38 @@ def main() -> int:
         step()
         torch.cuda.synchronize()
         log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
-    if not args.no_profile:
-        sk.set_option(sfd.OPT_PROFILE, 1)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        step()
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    elapsed = float("nan")
+    if not args.profile_only:
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            step()
+            log(f"step {k + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
     stats = sk.stats()
-    prof = sk.profile() if not args.no_profile else {}
     value = st.nnz / (elapsed / args.steps)
     log(f"{ms_per_step:.1f} ms/step, {value:.3e} nnz/s, flushes/step={stats['flushes']}")
 
-    # roofline of the dominant kernel class (largest device time); its unit is one call of the
-    # class (a whole sparse product: main kernel + long-row fix-up [+ band reduction])
+    # Per-kernel-class pass (after the timed steps): one more step with HIP events around every
+    # class's launches on the lane streams, buffers run one lane at a time so that each event
+    # pair brackets its kernels alone (concurrent lanes would add other lanes' work to the
+    # interval).  The roofline is that of the class with the most device time; its unit is one
+    # call of the class (for a sparse product: the main kernel; the long-row fix-up is "fixup").
     roof = None
     phases = {}
-    if prof:
+    if not args.no_profile:
+        sk.set_option(sfd.OPT_LANES, 1)
+        sk.set_option(sfd.OPT_PROFILE, 1)
+        step()
+        torch.cuda.synchronize()
+        prof = sk.profile()
+        sk.set_option(sfd.OPT_PROFILE, 0)
+        sk.set_option(sfd.OPT_LANES, 4)
         for name, p in prof.items():
             if p["calls"]:
-                phases[name] = {"ms_per_step": p["ms"] / args.steps, "calls_per_step": p["calls"] / args.steps,
-                                "launches_per_step": p["launches"] / args.steps,
+                phases[name] = {"ms": p["ms"], "calls": p["calls"], "launches": p["launches"],
                                 "avg_call_us": 1e3 * p["ms"] / p["calls"]}
         dom = max(prof, key=lambda k: prof[k]["ms"])
         p = prof[dom]
@@ -177,10 +189,13 @@ def main() -> int:
             achieved = p["bytes"] / p["calls"] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
-        roof["kernel"] = dom
-        roof["algorithmic_bytes_per_call"] = p["bytes"] / p["calls"]
-        roof["launches_per_call"] = p["launches"] / p["calls"]
-        roof["avg_call_us"] = avg_s * 1e6
+        roof["kernel"] = {"spmm_csc": "k_spmm<64, true, 8, true> (X = A'^T Y, CSC)",
+                          "spmm_csr": "k_spmm<64, true, 8, false> (Y = A' X, CSR)"}.get(dom, dom)
+        roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["calls"]
+        roof["avg_launch_us"] = avg_s * 1e6
+        roof["launches"] = p["calls"]
+        roof["timing"] = "HIP events on the lane stream, one-lane pass after the timed steps"
+        log(f"roofline: {dom} {roof['avg_launch_us']:.1f} us/launch, {achieved:.1f} {roof['unit']}")
 
     cpu = None
     parity = None

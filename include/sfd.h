@@ -54,10 +54,12 @@ enum {
   SFD_OPT_STREAM_ID = 5,    /* second word of the random key; default 0 */
   SFD_OPT_PROFILE = 6,      /* 1: time every kernel class with HIP events and clear the
                                counters; 0: stop timing.  Default 0. */
-  SFD_OPT_CSC_BANDS = 7     /* row bands of the transposed products A'^T Y (0..8): with k > 1 the
+  SFD_OPT_CSC_BANDS = 7,    /* row bands of the transposed products A'^T Y (0..8): with k > 1 the
                                buffer's rows are cut into k bands gathered by different XCDs and
                                the bands' sums added afterwards; 0 or 1 = one band (default).
                                Results agree to rounding. */
+  SFD_OPT_LANES = 8         /* lanes (HIP streams) that run successive buffers' SparseShrink
+                               concurrently, 1..4; default 4.  Results do not depend on it. */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */
@@ -71,7 +73,8 @@ enum {
   SFD_PROF_EIG = 6,       /* FP64 symmetric eigensolves */
   SFD_PROF_VS = 7,        /* VerifySpectral power steps (Alg 6) */
   SFD_PROF_OTHER = 8,     /* start blocks, shrink factors, copies */
-  SFD_PROF_COUNT = 9
+  SFD_PROF_FIXUP = 9,     /* long-row fix-ups (and band sums) that complete a sparse product */
+  SFD_PROF_COUNT = 10
 };
 
 /* Accumulated per-class figures since profiling was switched on: kernel launches, device time

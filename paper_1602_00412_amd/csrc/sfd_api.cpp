@@ -81,7 +81,8 @@ struct sfd_s {
   int q_override = 0;
   int max_attempts = 16;
   int verify = 1;
-  int bands_opt = 0;  // SFD_OPT_CSC_BANDS: 0 automatic
+  int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic
+  int nlanes = kLanes;    // SFD_OPT_LANES: lanes used for successive buffers
   // stream state
   int live = 0;
   int64_t flushes = 0, vs_calls = 0;
@@ -282,6 +283,7 @@ int alloc_state(sfd_t* h) {
     }
     ok = ok && dalloc(h, &ln.partial, slots * L) && dalloc(h, &ln.bandbuf, kMaxBands * d * L);
     ln.scs.bandbuf = ln.bandbuf;
+    ln.scs.transposed = true;
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
     ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
          dalloc(h, &ln.W2, 4 * L * L);
@@ -354,16 +356,24 @@ int orth(sfd_t* h, Lane& ln, const float* panel, int64_t rows) {
 }
 
 int spmm_csr(sfd_t* h, Lane& ln, const float* X, float* Y) {
-  ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false),
-               2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 2);
-  CK(spmm(ln.rowptr, ln.colidx, ln.val, ln.sr, X, h->L, Y, h->L, h->L, ln.partial, ln.T, ln.st));
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false),
+                 2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 1);
+    CK(spmm(ln.rowptr, ln.colidx, ln.val, ln.sr, X, h->L, Y, h->L, h->L, ln.partial, ln.T, ln.st));
+  }
+  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
+  CK(spmm_finish(ln.sr, ln.partial, ln.T, Y, h->L, h->L, ln.st));
   return SFD_OK;
 }
 
 int spmm_csc(sfd_t* h, Lane& ln, const float* Y, float* X) {
-  ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true),
-               2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, ln.scs.bands > 1 ? 3 : 2);
-  CK(spmm(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, Y, h->L, X, h->L, h->L, ln.partial, ln.T, ln.st));
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true),
+                 2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 1);
+    CK(spmm(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, Y, h->L, X, h->L, h->L, ln.partial, ln.T, ln.st));
+  }
+  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, ln.scs.bands > 1 ? 2 : 1);
+  CK(spmm_finish(ln.scs, ln.partial, ln.T, X, h->L, h->L, ln.st));
   return SFD_OK;
 }
 
@@ -587,22 +597,23 @@ int bind(sfd_t* h, Lane& ln, const BufferView& v, int64_t buffer, int pg, int px
 int run_flushes(sfd_t* h, const std::vector<BufferView>& views) {
   const int nbuf = (int)views.size();
   int rc;
-  for (int b = 0; b < nbuf && b < kLanes; ++b) {
-    Lane& ln = h->lanes[b % kLanes];
+  const int nl = h->nlanes;
+  for (int b = 0; b < nbuf && b < nl; ++b) {
+    Lane& ln = h->lanes[b % nl];
     if ((rc = bind(h, ln, views[b], h->flushes + b, kPurposeSI, kPurposeVS))) return rc;
     if ((rc = issue_shrink(h, ln))) return rc;
   }
   for (int b = 0; b < nbuf; ++b) {
-    Lane& ln = h->lanes[b % kLanes];
+    Lane& ln = h->lanes[b % nl];
     int live = 0;
     int64_t calls = 0;
     if ((rc = finish_step(h, ln, h->vs_calls, h->live, h->B, h->B, &live, &calls))) return rc;
     h->live = live;
     h->vs_calls += calls;
     h->flushes += 1;
-    if (b + kLanes < nbuf) {
+    if (b + nl < nbuf) {
       // same lane: ordered after this buffer's DenseShrink by the stream
-      if ((rc = bind(h, ln, views[b + kLanes], h->flushes - 1 + kLanes, kPurposeSI, kPurposeVS))) return rc;
+      if ((rc = bind(h, ln, views[b + nl], h->flushes - 1 + nl, kPurposeSI, kPurposeVS))) return rc;
       if ((rc = issue_shrink(h, ln))) return rc;
     }
   }
@@ -772,6 +783,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_STREAM_ID:
       if (!(value >= 0) || value > 9.0e15 || value != std::floor(value)) return SFD_E_ARG;
       h->stream_id = (uint64_t)value;
+      return SFD_OK;
+    case SFD_OPT_LANES:
+      if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;
+      h->nlanes = (int)value;
       return SFD_OK;
     case SFD_OPT_CSC_BANDS:
       if (!(value >= 0 && value <= kMaxBands) || value != std::floor(value)) return SFD_E_ARG;

@@ -83,6 +83,7 @@ struct Schedule {
   int bands = 1;
   int band_rows = 0;
   float* bandbuf = nullptr;
+  bool transposed = false;  // the CSC of a buffer (A'^T products); only names the kernels apart
 };
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation);
 // with s.bands > 1 the structure is a banded CSC of s.band_rows columns per band
@@ -90,8 +91,11 @@ hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, 
 // Y[r, :] = (sum_k val[k] X[idx[k], :]) * T  (rows of width L, pitches ldx / ldy; T: L x L f32,
 // nullptr for none; L <= 64 with T).  For a banded schedule r runs over the band_rows output
 // rows and the bands are added in band order.
+// (main kernel only; spmm_finish completes the product)
 hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* X, int ldx,
                 float* Y, int ldy, int L, float* partial, const float* T, hipStream_t st);
+// the long rows' fix-up of a product (and for a banded schedule the band sums times T)
+hipError_t spmm_finish(const Schedule& s, float* partial, const float* T, float* Y, int ldy, int L, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)
 hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* y,
                 const double* scale_ptr, float* z, float* partial, hipStream_t st);

@@ -103,7 +103,7 @@ __device__ inline void gather_block(int ci, float vi, const float4* __restrict__
 // its own band's rows of X only.  Output: a whole row goes to out[r] (times T when XF, T in LDS,
 // applied through in-group broadcasts), the chunks of a long row to their partial slots
 // (untransformed; the fix-up adds them and applies T).
-template <int L, bool XF, int U>
+template <int L, bool XF, int U, bool TRANSPOSED>
 __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ chunk_start,
                                               int bands, int band_rows, const int* __restrict__ idx,
                                               const float* __restrict__ val, const float* __restrict__ X, int ldx,
@@ -367,7 +367,13 @@ void launch_spmm(const Schedule& s, const int* idx, const float* val, const floa
   per = std::max<int64_t>(1, std::min<int64_t>(per, kSpmmMaxBlocks / s.bands));
   const unsigned grid = (unsigned)(per * s.bands);
   const int band_rows = s.bands > 1 ? s.band_rows : s.rows;
-  k_spmm<L, XF, U><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out, ldo, partial, T);
+  // TRANSPOSED (CSC products) only gives the two products different kernel names
+  if (s.transposed)
+    k_spmm<L, XF, U, true><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out, ldo,
+                                                 partial, T);
+  else
+    k_spmm<L, XF, U, false><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out, ldo,
+                                                  partial, T);
 }
 
 }  // namespace
@@ -390,20 +396,12 @@ hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule
                 int ldy, int L, float* partial, const float* T, hipStream_t st) {
   (void)ptr;
   if (L != 32 && L != 64) return hipErrorInvalidValue;
-  const int* nlong = s.counters;
-  const unsigned gfix = 256;
   if (s.bands > 1) {
-    // raw per-band rows, long rows fixed up in place, then the band sums times T
-    const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((s.band_rows + 3) / 4, 8192));
-    if (L == 32) {
+    // raw per-band rows; spmm_finish fixes up long rows in place and adds the bands times T
+    if (L == 32)
       launch_spmm<32, false, 4>(s, idx, val, X, ldx, s.bandbuf, 32, partial, nullptr, st);
-      k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 32);
-      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
-    } else {
+    else
       launch_spmm<64, false, 4>(s, idx, val, X, ldx, s.bandbuf, 64, partial, nullptr, st);
-      k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 64);
-      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
-    }
     return hipGetLastError();
   }
   if (L == 32) {
@@ -411,12 +409,31 @@ hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule
       launch_spmm<32, true, 8>(s, idx, val, X, ldx, Y, ldy, partial, T, st);
     else
       launch_spmm<32, false, 8>(s, idx, val, X, ldx, Y, ldy, partial, nullptr, st);
-    k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
   } else {
     if (T)
       launch_spmm<64, true, 8>(s, idx, val, X, ldx, Y, ldy, partial, T, st);
     else
       launch_spmm<64, false, 8>(s, idx, val, X, ldx, Y, ldy, partial, nullptr, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t spmm_finish(const Schedule& s, float* partial, const float* T, float* Y, int ldy, int L, hipStream_t st) {
+  if (L != 32 && L != 64) return hipErrorInvalidValue;
+  const int* nlong = s.counters;
+  const unsigned gfix = 256;
+  if (s.bands > 1) {
+    const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((s.band_rows + 3) / 4, 8192));
+    if (L == 32) {
+      k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 32);
+      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
+    } else {
+      k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 64);
+      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
+    }
+  } else if (L == 32) {
+    k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+  } else {
     k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
   }
   return hipGetLastError();

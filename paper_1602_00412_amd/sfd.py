@@ -31,7 +31,8 @@ OPT_VERIFY = 4
 OPT_STREAM_ID = 5
 OPT_PROFILE = 6
 OPT_CSC_BANDS = 7
-PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other"]
+OPT_LANES = 8
+PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
 
 EXPORTS = [
     "sfd_create",
