@@ -97,6 +97,9 @@ def main() -> int:
                     help="warm-up and the per-kernel-class pass only (no timed steps; for rocprofv3 runs)")
     ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
     ap.add_argument("--csc-bands", type=int, default=0, help="row bands of the transposed products (0: default)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 precision form's timing")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -133,7 +136,7 @@ def main() -> int:
     indices = torch.from_numpy(st.indices).cuda()
     values = torch.from_numpy(st.values).cuda()
     out = torch.empty((ell, st.d), dtype=torch.float32, device="cuda")
-    sk = sfd.Sketch(st.d, ell, 0.25, 0, csc_bands=args.csc_bands or None)
+    sk = sfd.Sketch(st.d, ell, 0.25, 0, csc_bands=args.csc_bands or None, precision=args.precision)
 
     def step():
         sk.reset()
@@ -189,13 +192,47 @@ def main() -> int:
             achieved = p["bytes"] / p["calls"] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
-        roof["kernel"] = {"spmm_csc": "k_spmm<64, true, 8, true> (X = A'^T Y, CSC)",
-                          "spmm_csr": "k_spmm<64, true, 8, false> (Y = A' X, CSR)"}.get(dom, dom)
+        bfk = args.precision == "bf16"
+        roof["kernel"] = {"spmm_csc": f"k_spmm<64, true, {4 if bfk else 8}, true, {str(bfk).lower()}, "
+                                      f"{str(bfk).lower()}> (X = A'^T Y, CSC)",
+                          "spmm_csr": f"k_spmm<64, true, {4 if bfk else 8}, false, {str(bfk).lower()}, "
+                                      f"{str(bfk).lower()}> (Y = A' X, CSR)"}.get(dom, dom)
         roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["calls"]
         roof["avg_launch_us"] = avg_s * 1e6
         roof["launches"] = p["calls"]
         roof["timing"] = "HIP events on the lane stream, one-lane pass after the timed steps"
         log(f"roofline: {dom} {roof['avg_launch_us']:.1f} us/launch, {achieved:.1f} {roof['unit']}")
+
+    # The BF16 precision form on the same resident stream: same q, same random blocks, panels of
+    # SimultaneousIteration in BF16 with FP32 accumulation.
+    forms = {}
+    sk_bf = None
+    if not args.no_forms and not args.profile_only and args.precision == "fp32":
+        sk_bf = sfd.Sketch(st.d, ell, 0.25, 0, precision="bf16")
+        out_bf = torch.empty_like(out)
+
+        def step_bf():
+            sk_bf.reset()
+            sk_bf.append_csr(indptr, indices, values)
+            sk_bf.sketch(out=out_bf)
+
+        for _ in range(args.warmup):
+            step_bf()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            step_bf()
+        torch.cuda.synchronize()
+        el_bf = time.perf_counter() - t_start
+        from oracle import evaluate as _ev
+
+        forms["bf16"] = {"value": st.nnz / (el_bf / args.steps), "unit": "nnz/s",
+                         "ms_per_step": 1e3 * el_bf / args.steps,
+                         "speedup_vs_fp32": elapsed / el_bf,
+                         "rel_frobenius_vs_fp32": _ev.gram_distance(out_bf.cpu().numpy().astype(np.float64),
+                                                                    out.cpu().numpy().astype(np.float64))}
+        log(f"bf16 form: {forms['bf16']['ms_per_step']:.1f} ms/step, {forms['bf16']['value']:.3e} nnz/s "
+            f"({forms['bf16']['speedup_vs_fp32']:.2f}x FP32)")
 
     cpu = None
     parity = None
@@ -212,7 +249,6 @@ def main() -> int:
         Bg = sk2.sketch().cpu().numpy().astype(np.float64)
         parity = evaluate.gram_distance(Bg, B_oracle)
         log(f"sample parity (rel. Frobenius of B^T B vs oracle): {parity:.2e}")
-
     line = {
         "metric": METRIC,
         "value": value,
@@ -224,7 +260,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16 panels, f32 accumulate",
         "data": "synthetic",
         "config": {
             "workload": f"zipf-poisson stream n={st.n} d={st.d} lambda=50 s=1.0 lognormal+planted rank-20 (30%), "
@@ -238,6 +274,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "sample_parity_rel_frobenius": parity,
+        "forms": forms,
         "phases": phases,
     }
     print(json.dumps(line), flush=True)

@@ -45,6 +45,8 @@ enum {
 
 enum { SFD_MEM_HOST = 0, SFD_MEM_DEVICE = 1 };
 
+enum { SFD_PRECISION_FP32 = 0, SFD_PRECISION_BF16 = 1 };
+
 /* Option keys for sfd_set_option. */
 enum {
   SFD_OPT_DELTA = 1,        /* failure probability delta of Alg 2 / Alg 6, in (0,1); default 0.01 */
@@ -58,8 +60,14 @@ enum {
                                buffer's rows are cut into k bands gathered by different XCDs and
                                the bands' sums added afterwards; 0 or 1 = one band (default).
                                Results agree to rounding. */
-  SFD_OPT_LANES = 8         /* lanes (HIP streams) that run successive buffers' SparseShrink
+  SFD_OPT_LANES = 8,        /* lanes (HIP streams) that run successive buffers' SparseShrink
                                concurrently, 1..4; default 4.  Results do not depend on it. */
+  SFD_OPT_PRECISION = 9     /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
+                               SimultaneousIteration (Alg 1) stored in BF16 with FP32 accumulation;
+                               the last product P^T = A'^T Y (Alg 3) reads the stored BF16 Y,
+                               takes its transform from that Y's own Gram and writes FP32, so
+                               B'^T B' <= A'^T A' (Property 1) still holds for the FP32 values.
+                               Only the subspace quality changes (cov-err, Sec. 4). */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */

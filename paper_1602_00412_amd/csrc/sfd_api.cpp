@@ -57,6 +57,7 @@ struct Lane {
   float* bandbuf = nullptr;  // per-band output rows of the banded CSC products (kMaxBands * d x L)
   // panels and small work
   float *X = nullptr, *Y = nullptr, *Pt = nullptr;
+  uint16_t *Xb = nullptr, *Yb = nullptr;  // BF16 panels of the precision form
   float* gram_part = nullptr;
   double *W = nullptr, *W2 = nullptr;
   double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
@@ -83,6 +84,7 @@ struct sfd_s {
   int verify = 1;
   int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic
   int nlanes = kLanes;    // SFD_OPT_LANES: lanes used for successive buffers
+  int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
   // stream state
   int live = 0;
   int64_t flushes = 0, vs_calls = 0;
@@ -285,6 +287,7 @@ int alloc_state(sfd_t* h) {
     ln.scs.bandbuf = ln.bandbuf;
     ln.scs.transposed = true;
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
+    ok = ok && dalloc(h, &ln.Xb, d * L) && dalloc(h, &ln.Yb, d * L);
     ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
          dalloc(h, &ln.W2, 4 * L * L);
     ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
@@ -333,20 +336,24 @@ int vs_steps(const sfd_t* h, int64_t i) {
 }
 
 // algorithmic bytes of one sparse product over the buffer: the stored entries (id + value)
-// and row pointers once, the input panel read once, the output panel written once
-double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed) {
+// and row pointers once, the input panel read once, the output panel written once (bx, by:
+// bytes per panel element)
+double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed, double bx, double by) {
   const double N = ln.nnz, m = ln.m, d = (double)h->d, ell = h->ell;
-  return 8.0 * N + 4.0 * ((transposed ? d : m) + 1) + 4.0 * ell * (m + d);
+  const double in_rows = transposed ? m : d, out_rows = transposed ? d : m;
+  return 8.0 * N + 4.0 * (out_rows + 1) + ell * (bx * in_rows + by * out_rows);
 }
+
+inline double pbytes(PanelType t) { return t == PanelType::BF16 ? 2.0 : 4.0; }
 
 // T <- R^{-1}, R the (pivoted) Cholesky factor of panel^T panel: panel * T has orthonormal
 // columns (the GramSchmidt of Alg 1 as CholeskyQR; the next sparse product applies T)
-int orth(sfd_t* h, Lane& ln, const float* panel, int64_t rows) {
+int orth(sfd_t* h, Lane& ln, const void* panel, PanelType pt, int64_t rows) {
   const int L = h->L;
   const double ell = h->ell;
   {
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 4.0 * rows * ell, 2.0 * rows * ell * ell, 2);
-    CK(gram(panel, L, rows, L, ln.gram_part, ln.W, ln.st));
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, pbytes(pt) * rows * ell, 2.0 * rows * ell * ell, 2);
+    CK(gram(panel, pt, L, rows, L, ln.gram_part, ln.W, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
@@ -355,25 +362,44 @@ int orth(sfd_t* h, Lane& ln, const float* panel, int64_t rows) {
   return SFD_OK;
 }
 
-int spmm_csr(sfd_t* h, Lane& ln, const float* X, float* Y) {
+// The output of a product whose input panel had transform T (the lane's current one):
+// panel <- panel T (so the product becomes A' (X T), resp. A'^T (Y T)), then the new T from
+// the transformed panel's Gram.
+int orth_out(sfd_t* h, Lane& ln, void* panel, PanelType pt, int64_t rows) {
+  const int L = h->L;
+  const double ell = h->ell;
   {
-    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false),
-                 2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 1);
-    CK(spmm(ln.rowptr, ln.colidx, ln.val, ln.sr, X, h->L, Y, h->L, h->L, ln.partial, ln.T, ln.st));
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 2.0 * pbytes(pt) * rows * ell, 4.0 * rows * ell * ell, 2);
+    CK(xform_gram(panel, pt, L, rows, L, ln.T, ln.gram_part, ln.W, ln.st));
   }
-  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
-  CK(spmm_finish(ln.sr, ln.partial, ln.T, Y, h->L, h->L, ln.st));
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
+    CK(chol_inv(ln.W, L, h->ell, L, kCholDropTol, ln.T, ln.sc, ln.st));
+  }
   return SFD_OK;
 }
 
-int spmm_csc(sfd_t* h, Lane& ln, const float* Y, float* X) {
+// Y = A' X (the input's transform is applied to Y by orth_out)
+int spmm_csr(sfd_t* h, Lane& ln, const void* X, PanelType xt, void* Y, PanelType yt) {
   {
-    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true),
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false, pbytes(xt), pbytes(yt)),
+                 2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 1);
+    CK(spmm(ln.sr, ln.colidx, ln.val, X, xt, h->L, Y, yt, h->L, h->L, ln.partial, ln.st));
+  }
+  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
+  CK(spmm_finish(ln.sr, ln.partial, Y, yt, h->L, h->L, ln.st));
+  return SFD_OK;
+}
+
+// X = A'^T Y
+int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType xt) {
+  {
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true, pbytes(yt), pbytes(xt)),
                  2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 1);
-    CK(spmm(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, Y, h->L, X, h->L, h->L, ln.partial, ln.T, ln.st));
+    CK(spmm(ln.scs, ln.cscrow, ln.cscval, Y, yt, h->L, X, xt, h->L, h->L, ln.partial, ln.st));
   }
   ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, ln.scs.bands > 1 ? 2 : 1);
-  CK(spmm_finish(ln.scs, ln.partial, ln.T, X, h->L, h->L, ln.st));
+  CK(spmm_finish(ln.scs, ln.partial, X, xt, h->L, h->L, ln.st));
   return SFD_OK;
 }
 
@@ -384,7 +410,7 @@ int spmm_csc(sfd_t* h, Lane& ln, const float* Y, float* X) {
 // buffer it cuts the product's L2 misses about 4x, but the band reduction costs more than the
 // product saves.
 int csc_bands(const sfd_t* h, const Lane& ln) {
-  if (ln.m <= h->ell || ln.nnz == 0) return 1;
+  if (ln.m <= h->ell || ln.nnz == 0 || h->precision != SFD_PRECISION_FP32) return 1;
   if ((int64_t)kMaxBands * h->d + 1 >= ((int64_t)1 << 31)) return 1;  // int32 keys and row ids
   return h->bands_opt > 0 ? std::min(h->bands_opt, kMaxBands) : 1;
 }
@@ -424,19 +450,29 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
     CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.pg, d, ell, ln.X, L,
                    ln.st));
   }
-  if ((rc = orth(h, ln, ln.X, d))) return rc;
+  // panels of the iteration: FP32, or BF16 in the precision form, where the products 1 .. 2q+1
+  // read and write BF16 panels (FP32 accumulation) and the last one, P^T = A'^T Y T_y, reads
+  // the stored BF16 Y with T_y from that Y's own Gram and writes FP32: P P^T is then the
+  // compression of A'^T A' onto span(Y), so B'^T B' <= A'^T A' still holds for the FP32 values
+  const bool bf = h->precision == SFD_PRECISION_BF16;
+  const PanelType pt = bf ? PanelType::BF16 : PanelType::F32;
+  void* X = bf ? static_cast<void*>(ln.Xb) : static_cast<void*>(ln.X);
+  void* Y = bf ? static_cast<void*>(ln.Yb) : static_cast<void*>(ln.Y);
+  if (bf) CK(to_bf16(ln.X, d * L, ln.Xb, ln.st));
+  if ((rc = orth(h, ln, X, pt, d))) return rc;
   for (int it = 0; it < ln.q; ++it) {
-    if ((rc = spmm_csr(h, ln, ln.X, ln.Y))) return rc;
-    if ((rc = orth(h, ln, ln.Y, m))) return rc;
-    if ((rc = spmm_csc(h, ln, ln.Y, ln.X))) return rc;
-    if ((rc = orth(h, ln, ln.X, d))) return rc;
+    if ((rc = spmm_csr(h, ln, X, pt, Y, pt))) return rc;
+    if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
+    if ((rc = spmm_csc(h, ln, Y, pt, X, pt))) return rc;
+    if ((rc = orth_out(h, ln, X, pt, d))) return rc;
   }
-  if ((rc = spmm_csr(h, ln, ln.X, ln.Y))) return rc;
-  if ((rc = orth(h, ln, ln.Y, m))) return rc;
-  if ((rc = spmm_csc(h, ln, ln.Y, ln.Pt))) return rc;
+  if ((rc = spmm_csr(h, ln, X, pt, Y, pt))) return rc;
+  if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
+  if ((rc = spmm_csc(h, ln, Y, pt, ln.Pt, PanelType::F32))) return rc;
   {
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 4.0 * d * ell, 2.0 * d * ell * ell, 2);
-    CK(gram(ln.Pt, L, d, L, ln.gram_part, ln.W, ln.st));
+    // P^T <- P^T T_y and W = P P^T
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 4.0 * d * ell * ell, 2);
+    CK(xform_gram(ln.Pt, PanelType::F32, L, d, L, ln.T, ln.gram_part, ln.W, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
@@ -783,6 +819,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_STREAM_ID:
       if (!(value >= 0) || value > 9.0e15 || value != std::floor(value)) return SFD_E_ARG;
       h->stream_id = (uint64_t)value;
+      return SFD_OK;
+    case SFD_OPT_PRECISION:
+      if (value != SFD_PRECISION_FP32 && value != SFD_PRECISION_BF16) return SFD_E_ARG;
+      h->precision = (int)value;
       return SFD_OK;
     case SFD_OPT_LANES:
       if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;

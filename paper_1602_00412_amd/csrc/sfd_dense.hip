@@ -5,6 +5,9 @@
 //
 // Panels are row-major and tall (d x L or m x L, L = ell rounded up to 32, zero-padded), so
 // every Gram has its contraction along the tall axis.
+#include <type_traits>
+#include <utility>
+
 #include "sfd_internal.h"
 
 namespace sfd {
@@ -19,25 +22,55 @@ constexpr int kGramMaxBlocks = 256;
 // float per lane, lane l holding row-of-A / column-of-B (l % 16) at k = l / 16; the 16 x 16
 // accumulator leaves 4 floats per lane, lane l holding column l % 16, rows 4*(l/16) .. +3.
 // For W = P^T P both operands are the same 4-row slab of the panel: lane l loads
-// P[k0 + l/16][16*s + l%16] for each 16-column strip s.  Eight waves per block split the rows
-// (and, for W = 128, the tiles); the next slab is loaded while the current one is multiplied.
+// P[k0 + l/16][16*s + l%16] for each 16-column strip s.  Only the tiles on and above the
+// diagonal are formed (the reduction mirrors them).  Eight waves per block split the rows; each
+// wave keeps kGramDepth slabs in flight: a slab's MFMAs
+// run while the loads of the slabs after it are outstanding.
 constexpr int kGramThreads = 512;
 constexpr int kGramWaves = kGramThreads / 64;
+constexpr int kGramDepth = 4;
+
+// the tiles of the upper triangle of an S x S tile grid in row-major order: (ti[u], tj[u]), ti <= tj
+template <int S>
+struct UpperTiles {
+  int ti[S * (S + 1) / 2];
+  int tj[S * (S + 1) / 2];
+  constexpr UpperTiles() : ti(), tj() {
+    int u = 0;
+    for (int i = 0; i < S; ++i)
+      for (int j = i; j < S; ++j) {
+        ti[u] = i;
+        tj[u] = j;
+        ++u;
+      }
+  }
+};
+template <int S>
+constexpr UpperTiles<S> kUpper{};
+
+// element e of a panel row stored as FP32 or as BF16 (the upper half of an FP32)
+template <bool BF>
+__device__ inline float panel_elem(const void* row, int e) {
+  if constexpr (BF)
+    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(row)[e] << 16);
+  else
+    return reinterpret_cast<const float*>(row)[e];
+}
 
 // TWO: the panel is [P | P2] side by side, each W/2 wide (strips of the right half from P2).
-template <int W, bool TWO>
-__global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __restrict__ P, int ld,
+// BF: P is a BF16 panel (products of BF16 values are exact in FP32, so its Gram is the exact
+// Gram of the stored values up to FP32 accumulation).
+template <int W, bool TWO, bool BF>
+__global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __restrict__ P, int ld,
                                                                const float* __restrict__ P2, int ld2, int64_t rows,
                                                                int rpb, float* __restrict__ partials) {
-  constexpr int S = W / 16;                // strips
-  constexpr int NT = S * S;                // 16 x 16 tiles
-  constexpr int TG = NT >= 64 ? 4 : 1;     // tile groups (waves split tiles)
-  constexpr int KG = kGramWaves / TG;      // k groups (waves split rows)
-  constexpr int TPW = NT / TG;             // tiles per wave
+  constexpr int S = W / 16;            // strips
+  constexpr int NU = S * (S + 1) / 2;  // tiles on and above the diagonal, all formed by every wave
+  constexpr int KG = kGramWaves;       // k groups (waves split rows)
+  constexpr int TPW = NU;
+  constexpr int D = kGramDepth;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int tg = wave % TG;
-  const int kg = wave / TG;
+  const int kg = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = min(rows, r0 + rpb);
   floatx4 acc[TPW];
@@ -46,49 +79,185 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __re
   const int lrow = lane >> 4;
   const int lcol = lane & 15;
   constexpr int SPLIT = TWO ? S / 2 : S;  // strips read from P; the rest from P2
-  float f[S], g[S];
+  const int64_t step = 4 * KG;
+  float f[D][S];
+#define SFD_GRAM_LOAD(dd, k)                                                                        \
+  do {                                                                                              \
+    const int64_t row_ = (k) + lrow;                                                                \
+    const bool ok_ = row_ < r1;                                                                     \
+    const char* pr_ = reinterpret_cast<const char*>(P) + (size_t)(ok_ ? row_ : 0) * ld * (BF ? 2 : 4); \
+    const float* pr2_ = P2 + (ok_ ? row_ : 0) * ld2 + lcol;                                         \
+    _Pragma("unroll") for (int s = 0; s < S; ++s) f[dd][s] =                                        \
+        ok_ ? (s < SPLIT ? panel_elem<BF>(pr_, 16 * s + lcol) : pr2_[16 * (s - SPLIT)]) : 0.f;      \
+  } while (0)
   int64_t k0 = r0 + 4 * kg;
-  {
-    const int64_t row = k0 + lrow;
-    const bool ok = row < r1;
-    const float* pr = P + (ok ? row : 0) * ld + lcol;
-    const float* pr2 = P2 + (ok ? row : 0) * ld2 + lcol;
 #pragma unroll
-    for (int s = 0; s < S; ++s) f[s] = ok ? (s < SPLIT ? pr[16 * s] : pr2[16 * (s - SPLIT)]) : 0.f;
-  }
-  for (; k0 < r1; k0 += 4 * KG) {
-    const int64_t nrow = k0 + 4 * KG + lrow;
-    const bool ok = nrow < r1;
-    const float* pr = P + (ok ? nrow : 0) * ld + lcol;
-    const float* pr2 = P2 + (ok ? nrow : 0) * ld2 + lcol;
+  for (int dd = 0; dd < D; ++dd) SFD_GRAM_LOAD(dd, k0 + dd * step);
+  for (; k0 < r1; k0 += D * step) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) g[s] = ok ? (s < SPLIT ? pr[16 * s] : pr2[16 * (s - SPLIT)]) : 0.f;
+    for (int dd = 0; dd < D; ++dd) {
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = tg * TPW + t;
-      const int ti = tile / S, tj = tile % S;
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[ti], f[tj], acc[t], 0, 0, 0);
+      for (int t = 0; t < TPW; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[dd][kUpper<S>.ti[t]], f[dd][kUpper<S>.tj[t]], acc[t], 0, 0,
+                                                      0);
+      SFD_GRAM_LOAD(dd, k0 + (dd + D) * step);
     }
+  }
+#undef SFD_GRAM_LOAD
+  // the k groups add their sums into one LDS copy in k-group order, then the block writes it
+  __shared__ float red[W * W];
+  for (int g2 = 0; g2 < KG; ++g2) {
+    if (kg == g2) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) f[s] = g[s];
+      for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int e = (16 * kUpper<S>.ti[t] + 4 * lrow + v) * W + 16 * kUpper<S>.tj[t] + lcol;
+          red[e] = g2 == 0 ? acc[t][v] : red[e] + acc[t][v];
+        }
+      }
+    }
+    __syncthreads();
   }
   float* out = partials + (int64_t)blockIdx.x * W * W;
-  // each k group writes its sums to its own LDS region; then all threads add the regions in
-  // k-group order (W = 64: 8 x 16 KiB, W = 128: 2 x 64 KiB)
-  __shared__ float red[KG][W * W];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = tg * TPW + t;
-    const int ti = tile / S, tj = tile % S;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) red[kg][(16 * ti + 4 * lrow + v) * W + 16 * tj + lcol] = acc[t][v];
-  }
-  __syncthreads();
   for (int e = threadIdx.x; e < W * W; e += kGramThreads) {
-    float sum = red[0][e];
+    const int i = e / W, j = e % W;
+    if (i / 16 <= j / 16) out[e] = red[e];
+  }
+}
+
+// P <- P T in place (rows x L panel, FP32 or BF16 elements, pitch ld; T: L x L FP32) and the
+// per-block partial Gram of the result as stored (BF16-rounded in the BF16 form), for
+// k_gram_reduce.  This applies the inverse Cholesky factor of a product's input panel to the
+// product's output (A'(X T) = (A' X) T), so the sparse products need no per-row epilogue.
+// Both the transform and the Gram run on MFMA (v_mfma_f32_16x16x4f32), 16 rows at a time per
+// wave (wave w of a block: tiles w, w + 8, ...):
+//  * the tile is loaded coalesced and staged in LDS (row pitch L + 4 floats: the A-operand reads
+//    below hit 64 distinct banks);
+//  * out (16 x L) = tile (16 x L) * T: k-step ks, strip n: A[m][k] = tile[m][4 ks + k] (lane l:
+//    m = l % 16, k = l / 16), B[k][n'] = T[4 ks + k][16 n + n'] (held in registers), C lane l:
+//    out[4 (l / 16) + v][16 n + l % 16];
+//  * the accumulator of strip n at fixed v is itself an A / B operand over the four rows
+//    4 k + v (k = l / 16), so Gram += out^T out is formed from the registers directly: for
+//    v = 0..3 and each upper tile (si, sj), MFMA(C_si[v], C_sj[v]).
+template <int L, bool BF>
+__global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ P, int ld, int64_t rows, int rpb,
+                                                             const float* __restrict__ T,
+                                                             float* __restrict__ partials) {
+  static_assert(L == 32 || L == 64, "panel width");
+  constexpr int S = L / 16;            // column strips
+  constexpr int KS = L / 4;            // k-steps of the transform
+  constexpr int NU = S * (S + 1) / 2;  // upper tiles of the Gram
+  constexpr int NW = kGramWaves;
+  constexpr int LP = L + 4;            // LDS row pitch (floats)
+  constexpr int EPL = BF ? 8 : 4;      // elements per lane per load (16 bytes)
+  constexpr int LPRW = L / EPL;        // lanes per row in a load pass
+  constexpr int RPP = 64 / LPRW;       // rows per load pass
+  constexpr int NP = 16 / RPP;         // load passes per 16-row tile
+  __shared__ float tile[NW][16 * LP];
+  __shared__ float red[L * L];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  float tb[KS][S];
 #pragma unroll
-    for (int g2 = 1; g2 < KG; ++g2) sum += red[g2][e];
-    out[e] = sum;
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int n = 0; n < S; ++n) tb[ks][n] = T[(4 * ks + lk) * L + 16 * n + lm];
+  floatx4 g[NU];
+#pragma unroll
+  for (int t = 0; t < NU; ++t) g[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = min(rows, r0 + rpb);
+  char* base = reinterpret_cast<char*>(P);
+  const size_t pitch = (size_t)ld * (BF ? 2 : 4);
+  const int prow = lane / LPRW, pcol = (lane % LPRW) * EPL;  // this lane's part of a load pass
+  float* my = tile[wave];
+  using raw = typename std::conditional<BF, uint4, float4>::type;
+  raw nxt[NP];
+  auto load_tile = [&](int64_t t0) {
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      const int64_t row = t0 + ip * RPP + prow;
+      if (row < r1)
+        nxt[ip] = *reinterpret_cast<const raw*>(base + row * pitch + (size_t)pcol * (BF ? 2 : 4));
+      else
+        nxt[ip] = raw{0, 0, 0, 0};
+    }
+  };
+  int64_t t0 = r0 + 16 * wave;
+  load_tile(t0);
+  for (; t0 < r1; t0 += 16 * NW) {
+    // stage the tile (as FP32) and start loading the next one
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      float* dst = my + (ip * RPP + prow) * LP + pcol;
+      if constexpr (BF) {
+        const uint4 w = nxt[ip];
+        reinterpret_cast<float4*>(dst)[0] = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                                                        __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+        reinterpret_cast<float4*>(dst)[1] = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xFFFF0000u),
+                                                        __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xFFFF0000u));
+      } else {
+        reinterpret_cast<float4*>(dst)[0] = nxt[ip];
+      }
+    }
+    load_tile(t0 + 16 * NW);
+    __builtin_amdgcn_wave_barrier();
+    // out = tile * T
+    floatx4 o[S];
+#pragma unroll
+    for (int n = 0; n < S; ++n) o[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const float a = my[lm * LP + 4 * ks + lk];
+#pragma unroll
+      for (int n = 0; n < S; ++n) o[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tb[ks][n], o[n], 0, 0, 0);
+    }
+    // round to the stored precision, store, and add the stored values' Gram
+#pragma unroll
+    for (int n = 0; n < S; ++n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = t0 + 4 * lk + v;
+        float x = o[n][v];
+        if constexpr (BF) {
+          uint32_t u = __float_as_uint(x);
+          u += 0x7FFFu + ((u >> 16) & 1u);
+          u &= 0xFFFF0000u;
+          x = __uint_as_float(u);
+          if (row < r1) reinterpret_cast<uint16_t*>(base + row * pitch)[16 * n + lm] = (uint16_t)(u >> 16);
+        } else {
+          if (row < r1) reinterpret_cast<float*>(base + row * pitch)[16 * n + lm] = x;
+        }
+        o[n][v] = row < r1 ? x : 0.f;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < NU; ++t)
+        g[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o[kUpper<S>.ti[t]][v], o[kUpper<S>.tj[t]][v], g[t], 0, 0, 0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  // the waves add their sums into one LDS copy in wave order, then the block writes it
+  for (int g2 = 0; g2 < NW; ++g2) {
+    if (wave == g2) {
+#pragma unroll
+      for (int t = 0; t < NU; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = (16 * kUpper<S>.ti[t] + 4 * lk + q) * L + 16 * kUpper<S>.tj[t] + lm;
+          red[e] = g2 == 0 ? g[t][q] : red[e] + g[t][q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partials + (int64_t)blockIdx.x * L * L;
+  for (int e = threadIdx.x; e < L * L; e += kGramThreads) {
+    const int i = e / L, j = e % L;
+    if (i / 16 <= j / 16) out[e] = red[e];
   }
 }
 
@@ -274,19 +443,52 @@ static void gram_grid(int64_t rows, int64_t& nb, int& rpb) {
   nb = rows > 0 ? (rows + rpb - 1) / rpb : 1;
 }
 
-hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st) {
+hipError_t gram(const void* P, PanelType pt, int ld, int64_t rows, int w, float* partials, double* W,
+                hipStream_t st) {
   int64_t nb;
   int rpb;
   gram_grid(rows, nb, rpb);
+  const float* none = nullptr;
+  const bool bf = pt == PanelType::BF16;
   switch (w) {
-    case 32: k_gram_partial<32, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials); break;
-    case 64: k_gram_partial<64, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials); break;
-    case 128:
-      k_gram_partial<128, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, P, ld, rows, rpb, partials);
+    case 32:
+      if (bf)
+        k_gram_partial<32, false, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
+      else
+        k_gram_partial<32, false, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
+      break;
+    case 64:
+      if (bf)
+        k_gram_partial<64, false, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
+      else
+        k_gram_partial<64, false, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
       break;
     default: return hipErrorInvalidValue;
   }
   k_gram_reduce<<<(unsigned)((w * w + 15) / 16), 256, 0, st>>>(partials, (int)nb, w, W);
+  return hipGetLastError();
+}
+
+hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
+                      hipStream_t st) {
+  int64_t nb;
+  int rpb;
+  gram_grid(rows, nb, rpb);
+  const bool bf = pt == PanelType::BF16;
+  if (L == 32) {
+    if (bf)
+      k_xform_gram<32, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+    else
+      k_xform_gram<32, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+  } else if (L == 64) {
+    if (bf)
+      k_xform_gram<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+    else
+      k_xform_gram<64, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  k_gram_reduce<<<(unsigned)((L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, L, W);
   return hipGetLastError();
 }
 
@@ -296,9 +498,11 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
   int rpb;
   gram_grid(rows, nb, rpb);
   switch (L) {
-    case 32: k_gram_partial<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials); break;
+    case 32:
+      k_gram_partial<64, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
+      break;
     case 64:
-      k_gram_partial<128, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
+      k_gram_partial<128, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -11,6 +11,10 @@ constexpr int kMaxEll = 56;      // 2*ell <= 112 keeps the FP64 eigensolver in o
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
 constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
 
+// element type of a dense panel (FP32, or BF16 in the precision form: the upper 16 bits of an
+// FP32 value, rounded to nearest even)
+enum class PanelType { F32, BF16 };
+
 // Small device-resident scalars of one buffer step.
 struct DevScalars {
   double fro2A;       // ||A'||_F^2 (repeated entries summed)
@@ -34,6 +38,8 @@ hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStrea
 int64_t scan_tmp_ints(int64_t n);
 // copy a d x w block between panels with pitches (elements)
 hipError_t copy_panel(const float* src, int lds, float* dst, int ldd, int64_t rows, int w, hipStream_t st);
+// dst[i] = BF16 rounding of src[i], n elements
+hipError_t to_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t st);
 // out (ell x d, row-major) = panel^T restricted to the first ell columns
 hipError_t transpose_out(const float* panel, int ld, int64_t d, int ell, float* out, hipStream_t st);
 
@@ -88,23 +94,29 @@ struct Schedule {
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation);
 // with s.bands > 1 the structure is a banded CSC of s.band_rows columns per band
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
-// Y[r, :] = (sum_k val[k] X[idx[k], :]) * T  (rows of width L, pitches ldx / ldy; T: L x L f32,
-// nullptr for none; L <= 64 with T).  For a banded schedule r runs over the band_rows output
-// rows and the bands are added in band order.
-// (main kernel only; spmm_finish completes the product)
-hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* X, int ldx,
-                float* Y, int ldy, int L, float* partial, const float* T, hipStream_t st);
-// the long rows' fix-up of a product (and for a banded schedule the band sums times T)
-hipError_t spmm_finish(const Schedule& s, float* partial, const float* T, float* Y, int ldy, int L, hipStream_t st);
+// Y[r, :] = sum_k val[k] X[idx[k], :] over the structure of schedule s (its entries idx, val);
+// rows of width L (32 or 64) with pitches ldx / ldy in elements; FP32 accumulation.  Panel
+// types: F32 -> F32, BF16 -> BF16 and BF16 -> F32.  For a banded schedule (F32 only) r runs over
+// the band_rows output rows and the bands are added in band order by spmm_finish.  This launches
+// the main kernel only; spmm_finish completes the product.
+hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
+                PanelType yt, int ldy, int L, float* partial, hipStream_t st);
+// the long rows' fix-up of a product (and for a banded schedule the band sums)
+hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)
 hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* y,
                 const double* scale_ptr, float* z, float* partial, hipStream_t st);
 
 // ---------------------------------------------------------------- dense panels (sfd_dense.hip)
-// Gram W = P^T P of a rows x w panel (w in {32, 64, 128}) into FP64 W (w x w); partials
-// hold at most gram_max_blocks() blocks of w*w floats
+// Gram W = P^T P of a rows x w panel (w in {32, 64}, FP32 or BF16 elements, pitch ld elements)
+// into FP64 W (w x w); partials hold at most gram_max_blocks() blocks of 4*w*w floats
 int gram_max_blocks();
-hipError_t gram(const float* P, int ld, int64_t rows, int w, float* partials, double* W, hipStream_t st);
+hipError_t gram(const void* P, PanelType pt, int ld, int64_t rows, int w, float* partials, double* W,
+                hipStream_t st);
+// P <- P T in place (rows x L, L in {32, 64}, FP32 or BF16; T: L x L f32) and W = Gram of the
+// result as stored (FP64, L x L)
+hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
+                      hipStream_t st);
 // Gram of the side-by-side panel [P1 | P2] (rows x 2L, each half L wide) into FP64 (2L x 2L)
 hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t rows, int L, float* partials, double* W,
                  hipStream_t st);

@@ -54,20 +54,21 @@ __global__ void k_sched_desc(const int* ptr, int rows, const int* chunk_start, c
   }
 }
 
-__device__ inline float4 fma4(float v, float4 x, float4 a) {
-  a.x = fmaf(v, x.x, a.x);
-  a.y = fmaf(v, x.y, a.y);
-  a.z = fmaf(v, x.z, a.z);
-  a.w = fmaf(v, x.w, a.w);
-  return a;
+// BF16 storage of panels: the upper 16 bits of an FP32 value, rounded to nearest even.
+__device__ inline uint32_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
 }
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// value of lane J of this lane's LPR-lane group (LPR = 8 or 16; groups never straddle a 32-lane
-// half): ds_swizzle in bit-mask mode, source = (lane & ~(LPR - 1) & 31) | J
+// value of lane J of this lane's LPR-lane group (LPR = 4, 8 or 16; groups never straddle a
+// 32-lane half): ds_swizzle in bit-mask mode, source = (lane & 31 & ~(LPR - 1)) | J
 template <int LPR, int J>
 __device__ inline int bcast_i(int v) {
-  static_assert(LPR == 8 || LPR == 16, "group width");
-  constexpr int and_mask = LPR == 16 ? 0x10 : 0x18;
+  static_assert(LPR == 4 || LPR == 8 || LPR == 16, "group width");
+  constexpr int and_mask = 0x1F & ~(LPR - 1);
   return __builtin_amdgcn_ds_swizzle(v, and_mask | (J << 5));
 }
 template <int LPR, int J>
@@ -75,43 +76,99 @@ __device__ inline float bcast_f(float v) {
   return __int_as_float(bcast_i<LPR, J>(__float_as_int(v)));
 }
 
+// A panel row segment of one lane: VEC consecutive columns, FP32 (VEC = 4, one float4) or BF16
+// (VEC = 8, one 16-byte word).
+template <bool BF>
+struct Seg;
+template <>
+struct Seg<false> {
+  static constexpr int VEC = 4;
+  using raw = float4;
+  __device__ static inline void fma(float v, const raw& x, float* a) {
+    a[0] = fmaf(v, x.x, a[0]);
+    a[1] = fmaf(v, x.y, a[1]);
+    a[2] = fmaf(v, x.z, a[2]);
+    a[3] = fmaf(v, x.w, a[3]);
+  }
+};
+template <>
+struct Seg<true> {
+  static constexpr int VEC = 8;
+  using raw = uint4;
+  __device__ static inline void fma(float v, const raw& x, float* a) {
+    a[0] = fmaf(v, bf16_lo(x.x), a[0]);
+    a[1] = fmaf(v, bf16_hi(x.x), a[1]);
+    a[2] = fmaf(v, bf16_lo(x.y), a[2]);
+    a[3] = fmaf(v, bf16_hi(x.y), a[3]);
+    a[4] = fmaf(v, bf16_lo(x.z), a[4]);
+    a[5] = fmaf(v, bf16_hi(x.z), a[5]);
+    a[6] = fmaf(v, bf16_lo(x.w), a[6]);
+    a[7] = fmaf(v, bf16_hi(x.w), a[7]);
+  }
+};
+
+// store VEC FP32 values of a row segment as FP32 or BF16
+template <int VEC, bool BF>
+__device__ inline void store_seg(void* row, int sub, const float* o) {
+  if constexpr (!BF) {
+    float4* d = reinterpret_cast<float4*>(row) + (VEC / 4) * sub;
+#pragma unroll
+    for (int q = 0; q < VEC / 4; ++q) d[q] = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else if constexpr (VEC == 8) {
+    uint4 w;
+    w.x = f32_to_bf16(o[0]) | (f32_to_bf16(o[1]) << 16);
+    w.y = f32_to_bf16(o[2]) | (f32_to_bf16(o[3]) << 16);
+    w.z = f32_to_bf16(o[4]) | (f32_to_bf16(o[5]) << 16);
+    w.w = f32_to_bf16(o[6]) | (f32_to_bf16(o[7]) << 16);
+    reinterpret_cast<uint4*>(row)[sub] = w;
+  } else {
+    uint2 w;
+    w.x = f32_to_bf16(o[0]) | (f32_to_bf16(o[1]) << 16);
+    w.y = f32_to_bf16(o[2]) | (f32_to_bf16(o[3]) << 16);
+    reinterpret_cast<uint2*>(row)[sub] = w;
+  }
+}
+
 // U entries of the group's current block, starting at entry T0 of the block: broadcast their
-// ids and values from the lanes that loaded them, gather the U dense rows, accumulate.
-template <int LPR, int U, int T0>
-__device__ inline void gather_block(int ci, float vi, const float4* __restrict__ X4, int ldx4, int sub, float4& acc) {
+// ids and values from the lanes that loaded them, gather the U dense row segments, accumulate.
+template <int LPR, int U, int T0, bool BF>
+__device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::raw* __restrict__ Xs, int lds, int sub,
+                                    float* acc) {
   int c[U];
   float v[U];
-  float4 x[U];
+  typename Seg<BF>::raw x[U];
   [&]<int... u>(std::integer_sequence<int, u...>) {
     ((c[u] = bcast_i<LPR, T0 + u>(ci), v[u] = bcast_f<LPR, T0 + u>(vi)), ...);
   }(std::make_integer_sequence<int, U>{});
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = X4[(int64_t)c[u] * ldx4 + sub];
+  for (int u = 0; u < U; ++u) x[u] = Xs[(int64_t)c[u] * lds + sub];
 #pragma unroll
-  for (int u = 0; u < U; ++u) acc = fma4(v[u], x[u], acc);
+  for (int u = 0; u < U; ++u) Seg<BF>::fma(v[u], x[u], acc);
 }
 
-// Y[r, :] = (sum_k val[k] X[idx[k], :]) [* T] over chunk descriptors.  Each L/4-lane group owns
-// a chunk at a time and walks it in blocks of L/4 entries: lane s of the group loads entry s of
-// the block (coalesced), then the entries are broadcast inside the group and their dense rows
-// gathered as float4 (lane s holds columns 4s..4s+3).  The next block's ids and values, and the
-// next chunk's descriptor, are loaded before the current block's gathers, so one memory latency
-// per block is exposed instead of three.  A group's chunks are c, c + S, c + 2S, ... in its
-// band's chunk range (S = all groups of the band).
+// Y[r, :] = sum_k val[k] X[idx[k], :] over chunk descriptors, X and Y FP32 or BF16
+// panels (BIN / BOUT), FP32 accumulation.  A group of L/VEC lanes owns a chunk at a time (lane s
+// holds columns VEC s .. VEC s + VEC - 1) and walks it in blocks of L/VEC entries: lane s of the
+// group loads entry s of the block (coalesced), then the entries are broadcast inside the group
+// and their dense row segments gathered.  The next block's ids and values, and the next chunk's
+// descriptor, are loaded before the current block's gathers, so one memory latency per block is
+// exposed instead of three.  A group's chunks are c, c + S, c + 2S, ... in its band's chunk
+// range (S = all groups of the band).
 // Bands (bands > 1, banded CSC): band b's chunks run on the blocks with blockIdx % bands == b;
 // workgroups are dispatched round-robin over the 8 XCDs, so with 8 bands each XCD gathers from
-// its own band's rows of X only.  Output: a whole row goes to out[r] (times T when XF, T in LDS,
-// applied through in-group broadcasts), the chunks of a long row to their partial slots
-// (untransformed; the fix-up adds them and applies T).
-template <int L, bool XF, int U, bool TRANSPOSED>
+// its own band's rows of X only.
+// Output: a whole row goes to out[r], the chunks of a long row to their FP32 partial slots (the
+// fix-up adds them in chunk order).  The inverse Cholesky factor of the input panel is applied to
+// the output afterwards (xform_gram), together with the output's Gram.
+template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT>
 __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ chunk_start,
                                               int bands, int band_rows, const int* __restrict__ idx,
-                                              const float* __restrict__ val, const float* __restrict__ X, int ldx,
-                                              float* __restrict__ out, int ldo, float* __restrict__ partial,
-                                              const float* __restrict__ T) {
-  constexpr int LPR = L / 4;   // lanes per group
-  constexpr int G = 64 / LPR;  // groups per wave
-  __shared__ float4 tl4[XF ? L * L / 4 : 1];
+                                              const float* __restrict__ val, const void* __restrict__ X, int ldx,
+                                              void* __restrict__ out, int ldo, float* __restrict__ partial) {
+  using S = Seg<BIN>;
+  constexpr int VEC = S::VEC;
+  constexpr int LPR = L / VEC;  // lanes per group
+  constexpr int G = 64 / LPR;   // groups per wave
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int sub = lane % LPR;
@@ -121,13 +178,9 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
   const int c0 = chunk_start[(int64_t)band * band_rows];
   const int c1 = chunk_start[(int64_t)(band + 1) * band_rows];
   const int64_t stride = (int64_t)(gridDim.x / bands) * 4 * G;
-  if (XF) {
-    const float4* T4 = reinterpret_cast<const float4*>(T);
-    for (int e = threadIdx.x; e < L * L / 4; e += 256) tl4[e] = T4[e];
-    __syncthreads();
-  }
-  const float4* X4 = reinterpret_cast<const float4*>(X);
-  const int ldx4 = ldx / 4;
+  const typename S::raw* Xs = reinterpret_cast<const typename S::raw*>(X);
+  const int lds = ldx / VEC;  // row pitch in segments
+  const size_t out_row_bytes = (size_t)ldo * (BOUT ? 2 : 4);
   int64_t cc = c0 + ((int64_t)slot * 4 + wave) * G + grp;
   int4 dc = cc < c1 ? desc[cc] : make_int4(0, 0, 0, -1);
   int64_t ncc = cc + stride;
@@ -139,7 +192,9 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
     ci = idx[p + sub];
     vi = val[p + sub];
   }
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  float acc[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) acc[q] = 0.f;
   while (cc < c1) {
     // where the next block starts: later in this chunk, or at the group's next chunk
     const bool same = p + LPR < dc.z;
@@ -153,33 +208,32 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
     }
     // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
     const int cnt = min(LPR, dc.z - p);
-    if (cnt > 0) gather_block<LPR, U, 0>(ci, vi, X4, ldx4, sub, acc);
+    if (cnt > 0) gather_block<LPR, U, 0, BIN>(ci, vi, Xs, lds, sub, acc);
     if constexpr (LPR > U) {
-      if (cnt > U) gather_block<LPR, U, U>(ci, vi, X4, ldx4, sub, acc);
+      if (cnt > U) gather_block<LPR, U, U, BIN>(ci, vi, Xs, lds, sub, acc);
     }
     if constexpr (LPR > 2 * U) {
-      if (cnt > 2 * U) gather_block<LPR, U, 2 * U>(ci, vi, X4, ldx4, sub, acc);
+      if (cnt > 2 * U) gather_block<LPR, U, 2 * U, BIN>(ci, vi, Xs, lds, sub, acc);
     }
     if constexpr (LPR > 3 * U) {
-      if (cnt > 3 * U) gather_block<LPR, U, 3 * U>(ci, vi, X4, ldx4, sub, acc);
+      if (cnt > 3 * U) gather_block<LPR, U, 3 * U, BIN>(ci, vi, Xs, lds, sub, acc);
     }
     if (!same) {
-      float* dst = dc.w < 0 ? out + (int64_t)dc.x * ldo : partial + (int64_t)dc.w * L;
-      if (XF) {
-        // o[4 sub + q] = sum_k acc_k T[k][4 sub + q]; acc_k sits in lane k / 4 of the group
-        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
-        [&]<int... j>(std::integer_sequence<int, j...>) {
-          ((o = fma4(bcast_f<LPR, j>(acc.x), tl4[(4 * j + 0) * (L / 4) + sub], o),
-            o = fma4(bcast_f<LPR, j>(acc.y), tl4[(4 * j + 1) * (L / 4) + sub], o),
-            o = fma4(bcast_f<LPR, j>(acc.z), tl4[(4 * j + 2) * (L / 4) + sub], o),
-            o = fma4(bcast_f<LPR, j>(acc.w), tl4[(4 * j + 3) * (L / 4) + sub], o)),
-           ...);
-        }(std::make_integer_sequence<int, LPR>{});
-        reinterpret_cast<float4*>(dst)[sub] = o;
+      float o[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) o[q] = acc[q];
+      if constexpr (BOUT) {
+        if (dc.w < 0)
+          store_seg<VEC, true>(reinterpret_cast<char*>(out) + (size_t)dc.x * out_row_bytes, sub, o);
+        else
+          store_seg<VEC, false>(partial + (int64_t)dc.w * L, sub, o);
       } else {
-        reinterpret_cast<float4*>(dst)[sub] = acc;
+        float* dst = dc.w < 0 ? reinterpret_cast<float*>(reinterpret_cast<char*>(out) + (size_t)dc.x * out_row_bytes)
+                              : partial + (int64_t)dc.w * L;
+        store_seg<VEC, false>(dst, sub, o);
       }
-      acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) acc[q] = 0.f;
       cc = ncc;
       dc = dn;
       ncc += stride;
@@ -193,11 +247,11 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
 
 // One block per long row: wave w adds the row's partials w, w + 4, ... (in order), then the
 // four wave sums are added in wave order.
-template <int L>
+template <int L, bool BOUT>
 __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ chunk_start,
                                                     const int* __restrict__ slot_start,
                                                     const int* __restrict__ long_rows, const int* __restrict__ nlong_ptr,
-                                                    const float* __restrict__ partial, float* __restrict__ Y,
+                                                    const float* __restrict__ partial, void* __restrict__ Y,
                                                     int ldy) {
   constexpr int CPL = (L + 63) / 64;  // columns per lane
   __shared__ float red[4][L];
@@ -236,8 +290,13 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ chun
     if (col < L) red[wave][col] = acc[u];
   }
   __syncthreads();
-  for (int col = threadIdx.x; col < L; col += 256)
-    Y[(int64_t)r * ldy + col] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+  for (int col = threadIdx.x; col < L; col += 256) {
+    const float v = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+    if constexpr (BOUT)
+      reinterpret_cast<uint16_t*>(Y)[(int64_t)r * ldy + col] = (uint16_t)f32_to_bf16(v);
+    else
+      reinterpret_cast<float*>(Y)[(int64_t)r * ldy + col] = v;
+  }
   __syncthreads();
   }
 }
@@ -357,10 +416,10 @@ __global__ __launch_bounds__(256) void k_band_reduce_vec(const int* __restrict__
   }
 }
 
-template <int L, bool XF, int U>
-void launch_spmm(const Schedule& s, const int* idx, const float* val, const float* X, int ldx, float* out, int ldo,
-                 float* partial, const float* T, hipStream_t st) {
-  constexpr int G = 64 / (L / 4);
+template <int L, int U, bool BIN, bool BOUT>
+void launch_spmm(const Schedule& s, const int* idx, const float* val, const void* X, int ldx, void* out, int ldo,
+                 float* partial, hipStream_t st) {
+  constexpr int G = 64 / (L / Seg<BIN>::VEC);
   // about four chunks per group; the grid is not persistent (finished blocks make room for
   // waiting ones, which balances uneven chunks), and a multiple of the band count
   int64_t per = ((int64_t)s.max_chunks / s.bands + 16 * G - 1) / (16 * G);
@@ -369,11 +428,31 @@ void launch_spmm(const Schedule& s, const int* idx, const float* val, const floa
   const int band_rows = s.bands > 1 ? s.band_rows : s.rows;
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
-    k_spmm<L, XF, U, true><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out, ldo,
-                                                 partial, T);
+    k_spmm<L, U, true, BIN, BOUT><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out,
+                                                        ldo, partial);
   else
-    k_spmm<L, XF, U, false><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out, ldo,
-                                                  partial, T);
+    k_spmm<L, U, false, BIN, BOUT><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out,
+                                                         ldo, partial);
+}
+
+template <int L>
+hipError_t spmm_l(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
+                  PanelType yt, int ldy, float* partial, hipStream_t st) {
+  const bool xb = xt == PanelType::BF16, yb = yt == PanelType::BF16;
+  if (s.bands > 1) {
+    // FP32 per-band rows; spmm_finish fixes up long rows in place and adds the bands
+    if (xb || yb) return hipErrorInvalidValue;
+    launch_spmm<L, 4, false, false>(s, idx, val, X, ldx, s.bandbuf, L, partial, st);
+  } else if (!xb && !yb) {
+    launch_spmm<L, 8, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  } else if (xb && yb) {
+    launch_spmm<L, 4, true, true>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  } else if (xb && !yb) {
+    launch_spmm<L, 4, true, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -392,49 +471,41 @@ hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, 
   return hipGetLastError();
 }
 
-hipError_t spmm(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* X, int ldx, float* Y,
-                int ldy, int L, float* partial, const float* T, hipStream_t st) {
-  (void)ptr;
-  if (L != 32 && L != 64) return hipErrorInvalidValue;
-  if (s.bands > 1) {
-    // raw per-band rows; spmm_finish fixes up long rows in place and adds the bands times T
-    if (L == 32)
-      launch_spmm<32, false, 4>(s, idx, val, X, ldx, s.bandbuf, 32, partial, nullptr, st);
-    else
-      launch_spmm<64, false, 4>(s, idx, val, X, ldx, s.bandbuf, 64, partial, nullptr, st);
-    return hipGetLastError();
-  }
-  if (L == 32) {
-    if (T)
-      launch_spmm<32, true, 8>(s, idx, val, X, ldx, Y, ldy, partial, T, st);
-    else
-      launch_spmm<32, false, 8>(s, idx, val, X, ldx, Y, ldy, partial, nullptr, st);
-  } else {
-    if (T)
-      launch_spmm<64, true, 8>(s, idx, val, X, ldx, Y, ldy, partial, T, st);
-    else
-      launch_spmm<64, false, 8>(s, idx, val, X, ldx, Y, ldy, partial, nullptr, st);
-  }
-  return hipGetLastError();
+hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
+                PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
+  if (L == 32) return spmm_l<32>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 64) return spmm_l<64>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  return hipErrorInvalidValue;
 }
 
-hipError_t spmm_finish(const Schedule& s, float* partial, const float* T, float* Y, int ldy, int L, hipStream_t st) {
+hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st) {
+  const float* T = nullptr;
   if (L != 32 && L != 64) return hipErrorInvalidValue;
   const int* nlong = s.counters;
   const unsigned gfix = 256;
+  const bool yb = yt == PanelType::BF16;
   if (s.bands > 1) {
+    if (yb) return hipErrorInvalidValue;
     const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((s.band_rows + 3) / 4, 8192));
     if (L == 32) {
-      k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 32);
-      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
+      k_spmm_fixup<32, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 32);
+      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, reinterpret_cast<float*>(Y),
+                                            ldy);
     } else {
-      k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 64);
-      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, Y, ldy);
+      k_spmm_fixup<64, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 64);
+      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, reinterpret_cast<float*>(Y),
+                                            ldy);
     }
   } else if (L == 32) {
-    k_spmm_fixup<32><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    if (yb)
+      k_spmm_fixup<32, true><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    else
+      k_spmm_fixup<32, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
   } else {
-    k_spmm_fixup<64><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    if (yb)
+      k_spmm_fixup<64, true><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    else
+      k_spmm_fixup<64, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
   }
   return hipGetLastError();
 }

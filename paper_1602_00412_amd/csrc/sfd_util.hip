@@ -148,7 +148,23 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
   return (unsigned)g;
 }
 
+__global__ void k_to_bf16(const float* __restrict__ src, int64_t n, uint16_t* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t u = __float_as_uint(src[i]);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    dst[i] = (uint16_t)(u >> 16);
+  }
+}
+
 }  // namespace
+
+hipError_t to_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  k_to_bf16<<<(unsigned)g, 256, 0, st>>>(src, n, dst);
+  return hipGetLastError();
+}
 
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
