@@ -20,6 +20,7 @@
  *  - Threads: a handle must not be used by two threads at once.  Different handles are
  *    independent.
  *  - Sizes: 1 <= ell <= min(d, 56) in this build; ell*d + d < 2^31 (int32 buffer indices).
+ *  - Streams: an sfd_t is one stream; an sfd_batch_t holds many (see the end of this file).
  */
 #ifndef SFD_H
 #define SFD_H
@@ -31,6 +32,7 @@ extern "C" {
 #endif
 
 typedef struct sfd_s sfd_t;
+typedef struct sfd_batch_s sfd_batch_t;
 
 enum {
   SFD_OK = 0,
@@ -178,6 +180,37 @@ int sfd_start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint64_t
 
 /* Static text for an SFD_E_* code. */
 const char *sfd_strerror(int code);
+
+/* ------------------------------------------------------------------ batched streams
+ * Many independent streams with identical per-stream semantics: stream s of a batch gives
+ * exactly the sketch of an sfd_t with the same (d, ell, eps, seed) and SFD_OPT_STREAM_ID = s
+ * fed the same rows (Alg 2 per stream; the streams share the device workspaces and their
+ * buffer steps run concurrently).  Memory per stream: the d x L sketch and a pending buffer of
+ * ell*d + d entries. */
+
+/* Create nstreams >= 1 streams.  Arguments and errors as sfd_create. */
+int sfd_batch_create(int32_t nstreams, int64_t d, int32_t ell, double eps, uint64_t seed, sfd_batch_t **out);
+int sfd_batch_destroy(sfd_batch_t *h);  /* NULL-safe */
+int sfd_batch_reset(sfd_batch_t *h);    /* every stream back to its initial state */
+/* Options as sfd_set_option, applied to every stream; SFD_OPT_STREAM_ID is rejected (stream s
+ * is keyed s).  SFD_OPT_LANES accepts 1..8 (default 8). */
+int sfd_batch_set_option(sfd_batch_t *h, int key, double value);
+int sfd_batch_set_stream(sfd_batch_t *h, void *hip_stream);
+/* Counters of stream s (as sfd_get_stats).  Errors: SFD_E_ARG. */
+int sfd_batch_get_stats(const sfd_batch_t *h, int32_t stream, sfd_stats_t *out);
+
+/* Append rows to several streams (Alg 2 per stream).  The rows form one CSR block
+ * (indptr/indices/values as in sfd_append_csr, in memory of kind mem); segment i is rows
+ * [seg_row_start[i], seg_row_start[i+1]) of the block and goes to stream stream_of_seg[i].
+ * stream_of_seg (nseg entries) and seg_row_start (nseg + 1, non-decreasing) are host arrays.
+ * A stream may appear in at most one segment per call.  Errors: SFD_E_ARG (bad table, repeated
+ * stream, bad row pointers), SFD_E_INDEX; validation happens before any stream changes. */
+int sfd_batch_append_csr(sfd_batch_t *h, int32_t nseg, const int32_t *stream_of_seg, const int64_t *seg_row_start,
+                         const int64_t *indptr, const int32_t *indices, const float *values, int mem);
+
+/* Query every stream (as sfd_sketch, non-destructive): B_out holds nstreams consecutive
+ * ell x d row-major sketches, caller-owned, in memory of kind mem. */
+int sfd_batch_sketch(sfd_batch_t *h, float *B_out, int mem);
 
 #ifdef __cplusplus
 }

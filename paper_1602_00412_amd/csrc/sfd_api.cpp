@@ -1,8 +1,9 @@
 // Host orchestrator and C ABI of the Sparse Frequent Directions library (declarations and
 // conventions in include/sfd.h).
 //
-// Device state of a handle: the sketch B stored transposed as a d x L panel (row-major,
-// L = ell rounded up to 32, zero-padded), the pending buffer A' as CSR, and kLanes "lanes".
+// Device state of a handle: per stream (one for sfd_t, nstreams for sfd_batch_t) the sketch B
+// stored transposed as a d x L panel (row-major, L = ell rounded up to 32, zero-padded) and the
+// pending buffer A' as CSR; and up to kLanes "lanes" shared by the streams.
 // A lane is the workspace of one buffer step with its own HIP stream: a CSR view of the buffer,
 // its CSC copy and chunk schedules, the SimultaneousIteration panels X (d x L) and Y (m x L),
 // P^T (d x L) and the small FP64 work.  The buffer step (Alg 2's flush) is:
@@ -20,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -34,7 +36,24 @@ constexpr double kAlpha = 6.0 / 41.0;                 // alpha of Alg 4 / Theore
 constexpr double kUnitRoundoff32 = 1.0 / 16777216.0;  // 2^-24: the panels' arithmetic
 constexpr double kCholDropTol = 1e-5;                 // relative residual^2 below which a column is dependent
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
-constexpr int kLanes = 4;
+constexpr int kLanes = 8;         // lanes of a batch handle; a single-stream handle uses 4
+constexpr int kLanesSingle = 4;
+
+// State of one stream (Alg 2): the sketch B (stored transposed, d x L), the pending buffer A'
+// (CSR), the flush index b, the persistent VerifySpectral counter i and the structural count
+// of live rows of B.
+struct StreamState {
+  uint64_t stream_id = 0;
+  int live = 0;
+  int64_t flushes = 0, vs_calls = 0;
+  sfd_stats_t stats{};
+  float* B = nullptr;
+  int* prow = nullptr;
+  int* pcol = nullptr;
+  float* pval = nullptr;
+  int pm = 0, pnnz = 0;
+  hipEvent_t ev_dsh = nullptr;  // the stream's last DenseShrink (B is current after it)
+};
 
 struct Lane {
   hipStream_t st = nullptr;
@@ -66,6 +85,8 @@ struct Lane {
   double* vs_npart = nullptr;
   DevScalars* sc = nullptr;
   DevScalars* sc_host = nullptr;  // pinned
+  StreamState* ss = nullptr;      // the stream whose buffer the lane holds
+  float* Bq = nullptr;            // d x L: a query's copy of B with the pending rows folded in
 };
 
 }  // namespace
@@ -77,34 +98,25 @@ struct sfd_s {
   int ell = 0;
   int L = 0;
   double eps = 0.25;
-  uint64_t seed = 0, stream_id = 0;
+  uint64_t seed = 0;
   double delta = 0.01;
   int q_override = 0;
   int max_attempts = 16;
   int verify = 1;
   int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic
-  int nlanes = kLanes;    // SFD_OPT_LANES: lanes used for successive buffers
+  int lanes_alloc = kLanesSingle;  // lanes with workspaces
+  int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
-  // stream state
-  int live = 0;
-  int64_t flushes = 0, vs_calls = 0;
+  // streams (one for an sfd_t handle, nstreams for a batch handle)
+  std::vector<StreamState> streams;
   int error = 0;
-  sfd_stats_t stats{};
   int64_t cap = 0;
-  // device memory
-  float* B = nullptr;   // d x L: the sketch, transposed
-  float* Bq = nullptr;  // d x L: a query's copy of B with the pending rows folded in
-  int* prow = nullptr;  // pending buffer (CSR): rows, entries
-  int* pcol = nullptr;
-  float* pval = nullptr;
-  int pm = 0, pnnz = 0;
   Lane lanes[kLanes];
   int* err_dev = nullptr;
   int64_t* cut_dev = nullptr;
   int64_t cut_cap = 0;
   int64_t* i64_host = nullptr;  // pinned small readbacks
   hipEvent_t ev_in = nullptr;   // caller's stream -> lanes
-  hipEvent_t ev_dsh = nullptr;  // the last DenseShrink (B is current after it)
   std::vector<void*> allocs;
   // per-class profile (SFD_OPT_PROFILE)
   int prof = 0;
@@ -159,11 +171,14 @@ void free_all(sfd_t* h) {
     if (ln.st) (void)hipStreamDestroy(ln.st);
     ln.st = nullptr;
   }
+  for (StreamState& ss : h->streams) {
+    if (ss.ev_dsh) (void)hipEventDestroy(ss.ev_dsh);
+    ss.ev_dsh = nullptr;
+  }
   if (h->i64_host) (void)hipHostFree(h->i64_host);
   h->i64_host = nullptr;
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
-  if (h->ev_dsh) (void)hipEventDestroy(h->ev_dsh);
-  h->ev_in = h->ev_dsh = nullptr;
+  h->ev_in = nullptr;
 }
 
 int fail(sfd_t* h, int code) {
@@ -236,7 +251,7 @@ int sync_lane(sfd_t* h, Lane& ln) {
 }
 
 int sync_all(sfd_t* h) {
-  for (Lane& ln : h->lanes) CK(hipStreamSynchronize(ln.st));
+  for (int i = 0; i < h->lanes_alloc; ++i) CK(hipStreamSynchronize(h->lanes[i].st));
   if (!h->pending.empty()) prof_resolve(h);
   return SFD_OK;
 }
@@ -245,7 +260,7 @@ int sync_all(sfd_t* h) {
 int order_after_caller(sfd_t* h) {
   if (!h->user_stream) return SFD_OK;
   CK(hipEventRecord(h->ev_in, h->user_stream));
-  for (Lane& ln : h->lanes) CK(hipStreamWaitEvent(ln.st, h->ev_in, 0));
+  for (int i = 0; i < h->lanes_alloc; ++i) CK(hipStreamWaitEvent(h->lanes[i].st, h->ev_in, 0));
   return SFD_OK;
 }
 
@@ -265,11 +280,16 @@ int alloc_state(sfd_t* h) {
   const int64_t slots = 2 * cap / kSpmmChunk + 16;
   const int64_t band_rows = kMaxBands * d + 1;
   bool ok = true;
-  ok = ok && dalloc(h, &h->B, d * L) && dalloc(h, &h->Bq, d * L);
-  ok = ok && dalloc(h, &h->prow, d + 1) && dalloc(h, &h->pcol, cap) && dalloc(h, &h->pval, cap);
+  for (StreamState& ss : h->streams) {
+    ok = ok && dalloc(h, &ss.B, d * L);
+    ok = ok && dalloc(h, &ss.prow, d + 1) && dalloc(h, &ss.pcol, cap) && dalloc(h, &ss.pval, cap);
+    if (!ok) return SFD_E_NOMEM;
+    if (hipEventCreateWithFlags(&ss.ev_dsh, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
+  }
   ok = ok && dalloc(h, &h->err_dev, 4);
-  for (Lane& ln : h->lanes) {
-    ok = ok && dalloc(h, &ln.own_rowptr, d + 1);
+  for (int li = 0; li < h->lanes_alloc; ++li) {
+    Lane& ln = h->lanes[li];
+    ok = ok && dalloc(h, &ln.own_rowptr, d + 1) && dalloc(h, &ln.Bq, d * L);
     ok = ok && dalloc(h, &ln.cscptr, band_rows) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
     ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
     ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
@@ -304,24 +324,25 @@ int alloc_state(sfd_t* h) {
   if (!ok) return SFD_E_NOMEM;
   if (hipHostMalloc((void**)&h->i64_host, sizeof(int64_t) * 16) != hipSuccess) return SFD_E_NOMEM;
   if (hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
-  if (hipEventCreateWithFlags(&h->ev_dsh, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   return SFD_OK;
 }
 
 int reset_state(sfd_t* h) {
-  h->live = 0;
-  h->flushes = 0;
-  h->vs_calls = 0;
-  h->pm = 0;
-  h->pnnz = 0;
   h->error = 0;
-  std::memset(&h->stats, 0, sizeof(h->stats));
   Lane& l0 = h->lanes[0];
   int rc = sync_all(h);
   if (rc) return rc;
-  CK(fill_f32(h->B, h->d * h->L, 0.f, l0.st));
-  CK(fill_i32(h->prow, 1, 0, l0.st));
-  CK(hipEventRecord(h->ev_dsh, l0.st));
+  for (StreamState& ss : h->streams) {
+    ss.live = 0;
+    ss.flushes = 0;
+    ss.vs_calls = 0;
+    ss.pm = 0;
+    ss.pnnz = 0;
+    std::memset(&ss.stats, 0, sizeof(ss.stats));
+    CK(fill_f32(ss.B, h->d * h->L, 0.f, l0.st));
+    CK(fill_i32(ss.prow, 1, 0, l0.st));
+    CK(hipEventRecord(ss.ev_dsh, l0.st));
+  }
   return sync_all(h);
 }
 
@@ -447,8 +468,8 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 4.0 * d * ell, 0.0, 2);
     CK(fill_f32(ln.X, d * L, 0.f, ln.st));
-    CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.pg, d, ell, ln.X, L,
-                   ln.st));
+    CK(start_block(h->seed, ln.ss->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.pg, d, ell, ln.X,
+                   L, ln.st));
   }
   // panels of the iteration: FP32, or BF16 in the precision form, where the products 1 .. 2q+1
   // read and write BF16 panels (FP32 accumulation) and the last one, P^T = A'^T Y T_y, reads
@@ -493,8 +514,8 @@ int verify_spectral(sfd_t* h, Lane& ln, int attempt, int t) {
   const int m = ln.m;
   ProfScope ps(h, ln.st, SFD_PROF_VS, t * (16.0 * ln.nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
                t * (4.0 * ln.nnz + 4.0 * d * ell), (ln.scs.bands > 1 ? 9 : 8) * t + 3);
-  CK(start_block(h->seed, h->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w, 1,
-                 ln.st));
+  CK(start_block(h->seed, ln.ss->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w,
+                 1, ln.st));
   CK(vs_init(ln.vs_w, d, ln.vs_npart, ln.sc, ln.st));
   for (int s = 0; s < t; ++s) {
     CK(spmv(ln.rowptr, ln.colidx, ln.val, ln.sr, ln.vs_w, &ln.sc->inv_norm, ln.vs_z, ln.partial, ln.st));
@@ -527,7 +548,7 @@ int issue_shrink(sfd_t* h, Lane& ln) {
 int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int lossless, float* out) {
   const int L = h->L, ell = h->ell;
   const int64_t d = h->d;
-  CK(hipStreamWaitEvent(ln.st, h->ev_dsh, 0));
+  CK(hipStreamWaitEvent(ln.st, ln.ss->ev_dsh, 0));
   {
     ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
     CK(gram2(Bin, L, Pt, L, d, L, ln.gram_part, ln.W2, ln.st));
@@ -548,7 +569,7 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
     ProfScope ps(h, ln.st, SFD_PROF_XFORM, 12.0 * d * ell, 4.0 * d * ell * ell, 1);
     CK(panel_xform2(Bin, L, Pt, L, L, ln.T2, out, L, d, ln.st));
   }
-  CK(hipEventRecord(h->ev_dsh, ln.st));
+  CK(hipEventRecord(ln.ss->ev_dsh, ln.st));
   return SFD_OK;
 }
 
@@ -568,11 +589,12 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
     for (int a = 0;; ++a) {
       if ((rc = read_scalars(h, ln))) return rc;
       const DevScalars s = *ln.sc_host;
-      h->stats.attempts += 1;
-      h->stats.last_q = ln.q;
-      h->stats.last_fro2_buffer = s.fro2A;
-      h->stats.last_lambda_ell2 = s.lam_ell2;
-      h->stats.last_delta = 2.0 * s.half_delta;
+      sfd_stats_t& stats = ln.ss->stats;
+      stats.attempts += 1;
+      stats.last_q = ln.q;
+      stats.last_fro2_buffer = s.fro2A;
+      stats.last_lambda_ell2 = s.lam_ell2;
+      stats.last_delta = 2.0 * s.half_delta;
       if (s.S <= 64.0 * kUnitRoundoff32 * ell * s.fro2A || !h->verify) {
         accepted = true;
         break;
@@ -582,13 +604,13 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
       if ((rc = verify_spectral(h, ln, a, t))) return rc;
       if ((rc = read_scalars(h, ln))) return rc;
       const double ln_norm = ln.sc_host->ln_norm;
-      h->stats.last_t = t;
-      h->stats.last_ln_norm = ln_norm;
+      ln.ss->stats.last_t = t;
+      ln.ss->stats.last_ln_norm = ln_norm;
       if (ln_norm <= 0.0) {
         accepted = true;
         break;
       }
-      h->stats.vs_rejects += 1;
+      ln.ss->stats.vs_rejects += 1;
       if (a + 1 >= h->max_attempts) break;
       if ((rc = sparse_shrink(h, ln, a + 1))) return rc;
     }
@@ -601,8 +623,9 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
   return SFD_OK;
 }
 
-// A buffer of the stream: a CSR view plus where its rows come from.
+// A buffer of a stream: a CSR view plus where its rows come from.
 struct BufferView {
+  StreamState* ss;
   const int* rowptr;      // int32 row pointers (if already rebased), else nullptr
   const int64_t* indptr;  // caller's int64 row pointers to rebase from (device), or nullptr
   int64_t r0;             // first row in indptr
@@ -612,6 +635,7 @@ struct BufferView {
 };
 
 int bind(sfd_t* h, Lane& ln, const BufferView& v, int64_t buffer, int pg, int px) {
+  ln.ss = v.ss;
   ln.m = v.m;
   ln.nnz = v.nnz;
   ln.colidx = v.colidx;
@@ -629,51 +653,64 @@ int bind(sfd_t* h, Lane& ln, const BufferView& v, int64_t buffer, int pg, int px
   return SFD_OK;
 }
 
-// Run the buffer steps of `views` (consecutive flushes of the stream) through the lanes.
+// Run the buffer steps of `views` through the lanes.  Views of one stream are consecutive
+// flushes of it, in order; the buffer steps finish (VerifySpectral, DenseShrink) in view order.
 int run_flushes(sfd_t* h, const std::vector<BufferView>& views) {
   const int nbuf = (int)views.size();
   int rc;
   const int nl = h->nlanes;
+  // flush index of each view: its stream's count so far plus the earlier views of the stream
+  std::vector<int64_t> index((size_t)nbuf);
+  {
+    std::map<const StreamState*, int64_t> earlier;
+    for (int b = 0; b < nbuf; ++b) index[(size_t)b] = views[b].ss->flushes + earlier[views[b].ss]++;
+  }
   for (int b = 0; b < nbuf && b < nl; ++b) {
     Lane& ln = h->lanes[b % nl];
-    if ((rc = bind(h, ln, views[b], h->flushes + b, kPurposeSI, kPurposeVS))) return rc;
+    if ((rc = bind(h, ln, views[b], index[(size_t)b], kPurposeSI, kPurposeVS))) return rc;
     if ((rc = issue_shrink(h, ln))) return rc;
   }
   for (int b = 0; b < nbuf; ++b) {
     Lane& ln = h->lanes[b % nl];
+    StreamState& ss = *views[b].ss;
     int live = 0;
     int64_t calls = 0;
-    if ((rc = finish_step(h, ln, h->vs_calls, h->live, h->B, h->B, &live, &calls))) return rc;
-    h->live = live;
-    h->vs_calls += calls;
-    h->flushes += 1;
+    if ((rc = finish_step(h, ln, ss.vs_calls, ss.live, ss.B, ss.B, &live, &calls))) return rc;
+    ss.live = live;
+    ss.vs_calls += calls;
+    ss.flushes += 1;
     if (b + nl < nbuf) {
       // same lane: ordered after this buffer's DenseShrink by the stream
-      if ((rc = bind(h, ln, views[b + nl], h->flushes - 1 + nl, kPurposeSI, kPurposeVS))) return rc;
+      if ((rc = bind(h, ln, views[b + nl], index[(size_t)(b + nl)], kPurposeSI, kPurposeVS))) return rc;
       if ((rc = issue_shrink(h, ln))) return rc;
     }
   }
   return SFD_OK;
 }
 
-// Query: B with the pending rows folded into a copy (purposes 2/3, counter from vs_calls + 1,
-// nothing stored).  Returns the panel holding the result.
-int query(sfd_t* h, const float** panel, int* live, int64_t* calls) {
+// Query of stream ss on lane ln: B with the pending rows folded into the lane's copy (purposes
+// 2/3, VerifySpectral counter from vs_calls + 1, nothing stored).  Returns the panel holding the
+// result (asynchronous on the lane's stream when *panel != ss.B).
+int query_issue(sfd_t* h, StreamState& ss, Lane& ln) {
+  BufferView v{&ss, ss.prow, nullptr, 0, ss.pcol, ss.pval, ss.pm, ss.pnnz};
+  int rc;
+  if ((rc = bind(h, ln, v, ss.flushes, kPurposeQuerySI, kPurposeQueryVS))) return rc;
+  return issue_shrink(h, ln);
+}
+
+int query(sfd_t* h, StreamState& ss, Lane& ln, const float** panel, int* live, int64_t* calls) {
   *calls = 0;
   int rc = sync_all(h);
   if (rc) return rc;
-  if (h->pm == 0) {
-    *panel = h->B;
-    *live = h->live;
+  if (ss.pm == 0) {
+    *panel = ss.B;
+    *live = ss.live;
     return SFD_OK;
   }
-  Lane& ln = h->lanes[0];
-  BufferView v{h->prow, nullptr, 0, h->pcol, h->pval, h->pm, h->pnnz};
-  if ((rc = bind(h, ln, v, h->flushes, kPurposeQuerySI, kPurposeQueryVS))) return rc;
-  if ((rc = issue_shrink(h, ln))) return rc;
-  if ((rc = finish_step(h, ln, h->vs_calls, h->live, h->B, h->Bq, live, calls))) return rc;
+  if ((rc = query_issue(h, ss, ln))) return rc;
+  if ((rc = finish_step(h, ln, ss.vs_calls, ss.live, ss.B, ln.Bq, live, calls))) return rc;
   if ((rc = sync_all(h))) return rc;
-  *panel = h->Bq;
+  *panel = ln.Bq;
   return SFD_OK;
 }
 
@@ -683,39 +720,41 @@ int check_handle(sfd_t* h) {
   return SFD_OK;
 }
 
-// Rows [r0, r1) (entries [p0, p1)) of a block appended to the pending buffer.
-int to_pending(sfd_t* h, bool host, const int64_t* indptr, const int32_t* indices, const float* values, int64_t r0,
-               int64_t r1, int64_t p0, int64_t p1) {
+// Rows [r0, r1) (entries [p0, p1)) of a block appended to the stream's pending buffer.
+int to_pending(sfd_t* h, StreamState& ss, bool host, const int64_t* indptr, const int32_t* indices,
+               const float* values, int64_t r0, int64_t r1, int64_t p0, int64_t p1) {
   Lane& l0 = h->lanes[0];
   const int64_t cnt = r1 - r0, nz = p1 - p0;
   if (cnt <= 0) return SFD_OK;
   const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   if (host) {
     std::vector<int> rp((size_t)cnt);
-    for (int64_t i = 0; i < cnt; ++i) rp[(size_t)i] = (int)(indptr[r0 + 1 + i] - p0) + h->pnnz;
-    CK(hipMemcpyAsync(h->prow + h->pm + 1, rp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, l0.st));
+    for (int64_t i = 0; i < cnt; ++i) rp[(size_t)i] = (int)(indptr[r0 + 1 + i] - p0) + ss.pnnz;
+    CK(hipMemcpyAsync(ss.prow + ss.pm + 1, rp.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, l0.st));
     if (nz > 0) {
-      CK(hipMemcpyAsync(h->pcol + h->pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
-      CK(hipMemcpyAsync(h->pval + h->pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(ss.pcol + ss.pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(ss.pval + ss.pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
     }
     int rc = sync_lane(h, l0);  // the staging vector goes out of scope
     if (rc) return rc;
   } else {
-    CK(append_rowptr(indptr, r0, cnt, h->prow, h->pm, h->pnnz, l0.st));
+    CK(append_rowptr(indptr, r0, cnt, ss.prow, ss.pm, ss.pnnz, l0.st));
     if (nz > 0) {
-      CK(hipMemcpyAsync(h->pcol + h->pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
-      CK(hipMemcpyAsync(h->pval + h->pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(ss.pcol + ss.pnnz, indices + p0, sizeof(int32_t) * nz, kind, l0.st));
+      CK(hipMemcpyAsync(ss.pval + ss.pnnz, values + p0, sizeof(float) * nz, kind, l0.st));
     }
   }
-  h->pm += (int)cnt;
-  h->pnnz += (int)nz;
+  ss.pm += (int)cnt;
+  ss.pnnz += (int)nz;
   return SFD_OK;
 }
 
-// Alg 2's rule on host row pointers: rows after which a flush happens.
-void host_cuts(const sfd_t* h, const int64_t* indptr, int64_t nrows, std::vector<int64_t>& cuts) {
+// Alg 2's rule on host row pointers (nrows rows, indptr[0] may be != 0), continuing the
+// stream's pending buffer: the rows after which a flush happens.
+void host_cuts(const sfd_t* h, const StreamState& ss, const int64_t* indptr, int64_t nrows,
+               std::vector<int64_t>& cuts) {
   const int64_t budget = (int64_t)h->ell * h->d;
-  int64_t r = 0, m = h->pm, z = h->pnnz;
+  int64_t r = 0, m = ss.pm, z = ss.pnnz;
   while (r < nrows) {
     const int64_t target = budget - z + indptr[r];
     const int64_t* it = std::lower_bound(indptr + r + 1, indptr + nrows + 1, target);
@@ -730,7 +769,194 @@ void host_cuts(const sfd_t* h, const int64_t* indptr, int64_t nrows, std::vector
   }
 }
 
+// One block of rows of one stream, validated: the cuts (rows after which a flush happens) and
+// the entry offset after each cut.
+struct Segment {
+  StreamState* ss;
+  const int64_t* indptr;  // the block's row pointers (nrows + 1, host or device)
+  const int32_t* indices;
+  const float* values;
+  int64_t nrows, lo, hi;  // entries [lo, hi) of indices / values
+  std::vector<int64_t> cuts, cut_ptr;
+};
+
+// Full buffers of a segment as views (the first one continues the stream's pending rows,
+// which are copied; the others are read in place from the caller's device arrays), and the
+// position where its remainder starts.
+int segment_views(sfd_t* h, Segment& sg, std::vector<BufferView>& views, int64_t* r_rem, int64_t* p_rem) {
+  int rc;
+  int64_t r = 0, p = sg.lo;
+  StreamState& ss = *sg.ss;
+  for (size_t k = 0; k < sg.cuts.size(); ++k) {
+    const int64_t r1 = sg.cuts[k] + 1, p1 = sg.cut_ptr[k];
+    if (k == 0 && ss.pm > 0) {
+      if ((rc = to_pending(h, ss, false, sg.indptr, sg.indices, sg.values, r, r1, p, p1))) return rc;
+      views.push_back({&ss, ss.prow, nullptr, 0, ss.pcol, ss.pval, ss.pm, ss.pnnz});
+    } else {
+      views.push_back({&ss, nullptr, sg.indptr, r, sg.indices + p, sg.values + p, (int)(r1 - r), (int)(p1 - p)});
+    }
+    r = r1;
+    p = p1;
+  }
+  *r_rem = r;
+  *p_rem = p;
+  return SFD_OK;
+}
+
+// Device block: entry range, validation (rows no longer than d, ids in [0, d)) and cuts.
+int device_segment(sfd_t* h, Segment& sg) {
+  Lane& l0 = h->lanes[0];
+  int rc;
+  int64_t* hv = h->i64_host;
+  const int64_t nrows = sg.nrows;
+  CK(hipMemcpyAsync(hv + 0, sg.indptr, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+  CK(hipMemcpyAsync(hv + 1, sg.indptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+  if ((rc = sync_lane(h, l0))) return rc;
+  sg.lo = hv[0];
+  sg.hi = hv[1];
+  if (sg.hi < sg.lo || sg.lo < 0) return SFD_E_ARG;
+  if (sg.hi > sg.lo && (!sg.indices || !sg.values)) return SFD_E_ARG;
+  CK(fill_i32(h->err_dev, 1, 0, l0.st));
+  CK(validate_rows(sg.indptr, nrows, h->d, h->err_dev, l0.st));
+  CK(validate_indices(sg.indices, sg.lo, sg.hi, h->d, h->err_dev, l0.st));
+  int* e32 = reinterpret_cast<int*>(hv + 2);
+  CK(hipMemcpyAsync(e32, h->err_dev, sizeof(int), hipMemcpyDeviceToHost, l0.st));
+  if ((rc = sync_lane(h, l0))) return rc;
+  if (*e32 & 1) return SFD_E_ARG;
+  if (*e32 & 2) return SFD_E_INDEX;
+  const int64_t max_cuts = (nrows + sg.ss->pm) / h->ell + 2;
+  if (max_cuts > h->cut_cap) {
+    int64_t* p = nullptr;
+    if (!dalloc(h, &p, 1 + 2 * max_cuts)) return SFD_E_NOMEM;
+    h->cut_dev = p;
+    h->cut_cap = max_cuts;
+  }
+  CK(find_cuts(sg.indptr, nrows, sg.ss->pm, sg.ss->pnnz, (int64_t)h->ell * h->d, h->d, max_cuts, h->cut_dev + 1,
+               h->cut_dev + 1 + h->cut_cap, h->cut_dev, l0.st));
+  CK(hipMemcpyAsync(hv + 3, h->cut_dev, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
+  if ((rc = sync_lane(h, l0))) return rc;
+  const int64_t ncuts = hv[3];
+  sg.cuts.resize((size_t)ncuts);
+  sg.cut_ptr.resize((size_t)ncuts);
+  if (ncuts > 0) {
+    CK(hipMemcpy(sg.cuts.data(), h->cut_dev + 1, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(sg.cut_ptr.data(), h->cut_dev + 1 + h->cut_cap, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
+  }
+  return SFD_OK;
+}
+
+// Host block: validation and cuts on the host.
+int host_segment(sfd_t* h, Segment& sg) {
+  const int64_t* indptr = sg.indptr;
+  sg.lo = indptr[0];
+  sg.hi = indptr[sg.nrows];
+  if (sg.hi < sg.lo || sg.lo < 0) return SFD_E_ARG;
+  if (sg.hi > sg.lo && (!sg.indices || !sg.values)) return SFD_E_ARG;
+  for (int64_t r = 0; r < sg.nrows; ++r) {
+    const int64_t len = indptr[r + 1] - indptr[r];
+    if (len < 0 || len > h->d) return SFD_E_ARG;
+  }
+  for (int64_t k = sg.lo; k < sg.hi; ++k)
+    if (sg.indices[k] < 0 || (int64_t)sg.indices[k] >= h->d) return SFD_E_INDEX;
+  host_cuts(h, *sg.ss, indptr, sg.nrows, sg.cuts);
+  for (int64_t c : sg.cuts) sg.cut_ptr.push_back(indptr[c + 1]);
+  return SFD_OK;
+}
+
+// Append validated device segments (at most one per stream): run all their full buffers through
+// the lanes, then move each remainder into its stream's pending buffer.
+int append_device_segments(sfd_t* h, std::vector<Segment>& segs) {
+  int rc;
+  std::vector<BufferView> views;
+  std::vector<int64_t> rrem(segs.size()), prem(segs.size());
+  std::vector<char> flushed(segs.size(), 0);
+  for (size_t i = 0; i < segs.size(); ++i) {
+    if ((rc = segment_views(h, segs[i], views, &rrem[i], &prem[i]))) return rc;
+    flushed[i] = !segs[i].cuts.empty();
+  }
+  if (!views.empty()) {
+    if ((rc = run_flushes(h, views))) return rc;
+    if ((rc = sync_all(h))) return rc;
+  }
+  for (size_t i = 0; i < segs.size(); ++i) {
+    Segment& sg = segs[i];
+    if (flushed[i]) sg.ss->pm = sg.ss->pnnz = 0;
+    if ((rc = to_pending(h, *sg.ss, false, sg.indptr, sg.indices, sg.values, rrem[i], sg.nrows, prem[i], sg.hi)))
+      return rc;
+    sg.ss->stats.rows_seen += sg.nrows;
+    sg.ss->stats.nnz_seen += sg.hi - sg.lo;
+  }
+  return sync_all(h);
+}
+
+// Append a validated host segment: each full buffer is staged through the pending buffer and run.
+int append_host_segment(sfd_t* h, Segment& sg) {
+  int rc;
+  StreamState& ss = *sg.ss;
+  int64_t r = 0, p = sg.lo;
+  for (size_t k = 0; k < sg.cuts.size(); ++k) {
+    const int64_t r1 = sg.cuts[k] + 1, p1 = sg.cut_ptr[k];
+    if ((rc = to_pending(h, ss, true, sg.indptr, sg.indices, sg.values, r, r1, p, p1))) return rc;
+    std::vector<BufferView> views{{&ss, ss.prow, nullptr, 0, ss.pcol, ss.pval, ss.pm, ss.pnnz}};
+    if ((rc = run_flushes(h, views))) return rc;
+    if ((rc = sync_all(h))) return rc;
+    ss.pm = ss.pnnz = 0;
+    r = r1;
+    p = p1;
+  }
+  if ((rc = to_pending(h, ss, true, sg.indptr, sg.indices, sg.values, r, sg.nrows, p, sg.hi))) return rc;
+  if ((rc = sync_all(h))) return rc;
+  ss.stats.rows_seen += sg.nrows;
+  ss.stats.nnz_seen += sg.hi - sg.lo;
+  return SFD_OK;
+}
+
+int create_handle(int64_t d, int32_t ell, double eps, uint64_t seed, int nstreams, int lanes, sfd_t** out) {
+  if (!out) return SFD_E_ARG;
+  *out = nullptr;
+  if (ell < 1 || d < ell || ell > kMaxEll) return SFD_E_ARG;
+  if (!(eps > 0.0 && eps < 1.0)) return SFD_E_ARG;
+  if ((int64_t)ell * d + d >= ((int64_t)1 << 31)) return SFD_E_ARG;
+  sfd_t* h = new (std::nothrow) sfd_t();
+  if (!h) return SFD_E_NOMEM;
+  h->d = d;
+  h->ell = ell;
+  h->L = ((ell + 31) / 32) * 32;
+  h->eps = eps;
+  h->seed = seed;
+  h->lanes_alloc = lanes;
+  h->nlanes = lanes;
+  h->streams.resize((size_t)nstreams);
+  for (int s = 0; s < nstreams; ++s) h->streams[(size_t)s].stream_id = (uint64_t)s;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return SFD_E_DEVICE;
+  }
+  int rc = alloc_state(h);
+  if (rc == SFD_OK) rc = reset_state(h);
+  if (rc != SFD_OK) {
+    free_all(h);
+    delete h;
+    return rc == SFD_E_NOMEM ? SFD_E_NOMEM : SFD_E_DEVICE;
+  }
+  *out = h;
+  return SFD_OK;
+}
+
+void fill_stats(const StreamState& ss, sfd_stats_t* out) {
+  *out = ss.stats;
+  out->flushes = ss.flushes;
+  out->vs_calls = ss.vs_calls;
+  out->live_rows = ss.live;
+  out->pending_rows = ss.pm;
+  out->pending_nnz = ss.pnnz;
+}
+
 }  // namespace
+
+struct sfd_batch_s {
+  sfd_t* core;
+};
 
 extern "C" {
 
@@ -749,38 +975,14 @@ const char* sfd_strerror(int code) {
 }
 
 int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t** out) {
-  if (!out) return SFD_E_ARG;
-  *out = nullptr;
-  if (ell < 1 || d < ell || ell > kMaxEll) return SFD_E_ARG;
-  if (!(eps > 0.0 && eps < 1.0)) return SFD_E_ARG;
-  if ((int64_t)ell * d + d >= ((int64_t)1 << 31)) return SFD_E_ARG;
-  sfd_t* h = new (std::nothrow) sfd_t();
-  if (!h) return SFD_E_NOMEM;
-  h->d = d;
-  h->ell = ell;
-  h->L = ((ell + 31) / 32) * 32;
-  h->eps = eps;
-  h->seed = seed;
-  if (hipGetDevice(&h->device) != hipSuccess) {
-    delete h;
-    return SFD_E_DEVICE;
-  }
-  int rc = alloc_state(h);
-  if (rc == SFD_OK) rc = reset_state(h);
-  if (rc != SFD_OK) {
-    free_all(h);
-    delete h;
-    return rc == SFD_E_NOMEM ? SFD_E_NOMEM : SFD_E_DEVICE;
-  }
-  *out = h;
-  return SFD_OK;
+  return create_handle(d, ell, eps, seed, 1, kLanesSingle, out);
 }
 
 int sfd_destroy(sfd_t* h) {
   if (!h) return SFD_OK;
   DeviceGuard g(h->device);
-  for (Lane& ln : h->lanes)
-    if (ln.st) (void)hipStreamSynchronize(ln.st);
+  for (int i = 0; i < h->lanes_alloc; ++i)
+    if (h->lanes[i].st) (void)hipStreamSynchronize(h->lanes[i].st);
   free_all(h);
   delete h;
   return SFD_OK;
@@ -817,15 +1019,16 @@ int sfd_set_option(sfd_t* h, int key, double value) {
       if (h->prof) std::memset(&h->profile, 0, sizeof(h->profile));
       return SFD_OK;
     case SFD_OPT_STREAM_ID:
+      if (h->streams.size() != 1) return SFD_E_ARG;  // a batch keys stream s as STREAM_ID = s
       if (!(value >= 0) || value > 9.0e15 || value != std::floor(value)) return SFD_E_ARG;
-      h->stream_id = (uint64_t)value;
+      h->streams[0].stream_id = (uint64_t)value;
       return SFD_OK;
     case SFD_OPT_PRECISION:
       if (value != SFD_PRECISION_FP32 && value != SFD_PRECISION_BF16) return SFD_E_ARG;
       h->precision = (int)value;
       return SFD_OK;
     case SFD_OPT_LANES:
-      if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;
+      if (!(value >= 1 && value <= h->lanes_alloc) || value != std::floor(value)) return SFD_E_ARG;
       h->nlanes = (int)value;
       return SFD_OK;
     case SFD_OPT_CSC_BANDS:
@@ -848,12 +1051,7 @@ int sfd_set_stream(sfd_t* h, void* hip_stream) {
 
 int sfd_get_stats(const sfd_t* h, sfd_stats_t* out) {
   if (!h || !out) return SFD_E_ARG;
-  *out = h->stats;
-  out->flushes = h->flushes;
-  out->vs_calls = h->vs_calls;
-  out->live_rows = h->live;
-  out->pending_rows = h->pm;
-  out->pending_nnz = h->pnnz;
+  fill_stats(h->streams[0], out);
   return SFD_OK;
 }
 
@@ -872,91 +1070,19 @@ int sfd_append_csr(sfd_t* h, int64_t nrows, const int64_t* indptr, const int32_t
   if (!indptr) return SFD_E_ARG;
   DeviceGuard g(h->device);
   if ((rc = order_after_caller(h))) return rc;
-  Lane& l0 = h->lanes[0];
-  const bool host = mem == SFD_MEM_HOST;
-  int64_t lo, hi;
-  std::vector<int64_t> cuts, cut_ptr;
-  if (host) {
-    lo = indptr[0];
-    hi = indptr[nrows];
-    if (hi < lo || lo < 0) return SFD_E_ARG;
-    if (hi > lo && (!indices || !values)) return SFD_E_ARG;
-    for (int64_t r = 0; r < nrows; ++r) {
-      const int64_t len = indptr[r + 1] - indptr[r];
-      if (len < 0 || len > h->d) return SFD_E_ARG;
-    }
-    for (int64_t k = lo; k < hi; ++k)
-      if (indices[k] < 0 || (int64_t)indices[k] >= h->d) return SFD_E_INDEX;
-    host_cuts(h, indptr, nrows, cuts);
-    for (int64_t c : cuts) cut_ptr.push_back(indptr[c + 1]);
-  } else {
-    int64_t* hv = h->i64_host;
-    CK(hipMemcpyAsync(hv + 0, indptr, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
-    CK(hipMemcpyAsync(hv + 1, indptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
-    if ((rc = sync_lane(h, l0))) return rc;
-    lo = hv[0];
-    hi = hv[1];
-    if (hi < lo || lo < 0) return SFD_E_ARG;
-    if (hi > lo && (!indices || !values)) return SFD_E_ARG;
-    CK(fill_i32(h->err_dev, 1, 0, l0.st));
-    CK(validate_rows(indptr, nrows, h->d, h->err_dev, l0.st));
-    CK(validate_indices(indices, lo, hi, h->d, h->err_dev, l0.st));
-    int* e32 = reinterpret_cast<int*>(hv + 2);
-    CK(hipMemcpyAsync(e32, h->err_dev, sizeof(int), hipMemcpyDeviceToHost, l0.st));
-    if ((rc = sync_lane(h, l0))) return rc;
-    if (*e32 & 1) return SFD_E_ARG;
-    if (*e32 & 2) return SFD_E_INDEX;
-    const int64_t max_cuts = (nrows + h->pm) / h->ell + 2;
-    if (max_cuts > h->cut_cap) {
-      int64_t* p = nullptr;
-      if (!dalloc(h, &p, 1 + 2 * max_cuts)) return SFD_E_NOMEM;
-      h->cut_dev = p;
-      h->cut_cap = max_cuts;
-    }
-    CK(find_cuts(indptr, nrows, h->pm, h->pnnz, (int64_t)h->ell * h->d, h->d, max_cuts, h->cut_dev + 1,
-                 h->cut_dev + 1 + h->cut_cap, h->cut_dev, l0.st));
-    CK(hipMemcpyAsync(hv + 3, h->cut_dev, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
-    if ((rc = sync_lane(h, l0))) return rc;
-    const int64_t ncuts = hv[3];
-    cuts.resize((size_t)ncuts);
-    cut_ptr.resize((size_t)ncuts);
-    if (ncuts > 0) {
-      CK(hipMemcpy(cuts.data(), h->cut_dev + 1, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
-      CK(hipMemcpy(cut_ptr.data(), h->cut_dev + 1 + h->cut_cap, sizeof(int64_t) * ncuts, hipMemcpyDeviceToHost));
-    }
+  std::vector<Segment> segs(1);
+  Segment& sg = segs[0];
+  sg.ss = &h->streams[0];
+  sg.indptr = indptr;
+  sg.indices = indices;
+  sg.values = values;
+  sg.nrows = nrows;
+  if (mem == SFD_MEM_HOST) {
+    if ((rc = host_segment(h, sg))) return rc;
+    return append_host_segment(h, sg);
   }
-  // the full buffers of this block: the first one continues the pending rows (copied), the
-  // others are read in place from the caller's device arrays; host blocks are staged one
-  // buffer at a time through the pending buffer
-  std::vector<BufferView> views;
-  int64_t r = 0, p = lo;
-  for (size_t k = 0; k < cuts.size(); ++k) {
-    const int64_t r1 = cuts[k] + 1, p1 = cut_ptr[k];
-    if (host && !views.empty()) {
-      if ((rc = run_flushes(h, views))) return rc;
-      views.clear();
-      if ((rc = sync_all(h))) return rc;
-      h->pm = h->pnnz = 0;
-    }
-    if (host || (k == 0 && h->pm > 0)) {
-      if ((rc = to_pending(h, host, indptr, indices, values, r, r1, p, p1))) return rc;
-      views.push_back({h->prow, nullptr, 0, h->pcol, h->pval, h->pm, h->pnnz});
-    } else {
-      views.push_back({nullptr, indptr, r, indices + p, values + p, (int)(r1 - r), (int)(p1 - p)});
-    }
-    r = r1;
-    p = p1;
-  }
-  if (!views.empty()) {
-    if ((rc = run_flushes(h, views))) return rc;
-    if ((rc = sync_all(h))) return rc;
-    h->pm = h->pnnz = 0;
-  }
-  if ((rc = to_pending(h, host, indptr, indices, values, r, nrows, p, hi))) return rc;
-  if ((rc = sync_all(h))) return rc;
-  h->stats.rows_seen += nrows;
-  h->stats.nnz_seen += hi - lo;
-  return SFD_OK;
+  if ((rc = device_segment(h, sg))) return rc;
+  return append_device_segments(h, segs);
 }
 
 int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
@@ -968,8 +1094,8 @@ int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
   const float* panel;
   int live;
   int64_t calls;
-  if ((rc = query(h, &panel, &live, &calls))) return rc;
   Lane& l0 = h->lanes[0];
+  if ((rc = query(h, h->streams[0], l0, &panel, &live, &calls))) return rc;
   if (mem == SFD_MEM_DEVICE) {
     CK(transpose_out(panel, h->L, h->d, h->ell, B_out, l0.st));
   } else {
@@ -988,25 +1114,28 @@ int sfd_merge(sfd_t* dst, sfd_t* src) {
   if ((rc = check_handle(src))) return rc;
   if (dst->d != src->d || dst->ell != src->ell) return SFD_E_SHAPE;
   if (dst->device != src->device) return SFD_E_ARG;
+  if (dst->streams.size() != 1 || src->streams.size() != 1) return SFD_E_ARG;
   DeviceGuard g(dst->device);
   sfd_t* h = dst;
   if ((rc = order_after_caller(dst))) return rc;
   if ((rc = order_after_caller(src))) return rc;
+  StreamState& sd = dst->streams[0];
   const float *ps, *pd;
   int live_s, live_d;
   int64_t calls_s, calls_d;
-  if ((rc = query(src, &ps, &live_s, &calls_s))) return rc;
-  if ((rc = query(dst, &pd, &live_d, &calls_d))) return rc;
+  if ((rc = query(src, src->streams[0], src->lanes[0], &ps, &live_s, &calls_s))) return rc;
+  if ((rc = query(dst, sd, dst->lanes[0], &pd, &live_d, &calls_d))) return rc;
   // stack [query(dst); query(src)], DenseShrink with M = I
   Lane& ln = h->lanes[0];
+  ln.ss = &sd;
   CK(ssh_identity(h->ell, h->L, ln.M64, ln.M32, ln.sc, ln.st));
   const int lossless = (live_d + live_s <= h->ell) ? 1 : 0;
-  if ((rc = dense_shrink(h, ln, pd, ps, lossless, h->B))) return rc;
+  if ((rc = dense_shrink(h, ln, pd, ps, lossless, sd.B))) return rc;
   if ((rc = sync_all(h))) return rc;
-  h->live = lossless ? live_d + live_s : h->ell - 1;
-  h->vs_calls += calls_d;
-  h->flushes += 1;
-  h->pm = h->pnnz = 0;
+  sd.live = lossless ? live_d + live_s : h->ell - 1;
+  sd.vs_calls += calls_d;
+  sd.flushes += 1;
+  sd.pm = sd.pnnz = 0;
   return SFD_OK;
 }
 
@@ -1017,6 +1146,144 @@ int sfd_start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint64_t
     return SFD_E_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return SFD_E_DEVICE;
   return SFD_OK;
+}
+
+// ------------------------------------------------------------------ batched streams
+
+int sfd_batch_create(int32_t nstreams, int64_t d, int32_t ell, double eps, uint64_t seed, sfd_batch_t** out) {
+  if (!out) return SFD_E_ARG;
+  *out = nullptr;
+  if (nstreams < 1) return SFD_E_ARG;
+  sfd_batch_t* b = new (std::nothrow) sfd_batch_t();
+  if (!b) return SFD_E_NOMEM;
+  int rc = create_handle(d, ell, eps, seed, nstreams, kLanes, &b->core);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SFD_OK;
+}
+
+int sfd_batch_destroy(sfd_batch_t* b) {
+  if (!b) return SFD_OK;
+  int rc = sfd_destroy(b->core);
+  delete b;
+  return rc;
+}
+
+int sfd_batch_reset(sfd_batch_t* b) { return b ? sfd_reset(b->core) : SFD_E_ARG; }
+
+int sfd_batch_set_option(sfd_batch_t* b, int key, double value) {
+  if (!b || key == SFD_OPT_STREAM_ID) return SFD_E_ARG;
+  return sfd_set_option(b->core, key, value);
+}
+
+int sfd_batch_set_stream(sfd_batch_t* b, void* hip_stream) { return b ? sfd_set_stream(b->core, hip_stream) : SFD_E_ARG; }
+
+int sfd_batch_get_stats(const sfd_batch_t* b, int32_t stream, sfd_stats_t* out) {
+  if (!b || !out || stream < 0 || stream >= (int32_t)b->core->streams.size()) return SFD_E_ARG;
+  fill_stats(b->core->streams[(size_t)stream], out);
+  return SFD_OK;
+}
+
+int sfd_batch_append_csr(sfd_batch_t* b, int32_t nseg, const int32_t* stream_of_seg, const int64_t* seg_row_start,
+                         const int64_t* indptr, const int32_t* indices, const float* values, int mem) {
+  if (!b) return SFD_E_ARG;
+  sfd_t* h = b->core;
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nseg < 0 || (nseg > 0 && (!stream_of_seg || !seg_row_start || !indptr))) return SFD_E_ARG;
+  if (mem != SFD_MEM_HOST && mem != SFD_MEM_DEVICE) return SFD_E_ARG;
+  if (nseg == 0) return SFD_OK;
+  // segment table: streams in range and each stream at most once, row ranges non-decreasing
+  const int32_t ns = (int32_t)h->streams.size();
+  std::vector<char> used((size_t)ns, 0);
+  for (int32_t i = 0; i < nseg; ++i) {
+    const int32_t s = stream_of_seg[i];
+    if (s < 0 || s >= ns || used[(size_t)s]) return SFD_E_ARG;
+    used[(size_t)s] = 1;
+    if (seg_row_start[i] < 0 || seg_row_start[i + 1] < seg_row_start[i]) return SFD_E_ARG;
+  }
+  DeviceGuard g(h->device);
+  if ((rc = order_after_caller(h))) return rc;
+  std::vector<Segment> segs((size_t)nseg);
+  for (int32_t i = 0; i < nseg; ++i) {
+    Segment& sg = segs[(size_t)i];
+    sg.ss = &h->streams[(size_t)stream_of_seg[i]];
+    sg.indptr = indptr + seg_row_start[i];
+    sg.indices = indices;
+    sg.values = values;
+    sg.nrows = seg_row_start[i + 1] - seg_row_start[i];
+  }
+  if (mem == SFD_MEM_HOST) {
+    // validate every segment before any state changes, then stage them one at a time
+    for (Segment& sg : segs)
+      if ((rc = host_segment(h, sg))) return rc;
+    for (Segment& sg : segs)
+      if (sg.nrows > 0 && (rc = append_host_segment(h, sg))) return rc;
+    return SFD_OK;
+  }
+  for (Segment& sg : segs) {
+    if (sg.nrows == 0) {
+      sg.lo = sg.hi = 0;
+      continue;
+    }
+    if ((rc = device_segment(h, sg))) return rc;
+  }
+  std::vector<Segment> live_segs;
+  for (Segment& sg : segs)
+    if (sg.nrows > 0) live_segs.push_back(std::move(sg));
+  return append_device_segments(h, live_segs);
+}
+
+int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
+  if (!b) return SFD_E_ARG;
+  sfd_t* h = b->core;
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!B_out || (mem != SFD_MEM_HOST && mem != SFD_MEM_DEVICE)) return SFD_E_ARG;
+  DeviceGuard g(h->device);
+  if ((rc = order_after_caller(h))) return rc;
+  if ((rc = sync_all(h))) return rc;
+  const int64_t per = (int64_t)h->ell * h->d;
+  const int nl = h->nlanes;
+  // queries of the streams with pending rows go through the lanes (issued up to nl ahead,
+  // finished in stream order); the others are B itself
+  std::vector<int32_t> q;
+  for (int32_t s = 0; s < (int32_t)h->streams.size(); ++s) {
+    StreamState& ss = h->streams[(size_t)s];
+    Lane& l0 = h->lanes[0];
+    if (ss.pm == 0) {
+      float* dst = mem == SFD_MEM_DEVICE ? B_out + s * per : l0.X;
+      CK(transpose_out(ss.B, h->L, h->d, h->ell, dst, l0.st));
+      if (mem == SFD_MEM_HOST) {
+        CK(hipMemcpyAsync(B_out + s * per, l0.X, sizeof(float) * per, hipMemcpyDeviceToHost, l0.st));
+        if ((rc = sync_lane(h, l0))) return rc;
+      }
+    } else {
+      q.push_back(s);
+    }
+  }
+  const int nq = (int)q.size();
+  for (int k = 0; k < nq && k < nl; ++k)
+    if ((rc = query_issue(h, h->streams[(size_t)q[(size_t)k]], h->lanes[k % nl]))) return rc;
+  for (int k = 0; k < nq; ++k) {
+    Lane& ln = h->lanes[k % nl];
+    StreamState& ss = h->streams[(size_t)q[(size_t)k]];
+    int live = 0;
+    int64_t calls = 0;
+    if ((rc = finish_step(h, ln, ss.vs_calls, ss.live, ss.B, ln.Bq, &live, &calls))) return rc;
+    float* dst = mem == SFD_MEM_DEVICE ? B_out + q[(size_t)k] * per : ln.X;
+    CK(transpose_out(ln.Bq, h->L, h->d, h->ell, dst, ln.st));
+    if (mem == SFD_MEM_HOST) {
+      CK(hipMemcpyAsync(B_out + q[(size_t)k] * per, ln.X, sizeof(float) * per, hipMemcpyDeviceToHost, ln.st));
+      if ((rc = sync_lane(h, ln))) return rc;
+    }
+    if (k + nl < nq)
+      if ((rc = query_issue(h, h->streams[(size_t)q[(size_t)(k + nl)]], ln))) return rc;
+  }
+  return sync_all(h);
 }
 
 }  // extern "C"

@@ -50,6 +50,14 @@ EXPORTS = [
     "sfd_get_profile",
     "sfd_start_block",
     "sfd_strerror",
+    "sfd_batch_create",
+    "sfd_batch_destroy",
+    "sfd_batch_reset",
+    "sfd_batch_set_option",
+    "sfd_batch_set_stream",
+    "sfd_batch_get_stats",
+    "sfd_batch_append_csr",
+    "sfd_batch_sketch",
 ]
 
 
@@ -122,6 +130,14 @@ def load(path: str = LIB_PATH):
         "sfd_get_profile": (i, [vp, ctypes.POINTER(Profile)]),
         "sfd_start_block": (i, [u64, u64, u64, u64, u64, i64, i32, vp]),
         "sfd_strerror": (ctypes.c_char_p, [i]),
+        "sfd_batch_create": (i, [i32, i64, i32, dbl, u64, ctypes.POINTER(vp)]),
+        "sfd_batch_destroy": (i, [vp]),
+        "sfd_batch_reset": (i, [vp]),
+        "sfd_batch_set_option": (i, [vp, i, dbl]),
+        "sfd_batch_set_stream": (i, [vp, vp]),
+        "sfd_batch_get_stats": (i, [vp, i32, ctypes.POINTER(Stats)]),
+        "sfd_batch_append_csr": (i, [vp, i32, vp, vp, vp, vp, vp, i]),
+        "sfd_batch_sketch": (i, [vp, vp, i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -239,6 +255,80 @@ class Sketch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().sfd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent streams (sfd_batch_create ... sfd_batch_destroy); stream s behaves as a
+    Sketch with stream_id = s."""
+
+    def __init__(self, nstreams: int, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, precision=None,
+                 lanes=None, use_torch_stream: bool = True):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.sfd_batch_create(int(nstreams), int(d), int(ell), float(eps), int(seed), ctypes.byref(h)),
+               "sfd_batch_create")
+        self._h = h
+        self.nstreams, self.d, self.ell = int(nstreams), int(d), int(ell)
+        if precision is not None:
+            self.set_option(OPT_PRECISION, {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision))
+        if lanes is not None:
+            self.set_option(OPT_LANES, lanes)
+        if use_torch_stream:
+            s = _torch_stream_handle()
+            if s is not None:
+                _check(lib.sfd_batch_set_stream(self._h, ctypes.c_void_p(s)), "sfd_batch_set_stream")
+
+    def set_option(self, key: int, value: float):
+        _check(load().sfd_batch_set_option(self._h, int(key), float(value)), "sfd_batch_set_option")
+
+    def append_csr(self, stream_of_seg, seg_row_start, indptr, indices, values):
+        """Append a CSR block whose row segments go to the given streams (host segment table)."""
+        sos = np.ascontiguousarray(stream_of_seg, dtype=np.int32)
+        srs = np.ascontiguousarray(seg_row_start, dtype=np.int64)
+        if srs.size != sos.size + 1:
+            raise ValueError("seg_row_start needs one more entry than stream_of_seg")
+        p_ptr, p_kind, k1 = _ptr_kind(indptr, np.int64)
+        i_ptr, i_kind, k2 = _ptr_kind(indices, np.int32)
+        v_ptr, v_kind, k3 = _ptr_kind(values, np.float32)
+        if not (p_kind == i_kind == v_kind):
+            raise ValueError("indptr, indices and values must live in the same kind of memory")
+        _check(load().sfd_batch_append_csr(self._h, int(sos.size), sos.ctypes.data, srs.ctypes.data, p_ptr, i_ptr,
+                                           v_ptr, p_kind), "sfd_batch_append_csr")
+        del k1, k2, k3
+
+    def sketch(self, out=None, device: bool = True):
+        """All sketches (nstreams x ell x d, FP32): a torch CUDA tensor or a numpy array."""
+        shape = (self.nstreams, self.ell, self.d)
+        if device:
+            import torch
+
+            if out is None:
+                out = torch.empty(shape, dtype=torch.float32, device="cuda")
+            _check(load().sfd_batch_sketch(self._h, out.data_ptr(), MEM_DEVICE), "sfd_batch_sketch")
+        else:
+            if out is None:
+                out = np.empty(shape, dtype=np.float32)
+            _check(load().sfd_batch_sketch(self._h, out.ctypes.data, MEM_HOST), "sfd_batch_sketch")
+        return out
+
+    def reset(self):
+        _check(load().sfd_batch_reset(self._h), "sfd_batch_reset")
+
+    def stats(self, stream: int) -> dict:
+        s = Stats()
+        _check(load().sfd_batch_get_stats(self._h, int(stream), ctypes.byref(s)), "sfd_batch_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().sfd_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

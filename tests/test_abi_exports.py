@@ -46,3 +46,17 @@ def test_strerror_and_argument_errors_without_a_gpu():
     assert lib.sfd_create(1 << 30, 5, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
     assert lib.sfd_destroy(None) == sfd.SFD_OK
     assert lib.sfd_merge(None, None) == sfd.SFD_E_ARG
+
+
+def test_batch_argument_errors_without_a_gpu():
+    from paper_1602_00412_amd import sfd
+
+    lib = sfd.load()
+    h = ctypes.c_void_p()
+    assert lib.sfd_batch_create(0, 100, 5, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_batch_create(4, 10, 11, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_batch_create(4, 100, 5, 0.0, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
+    assert lib.sfd_batch_destroy(None) == sfd.SFD_OK
+    assert lib.sfd_batch_sketch(None, None, 0) == sfd.SFD_E_ARG
+    assert lib.sfd_batch_append_csr(None, 0, None, None, None, None, None, 0) == sfd.SFD_E_ARG
+    assert lib.sfd_batch_set_option(None, sfd.OPT_DELTA, 0.1) == sfd.SFD_E_ARG
