@@ -97,7 +97,9 @@ def main() -> int:
                     help="warm-up and the per-kernel-class pass only (no timed steps; for rocprofv3 runs)")
     ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
     ap.add_argument("--csc-bands", type=int, default=0, help="row bands of the transposed products (0: default)")
-    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 precision form's timing")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
+    ap.add_argument("--batch-streams", type=int, default=64,
+                    help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -233,6 +235,68 @@ def main() -> int:
                                                                     out.cpu().numpy().astype(np.float64))}
         log(f"bf16 form: {forms['bf16']['ms_per_step']:.1f} ms/step, {forms['bf16']['value']:.3e} nnz/s "
             f"({forms['bf16']['speedup_vs_fp32']:.2f}x FP32)")
+
+    # The batched form: the first `batch_streams` streams of the 4,096-stream recipe (d = 2e4,
+    # ell = 32, log-uniform lengths 1e3..1e5 rows), resident in HBM, appended in one call and
+    # queried; compared with the same streams fed one at a time through a single-stream handle.
+    if not args.no_forms and not args.profile_only and args.precision == "fp32" and args.batch_streams > 0:
+        from workloads import config4_batch_stream
+
+        t = time.perf_counter()
+        bst = [config4_batch_stream(s) for s in range(args.batch_streams)]
+        bd, bell = bst[0].d, 32
+        b_ptr = np.zeros(1 + sum(x.n for x in bst), dtype=np.int64)
+        starts = np.zeros(len(bst) + 1, dtype=np.int64)
+        pos, base = 1, 0
+        for i, x in enumerate(bst):
+            b_ptr[pos:pos + x.n] = x.indptr[1:] - x.indptr[0] + base
+            pos += x.n
+            base += x.nnz
+            starts[i + 1] = starts[i] + x.n
+        b_nnz = int(base)
+        g_ptr = torch.from_numpy(b_ptr).cuda()
+        g_idx = torch.from_numpy(np.concatenate([x.indices for x in bst])).cuda()
+        g_val = torch.from_numpy(np.concatenate([x.values for x in bst])).cuda()
+        log(f"batched form: {len(bst)} streams, {starts[-1]} rows, {b_nnz} nnz generated in "
+            f"{time.perf_counter() - t:.1f} s")
+        bat = sfd.Batch(len(bst), bd, bell)
+        b_out = torch.empty((len(bst), bell, bd), dtype=torch.float32, device="cuda")
+        sos = np.arange(len(bst), dtype=np.int32)
+
+        def step_batch():
+            bat.reset()
+            bat.append_csr(sos, starts, g_ptr, g_idx, g_val)
+            bat.sketch(out=b_out)
+
+        single = sfd.Sketch(bd, bell, 0.25, 0)
+        s_out = torch.empty((bell, bd), dtype=torch.float32, device="cuda")
+
+        def step_single():
+            for i in range(len(bst)):
+                single.reset()
+                single.set_option(sfd.OPT_STREAM_ID, i)
+                lo, hi = int(starts[i]), int(starts[i + 1])
+                single.append_csr(g_ptr[lo:hi + 1], g_idx, g_val)
+                single.sketch(out=s_out)
+
+        res = {}
+        for name, fn in (("batched", step_batch), ("single", step_single)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t) / args.steps
+        forms["batched"] = {"value": b_nnz / res["batched"], "unit": "nnz/s", "ms_per_step": 1e3 * res["batched"],
+                            "streams": len(bst), "rows": int(starts[-1]), "nnz": b_nnz, "d": bd, "ell": bell,
+                            "single_stream_value": b_nnz / res["single"],
+                            "speedup_vs_single_streams": res["single"] / res["batched"],
+                            "ratio_vs_fp32_value": (b_nnz / res["batched"]) / value}
+        log(f"batched form: {1e3 * res['batched']:.1f} ms/step, {b_nnz / res['batched']:.3e} nnz/s "
+            f"({res['single'] / res['batched']:.2f}x one stream at a time)")
+        del bat, single
 
     cpu = None
     parity = None
