@@ -31,155 +31,103 @@ __device__ inline double rcp_nr(double x) {
 }
 constexpr int kEigMax = 2 * kMaxEll;
 
-// Blocked right-looking Cholesky W = R^T R of the ell x ell leading block, 4 columns per step,
-// with the matrix in registers: thread t owns column j = t % 64 and rows i = t / 64 + 4 s, so
-// the rows of block K are slot K of the four thread groups.  A step broadcasts the block's 4
-// rows through LDS, every thread factors the 4 x 4 diagonal block itself, the 64 threads of
-// group 0 solve the block row of R, and everyone applies the rank-4 update to the rows below.
-// A pivot that has fallen to tau * W_kk (the column's own squared norm) marks column k as
-// dependent on the earlier ones: it is skipped and its row of R is zero.  T = R^{-1} on the kept
-// columns follows by blocked back substitution, bottom-up (R_KK T_K = B_K, then the rows above
-// subtract R_{:,K} T_K), so panel * T has orthonormal kept columns spanning the panel's
-// numerical column space.
+__device__ inline double readlane_d(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)bits, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Right-looking Cholesky W = R^T R of the n x n leading block with the matrix in registers:
+// thread (w, j) (wave w, lane j) holds column j, rows i = 4 s + w.  One pivot per step: the wave
+// owning row k scales it into row k of R and publishes it in LDS; after one barrier every thread
+// updates its rows below k, reading the published row as LDS broadcasts.  A pivot that has
+// fallen to tau * W_kk (the column's own squared norm) marks column k as dependent on the earlier
+// ones: its row of R is zero.  T = R^{-1} on the kept columns follows by right-looking back
+// substitution, last row first: the wave owning row i finishes row i of T and publishes it; the
+// rows above subtract R[l][i] T[i][:], R[l][i] being lane i's entry of row l (a readlane inside
+// the wave).  Steps are unrolled, so register indices are static; the published rows alternate
+// between two LDS buffers, so one barrier per step suffices.  panel * T then has orthonormal kept
+// columns spanning the panel's numerical column space.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ W, int ldw, int n, int L, double tau,
                                                   float* __restrict__ T, DevScalars* sc) {
-  constexpr int S = kCholMax / 4;  // row slots per thread = block steps
-  __shared__ double rows[4][kCholMax];  // the current block's rows (factor) / rows of B (inverse)
-  __shared__ double rp[4][kCholMax];    // solved block row of R (factor) / column block of R (inverse)
-  __shared__ double d0[kCholMax];
-  __shared__ double inv[kCholMax];
-  const int tid = threadIdx.x;
-  const int j = tid & 63;
-  const int r0 = tid >> 6;
+  constexpr int S = kCholMax / 4;  // row slots per thread
+  __shared__ double pub[2][kCholMax];
+  __shared__ int ndrop[4];
+  const int j = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const bool jn = j < n;
-  double a[S], b[S];
+  double a[S], t[S], iv[S];
   {
     // unconditional loads from clamped indices (all in flight together), then masked
     const int jc = jn ? j : 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int i = r0 + 4 * s;
-      const double w = W[(i < n ? i : 0) * ldw + jc];
-      a[s] = (i < n && jn) ? w : 0.0;
-      b[s] = (i == j && i < n) ? 1.0 : 0.0;
+      const int i = 4 * s + w;
+      const double x = W[(i < n ? i : 0) * ldw + jc];
+      a[s] = (i < n && jn) ? x : 0.0;
+      t[s] = 0.0;
+      iv[s] = 0.0;
     }
-    const int tc = tid < n ? tid : 0;
-    const double dd = W[tc * ldw + tc];
-    if (tid < kCholMax) d0[tid] = tid < n ? dd : 0.0;
   }
-  const int nblk = (n + 3) / 4;
-  for (int K = 0; K < nblk; ++K) {
-    const int k0 = 4 * K;
-    double mine = a[0];
+  const double d0 = W[(jn ? j : 0) * ldw + (jn ? j : 0)];  // W_jj
+  int drops = 0;
 #pragma unroll
-    for (int s = 1; s < S; ++s) mine = (s == K) ? a[s] : mine;
-    rows[r0][j] = mine;  // row k0 + r0, column j
-    __syncthreads();
-    // 4 x 4 diagonal block, factored by every thread (upper factor U, inverse pivots iv)
-    double D[4][4], U[4][4], iv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) D[t][u] = (k0 + t < n && k0 + u < n) ? rows[t][k0 + u] : 0.0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double p = D[t][t];
-      const double dk = k0 + t < n ? d0[k0 + t] : 0.0;
+  for (int k = 0; k < kCholMax; ++k) {
+    if (k >= n) break;
+    const int wk = k & 3, sk = k >> 2;
+    if (w == wk) {
+      const double p = readlane_d(a[sk], k);
+      const double dk = readlane_d(d0, k);
       const bool keep = (dk > 0.0) && (p > tau * dk);
       const double is = keep ? rsqrt_nr(p) : 0.0;
-      iv[t] = is;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) U[t][u] = u >= t ? D[t][u] * is : 0.0;
-#pragma unroll
-      for (int u = t + 1; u < 4; ++u)
-#pragma unroll
-        for (int v = u; v < 4; ++v) D[u][v] = fma(-U[t][u], U[t][v], D[u][v]);
-    }
-    if (tid < 4 && k0 + tid < n) inv[k0 + tid] = iv[tid];
-    if (r0 == 0) {
-      // block row of R for column j: U^T r = rows[:, j] (columns right of the block), U itself inside
-      double r[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        double x = rows[t][j];
-#pragma unroll
-        for (int v = 0; v < t; ++v) x = fma(-U[v][t], r[v], x);
-        r[t] = x * iv[t];
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        double val = 0.0;
-        if (jn && j >= k0 + 4) val = r[t];
-        if (j >= k0 && j < k0 + 4) val = U[t][j - k0];
-        rp[t][j] = val;
-      }
+      iv[sk] = is;
+      drops += keep ? 0 : 1;
+      const double r = (j >= k && jn) ? a[sk] * is : 0.0;
+      a[sk] = r;  // row k of R
+      pub[k & 1][j] = r;
     }
     __syncthreads();
-    const double rkj[4] = {rp[0][j], rp[1][j], rp[2][j], rp[3][j]};
+    // branch-free update (masked multipliers), so the broadcast reads are issued together
+    const double rkj = pub[k & 1][j];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int i = r0 + 4 * s;
-      if (s == K) {
-        a[s] = rkj[r0];  // final row k0 + r0 of R
-      } else if (s > K) {
-        const double f = (i <= j) ? 1.0 : 0.0;
-        double x = a[s];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) x = fma(-rp[t][i] * f, rkj[t], x);
-        a[s] = x;
-      }
+      if (s < sk) continue;  // rows 4 s + w <= k
+      const int i = 4 * s + w;
+      const double f = (i > k && i < n) ? pub[k & 1][i] : 0.0;
+      a[s] = fma(-f, rkj, a[s]);
     }
   }
+  // T = R^{-1}: t[s] accumulates row i = 4 s + w of T (column j)
+#pragma unroll
+  for (int i = kCholMax - 1; i >= 0; --i) {
+    if (i >= n) continue;
+    const int wi = i & 3, si = i >> 2;
+    if (w == wi) {
+      const double x = ((i == j) ? 1.0 : 0.0) - t[si];
+      const double ti = jn ? x * iv[si] : 0.0;
+      t[si] = ti;
+      pub[i & 1][j] = ti;
+    }
+    __syncthreads();
+    const double tij = pub[i & 1][j];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s > si) continue;  // rows 4 s + w >= i
+      const int l = 4 * s + w;
+      const double r = readlane_d(a[s], i);
+      t[s] = fma(l < i ? r : 0.0, tij, t[s]);
+    }
+  }
+  // T (L x L, zero-padded)
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = 4 * s + w;
+    if (i < L && j < L) T[i * L + j] = (i < n && jn) ? (float)t[s] : 0.f;
+  }
+  if (j == 0) ndrop[w] = drops;
   __syncthreads();
-  // T = R^{-1}, bottom-up by blocks
-  for (int K = nblk - 1; K >= 0; --K) {
-    const int k0 = 4 * K;
-    double mine = b[0];
-#pragma unroll
-    for (int s = 1; s < S; ++s) mine = (s == K) ? b[s] : mine;
-    rows[r0][j] = mine;  // row k0 + r0 of B
-    if (j >= k0 && j < k0 + 4) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) rp[j - k0][r0 + 4 * s] = a[s];  // R[i][j] for all i
-    }
-    __syncthreads();
-    // T rows of the block for column j: U t = B_block[:, j] (U = R_KK, back substitution)
-    double tk[4];
-#pragma unroll
-    for (int t = 3; t >= 0; --t) {
-      double x = rows[t][j];
-#pragma unroll
-      for (int v = t + 1; v < 4; ++v) x = fma(-rp[v][k0 + t], tk[v], x);
-      tk[t] = (k0 + t < n) ? x * inv[k0 + t] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int i = r0 + 4 * s;
-      if (s == K) {
-        b[s] = tk[r0];
-      } else if (s < K) {
-        double x = b[s];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) x = fma(-rp[t][i], tk[t], x);
-        b[s] = x;
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < L * L; e += 256) T[e] = 0.f;
-  __syncthreads();
-  if (jn) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int i = r0 + 4 * s;
-      if (i < n) T[i * L + j] = (float)b[s];
-    }
-  }
-  if (tid == 0) {
-    int nd = 0;
-    for (int k = 0; k < n; ++k) nd += inv[k] == 0.0;
-    sc->dropped = nd;
-  }
+  if (threadIdx.x == 0) sc->dropped = ndrop[0] + ndrop[1] + ndrop[2] + ndrop[3];
 }
 
 __device__ inline int packed_index(int i, int j, int N) {
