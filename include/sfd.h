@@ -49,6 +49,8 @@ enum { SFD_MEM_HOST = 0, SFD_MEM_DEVICE = 1 };
 
 enum { SFD_PRECISION_FP32 = 0, SFD_PRECISION_BF16 = 1 };
 
+enum { SFD_ALGO_SFD = 0, SFD_ALGO_FD = 1 };
+
 /* Option keys for sfd_set_option. */
 enum {
   SFD_OPT_DELTA = 1,        /* failure probability delta of Alg 2 / Alg 6, in (0,1); default 0.01 */
@@ -64,12 +66,17 @@ enum {
                                Results agree to rounding. */
   SFD_OPT_LANES = 8,        /* lanes (HIP streams) that run successive buffers' SparseShrink
                                concurrently, 1..4; default 4.  Results do not depend on it. */
-  SFD_OPT_PRECISION = 9     /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
+  SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
                                SimultaneousIteration (Alg 1) stored in BF16 with FP32 accumulation;
                                the last product P^T = A'^T Y (Alg 3) reads the stored BF16 Y,
                                takes its transform from that Y's own Gram and writes FP32, so
                                B'^T B' <= A'^T A' (Property 1) still holds for the FP32 values.
                                Only the subspace quality changes (cov-err, Sec. 4). */
+  SFD_OPT_ALGORITHM = 10    /* SFD_ALGO_SFD (default): Alg 2's flush rule (rows(A') = d or
+                               nnz(A') >= ell*d) and BoostedSparseShrink; SFD_ALGO_FD: the
+                               paper's comparator FrequentDirections (Sec. 2.1) in batches of
+                               ell rows -- the buffer flushes at ell rows and is folded exactly
+                               by DenseShrink (Alg 5).  Applies to the flushes that follow. */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */

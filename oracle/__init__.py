@@ -37,7 +37,7 @@ from .shrink import (
     vs_steps,
     NoConvergence,
 )
-from .stream import SFDOracle, FDOracle
+from .stream import SFDOracle, FDOracle, FDBatchOracle
 from . import evaluate
 
 __all__ = [

@@ -67,7 +67,7 @@ class SFDOracle:
     """
 
     def __init__(self, d, ell, eps=0.25, seed=0, stream_id=0, *, delta=0.01, q=None,
-                 max_attempts=16, verify=True, unit_roundoff=2.0 ** -53):
+                 max_attempts=16, verify=True, unit_roundoff=2.0 ** -53, flush_rows=None, flush_nnz=None):
         if not (1 <= ell <= d):
             raise ValueError("need 1 <= ell <= d")
         if not (0.0 < eps < 1.0):
@@ -76,6 +76,9 @@ class SFDOracle:
         self.seed, self.stream_id = int(seed), int(stream_id)
         self.delta, self.q_override = float(delta), q
         self.max_attempts, self.verify, self.unit_roundoff = int(max_attempts), bool(verify), float(unit_roundoff)
+        # Alg 2's flush rule: rows(A') = d or nnz(A') >= ell*d (overridable, see FDBatchOracle)
+        self.flush_rows = int(flush_rows) if flush_rows is not None else self.d
+        self.flush_nnz = flush_nnz if flush_nnz is not None else self.ell * self.d
         self.B = np.zeros((self.ell, self.d))
         self.live = 0          # structural count of rows of B that may be non-zero
         self.flushes = 0       # b: completed flushes (buffer index of the pending buffer)
@@ -105,7 +108,7 @@ class SFDOracle:
     def append_csr(self, indptr, indices, values):
         """Append rows given in CSR form (indptr[0] may be non-zero); Alg 2's row loop."""
         indptr, indices, values = _check_csr(indptr, indices, values, self.d)
-        full = self.ell * self.d
+        full = self.flush_nnz
         n = len(indptr) - 1
         r = 0
         while r < n:
@@ -113,7 +116,7 @@ class SFDOracle:
             lens = np.diff(indptr[r:])
             cum = self.buf_nnz + np.cumsum(lens)
             by_nnz = int(np.searchsorted(cum, full, side="left"))
-            by_rows = self.d - self.buf_rows - 1
+            by_rows = self.flush_rows - self.buf_rows - 1
             cut = min(by_nnz, by_rows)
             last = min(cut, n - r - 1)
             for k in range(r, r + last + 1):
@@ -185,6 +188,17 @@ class SFDOracle:
 
     def copy(self) -> "SFDOracle":
         return copy.deepcopy(self)
+
+
+class FDBatchOracle(SFDOracle):
+    """FrequentDirections (Sec. 2.1) in batches of ell rows: the buffer is flushed every ell rows
+    and, holding at most ell rows, is folded exactly, so the sketch changes only through
+    DenseShrink (Alg 5) of [B; buffer] -- the paper's FD comparator with the stack's new rows
+    arriving ell at a time instead of one at a time (it agrees with FDOracle up to its first
+    shrink, at 2 ell rows)."""
+
+    def __init__(self, d, ell, **kw):
+        super().__init__(d, ell, flush_rows=ell, flush_nnz=float("inf"), **kw)
 
 
 class FDOracle:

@@ -107,6 +107,7 @@ struct sfd_s {
   int lanes_alloc = kLanesSingle;  // lanes with workspaces
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
+  int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
   // streams (one for an sfd_t handle, nstreams for a batch handle)
   std::vector<StreamState> streams;
   int error = 0;
@@ -349,6 +350,13 @@ int reset_state(sfd_t* h) {
 int si_iterations(const sfd_t* h, int m) {
   if (h->q_override > 0) return h->q_override;
   return (int)std::ceil(std::log((double)m / h->eps) / h->eps);
+}
+
+// Alg 2's flush rule: rows(A') = d or nnz(A') >= ell*d; FrequentDirections (Sec. 2.1) in
+// batches of ell rows: rows(A') = ell, each buffer folded exactly by DenseShrink.
+int64_t flush_rows(const sfd_t* h) { return h->algorithm == SFD_ALGO_FD ? (int64_t)h->ell : h->d; }
+int64_t flush_nnz(const sfd_t* h) {
+  return h->algorithm == SFD_ALGO_FD ? ((int64_t)1 << 62) : (int64_t)h->ell * h->d;
 }
 
 int vs_steps(const sfd_t* h, int64_t i) {
@@ -753,13 +761,13 @@ int to_pending(sfd_t* h, StreamState& ss, bool host, const int64_t* indptr, cons
 // stream's pending buffer: the rows after which a flush happens.
 void host_cuts(const sfd_t* h, const StreamState& ss, const int64_t* indptr, int64_t nrows,
                std::vector<int64_t>& cuts) {
-  const int64_t budget = (int64_t)h->ell * h->d;
+  const int64_t budget = flush_nnz(h), row_limit = flush_rows(h);
   int64_t r = 0, m = ss.pm, z = ss.pnnz;
   while (r < nrows) {
     const int64_t target = budget - z + indptr[r];
     const int64_t* it = std::lower_bound(indptr + r + 1, indptr + nrows + 1, target);
     const int64_t by_nnz = (it - indptr) - 1;
-    const int64_t by_rows = r + (h->d - m) - 1;
+    const int64_t by_rows = r + (row_limit - m) - 1;
     const int64_t cut = std::min(by_nnz, by_rows);
     if (cut >= nrows) break;
     cuts.push_back(cut);
@@ -824,14 +832,14 @@ int device_segment(sfd_t* h, Segment& sg) {
   if ((rc = sync_lane(h, l0))) return rc;
   if (*e32 & 1) return SFD_E_ARG;
   if (*e32 & 2) return SFD_E_INDEX;
-  const int64_t max_cuts = (nrows + sg.ss->pm) / h->ell + 2;
+  const int64_t max_cuts = (nrows + sg.ss->pm) / std::min<int64_t>(h->ell, flush_rows(h)) + 2;
   if (max_cuts > h->cut_cap) {
     int64_t* p = nullptr;
     if (!dalloc(h, &p, 1 + 2 * max_cuts)) return SFD_E_NOMEM;
     h->cut_dev = p;
     h->cut_cap = max_cuts;
   }
-  CK(find_cuts(sg.indptr, nrows, sg.ss->pm, sg.ss->pnnz, (int64_t)h->ell * h->d, h->d, max_cuts, h->cut_dev + 1,
+  CK(find_cuts(sg.indptr, nrows, sg.ss->pm, sg.ss->pnnz, flush_nnz(h), flush_rows(h), max_cuts, h->cut_dev + 1,
                h->cut_dev + 1 + h->cut_cap, h->cut_dev, l0.st));
   CK(hipMemcpyAsync(hv + 3, h->cut_dev, sizeof(int64_t), hipMemcpyDeviceToHost, l0.st));
   if ((rc = sync_lane(h, l0))) return rc;
@@ -1030,6 +1038,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_LANES:
       if (!(value >= 1 && value <= h->lanes_alloc) || value != std::floor(value)) return SFD_E_ARG;
       h->nlanes = (int)value;
+      return SFD_OK;
+    case SFD_OPT_ALGORITHM:
+      if (value != SFD_ALGO_SFD && value != SFD_ALGO_FD) return SFD_E_ARG;
+      h->algorithm = (int)value;
       return SFD_OK;
     case SFD_OPT_CSC_BANDS:
       if (!(value >= 0 && value <= kMaxBands) || value != std::floor(value)) return SFD_E_ARG;

@@ -219,13 +219,14 @@ __global__ __launch_bounds__(256) void k_sum_to_scalar(const double* part, int n
   if (threadIdx.x == 0) *out = s[0];
 }
 
+// out row j (already zeroed) += the entries of column j; one thread per column, so repeated
+// (row, column) entries are added in CSC order
 __global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
-                                 int ld, int L) {
+                                 int ld) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; j < d; j += stride) {
     float* o = out + j * ld;
-    for (int c = 0; c < L; ++c) o[c] = 0.f;
     for (int k = cscptr[j]; k < cscptr[j + 1]; ++k) o[cscrow[k]] += cscval[k];
   }
 }
@@ -302,7 +303,10 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
 
 hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
                           int ld, int L, hipStream_t st) {
-  k_dense_from_csc<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, cscval, d, out, ld, L);
+  hipError_t e = fill_f32(out, d * ld, 0.f, st);  // coalesced zeroing of the whole panel
+  if (e != hipSuccess) return e;
+  (void)L;
+  k_dense_from_csc<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, cscval, d, out, ld);
   return hipGetLastError();
 }
 

@@ -35,6 +35,9 @@ OPT_LANES = 8
 OPT_PRECISION = 9
 PRECISION_FP32 = 0
 PRECISION_BF16 = 1
+OPT_ALGORITHM = 10
+ALGO_SFD = 0
+ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
 
 EXPORTS = [
@@ -188,7 +191,7 @@ class Sketch:
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
                  max_attempts=None, verify=None, stream_id=None, csc_bands=None, precision=None,
-                 use_torch_stream: bool = True):
+                 algorithm=None, use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
@@ -198,7 +201,9 @@ class Sketch:
                          (OPT_VERIFY, None if verify is None else float(bool(verify))), (OPT_STREAM_ID, stream_id),
                          (OPT_CSC_BANDS, csc_bands),
                          (OPT_PRECISION, None if precision is None else
-                          {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision))):
+                          {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision)),
+                         (OPT_ALGORITHM, None if algorithm is None else
+                          {"sfd": ALGO_SFD, "fd": ALGO_FD}.get(algorithm, algorithm))):
             if val is not None:
                 self.set_option(key, val)
         if use_torch_stream:

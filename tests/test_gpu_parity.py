@@ -218,3 +218,44 @@ def test_errors_leave_state_unchanged(gpu_lib):
     assert torch.equal(sk.sketch(), before)
     with pytest.raises(gpu_lib.SfdError):
         gpu_lib.Sketch(10, 11)
+
+
+@pytest.mark.parametrize("n,d,ell,seed", [(300, 60, 8, 0), (1000, 200, 20, 1), (700, 150, 50, 2)])
+def test_fd_mode_matches_fd_oracle(gpu_lib, n, d, ell, seed):
+    # FrequentDirections (Sec. 2.1) in batches of ell rows through the same DenseShrink kernels
+    from oracle import FDBatchOracle
+
+    st = small_random_csr(n, d, 6, seed, dist="lognormal")
+    o = FDBatchOracle(d, ell)
+    o.append_csr(st.indptr, st.indices, st.values)
+    sk, B = _gpu_sketch(gpu_lib, st, ell, algorithm="fd")
+    assert sk.stats()["flushes"] == o.flushes == n // ell
+    assert sk.stats()["vs_calls"] == 0
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+    A = st.to_scipy()
+    lmin, lmax = evaluate.cov_extremes(A, B)
+    assert lmin >= -1e-5 * evaluate.fro2(A)
+    assert lmax <= evaluate.fd_bound(A, ell, ell // 2) * (1 + 1e-4)
+
+
+def test_sharded_merge_tree_matches_oracle(gpu_lib):
+    # the multi-GPU design on one GPU: shards sketched independently, then a merge tree
+    # (mergeability, Sec. 2.1); parity against the oracle run with the same sharding and tree
+    st = small_random_csr(2400, 120, 10, 21, dist="lognormal")
+    bounds = [0, 500, 1300, 1750, 2400]
+    gs, os_ = [], []
+    for k in range(4):
+        sub = st.rows(bounds[k], bounds[k + 1])
+        g = gpu_lib.Sketch(st.d, 16, stream_id=k)
+        g.append_csr(*_dev(sub))
+        gs.append(g)
+        o = SFDOracle(st.d, 16, 0.25, 0, stream_id=k, unit_roundoff=U32)
+        o.append_csr(sub.indptr, sub.indices, sub.values)
+        os_.append(o)
+    for a, b in [(0, 1), (2, 3), (0, 2)]:
+        gs[a].merge(gs[b])
+        os_[a].merge(os_[b])
+    B = gs[0].sketch().cpu().numpy().astype(np.float64)
+    assert evaluate.gram_distance(B, os_[0].sketch()) <= TOL
+    lmin, _ = evaluate.cov_extremes(st.to_scipy(), B)
+    assert lmin >= -1e-5 * evaluate.fro2(st.to_scipy())

@@ -14,7 +14,7 @@ import scipy.sparse as sp
 
 import oracle.shrink as osh
 import oracle.stream as ost
-from oracle import FDOracle, SFDOracle, evaluate
+from oracle import FDBatchOracle, FDOracle, SFDOracle, evaluate
 from oracle.rng import PURPOSE_SI, PURPOSE_VS, sphere_vector, start_block
 from oracle.shrink import ALPHA, si_iterations, vs_steps
 from workloads import config1_fp64_reference, small_random_csr
@@ -100,6 +100,40 @@ def test_fd_merge_guarantee():
     _, lmax = evaluate.cov_extremes(A, B)
     for k in range(6):
         assert lmax <= evaluate.fd_bound(A, 6, k) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fd_batch_guarantee(seed):
+    # FD in batches of ell rows keeps Lemma 2.1's bound and B^T B <= A^T A
+    st = small_random_csr(260, 30, 6, 10 + seed, dist="lognormal")
+    A = st.to_scipy()
+    f = FDBatchOracle(st.d, 8)
+    f.append_csr(st.indptr, st.indices, st.values)
+    assert f.flushes == 260 // 8
+    assert all(r["attempts"] == [] for r in f.log)  # every flush is an exact fold
+    B = f.sketch()
+    lmin, lmax = evaluate.cov_extremes(A, B)
+    assert lmin >= -1e-9 * evaluate.fro2(A)
+    for k in range(8):
+        assert lmax <= evaluate.fd_bound(A, 8, k) * (1 + 1e-9)
+
+
+def test_fd_batch_agrees_with_row_at_a_time_fd_up_to_the_first_shrink():
+    ell = 7
+    st = small_random_csr(2 * ell, 40, 6, 3, dist="lognormal")
+    fb = FDBatchOracle(st.d, ell)
+    fb.append_csr(st.indptr, st.indices, st.values)
+    f1 = FDOracle(st.d, ell)
+    f1.append_csr(st.indptr, st.indices, st.values)
+    B1, B2 = fb.sketch(), f1.sketch()
+    np.testing.assert_allclose(B1.T @ B1, B2.T @ B2, atol=1e-9 * np.abs(B2.T @ B2).max())
+    # and B^T B = A^T A while n <= ell
+    sub = st.rows(0, ell)
+    fe = FDBatchOracle(st.d, ell)
+    fe.append_csr(sub.indptr, sub.indices, sub.values)
+    A = sub.to_scipy().toarray()
+    Be = fe.sketch()
+    np.testing.assert_allclose(Be.T @ Be, A.T @ A, atol=1e-9 * np.abs(A.T @ A).max())
 
 
 # ---------------------------------------------------------------------------- SparseFrequentDirections
