@@ -200,7 +200,7 @@ int sfd_batch_create(int32_t nstreams, int64_t d, int32_t ell, double eps, uint6
 int sfd_batch_destroy(sfd_batch_t *h);  /* NULL-safe */
 int sfd_batch_reset(sfd_batch_t *h);    /* every stream back to its initial state */
 /* Options as sfd_set_option, applied to every stream; SFD_OPT_STREAM_ID is rejected (stream s
- * is keyed s).  SFD_OPT_LANES accepts 1..8 (default 8). */
+ * is keyed s).  SFD_OPT_LANES accepts 1..16 (default 16). */
 int sfd_batch_set_option(sfd_batch_t *h, int key, double value);
 int sfd_batch_set_stream(sfd_batch_t *h, void *hip_stream);
 /* Counters of stream s (as sfd_get_stats).  Errors: SFD_E_ARG. */

@@ -36,7 +36,7 @@ constexpr double kAlpha = 6.0 / 41.0;                 // alpha of Alg 4 / Theore
 constexpr double kUnitRoundoff32 = 1.0 / 16777216.0;  // 2^-24: the panels' arithmetic
 constexpr double kCholDropTol = 1e-5;                 // relative residual^2 below which a column is dependent
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
-constexpr int kLanes = 8;         // lanes of a batch handle; a single-stream handle uses 4
+constexpr int kLanes = 16;        // lanes of a batch handle; a single-stream handle uses 4
 constexpr int kLanesSingle = 4;
 
 // State of one stream (Alg 2): the sketch B (stored transposed, d x L), the pending buffer A'
@@ -89,6 +89,38 @@ struct Lane {
   float* Bq = nullptr;            // d x L: a query's copy of B with the pending rows folded in
 };
 
+// Workspace of a lockstep group: up to kmax buffers of different streams stacked into one
+// block-diagonal buffer (rows one after another, buffer k's columns moved to k d ..), so each
+// step of their SimultaneousIteration and VerifySpectral is one launch for all of them.
+struct GroupWork {
+  int kmax = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  int *rowptr = nullptr, *colidx = nullptr;
+  float* val = nullptr;
+  int *cscptr = nullptr, *cscrow = nullptr;
+  float* cscval = nullptr;
+  CscWork csc{};
+  int* scan_tmp = nullptr;
+  Schedule sr{}, scs{};
+  float* partial = nullptr;
+  float *X = nullptr, *Y = nullptr, *Pt = nullptr;
+  float* gram_part = nullptr;
+  double *W = nullptr, *Wp = nullptr;
+  float* T = nullptr;
+  double *evals = nullptr, *evecs = nullptr, *M64 = nullptr;
+  float* M32 = nullptr;
+  DevScalars* sc = nullptr;
+  DevScalars* sc_host = nullptr;  // pinned
+  GroupSeg *segs_x = nullptr, *segs_y = nullptr;
+  int64_t* seg_rows = nullptr;
+  int* tsteps = nullptr;
+  GroupSeg* segs_host = nullptr;  // pinned: 2 kmax segments, kmax + 1 row offsets, kmax steps
+  float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
+  double *vs_npart = nullptr, *fro_part = nullptr;
+  int64_t cap_rows = 0, cap_nnz = 0;
+};
+
 }  // namespace
 
 struct sfd_s {
@@ -110,6 +142,7 @@ struct sfd_s {
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
   // streams (one for an sfd_t handle, nstreams for a batch handle)
   std::vector<StreamState> streams;
+  GroupWork grp;  // batch handles: lockstep groups of buffers (grp.kmax = 0: none)
   int error = 0;
   int64_t cap = 0;
   Lane lanes[kLanes];
@@ -176,6 +209,14 @@ void free_all(sfd_t* h) {
     if (ss.ev_dsh) (void)hipEventDestroy(ss.ev_dsh);
     ss.ev_dsh = nullptr;
   }
+  if (h->grp.sc_host) (void)hipHostFree(h->grp.sc_host);
+  if (h->grp.segs_host) (void)hipHostFree(h->grp.segs_host);
+  if (h->grp.st) (void)hipStreamDestroy(h->grp.st);
+  if (h->grp.done) (void)hipEventDestroy(h->grp.done);
+  h->grp.sc_host = nullptr;
+  h->grp.segs_host = nullptr;
+  h->grp.st = nullptr;
+  h->grp.done = nullptr;
   if (h->i64_host) (void)hipHostFree(h->i64_host);
   h->i64_host = nullptr;
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
@@ -253,6 +294,7 @@ int sync_lane(sfd_t* h, Lane& ln) {
 
 int sync_all(sfd_t* h) {
   for (int i = 0; i < h->lanes_alloc; ++i) CK(hipStreamSynchronize(h->lanes[i].st));
+  if (h->grp.st) CK(hipStreamSynchronize(h->grp.st));
   if (!h->pending.empty()) prof_resolve(h);
   return SFD_OK;
 }
@@ -375,22 +417,6 @@ double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed, double bx, do
 
 inline double pbytes(PanelType t) { return t == PanelType::BF16 ? 2.0 : 4.0; }
 
-// T <- R^{-1}, R the (pivoted) Cholesky factor of panel^T panel: panel * T has orthonormal
-// columns (the GramSchmidt of Alg 1 as CholeskyQR; the next sparse product applies T)
-int orth(sfd_t* h, Lane& ln, const void* panel, PanelType pt, int64_t rows) {
-  const int L = h->L;
-  const double ell = h->ell;
-  {
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, pbytes(pt) * rows * ell, 2.0 * rows * ell * ell, 2);
-    CK(gram(panel, pt, L, rows, L, ln.gram_part, ln.W, ln.st));
-  }
-  {
-    ProfScope ps(h, ln.st, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
-    CK(chol_inv(ln.W, L, h->ell, L, kCholDropTol, ln.T, ln.sc, ln.st));
-  }
-  return SFD_OK;
-}
-
 // The output of a product whose input panel had transform T (the lane's current one):
 // panel <- panel T (so the product becomes A' (X T), resp. A'^T (Y T)), then the new T from
 // the transformed panel's Gram.
@@ -451,6 +477,7 @@ int prepare(sfd_t* h, Lane& ln) {
     ProfScope ps(h, ln.st, SFD_PROF_CSC_BUILD, 16.0 * ln.nnz + 4.0 * (ln.m + d), 0.0, 1);
     CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, bands, ln.cscptr, ln.cscrow, ln.cscval, ln.csc,
                  ln.sc, ln.st));
+    CK(fro2_segments(ln.cscptr, ln.cscrow, ln.cscval, bands * d, 1, ln.csc.part, ln.sc, ln.st));
   }
   ln.scs.bands = bands;
   ln.scs.band_rows = (int)d;
@@ -488,7 +515,9 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   void* X = bf ? static_cast<void*>(ln.Xb) : static_cast<void*>(ln.X);
   void* Y = bf ? static_cast<void*>(ln.Yb) : static_cast<void*>(ln.Y);
   if (bf) CK(to_bf16(ln.X, d * L, ln.Xb, ln.st));
-  if ((rc = orth(h, ln, X, pt, d))) return rc;
+  // the first transform from the Gram of G itself (G T = G with T = I)
+  CK(set_identity(ln.T, L, 1, ln.st));
+  if ((rc = orth_out(h, ln, X, pt, d))) return rc;
   for (int it = 0; it < ln.q; ++it) {
     if ((rc = spmm_csr(h, ln, X, pt, Y, pt))) return rc;
     if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
@@ -553,9 +582,11 @@ int issue_shrink(sfd_t* h, Lane& ln) {
 // DenseShrink (Alg 5) of [B; B'] with B'^T = P^T M (M = I for an exact block); the stack is
 // kept exactly when it has at most ell live rows.  B is read from `Bin`, the result goes to
 // `out` (both d x L).  Waits for the previous DenseShrink and records its own completion.
-int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int lossless, float* out) {
+int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int lossless, float* out,
+                 const double* M64 = nullptr) {
   const int L = h->L, ell = h->ell;
   const int64_t d = h->d;
+  if (!M64) M64 = ln.M64;
   CK(hipStreamWaitEvent(ln.st, ln.ss->ev_dsh, 0));
   {
     ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
@@ -563,7 +594,7 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(dsh_assemble(ln.W2, L, ell, ln.M64, ln.SS, ln.st));
+    CK(dsh_assemble(ln.W2, L, ell, M64, ln.SS, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
@@ -571,7 +602,7 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(dsh_post(ln.evals, ln.evecs, ell, L, ln.M64, lossless, ln.T2, ln.sc, ln.st));
+    CK(dsh_post(ln.evals, ln.evecs, ell, L, M64, lossless, ln.T2, ln.sc, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_XFORM, 12.0 * d * ell, 4.0 * d * ell * ell, 1);
@@ -584,17 +615,19 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
 // The in-order part of a buffer step: BoostedSparseShrink's acceptance (Alg 4, with the
 // VerifySpectral counter continued from vs_base) and the DenseShrink into `out`.
 // *live = structural live rows of the result, *calls = VerifySpectral calls made.
+// (a0 > 0: attempts 0 .. a0 - 1 were made and rejected elsewhere, with calls0 VerifySpectral
+// calls; attempt a0's SparseShrink has been issued on the lane)
 int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* Bin, float* out, int* live,
-                int64_t* calls) {
+                int64_t* calls, int a0 = 0, int64_t calls0 = 0) {
   const int ell = h->ell;
   int rc;
-  *calls = 0;
+  *calls = calls0;
   int r_add;
   if (ln.m <= ell) {
     r_add = ln.m;
   } else {
     bool accepted = false;
-    for (int a = 0;; ++a) {
+    for (int a = a0;; ++a) {
       if ((rc = read_scalars(h, ln))) return rc;
       const DevScalars s = *ln.sc_host;
       sfd_stats_t& stats = ln.ss->stats;
@@ -628,6 +661,51 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
   const int lossless = (live_in + r_add <= ell) ? 1 : 0;
   if ((rc = dense_shrink(h, ln, Bin, ln.Pt, lossless, out))) return rc;
   *live = lossless ? live_in + r_add : ell - 1;
+  return SFD_OK;
+}
+
+// Group workspace for up to kmax buffers (batch handles).
+int alloc_group(sfd_t* h, int kmax) {
+  GroupWork& g = h->grp;
+  const int64_t d = h->d, L = h->L, cap = h->cap;
+  g.kmax = kmax;
+  g.cap_rows = kmax * d;
+  g.cap_nnz = kmax * cap;
+  const int64_t tiles = (g.cap_nnz + 2047) / 2048;
+  const int64_t max_chunks = g.cap_rows + g.cap_nnz / kSpmmChunk + 2;
+  bool ok = true;
+  ok = ok && dalloc(h, &g.rowptr, g.cap_rows + 1) && dalloc(h, &g.colidx, g.cap_nnz) && dalloc(h, &g.val, g.cap_nnz);
+  ok = ok && dalloc(h, &g.cscptr, kmax * d + 1) && dalloc(h, &g.cscrow, g.cap_nnz) && dalloc(h, &g.cscval, g.cap_nnz);
+  ok = ok && dalloc(h, &g.csc.counts, 1) && dalloc(h, &g.csc.rowid, g.cap_nnz);
+  ok = ok && dalloc(h, &g.csc.keys0, g.cap_nnz) && dalloc(h, &g.csc.keys1, g.cap_nnz);
+  ok = ok && dalloc(h, &g.csc.vals0, g.cap_nnz) && dalloc(h, &g.csc.vals1, g.cap_nnz);
+  ok = ok && dalloc(h, &g.csc.hist, 256 * tiles + 1) && dalloc(h, &g.csc.part, 1024);
+  ok = ok && dalloc(h, &g.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, g.cap_rows + 1)) + 16);
+  g.csc.scan_tmp = g.scan_tmp;
+  for (Schedule* sch : {&g.sr, &g.scs}) {
+    const int64_t rows = g.cap_rows + 1;
+    ok = ok && dalloc(h, &sch->nch, rows) && dalloc(h, &sch->pslot, rows) && dalloc(h, &sch->desc, max_chunks) &&
+         dalloc(h, &sch->long_rows, rows) && dalloc(h, &sch->counters, 4);
+    sch->max_chunks = max_chunks;
+  }
+  g.scs.transposed = true;
+  ok = ok && dalloc(h, &g.partial, (2 * g.cap_nnz / kSpmmChunk + 16) * L);
+  ok = ok && dalloc(h, &g.X, kmax * d * L) && dalloc(h, &g.Y, kmax * d * L) && dalloc(h, &g.Pt, kmax * d * L);
+  ok = ok && dalloc(h, &g.gram_part, kmax * gram_partial_stride((int)L));
+  ok = ok && dalloc(h, &g.W, kmax * L * L) && dalloc(h, &g.Wp, kmax * L * L) && dalloc(h, &g.T, kmax * L * L);
+  ok = ok && dalloc(h, &g.evals, kmax * 2 * L) && dalloc(h, &g.evecs, kmax * 4 * L * L);
+  ok = ok && dalloc(h, &g.M64, kmax * L * L) && dalloc(h, &g.M32, kmax * L * L) && dalloc(h, &g.sc, kmax);
+  ok = ok && dalloc(h, &g.segs_x, kmax) && dalloc(h, &g.segs_y, kmax) && dalloc(h, &g.seg_rows, kmax + 1) &&
+       dalloc(h, &g.tsteps, kmax);
+  ok = ok && dalloc(h, &g.vs_w, kmax * d) && dalloc(h, &g.vs_wraw, kmax * d) && dalloc(h, &g.vs_z, g.cap_rows) &&
+       dalloc(h, &g.vs_c2, kmax * 2 * L) && dalloc(h, &g.vs_gpart, kmax * gemv_blocks(d) * L) &&
+       dalloc(h, &g.vs_npart, kmax * 1024) && dalloc(h, &g.fro_part, fro2_part_doubles(kmax));
+  if (!ok) return SFD_E_NOMEM;
+  if (hipHostMalloc((void**)&g.sc_host, sizeof(DevScalars) * kmax) != hipSuccess) return SFD_E_NOMEM;
+  const size_t hbytes = sizeof(GroupSeg) * 2 * kmax + sizeof(int64_t) * (kmax + 1) + sizeof(int) * kmax;
+  if (hipHostMalloc((void**)&g.segs_host, hbytes) != hipSuccess) return SFD_E_NOMEM;
+  if (hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking) != hipSuccess) return SFD_E_DEVICE;
+  if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   return SFD_OK;
 }
 
@@ -691,6 +769,248 @@ int run_flushes(sfd_t* h, const std::vector<BufferView>& views) {
       // same lane: ordered after this buffer's DenseShrink by the stream
       if ((rc = bind(h, ln, views[b + nl], index[(size_t)(b + nl)], kPurposeSI, kPurposeVS))) return rc;
       if ((rc = issue_shrink(h, ln))) return rc;
+    }
+  }
+  return SFD_OK;
+}
+
+// ------------------------------------------------------------------ lockstep groups
+// One buffer of a group: the view, the key of its random draws, where its DenseShrink goes,
+// and (after run_group) its results.
+struct GroupItem {
+  BufferView v;
+  int64_t buffer;
+  int pg, px;
+  float* out;  // DenseShrink destination (the stream's B, or a query's panel)
+  int live = 0;
+  int64_t calls = 0;
+};
+
+// Buffer steps of K buffers of different streams (each with m > ell) in lockstep: one launch per
+// step for all of them.  Every per-buffer result is bit for bit the one the single-buffer path
+// gives (same chunks, Gram geometry and reductions per buffer).  Buffers whose q is reached keep
+// their P^T and P P^T while the others go on; VerifySpectral runs max t steps with each buffer's
+// log-norm frozen after its own t.  A rejected buffer retries alone on a lane (Alg 4).
+int run_group(sfd_t* h, std::vector<GroupItem>& items) {
+  GroupWork& g = h->grp;
+  const int K = (int)items.size();
+  const int64_t d = h->d;
+  const int L = h->L, ell = h->ell;
+  const int64_t LL = (int64_t)L * L;
+  int rc;
+  if (K == 0) return SFD_OK;
+  hipStream_t st = g.st;
+  // the lanes' previous DenseShrinks read Pt / M64 of the previous group
+  for (int i = 0; i < h->nlanes; ++i) CK(hipStreamSynchronize(h->lanes[i].st));
+  // ---- stack the buffers
+  std::vector<int64_t> R((size_t)K + 1, 0), E((size_t)K + 1, 0);
+  std::vector<int> q((size_t)K);
+  int qmax = 0;
+  for (int k = 0; k < K; ++k) {
+    R[(size_t)k + 1] = R[(size_t)k] + items[(size_t)k].v.m;
+    E[(size_t)k + 1] = E[(size_t)k] + items[(size_t)k].v.nnz;
+    q[(size_t)k] = si_iterations(h, items[(size_t)k].v.m);
+    qmax = std::max(qmax, q[(size_t)k]);
+  }
+  const int64_t M = R[(size_t)K], NNZ = E[(size_t)K];
+  CK(fill_i32(g.rowptr, 1, 0, st));
+  for (int k = 0; k < K; ++k) {
+    const BufferView& v = items[(size_t)k].v;
+    if (v.rowptr)
+      CK(offset_copy(v.rowptr + 1, v.m, (int)E[(size_t)k], g.rowptr + R[(size_t)k] + 1, st));
+    else
+      CK(append_rowptr(v.indptr, v.r0, v.m, g.rowptr, (int)R[(size_t)k], (int)E[(size_t)k], st));
+    CK(offset_copy(v.colidx, v.nnz, (int)(k * d), g.colidx + E[(size_t)k], st));
+    if (v.nnz > 0)
+      CK(hipMemcpyAsync(g.val + E[(size_t)k], v.val, sizeof(float) * v.nnz, hipMemcpyDeviceToDevice, st));
+  }
+  CK(build_csc(g.rowptr, g.colidx, g.val, (int)M, (int)NNZ, (int64_t)K * d, 1, g.cscptr, g.cscrow, g.cscval, g.csc,
+               g.sc, st));
+  CK(fro2_segments(g.cscptr, g.cscrow, g.cscval, d, K, g.fro_part, g.sc, st));
+  g.sr.max_chunks = M + NNZ / kSpmmChunk + 2;
+  g.scs.max_chunks = (int64_t)K * d + NNZ / kSpmmChunk + 2;
+  CK(schedule_build(g.rowptr, (int)M, g.sr, g.scan_tmp, st));
+  CK(schedule_build(g.cscptr, (int)(K * d), g.scs, g.scan_tmp, st));
+  // ---- per-buffer geometry
+  GroupSeg* hx = g.segs_host;
+  GroupSeg* hy = hx + g.kmax;
+  int64_t* hrows = reinterpret_cast<int64_t*>(hy + g.kmax);
+  int* hsteps = reinterpret_cast<int*>(hrows + g.kmax + 1);
+  CK(hipStreamSynchronize(st));  // the pinned staging may still be read by the previous group
+  int nbx = 1, nby = 1;
+  for (int k = 0; k < K; ++k) {
+    GroupSeg& sx = hx[k];
+    sx.row0 = k * d;
+    sx.rows = d;
+    gram_geometry(d, &sx.nb, &sx.rpb);
+    GroupSeg& sy = hy[k];
+    sy.row0 = R[(size_t)k];
+    sy.rows = items[(size_t)k].v.m;
+    gram_geometry(sy.rows, &sy.nb, &sy.rpb);
+    nbx = std::max(nbx, sx.nb);
+    nby = std::max(nby, sy.nb);
+    hrows[k] = R[(size_t)k];
+  }
+  hrows[K] = M;
+  CK(hipMemcpyAsync(g.segs_x, hx, sizeof(GroupSeg) * K, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(g.segs_y, hy, sizeof(GroupSeg) * K, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(g.seg_rows, hrows, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
+  // ---- SimultaneousIteration (Alg 1) of all buffers
+  CK(fill_f32(g.X, (int64_t)K * d * L, 0.f, st));
+  for (int k = 0; k < K; ++k) {
+    const GroupItem& it = items[(size_t)k];
+    CK(start_block(h->seed, it.v.ss->stream_id, (uint64_t)it.buffer, 0, (uint64_t)it.pg, d, ell, g.X + k * d * L, L,
+                   st));
+  }
+  CK(set_identity(g.T, L, K, st));
+  CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
+  CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+  for (int iter = 0; iter <= qmax; ++iter) {
+    CK(spmm(g.sr, g.colidx, g.val, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, st));
+    CK(spmm_finish(g.sr, g.partial, g.Y, PanelType::F32, L, L, st));
+    CK(xform_gram_group(g.Y, PanelType::F32, L, 0, 0, nby, g.segs_y, K, L, g.T, g.gram_part, g.W, st));
+    CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+    CK(spmm(g.scs, g.cscrow, g.cscval, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, st));
+    CK(spmm_finish(g.scs, g.partial, g.X, PanelType::F32, L, L, st));
+    CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
+    // buffers at their final product: P^T = A'^T Y T_y and W = P P^T
+    for (int k = 0; k < K; ++k) {
+      if (q[(size_t)k] != iter) continue;
+      CK(hipMemcpyAsync(g.Pt + k * d * L, g.X + k * d * L, sizeof(float) * d * L, hipMemcpyDeviceToDevice, st));
+      CK(hipMemcpyAsync(g.Wp + k * LL, g.W + k * LL, sizeof(double) * LL, hipMemcpyDeviceToDevice, st));
+    }
+    if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+  }
+  // ---- SparseShrink (Alg 3): eig of P P^T, M = H D, the scalars of Alg 4
+  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, st));
+  CK(ssh_post_group(g.evals, g.evecs, ell, L, kAlpha, g.M64, g.M32, g.sc, K, 2 * L, 4 * LL, st));
+  CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  // ---- BoostedSparseShrink (Alg 4): lossless accept, else VerifySpectral (Alg 6)
+  std::vector<char> verdict((size_t)K, 0);  // 1 accepted, 0 needs VerifySpectral, 2 rejected
+  int tmax = 0;
+  for (int k = 0; k < K; ++k) {
+    const DevScalars sk = g.sc_host[k];
+    StreamState& ss = *items[(size_t)k].v.ss;
+    ss.stats.attempts += 1;
+    ss.stats.last_q = q[(size_t)k];
+    ss.stats.last_fro2_buffer = sk.fro2A;
+    ss.stats.last_lambda_ell2 = sk.lam_ell2;
+    ss.stats.last_delta = 2.0 * sk.half_delta;
+    hsteps[k] = 0;
+    if (sk.S <= 64.0 * kUnitRoundoff32 * ell * sk.fro2A || !h->verify) {
+      verdict[(size_t)k] = 1;
+    } else {
+      items[(size_t)k].calls = 1;
+      hsteps[k] = vs_steps(h, ss.vs_calls + 1);
+      tmax = std::max(tmax, hsteps[k]);
+    }
+  }
+  if (tmax > 0) {
+    CK(hipMemcpyAsync(g.tsteps, hsteps, sizeof(int) * K, hipMemcpyHostToDevice, st));
+    CK(fill_f32(g.vs_w, (int64_t)K * d, 0.f, st));
+    for (int k = 0; k < K; ++k) {
+      if (hsteps[k] == 0) continue;
+      const GroupItem& it = items[(size_t)k];
+      CK(start_block(h->seed, it.v.ss->stream_id, (uint64_t)it.buffer, 0, (uint64_t)it.px, d, 1, g.vs_w + k * d, 1,
+                     st));
+    }
+    constexpr int kScStride = (int)(sizeof(DevScalars) / sizeof(double));
+    CK(vs_init(g.vs_w, d, g.vs_npart, g.sc, st, K));
+    for (int s2 = 0; s2 < tmax; ++s2) {
+      CK(spmv(g.rowptr, g.colidx, g.val, g.sr, g.vs_w, &g.sc->inv_norm, g.vs_z, g.partial, st, g.seg_rows, K,
+              kScStride));
+      CK(panel_gemv_t(g.Pt, L, L, d, g.vs_w, &g.sc->inv_norm, g.vs_gpart, st, K, kScStride));
+      CK(spmv(g.cscptr, g.cscrow, g.cscval, g.scs, g.vs_z, nullptr, g.vs_wraw, g.partial, st));
+      CK(vs_small(g.vs_gpart, gemv_blocks(d), g.M64, ell, L, g.vs_c2, st, K));
+      CK(vs_finish(g.vs_wraw, g.Pt, L, L, ell, g.vs_c2, d, g.vs_w, g.vs_npart, st, K));
+      CK(vs_norm(g.vs_npart, vs_finish_blocks(d), g.sc, st, K, s2, g.tsteps));
+    }
+    CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int k = 0; k < K; ++k) {
+      if (hsteps[k] == 0) continue;
+      StreamState& ss = *items[(size_t)k].v.ss;
+      const double ln_norm = g.sc_host[k].ln_norm;
+      ss.stats.last_t = hsteps[k];
+      ss.stats.last_ln_norm = ln_norm;
+      if (ln_norm <= 0.0) {
+        verdict[(size_t)k] = 1;
+      } else {
+        ss.stats.vs_rejects += 1;
+        verdict[(size_t)k] = 2;
+      }
+    }
+  }
+  CK(hipEventRecord(g.done, st));
+  // ---- DenseShrink (Alg 5) per buffer on the lanes; rejected buffers retry there (Alg 4)
+  const int nl = h->nlanes;
+  for (int k = 0; k < K; ++k) {
+    GroupItem& it = items[(size_t)k];
+    Lane& ln = h->lanes[k % nl];
+    StreamState& ss = *it.v.ss;
+    CK(hipStreamWaitEvent(ln.st, g.done, 0));
+    if (verdict[(size_t)k] == 1) {
+      ln.ss = &ss;
+      const int r_add = ell - 1;
+      const int lossless = (ss.live + r_add <= ell) ? 1 : 0;
+      if ((rc = dense_shrink(h, ln, ss.B, g.Pt + k * d * L, lossless, it.out, g.M64 + k * LL))) return rc;
+      it.live = lossless ? ss.live + r_add : ell - 1;
+    } else {
+      if (h->max_attempts <= 1) return fail(h, SFD_E_NOCONVERGE);
+      if ((rc = bind(h, ln, it.v, it.buffer, it.pg, it.px))) return rc;
+      if ((rc = prepare(h, ln))) return rc;
+      ln.q = q[(size_t)k];
+      if ((rc = sparse_shrink(h, ln, 1))) return rc;
+      if ((rc = finish_step(h, ln, ss.vs_calls, ss.live, ss.B, it.out, &it.live, &it.calls, 1, 1))) return rc;
+    }
+  }
+  for (int i = 0; i < nl; ++i) CK(hipStreamSynchronize(h->lanes[i].st));
+  return SFD_OK;
+}
+
+// Buffer steps of `views` (consecutive flushes per stream, any streams) for a batch handle:
+// rounds of at most one buffer per stream (the r-th pending flush of each stream), each round in
+// lockstep groups of at most kmax buffers; buffers of at most ell rows take the lane path.
+int run_batched(sfd_t* h, const std::vector<BufferView>& views) {
+  int rc;
+  std::map<const StreamState*, int64_t> earlier;
+  std::vector<std::vector<std::pair<BufferView, int64_t>>> rounds;
+  for (const BufferView& v : views) {
+    const int64_t r = earlier[v.ss]++;
+    if ((int64_t)rounds.size() <= r) rounds.resize((size_t)r + 1);
+    rounds[(size_t)r].push_back({v, v.ss->flushes + r});
+  }
+  for (auto& round : rounds) {
+    std::vector<BufferView> small;
+    std::vector<GroupItem> items;
+    for (auto& e : round) {
+      if (e.first.m <= h->ell || h->grp.kmax == 0) {
+        small.push_back(e.first);
+        continue;
+      }
+      items.push_back({e.first, e.second, kPurposeSI, kPurposeVS, e.first.ss->B});
+      if ((int)items.size() == h->grp.kmax) {
+        if ((rc = run_group(h, items))) return rc;
+        for (GroupItem& it : items) {
+          it.v.ss->live = it.live;
+          it.v.ss->vs_calls += it.calls;
+          it.v.ss->flushes += 1;
+        }
+        items.clear();
+      }
+    }
+    if (!items.empty()) {
+      if ((rc = run_group(h, items))) return rc;
+      for (GroupItem& it : items) {
+        it.v.ss->live = it.live;
+        it.v.ss->vs_calls += it.calls;
+        it.v.ss->flushes += 1;
+      }
+    }
+    if (!small.empty()) {
+      if ((rc = run_flushes(h, small))) return rc;
+      if ((rc = sync_all(h))) return rc;
     }
   }
   return SFD_OK;
@@ -883,7 +1203,7 @@ int append_device_segments(sfd_t* h, std::vector<Segment>& segs) {
     flushed[i] = !segs[i].cuts.empty();
   }
   if (!views.empty()) {
-    if ((rc = run_flushes(h, views))) return rc;
+    if ((rc = h->grp.kmax > 0 ? run_batched(h, views) : run_flushes(h, views))) return rc;
     if ((rc = sync_all(h))) return rc;
   }
   for (size_t i = 0; i < segs.size(); ++i) {
@@ -1173,6 +1493,19 @@ int sfd_batch_create(int32_t nstreams, int64_t d, int32_t ell, double eps, uint6
     delete b;
     return rc;
   }
+  if (nstreams > 1) {
+    // lockstep groups of up to 64 buffers, within about 4 GiB of workspace
+    sfd_t* h = b->core;
+    const int64_t L = h->L;
+    const int64_t per = h->cap * 40 + h->d * L * 4 * 3 + gram_partial_stride((int)L) * 4 + h->d * 64;
+    int kmax = (int)std::min<int64_t>({(int64_t)nstreams, 64, std::max<int64_t>(1, ((int64_t)4 << 30) / per)});
+    DeviceGuard g(h->device);
+    if (kmax >= 2 && (rc = alloc_group(h, kmax)) != SFD_OK) {
+      sfd_destroy(h);
+      delete b;
+      return rc;
+    }
+  }
   *out = b;
   return SFD_OK;
 }
@@ -1260,40 +1593,56 @@ int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
   if ((rc = sync_all(h))) return rc;
   const int64_t per = (int64_t)h->ell * h->d;
   const int nl = h->nlanes;
-  // queries of the streams with pending rows go through the lanes (issued up to nl ahead,
-  // finished in stream order); the others are B itself
-  std::vector<int32_t> q;
+  Lane& l0 = h->lanes[0];
+  // one query result (d x L panel) -> stream s's ell x d block of B_out
+  auto emit = [&](const float* panel, int32_t s, hipStream_t st, float* stage) -> int {
+    float* dst = mem == SFD_MEM_DEVICE ? B_out + s * per : stage;
+    CK(transpose_out(panel, h->L, h->d, h->ell, dst, st));
+    if (mem == SFD_MEM_HOST) {
+      CK(hipMemcpyAsync(B_out + s * per, stage, sizeof(float) * per, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+    }
+    return SFD_OK;
+  };
+  // streams without pending rows: B itself; pending buffers of more than ell rows: lockstep
+  // groups (purposes 2/3, nothing stored); the others: the lanes
+  std::vector<int32_t> lane_q, grp_q;
   for (int32_t s = 0; s < (int32_t)h->streams.size(); ++s) {
     StreamState& ss = h->streams[(size_t)s];
-    Lane& l0 = h->lanes[0];
     if (ss.pm == 0) {
-      float* dst = mem == SFD_MEM_DEVICE ? B_out + s * per : l0.X;
-      CK(transpose_out(ss.B, h->L, h->d, h->ell, dst, l0.st));
-      if (mem == SFD_MEM_HOST) {
-        CK(hipMemcpyAsync(B_out + s * per, l0.X, sizeof(float) * per, hipMemcpyDeviceToHost, l0.st));
-        if ((rc = sync_lane(h, l0))) return rc;
-      }
+      if ((rc = emit(ss.B, s, l0.st, l0.X))) return rc;
+    } else if (ss.pm > h->ell && h->grp.kmax > 0) {
+      grp_q.push_back(s);
     } else {
-      q.push_back(s);
+      lane_q.push_back(s);
     }
   }
-  const int nq = (int)q.size();
+  if ((rc = sync_all(h))) return rc;
+  for (size_t i0 = 0; i0 < grp_q.size(); i0 += (size_t)h->grp.kmax) {
+    const size_t i1 = std::min(grp_q.size(), i0 + (size_t)h->grp.kmax);
+    std::vector<GroupItem> items;
+    for (size_t i = i0; i < i1; ++i) {
+      StreamState& ss = h->streams[(size_t)grp_q[i]];
+      BufferView v{&ss, ss.prow, nullptr, 0, ss.pcol, ss.pval, ss.pm, ss.pnnz};
+      items.push_back({v, ss.flushes, kPurposeQuerySI, kPurposeQueryVS, h->grp.X + (int64_t)(i - i0) * h->d * h->L});
+    }
+    if ((rc = run_group(h, items))) return rc;
+    for (size_t i = i0; i < i1; ++i)
+      if ((rc = emit(items[i - i0].out, grp_q[i], h->grp.st, h->grp.Y))) return rc;
+    CK(hipStreamSynchronize(h->grp.st));
+  }
+  const int nq = (int)lane_q.size();
   for (int k = 0; k < nq && k < nl; ++k)
-    if ((rc = query_issue(h, h->streams[(size_t)q[(size_t)k]], h->lanes[k % nl]))) return rc;
+    if ((rc = query_issue(h, h->streams[(size_t)lane_q[(size_t)k]], h->lanes[k % nl]))) return rc;
   for (int k = 0; k < nq; ++k) {
     Lane& ln = h->lanes[k % nl];
-    StreamState& ss = h->streams[(size_t)q[(size_t)k]];
+    StreamState& ss = h->streams[(size_t)lane_q[(size_t)k]];
     int live = 0;
     int64_t calls = 0;
     if ((rc = finish_step(h, ln, ss.vs_calls, ss.live, ss.B, ln.Bq, &live, &calls))) return rc;
-    float* dst = mem == SFD_MEM_DEVICE ? B_out + q[(size_t)k] * per : ln.X;
-    CK(transpose_out(ln.Bq, h->L, h->d, h->ell, dst, ln.st));
-    if (mem == SFD_MEM_HOST) {
-      CK(hipMemcpyAsync(B_out + q[(size_t)k] * per, ln.X, sizeof(float) * per, hipMemcpyDeviceToHost, ln.st));
-      if ((rc = sync_lane(h, ln))) return rc;
-    }
+    if ((rc = emit(ln.Bq, lane_q[(size_t)k], ln.st, ln.X))) return rc;
     if (k + nl < nq)
-      if ((rc = query_issue(h, h->streams[(size_t)q[(size_t)(k + nl)]], ln))) return rc;
+      if ((rc = query_issue(h, h->streams[(size_t)lane_q[(size_t)(k + nl)]], ln))) return rc;
   }
   return sync_all(h);
 }

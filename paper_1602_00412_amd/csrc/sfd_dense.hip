@@ -140,10 +140,23 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __res
 //  * the accumulator of strip n at fixed v is itself an A / B operand over the four rows
 //    4 k + v (k = l / 16), so Gram += out^T out is formed from the registers directly: for
 //    v = 0..3 and each upper tile (si, sj), MFMA(C_si[v], C_sj[v]).
+// Groups (segs != nullptr): buffer k = blockIdx.y owns rows [segs[k].row0, + segs[k].rows) of P
+// with its own T (T + k L L) and partials (partials + k pstride), and the block geometry a
+// single-buffer launch over that many rows has (segs[k].rpb, .nb), so its result is the same.
 template <int L, bool BF>
 __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ P, int ld, int64_t rows, int rpb,
                                                              const float* __restrict__ T,
-                                                             float* __restrict__ partials) {
+                                                             float* __restrict__ partials, const GroupSeg* segs,
+                                                             int64_t pstride) {
+  if (segs) {
+    const GroupSeg g = segs[blockIdx.y];
+    if ((int)blockIdx.x >= g.nb) return;
+    P = reinterpret_cast<char*>(P) + (size_t)g.row0 * ld * (BF ? 2 : 4);
+    rows = g.rows;
+    rpb = g.rpb;
+    T += (int64_t)blockIdx.y * L * L;
+    partials += (int64_t)blockIdx.y * pstride;
+  }
   static_assert(L == 32 || L == 64, "panel width");
   constexpr int S = L / 16;            // column strips
   constexpr int KS = L / 4;            // k-steps of the transform
@@ -265,8 +278,14 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
 // symmetric.  A block owns 16 entries; sixteen thread groups sum interleaved sixteenths of the
 // partials (fixed order) and the group sums are added in group order.
 __global__ __launch_bounds__(256) void k_gram_reduce(const float* __restrict__ partials, int nb, int W,
-                                                     double* __restrict__ Wout) {
+                                                     double* __restrict__ Wout, const GroupSeg* segs,
+                                                     int64_t pstride) {
   __shared__ double red[16][16];
+  if (segs) {  // buffer k = blockIdx.y of a group
+    nb = segs[blockIdx.y].nb;
+    partials += (int64_t)blockIdx.y * pstride;
+    Wout += (int64_t)blockIdx.y * W * W;
+  }
   const int q = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
   const int e = blockIdx.x * 16 + q;
@@ -330,10 +349,20 @@ __global__ __launch_bounds__(256) void k_panel_xform2(const float* P1, int ld1, 
   }
 }
 
+// Groups: buffer k = blockIdx.y has panel P + k rows ld, vector y + k rows, scale
+// scale_ptr + k sstride and partials part + k gridDim.x L.
 __global__ __launch_bounds__(256) void k_panel_gemv_t(const float* __restrict__ P, int ld, int L, int64_t rows,
                                                       int rpb, const float* __restrict__ y,
-                                                      const double* __restrict__ scale_ptr, float* __restrict__ part) {
+                                                      const double* __restrict__ scale_ptr, float* __restrict__ part,
+                                                      int sstride) {
   __shared__ float red[4][128];
+  {
+    const int64_t k = blockIdx.y;
+    P += k * rows * ld;
+    y += k * rows;
+    if (scale_ptr) scale_ptr += k * sstride;
+    part += k * gridDim.x * L;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
@@ -443,52 +472,41 @@ static void gram_grid(int64_t rows, int64_t& nb, int& rpb) {
   nb = rows > 0 ? (rows + rpb - 1) / rpb : 1;
 }
 
-hipError_t gram(const void* P, PanelType pt, int ld, int64_t rows, int w, float* partials, double* W,
-                hipStream_t st) {
-  int64_t nb;
-  int rpb;
-  gram_grid(rows, nb, rpb);
-  const float* none = nullptr;
-  const bool bf = pt == PanelType::BF16;
-  switch (w) {
-    case 32:
-      if (bf)
-        k_gram_partial<32, false, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
-      else
-        k_gram_partial<32, false, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
-      break;
-    case 64:
-      if (bf)
-        k_gram_partial<64, false, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
-      else
-        k_gram_partial<64, false, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, none, 0, rows, rpb, partials);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  k_gram_reduce<<<(unsigned)((w * w + 15) / 16), 256, 0, st>>>(partials, (int)nb, w, W);
-  return hipGetLastError();
-}
-
 hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
                       hipStream_t st) {
   int64_t nb;
   int rpb;
   gram_grid(rows, nb, rpb);
+  return xform_gram_group(P, pt, ld, rows, rpb, (int)nb, nullptr, 1, L, T, partials, W, st);
+}
+
+void gram_geometry(int64_t rows, int* nb, int* rpb) {
+  int64_t n;
+  gram_grid(rows, n, *rpb);
+  *nb = (int)n;
+}
+
+int64_t gram_partial_stride(int L) { return (int64_t)kGramMaxBlocks * L * L; }
+
+hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,
+                            int L, const float* T, float* partials, double* W, hipStream_t st) {
   const bool bf = pt == PanelType::BF16;
+  const int64_t ps = gram_partial_stride(L);
+  const dim3 grid((unsigned)nb, (unsigned)K);
   if (L == 32) {
     if (bf)
-      k_xform_gram<32, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+      k_xform_gram<32, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
     else
-      k_xform_gram<32, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+      k_xform_gram<32, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
   } else if (L == 64) {
     if (bf)
-      k_xform_gram<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+      k_xform_gram<64, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
     else
-      k_xform_gram<64, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials);
+      k_xform_gram<64, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
   } else {
     return hipErrorInvalidValue;
   }
-  k_gram_reduce<<<(unsigned)((L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, L, W);
+  k_gram_reduce<<<dim3((unsigned)((L * L + 15) / 16), (unsigned)K), 256, 0, st>>>(partials, nb, L, W, segs, ps);
   return hipGetLastError();
 }
 
@@ -506,7 +524,7 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
       break;
     default: return hipErrorInvalidValue;
   }
-  k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W);
+  k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W, nullptr, 0);
   return hipGetLastError();
 }
 
@@ -531,10 +549,10 @@ int gemv_blocks(int64_t rows) {
 }
 
 hipError_t panel_gemv_t(const float* P, int ld, int L, int64_t rows, const float* y, const double* scale_ptr,
-                        float* part, hipStream_t st) {
+                        float* part, hipStream_t st, int K, int sstride) {
   int nb = gemv_blocks(rows);
   int rpb = (int)((rows + nb - 1) / nb);
-  k_panel_gemv_t<<<nb, 256, 0, st>>>(P, ld, L, rows, rpb, y, scale_ptr, part);
+  k_panel_gemv_t<<<dim3((unsigned)nb, (unsigned)K), 256, 0, st>>>(P, ld, L, rows, rpb, y, scale_ptr, part, sstride);
   return hipGetLastError();
 }
 

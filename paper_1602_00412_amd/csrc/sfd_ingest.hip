@@ -182,43 +182,6 @@ __global__ void k_csc_gather(const int* perm, const int* rowid, const float* val
   }
 }
 
-// ||A'||_F^2 with repeated (row, col) entries summed: each run of equal (col, row) in the
-// sorted order contributes (sum of its values)^2, accumulated in FP64.
-__global__ __launch_bounds__(256) void k_fro2_runs(const int* keys, const int* cscrow, const float* cscval, int nnz,
-                                                   double* part) {
-  __shared__ double s[256];
-  double acc = 0.0;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int stride = gridDim.x * blockDim.x;
-  for (; i < nnz; i += stride) {
-    bool start = (i == 0) || keys[i - 1] != keys[i] || cscrow[i - 1] != cscrow[i];
-    if (!start) continue;
-    double v = cscval[i];
-    for (int j = i + 1; j < nnz && keys[j] == keys[i] && cscrow[j] == cscrow[i]; ++j) v += cscval[j];
-    acc += v * v;
-  }
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
-
-__global__ __launch_bounds__(256) void k_sum_to_scalar(const double* part, int nb, double* out) {
-  __shared__ double s[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = s[0];
-}
-
 // out row j (already zeroed) += the entries of column j; one thread per column, so repeated
 // (row, column) entries are added in CSC order
 __global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
@@ -231,7 +194,49 @@ __global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const flo
   }
 }
 
-constexpr int kFroBlocks = 512;
+constexpr int kFroBlocks = 64;  // blocks per column segment
+
+// ||A'||_F^2 of each of K column segments of d columns (the buffers of a group, K = 1 for one
+// buffer), repeated (row, column) entries summed: thread t of block b takes columns
+// b 256 + t, + 64 * 256, ... of its segment; a column's entries are sorted by row, so repeats
+// are adjacent runs.  part[k][b] = the block's sum (fixed-order tree).
+__global__ __launch_bounds__(256) void k_fro2_cols(const int* __restrict__ cscptr, const int* __restrict__ cscrow,
+                                                   const float* __restrict__ cscval, int64_t d,
+                                                   double* __restrict__ part) {
+  __shared__ double s[256];
+  const int64_t c0 = (int64_t)blockIdx.y * d;
+  double acc = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < d; c += (int64_t)gridDim.x * 256) {
+    const int e = cscptr[c0 + c + 1];
+    int k = cscptr[c0 + c];
+    while (k < e) {
+      const int r = cscrow[k];
+      double v = cscval[k];
+      for (++k; k < e && cscrow[k] == r; ++k) v += cscval[k];
+      acc += v * v;
+    }
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(64) void k_fro2_sum(const double* __restrict__ part, int nb, DevScalars* sc) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[(int64_t)blockIdx.x * nb + b];
+  sc[blockIdx.x].fro2A = t;
+}
+
+// dst[i] = src[i] + add (column ids of buffer k moved to the group's columns k d ..)
+__global__ void k_offset_copy(const int* __restrict__ src, int64_t n, int add, int* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] + add;
+}
 
 }  // namespace
 
@@ -264,10 +269,7 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st) {
   hipError_t e;
   const int64_t rows = d * bands;
-  if (nnz == 0) {
-    if ((e = fill_i32(cscptr, rows + 1, 0, st)) != hipSuccess) return e;
-    return fill_i32(reinterpret_cast<int*>(&sc->fro2A), 2, 0, st);  // fro2A = +0.0
-  }
+  if (nnz == 0) return fill_i32(cscptr, rows + 1, 0, st);
   k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid, colidx, nnz, bands, (int)d,
                                                          bands > 1 ? w.keys1 : nullptr);
   // stable LSD radix sort of the (band, column) keys, payload = entry index
@@ -296,8 +298,22 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
   }
   k_colptr_from_sorted<<<grid_for((int64_t)nnz + 1, 256, 8192), 256, 0, st>>>(kin, nnz, rows, cscptr);
   k_csc_gather<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(vin, w.rowid, val, nnz, cscrow, cscval);
-  k_fro2_runs<<<kFroBlocks, 256, 0, st>>>(kin, cscrow, cscval, nnz, w.part);
-  k_sum_to_scalar<<<1, 256, 0, st>>>(w.part, kFroBlocks, &sc->fro2A);
+  (void)sc;
+  return hipGetLastError();
+}
+
+hipError_t fro2_segments(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, int K, double* part,
+                         DevScalars* sc, hipStream_t st) {
+  k_fro2_cols<<<dim3(kFroBlocks, K), 256, 0, st>>>(cscptr, cscrow, cscval, d, part);
+  k_fro2_sum<<<K, 64, 0, st>>>(part, kFroBlocks, sc);
+  return hipGetLastError();
+}
+
+int fro2_part_doubles(int K) { return kFroBlocks * K; }
+
+hipError_t offset_copy(const int* src, int64_t n, int add, int* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_offset_copy<<<grid_for(n, 256, 8192), 256, 0, st>>>(src, n, add, dst);
   return hipGetLastError();
 }
 

@@ -11,6 +11,17 @@ constexpr int kMaxEll = 56;      // 2*ell <= 112 keeps the FP64 eigensolver in o
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
 constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
 
+// One buffer of a lockstep group (buffers of several streams running their SimultaneousIteration
+// together, one launch per step for all of them): its segment of a stacked panel (first row,
+// rows) and the Gram launch geometry a single-buffer launch over that many rows has, so every
+// per-buffer result equals the single-buffer one.
+struct GroupSeg {
+  int64_t row0;
+  int64_t rows;
+  int rpb;  // rows per Gram block
+  int nb;   // Gram blocks
+};
+
 // element type of a dense panel (FP32, or BF16 in the precision form: the upper 16 bits of an
 // FP32 value, rounded to nearest even)
 enum class PanelType { F32, BF16 };
@@ -38,6 +49,8 @@ hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStrea
 int64_t scan_tmp_ints(int64_t n);
 // copy a d x w block between panels with pitches (elements)
 hipError_t copy_panel(const float* src, int lds, float* dst, int ldd, int64_t rows, int w, hipStream_t st);
+// K consecutive L x L identity matrices
+hipError_t set_identity(float* T, int L, int K, hipStream_t st);
 // dst[i] = BF16 rounding of src[i], n elements
 hipError_t to_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t st);
 // out (ell x d, row-major) = panel^T restricted to the first ell columns
@@ -54,8 +67,7 @@ hipError_t find_cuts(const int64_t* indptr, int64_t nrows, int64_t buf_rows, int
 // rowptr[m0 + 1 + i] = indptr[r0 + 1 + i] - indptr[r0] + nnz0 for i < cnt
 hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* rowptr, int m0, int nnz0,
                          hipStream_t st);
-// CSR -> CSC by a stable LSD radix sort of the column ids; also ||A'||_F^2 with repeated (row, col)
-// entries summed, into sc->fro2A
+// CSR -> CSC by a stable LSD radix sort of the column ids
 struct CscWork {
   int* counts;    // d + 1
   int* scan_tmp;
@@ -70,6 +82,14 @@ struct CscWork {
 // entries of column c in band b.  Rows stay ascending inside every column.
 hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st);
+// ||A'||_F^2 with repeated (row, column) entries summed, for each of K column segments of d
+// columns of a CSC (the buffers of a group; K = 1 for one buffer) into sc[k].fro2A; part holds
+// fro2_part_doubles(K) doubles
+hipError_t fro2_segments(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, int K, double* part,
+                         DevScalars* sc, hipStream_t st);
+int fro2_part_doubles(int K);
+// dst[i] = src[i] + add, i < n
+hipError_t offset_copy(const int* src, int64_t n, int add, int* dst, hipStream_t st);
 // dense transpose of a small buffer (m <= L rows): out[j][r] = sum of A'[r][j], pitch ld, width L
 hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, float* out,
                           int ld, int L, hipStream_t st);
@@ -103,20 +123,27 @@ hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void*
                 PanelType yt, int ldy, int L, float* partial, hipStream_t st);
 // the long rows' fix-up of a product (and for a banded schedule the band sums)
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st);
-// z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1)
+// z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1); for a group's stacked
+// structure (seg_rows: K + 1 row offsets, device) row r of buffer k is scaled by
+// scale_ptr[k sstride]
 hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* y,
-                const double* scale_ptr, float* z, float* partial, hipStream_t st);
+                const double* scale_ptr, float* z, float* partial, hipStream_t st, const int64_t* seg_rows = nullptr,
+                int K = 1, int sstride = 0);
 
 // ---------------------------------------------------------------- dense panels (sfd_dense.hip)
-// Gram W = P^T P of a rows x w panel (w in {32, 64}, FP32 or BF16 elements, pitch ld elements)
-// into FP64 W (w x w); partials hold at most gram_max_blocks() blocks of 4*w*w floats
+// partial buffers of the Gram kernels hold at most gram_max_blocks() blocks of 4*L*L floats
 int gram_max_blocks();
-hipError_t gram(const void* P, PanelType pt, int ld, int64_t rows, int w, float* partials, double* W,
-                hipStream_t st);
 // P <- P T in place (rows x L, L in {32, 64}, FP32 or BF16; T: L x L f32) and W = Gram of the
 // result as stored (FP64, L x L)
 hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
                       hipStream_t st);
+// the same for the K buffers of a group: segs (device, K entries) give each buffer's rows of P;
+// buffer k uses T + k L L, partials + k gram_partial_stride(L), W + k L L; nb = max segs[k].nb.
+// With segs = nullptr and K = 1 it is the single-buffer launch over (rows, rpb, nb).
+hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,
+                            int L, const float* T, float* partials, double* W, hipStream_t st);
+void gram_geometry(int64_t rows, int* nb, int* rpb);
+int64_t gram_partial_stride(int L);
 // Gram of the side-by-side panel [P1 | P2] (rows x 2L, each half L wide) into FP64 (2L x 2L)
 hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t rows, int L, float* partials, double* W,
                  hipStream_t st);
@@ -125,8 +152,10 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
                         int ldo, int64_t rows, hipStream_t st);
 // partial sums of P^T y over row blocks: part[b][k] = sum_{j in block} P[j][k] * y[j] * scale
 int gemv_blocks(int64_t rows);
+// K > 1: buffer k reads P + k rows ld, y + k rows, scale_ptr + k sstride (doubles) and writes
+// part + k gemv_blocks(rows) L
 hipError_t panel_gemv_t(const float* P, int ld, int L, int64_t rows, const float* y, const double* scale_ptr,
-                        float* part, hipStream_t st);
+                        float* part, hipStream_t st, int K = 1, int sstride = 0);
 // Philox4x64-10 start block: out[row][col] for row < d, col < ell (pitch ld); pads untouched
 hipError_t start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint64_t attempt, uint64_t purpose,
                        int64_t d, int ell, float* out, int ld, hipStream_t st);
@@ -136,6 +165,15 @@ hipError_t start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint6
 // f32, zero-padded); columns whose residual falls to tau * (their norm^2) are dropped
 hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
                     hipStream_t st);
+// group launches (one workgroup per buffer k): chol_inv on W + k wstride -> T + k L L, sc + k;
+// eig_sym on A + k astride -> evals + k estride, evecs + k vstride; ssh_post on evals + k estride,
+// H + k vstride -> M64 / M32 + k L L, sc + k
+hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
+                          int64_t wstride, hipStream_t st);
+hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
+                         int64_t estride, int64_t vstride, hipStream_t st);
+hipError_t ssh_post_group(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
+                          DevScalars* sc, int K, int64_t estride, int64_t vstride, hipStream_t st);
 // symmetric eigensolver (cyclic Jacobi, FP64) of the n x n matrix A (pitch lda), n <= 2*kMaxEll:
 // evals descending, evecs column i <-> evals[i], pitch n
 hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, hipStream_t st);
@@ -152,15 +190,21 @@ hipError_t dsh_post(const double* evals, const double* U, int ell, int L, const 
                     float* T2, DevScalars* sc, hipStream_t st);
 
 // ---------------------------------------------------------------- VerifySpectral (sfd_vs.hip)
+// The VerifySpectral launches take K buffers of a group (K = 1: one buffer); buffer k uses
+// vectors at k d, partials at k (blocks), M64 at k L L, c2 at k 2 L, scalars sc + k.
 // x: gaussian vector already in w; sets sc->inv_norm = 1/||w||, ln_norm = 0, zero_flag = 0
-hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st);
+hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st, int K = 1);
+int vs_norm_blocks();
 // c2 = M M^T c with c = sum of gemv partials (nb blocks)
-hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st);
+hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st,
+                    int K = 1);
 // w = w_raw - P c2; partial ||w||^2 per block
 int vs_finish_blocks(int64_t d);
 hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
-                     float* w, double* part, hipStream_t st);
-// reduce ||w||^2, ln_norm += ln||w|| - ln(Delta/2), inv_norm = 1/||w||
-hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st);
+                     float* w, double* part, hipStream_t st, int K = 1);
+// reduce ||w||^2, ln_norm += ln||w|| - ln(Delta/2), inv_norm = 1/||w||; in a group a buffer
+// whose step count tsteps[k] is reached (step >= tsteps[k]) is left as it is
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K = 1, int step = 0,
+                   const int* tsteps = nullptr);
 
 }  // namespace sfd

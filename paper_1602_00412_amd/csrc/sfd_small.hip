@@ -49,8 +49,12 @@ __device__ inline double readlane_d(double v, int l) {
 // the wave).  Steps are unrolled, so register indices are static; the published rows alternate
 // between two LDS buffers, so one barrier per step suffices.  panel * T then has orthonormal kept
 // columns spanning the panel's numerical column space.
+// (a group launch runs one workgroup per buffer k = blockIdx.x on W + k wstride, T + k L L, sc + k)
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ W, int ldw, int n, int L, double tau,
-                                                  float* __restrict__ T, DevScalars* sc) {
+                                                  float* __restrict__ T, DevScalars* sc, int64_t wstride) {
+  W += blockIdx.x * wstride;
+  T += (int64_t)blockIdx.x * L * L;
+  sc += blockIdx.x;
   constexpr int S = kCholMax / 4;  // row slots per thread
   __shared__ double pub[2][kCholMax];
   __shared__ int ndrop[4];
@@ -145,9 +149,15 @@ constexpr int kJacobiMaxBlocksPerThread = (kEigMax / 2) * (kEigMax / 2 + 1) / 2 
 // owns and the V entries it rotates are fixed for the whole solve.  Sweeps repeat until no
 // off-diagonal entry exceeds 1e-15 sqrt(|a_pp a_qq|) (and 1e-18 of the largest diagonal entry).
 // An odd n is padded with a zero row and column, which is never rotated.
+// (a group launch runs one workgroup per buffer k = blockIdx.x on Ain + k astride,
+// evals + k estride, evecs + k vstride)
 __global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __restrict__ Ain, int lda, int n,
-                                                    double* __restrict__ evals, double* __restrict__ evecs) {
+                                                    double* __restrict__ evals, double* __restrict__ evecs,
+                                                    int64_t astride, int64_t estride, int64_t evstride) {
   extern __shared__ double lds[];
+  Ain += blockIdx.x * astride;
+  evals += blockIdx.x * estride;
+  evecs += blockIdx.x * evstride;
   const int N = n + (n & 1);
   const int P = N / 2;
   double* A = lds;                           // N (N + 1) / 2
@@ -283,9 +293,17 @@ __global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __r
   }
 }
 
+// (a group launch: buffer k = blockIdx.x on evals + k estride, H + k vstride, M64 / M32 + k L L,
+// sc + k)
 __global__ __launch_bounds__(256) void k_ssh_post(const double* __restrict__ evals, const double* __restrict__ H,
                                                   int ell, int L, double alpha, double* __restrict__ M64,
-                                                  float* __restrict__ M32, DevScalars* sc) {
+                                                  float* __restrict__ M32, DevScalars* sc, int64_t estride,
+                                                  int64_t vstride) {
+  evals += blockIdx.x * estride;
+  H += blockIdx.x * vstride;
+  M64 += (int64_t)blockIdx.x * L * L;
+  M32 += (int64_t)blockIdx.x * L * L;
+  sc += blockIdx.x;
   __shared__ double D[kMaxEll];
   __shared__ double pivot;
   const int tid = threadIdx.x;
@@ -396,29 +414,51 @@ __global__ __launch_bounds__(256) void k_dsh_post(const double* __restrict__ eva
 hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
                     hipStream_t st) {
   if (ell > kCholMax || L > kCholMax) return hipErrorInvalidValue;
-  k_chol_inv<<<1, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc);
+  k_chol_inv<<<1, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, 0);
+  return hipGetLastError();
+}
+
+// dynamic LDS of the Jacobi solver for an n x n problem: packed upper A, V, pair lists
+size_t eig_lds_bytes(int n) {
+  const int N = n + (n & 1);
+  const int P = N / 2;
+  return sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N * N + 2 * P) + sizeof(int) * 2 * P;
+}
+
+hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
+                         int64_t estride, int64_t vstride, hipStream_t st) {
+  if (n < 1 || n > kEigMax || K < 1) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    // allow the largest problem's dynamic LDS (more than the default 64 KiB; gfx950 has 160 KiB)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(kEigMax));
+    attr_set = true;
+  }
+  k_eig_jacobi<<<K, kJacobiThreads, eig_lds_bytes(n), st>>>(A, lda, n, evals, evecs, astride, estride, vstride);
   return hipGetLastError();
 }
 
 hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, hipStream_t st) {
-  if (n < 1 || n > kEigMax) return hipErrorInvalidValue;
-  const int N = n + (n & 1);
-  const int P = N / 2;
-  size_t bytes = sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N * N + 2 * P) + sizeof(int) * 2 * P;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // allow more than the default 64 KiB of dynamic LDS (gfx950 has 160 KiB per workgroup)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    attr_set = true;
-  }
-  k_eig_jacobi<<<1, kJacobiThreads, bytes, st>>>(A, lda, n, evals, evecs);
-  return hipGetLastError();
+  return eig_sym_group(A, lda, n, evals, evecs, 1, 0, 0, 0, st);
 }
 
 hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
                     DevScalars* sc, hipStream_t st) {
-  k_ssh_post<<<1, 256, 0, st>>>(evals, H, ell, L, alpha, M64, M32, sc);
+  k_ssh_post<<<1, 256, 0, st>>>(evals, H, ell, L, alpha, M64, M32, sc, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
+                          int64_t wstride, hipStream_t st) {
+  if (ell > kCholMax || L > kCholMax) return hipErrorInvalidValue;
+  k_chol_inv<<<K, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
+  return hipGetLastError();
+}
+
+hipError_t ssh_post_group(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
+                          DevScalars* sc, int K, int64_t estride, int64_t vstride, hipStream_t st) {
+  k_ssh_post<<<K, 256, 0, st>>>(evals, H, ell, L, alpha, M64, M32, sc, estride, vstride);
   return hipGetLastError();
 }
 

@@ -303,15 +303,18 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ chun
 
 // Four chunks per wave, one per 16-lane group; a group strides its chunk's entries and
 // reduces with a 16-lane xor tree.
+// In a group (seg_rows != nullptr) row r belongs to the buffer k with seg_rows[k] <= r <
+// seg_rows[k + 1] and is scaled by scale_ptr[k sstride].
 __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, const int* __restrict__ nchunks_ptr,
                                               const int* __restrict__ idx, const float* __restrict__ val,
                                               const float* __restrict__ y, const double* __restrict__ scale_ptr,
-                                              float* __restrict__ z, float* __restrict__ partial) {
+                                              float* __restrict__ z, float* __restrict__ partial,
+                                              const int64_t* __restrict__ seg_rows, int K, int sstride) {
   const int nchunks = *nchunks_ptr;
   const int lane = threadIdx.x & 63;
   const int sub = lane & 15;
   const int grp = lane >> 4;
-  const float scale = scale_ptr ? (float)(*scale_ptr) : 1.f;
+  const float scale1 = (scale_ptr && !seg_rows) ? (float)(*scale_ptr) : 1.f;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
   for (int64_t base = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 4; base < nchunks; base += nwaves * 4) {
     const int64_t cc = base + grp;
@@ -329,6 +332,15 @@ __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, con
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (active && sub == 0) {
+      float scale = scale1;
+      if (scale_ptr && seg_rows) {
+        int lo = 0, hi = K;  // last k with seg_rows[k] <= row
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (seg_rows[mid] <= dc.x) lo = mid; else hi = mid;
+        }
+        scale = (float)scale_ptr[(int64_t)lo * sstride];
+      }
       const float v = acc * scale;
       if (dc.w < 0)
         z[dc.x] = v;
@@ -511,14 +523,15 @@ hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt,
 }
 
 hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule& s, const float* y,
-                const double* scale_ptr, float* z, float* partial, hipStream_t st) {
+                const double* scale_ptr, float* z, float* partial, hipStream_t st, const int64_t* seg_rows, int K,
+                int sstride) {
   (void)ptr;
   const int* nchunks = s.nch + s.rows;
   int64_t g = ((int64_t)s.max_chunks + 15) / 16;
   if (g > kSpmmMaxBlocks) g = kSpmmMaxBlocks;
   if (g < 1) g = 1;
   float* zo = s.bands > 1 ? s.bandbuf : z;
-  k_spmv<<<(unsigned)g, 256, 0, st>>>(s.desc, nchunks, idx, val, y, scale_ptr, zo, partial);
+  k_spmv<<<(unsigned)g, 256, 0, st>>>(s.desc, nchunks, idx, val, y, scale_ptr, zo, partial, seg_rows, K, sstride);
   k_spmv_fixup<<<64, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, zo);
   if (s.bands > 1)
     k_band_reduce_vec<<<grid_for(s.band_rows, 256, 4096), 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, z);

@@ -1,4 +1,6 @@
 // Utility kernels: fills, device-wide exclusive scan, panel copies and the output transpose.
+#include <algorithm>
+
 #include "sfd_internal.h"
 
 namespace sfd {
@@ -156,7 +158,21 @@ __global__ void k_to_bf16(const float* __restrict__ src, int64_t n, uint16_t* __
   }
 }
 
+__global__ void k_set_identity(float* __restrict__ T, int L, int K) {
+  const int64_t n = (int64_t)K * L * L;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % ((int64_t)L * L);
+    T[e] = (r / L == r % L) ? 1.f : 0.f;
+  }
+}
+
 }  // namespace
+
+hipError_t set_identity(float* T, int L, int K, hipStream_t st) {
+  const int64_t n = (int64_t)K * L * L;
+  k_set_identity<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, st>>>(T, L, K);
+  return hipGetLastError();
+}
 
 hipError_t to_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -12,8 +12,12 @@ namespace {
 
 constexpr int kNormBlocks = 512;
 
+// Group launches: buffer k = blockIdx.y (k_sumsq, k_vs_finish) or blockIdx.x (the one-block
+// kernels) works on its own vectors, partials, matrices and scalars at fixed strides.
 __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
   __shared__ double s[256];
+  x += (int64_t)blockIdx.y * n;
+  part += (int64_t)blockIdx.y * gridDim.x;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double v = x[i];
@@ -42,6 +46,8 @@ __device__ double block_sum(const double* part, int nb, double* s) {
 
 __global__ __launch_bounds__(256) void k_vs_init(const double* __restrict__ part, int nb, DevScalars* sc) {
   __shared__ double s[256];
+  part += (int64_t)blockIdx.x * nb;
+  sc += blockIdx.x;
   double tot = block_sum(part, nb, s);
   if (threadIdx.x == 0) {
     double nrm = sqrt(tot);
@@ -57,6 +63,9 @@ __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ par
                                                    const double* __restrict__ M, int ell, int L,
                                                    float* __restrict__ c2) {
   __shared__ double red[16][64];
+  part += (int64_t)blockIdx.x * nb * L;
+  M += (int64_t)blockIdx.x * L * L;
+  c2 += (int64_t)blockIdx.x * 2 * L;
   __shared__ double c[kMaxEll];
   __shared__ double u[kMaxEll];
   const int tid = threadIdx.x;
@@ -104,6 +113,14 @@ __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_r
                                                    int ld, int L, const float* __restrict__ c2, int64_t d,
                                                    float* __restrict__ w, double* __restrict__ part) {
   __shared__ double s[4];
+  {
+    const int64_t k = blockIdx.y;
+    w_raw += k * d;
+    P += k * d * ld;
+    c2 += k * 2 * L;
+    w += k * d;
+    part += k * gridDim.x;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float cA = lane < L ? c2[lane] : 0.f;
@@ -125,8 +142,14 @@ __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_r
   if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-__global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part, int nb, DevScalars* sc) {
+// steps: the step being taken and, for a group, each buffer's step count (a buffer past its
+// count keeps its norm)
+__global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part, int nb, DevScalars* sc, int step,
+                                                 const int* __restrict__ tsteps) {
   __shared__ double s[256];
+  part += (int64_t)blockIdx.x * nb;
+  sc += blockIdx.x;
+  if (tsteps && step >= tsteps[blockIdx.x]) return;
   double tot = block_sum(part, nb, s);
   if (threadIdx.x == 0) {
     double nrm = sqrt(tot);
@@ -143,14 +166,16 @@ __global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part
 
 }  // namespace
 
-hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st) {
-  k_sumsq<<<kNormBlocks, 256, 0, st>>>(w, d, part);
-  k_vs_init<<<1, 256, 0, st>>>(part, kNormBlocks, sc);
+hipError_t vs_init(const float* w, int64_t d, double* part, DevScalars* sc, hipStream_t st, int K) {
+  k_sumsq<<<dim3(kNormBlocks, K), 256, 0, st>>>(w, d, part);
+  k_vs_init<<<K, 256, 0, st>>>(part, kNormBlocks, sc);
   return hipGetLastError();
 }
 
-hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st) {
-  k_vs_small<<<1, 1024, 0, st>>>(part, nb, M64, ell, L, c2);
+int vs_norm_blocks() { return kNormBlocks; }
+
+hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L, float* c2, hipStream_t st, int K) {
+  k_vs_small<<<K, 1024, 0, st>>>(part, nb, M64, ell, L, c2);
   return hipGetLastError();
 }
 
@@ -162,14 +187,14 @@ int vs_finish_blocks(int64_t d) {
 }
 
 hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
-                     float* w, double* part, hipStream_t st) {
+                     float* w, double* part, hipStream_t st, int K) {
   (void)ell;
-  k_vs_finish<<<vs_finish_blocks(d), 256, 0, st>>>(w_raw, P, ld, L, c2, d, w, part);
+  k_vs_finish<<<dim3(vs_finish_blocks(d), K), 256, 0, st>>>(w_raw, P, ld, L, c2, d, w, part);
   return hipGetLastError();
 }
 
-hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st) {
-  k_vs_norm<<<1, 256, 0, st>>>(part, nb, sc);
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K, int step, const int* tsteps) {
+  k_vs_norm<<<K, 256, 0, st>>>(part, nb, sc, step, tsteps);
   return hipGetLastError();
 }
 
