@@ -475,9 +475,10 @@ int prepare(sfd_t* h, Lane& ln) {
   const int bands = csc_bands(h, ln);
   {
     ProfScope ps(h, ln.st, SFD_PROF_CSC_BUILD, 16.0 * ln.nnz + 4.0 * (ln.m + d), 0.0, 1);
+    const int* keys = nullptr;
     CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, bands, ln.cscptr, ln.cscrow, ln.cscval, ln.csc,
-                 ln.sc, ln.st));
-    CK(fro2_segments(ln.cscptr, ln.cscrow, ln.cscval, bands * d, 1, ln.csc.part, ln.sc, ln.st));
+                 &keys, ln.st));
+    CK(fro2_segments(ln.cscptr, keys, ln.cscrow, ln.cscval, bands * d, 1, ln.csc.part, ln.sc, ln.st));
   }
   ln.scs.bands = bands;
   ln.scs.band_rows = (int)d;
@@ -824,9 +825,10 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     if (v.nnz > 0)
       CK(hipMemcpyAsync(g.val + E[(size_t)k], v.val, sizeof(float) * v.nnz, hipMemcpyDeviceToDevice, st));
   }
+  const int* keys = nullptr;
   CK(build_csc(g.rowptr, g.colidx, g.val, (int)M, (int)NNZ, (int64_t)K * d, 1, g.cscptr, g.cscrow, g.cscval, g.csc,
-               g.sc, st));
-  CK(fro2_segments(g.cscptr, g.cscrow, g.cscval, d, K, g.fro_part, g.sc, st));
+               &keys, st));
+  CK(fro2_segments(g.cscptr, keys, g.cscrow, g.cscval, d, K, g.fro_part, g.sc, st));
   g.sr.max_chunks = M + NNZ / kSpmmChunk + 2;
   g.scs.max_chunks = (int64_t)K * d + NNZ / kSpmmChunk + 2;
   CK(schedule_build(g.rowptr, (int)M, g.sr, g.scan_tmp, st));

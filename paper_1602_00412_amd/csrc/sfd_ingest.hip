@@ -197,24 +197,23 @@ __global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const flo
 constexpr int kFroBlocks = 64;  // blocks per column segment
 
 // ||A'||_F^2 of each of K column segments of d columns (the buffers of a group, K = 1 for one
-// buffer), repeated (row, column) entries summed: thread t of block b takes columns
-// b 256 + t, + 64 * 256, ... of its segment; a column's entries are sorted by row, so repeats
-// are adjacent runs.  part[k][b] = the block's sum (fixed-order tree).
-__global__ __launch_bounds__(256) void k_fro2_cols(const int* __restrict__ cscptr, const int* __restrict__ cscrow,
-                                                   const float* __restrict__ cscval, int64_t d,
-                                                   double* __restrict__ part) {
+// buffer), repeated (row, column) entries summed.  Entry-parallel over the segment's entries
+// (keys: the sorted column ids): an entry that starts a run of equal (column, row) adds the
+// square of the run's sum; block b of segment k takes entries b 256 + t, + gridDim.x 256, ...
+// part[k][b] = the block's sum (fixed-order tree).
+__global__ __launch_bounds__(256) void k_fro2_cols(const int* __restrict__ cscptr, const int* __restrict__ keys,
+                                                   const int* __restrict__ cscrow, const float* __restrict__ cscval,
+                                                   int64_t d, double* __restrict__ part) {
   __shared__ double s[256];
-  const int64_t c0 = (int64_t)blockIdx.y * d;
+  const int e0 = cscptr[(int64_t)blockIdx.y * d];
+  const int e1 = cscptr[(int64_t)(blockIdx.y + 1) * d];
   double acc = 0.0;
-  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < d; c += (int64_t)gridDim.x * 256) {
-    const int e = cscptr[c0 + c + 1];
-    int k = cscptr[c0 + c];
-    while (k < e) {
-      const int r = cscrow[k];
-      double v = cscval[k];
-      for (++k; k < e && cscrow[k] == r; ++k) v += cscval[k];
-      acc += v * v;
-    }
+  for (int64_t i = e0 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < e1; i += (int64_t)gridDim.x * 256) {
+    const int key = keys[i], row = cscrow[i];
+    if (i > e0 && keys[i - 1] == key && cscrow[i - 1] == row) continue;
+    double v = cscval[i];
+    for (int64_t j = i + 1; j < e1 && keys[j] == key && cscrow[j] == row; ++j) v += cscval[j];
+    acc += v * v;
   }
   s[threadIdx.x] = acc;
   __syncthreads();
@@ -266,9 +265,10 @@ hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* ro
 }
 
 hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
-                     int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st) {
+                     int* cscptr, int* cscrow, float* cscval, CscWork& w, const int** sorted_keys, hipStream_t st) {
   hipError_t e;
   const int64_t rows = d * bands;
+  *sorted_keys = w.keys0;
   if (nnz == 0) return fill_i32(cscptr, rows + 1, 0, st);
   k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid, colidx, nnz, bands, (int)d,
                                                          bands > 1 ? w.keys1 : nullptr);
@@ -298,13 +298,13 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
   }
   k_colptr_from_sorted<<<grid_for((int64_t)nnz + 1, 256, 8192), 256, 0, st>>>(kin, nnz, rows, cscptr);
   k_csc_gather<<<grid_for(nnz, 256, 8192), 256, 0, st>>>(vin, w.rowid, val, nnz, cscrow, cscval);
-  (void)sc;
+  *sorted_keys = kin;
   return hipGetLastError();
 }
 
-hipError_t fro2_segments(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, int K, double* part,
-                         DevScalars* sc, hipStream_t st) {
-  k_fro2_cols<<<dim3(kFroBlocks, K), 256, 0, st>>>(cscptr, cscrow, cscval, d, part);
+hipError_t fro2_segments(const int* cscptr, const int* keys, const int* cscrow, const float* cscval, int64_t d, int K,
+                         double* part, DevScalars* sc, hipStream_t st) {
+  k_fro2_cols<<<dim3(kFroBlocks, K), 256, 0, st>>>(cscptr, keys, cscrow, cscval, d, part);
   k_fro2_sum<<<K, 64, 0, st>>>(part, kFroBlocks, sc);
   return hipGetLastError();
 }

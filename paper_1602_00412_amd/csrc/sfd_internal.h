@@ -80,13 +80,14 @@ struct CscWork {
 // entries (row r is in band floor(rowptr[r] * bands / nnz)) and the structure becomes the
 // concatenation of the bands' CSCs: "row" b*d + c of cscptr (bands*d + 1 entries) holds the
 // entries of column c in band b.  Rows stay ascending inside every column.
+// *sorted_keys: the entries' sorted keys (band * d + column), in one of w's arrays
 hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
-                     int* cscptr, int* cscrow, float* cscval, CscWork& w, DevScalars* sc, hipStream_t st);
+                     int* cscptr, int* cscrow, float* cscval, CscWork& w, const int** sorted_keys, hipStream_t st);
 // ||A'||_F^2 with repeated (row, column) entries summed, for each of K column segments of d
-// columns of a CSC (the buffers of a group; K = 1 for one buffer) into sc[k].fro2A; part holds
+// columns of a CSC (keys: its entries' sorted column ids, from build_csc) (the buffers of a group; K = 1 for one buffer) into sc[k].fro2A; part holds
 // fro2_part_doubles(K) doubles
-hipError_t fro2_segments(const int* cscptr, const int* cscrow, const float* cscval, int64_t d, int K, double* part,
-                         DevScalars* sc, hipStream_t st);
+hipError_t fro2_segments(const int* cscptr, const int* keys, const int* cscrow, const float* cscval, int64_t d, int K,
+                         double* part, DevScalars* sc, hipStream_t st);
 int fro2_part_doubles(int K);
 // dst[i] = src[i] + add, i < n
 hipError_t offset_copy(const int* src, int64_t n, int add, int* dst, hipStream_t st);
