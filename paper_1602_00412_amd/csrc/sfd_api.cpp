@@ -2,7 +2,7 @@
 // conventions in include/sfd.h).
 //
 // Device state of a handle: per stream (one for sfd_t, nstreams for sfd_batch_t) the sketch B
-// stored transposed as a d x L panel (row-major, L = ell rounded up to 32, zero-padded) and the
+// stored transposed as a d x L panel (row-major, L = 32, 64 or 128 >= ell, zero-padded) and the
 // pending buffer A' as CSR; and up to kLanes "lanes" shared by the streams.
 // A lane is the workspace of one buffer step with its own HIP stream: a CSR view of the buffer,
 // its CSC copy and chunk schedules, the SimultaneousIteration panels X (d x L) and Y (m x L),
@@ -80,6 +80,7 @@ struct Lane {
   float* gram_part = nullptr;
   double *W = nullptr, *W2 = nullptr;
   double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
+  char* eig_work = nullptr;  // the 2 ell x 2 ell eigensolver's rotation log (2 ell > 112)
   float *M32 = nullptr, *T = nullptr, *T2 = nullptr;
   float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
   double* vs_npart = nullptr;
@@ -346,7 +347,8 @@ int alloc_state(sfd_t* h) {
            dalloc(h, &s->long_rows, rows) && dalloc(h, &s->counters, 4);
       s->max_chunks = max_chunks;
     }
-    ok = ok && dalloc(h, &ln.partial, slots * L) && dalloc(h, &ln.bandbuf, kMaxBands * d * L);
+    // the banded CSC is offered for L <= 64 only
+    ok = ok && dalloc(h, &ln.partial, slots * L) && dalloc(h, &ln.bandbuf, L <= 64 ? kMaxBands * d * L : 1);
     ln.scs.bandbuf = ln.bandbuf;
     ln.scs.transposed = true;
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
@@ -354,6 +356,7 @@ int alloc_state(sfd_t* h) {
     ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
          dalloc(h, &ln.W2, 4 * L * L);
     ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
+    ok = ok && dalloc(h, &ln.eig_work, eig_work_bytes(2 * h->ell));
     ok = ok && dalloc(h, &ln.M64, L * L) && dalloc(h, &ln.M32, L * L) && dalloc(h, &ln.T, L * L) &&
          dalloc(h, &ln.T2, 2 * L * L);
     ok = ok && dalloc(h, &ln.vs_w, d) && dalloc(h, &ln.vs_wraw, d) && dalloc(h, &ln.vs_z, d) &&
@@ -465,7 +468,7 @@ int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType
 // buffer it cuts the product's L2 misses about 4x, but the band reduction costs more than the
 // product saves.
 int csc_bands(const sfd_t* h, const Lane& ln) {
-  if (ln.m <= h->ell || ln.nnz == 0 || h->precision != SFD_PRECISION_FP32) return 1;
+  if (ln.m <= h->ell || ln.nnz == 0 || h->precision != SFD_PRECISION_FP32 || h->L > 64) return 1;
   if ((int64_t)kMaxBands * h->d + 1 >= ((int64_t)1 << 31)) return 1;  // int32 keys and row ids
   return h->bands_opt > 0 ? std::min(h->bands_opt, kMaxBands) : 1;
 }
@@ -535,7 +538,7 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(ln.W, L, ell, ln.evals, ln.evecs, ln.st));
+    CK(eig_sym(ln.W, L, ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
@@ -595,11 +598,11 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
-    CK(dsh_assemble(ln.W2, L, ell, M64, ln.SS, ln.st));
+    CK(dsh_assemble(ln.W2, L, ell, M64, ln.SS, ln.evecs, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(ln.SS, 2 * ell, 2 * ell, ln.evals, ln.evecs, ln.st));
+    CK(eig_sym(ln.SS, 2 * ell, 2 * ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
@@ -884,7 +887,7 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
   }
   // ---- SparseShrink (Alg 3): eig of P P^T, M = H D, the scalars of Alg 4
-  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, st));
+  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, nullptr, 0, st));
   CK(ssh_post_group(g.evals, g.evecs, ell, L, kAlpha, g.M64, g.M32, g.sc, K, 2 * L, 4 * LL, st));
   CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1251,7 +1254,7 @@ int create_handle(int64_t d, int32_t ell, double eps, uint64_t seed, int nstream
   if (!h) return SFD_E_NOMEM;
   h->d = d;
   h->ell = ell;
-  h->L = ((ell + 31) / 32) * 32;
+  h->L = ell <= 32 ? 32 : ell <= 64 ? 64 : 128;
   h->eps = eps;
   h->seed = seed;
   h->lanes_alloc = lanes;

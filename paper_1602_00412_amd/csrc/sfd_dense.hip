@@ -3,7 +3,7 @@
 // transforms panel * T, the panel-transpose matrix-vector product of VerifySpectral, and the
 // counter-based start block G of Alg 1.
 //
-// Panels are row-major and tall (d x L or m x L, L = ell rounded up to 32, zero-padded), so
+// Panels are row-major and tall (d x L or m x L, L = 32, 64 or 128 >= ell, zero-padded), so
 // every Gram has its contraction along the tall axis.
 #include <type_traits>
 #include <utility>
@@ -274,6 +274,190 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   }
 }
 
+// Wide panels (L = 128): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), FP32 or BF16 panels,
+// and with ACC out <- out + Pin T (FP32 only; used for [P1 | P2] T2 as two passes).  Wave w of a
+// block computes output strip w (columns 16 w .. 16 w + 15) and keeps its strip of T as MFMA B
+// operands in registers (lane l: T[4 ks + l / 16][16 w + l % 16]); the 16-row input tile is loaded
+// by the whole block (16 bytes per thread), staged in LDS as FP32 (pitch L + 4, two buffers, so
+// one barrier per tile), and read as A operands by every wave.  A tile is read completely before
+// any of it is written, so out may be Pin.
+// Groups: buffer k = blockIdx.z owns rows [segs[k].row0, + segs[k].rows) with T + k L L.
+template <int L, bool BF, bool ACC>
+__global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi, void* out, int ldo, int64_t rows,
+                                                        int rpb, const float* __restrict__ T, int ldt,
+                                                        const GroupSeg* segs) {
+  static_assert(L == 128, "strip-per-wave transform");
+  static_assert(!(BF && ACC), "accumulation is FP32 only");
+  constexpr int NT = L * 4;  // threads: one wave per 16-column strip
+  constexpr int KS = L / 4;
+  constexpr int LP = L + 4;
+  constexpr int EB = BF ? 2 : 4;  // bytes per element
+  if (segs) {
+    const GroupSeg g = segs[blockIdx.z];
+    if ((int)blockIdx.x >= g.nb) return;
+    Pin = reinterpret_cast<const char*>(Pin) + (size_t)g.row0 * ldi * EB;
+    out = reinterpret_cast<char*>(out) + (size_t)g.row0 * ldo * EB;
+    rows = g.rows;
+    rpb = g.rpb;
+    T += (int64_t)blockIdx.z * L * L;
+  }
+  __shared__ float tile[2][16 * LP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  float tb[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) tb[ks] = T[(4 * ks + lk) * ldt + 16 * w + lm];
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = min(rows, r0 + rpb);
+  const char* src = reinterpret_cast<const char*>(Pin);
+  char* dst = reinterpret_cast<char*>(out);
+  const size_t ipitch = (size_t)ldi * EB, opitch = (size_t)ldo * EB;
+  // this thread's 4 elements of a tile: row tid / (L / 4), columns 4 (tid % (L / 4)) .. + 3
+  const int trow = tid / (L / 4), tcol = 4 * (tid % (L / 4));
+  using raw = typename std::conditional<BF, uint2, float4>::type;
+  auto load = [&](int64_t t0) -> raw {
+    const int64_t row = t0 + trow;
+    if (row < r1) return *reinterpret_cast<const raw*>(src + row * ipitch + (size_t)tcol * EB);
+    return raw{};
+  };
+  raw nxt = load(r0);
+  int buf = 0;
+  for (int64_t t0 = r0; t0 < r1; t0 += 16, buf ^= 1) {
+    float* my = tile[buf] + trow * LP + tcol;
+    if constexpr (BF) {
+      reinterpret_cast<float4*>(my)[0] = make_float4(__uint_as_float(nxt.x << 16), __uint_as_float(nxt.x & 0xFFFF0000u),
+                                                     __uint_as_float(nxt.y << 16), __uint_as_float(nxt.y & 0xFFFF0000u));
+    } else {
+      reinterpret_cast<float4*>(my)[0] = nxt;
+    }
+    __syncthreads();
+    nxt = load(t0 + 16);
+    floatx4 o = floatx4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (ACC) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = t0 + 4 * lk + v;
+        o[v] = row < r1 ? reinterpret_cast<const float*>(dst + row * opitch)[16 * w + lm] : 0.f;
+      }
+    }
+    const float* tl = tile[buf];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) o = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[lm * LP + 4 * ks + lk], tb[ks], o, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = t0 + 4 * lk + v;
+      if (row < r1) {
+        if constexpr (BF) {
+          uint32_t u = __float_as_uint(o[v]);
+          u += 0x7FFFu + ((u >> 16) & 1u);
+          reinterpret_cast<uint16_t*>(dst + row * opitch)[16 * w + lm] = (uint16_t)(u >> 16);
+        } else {
+          reinterpret_cast<float*>(dst + row * opitch)[16 * w + lm] = o[v];
+        }
+      }
+    }
+  }
+}
+
+// Gram partials of wide panels by 64 x 64 output tiles: block (x, y, z) forms tile pair
+// y = (I, J), I <= J, of the W x W Gram of the panel [P | P2] (64-column slices; slices below
+// SPLIT = W1 / 64 come from P, the rest from P2) over row block x, for buffer z of a group.
+// Four waves split the rows in 4-row slabs (MFMA operands as in k_gram_partial); their sums are
+// added in wave order and the tile is written at its place in the block's W x W partial.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_gram_tiles(const void* __restrict__ P, int ld, const float* __restrict__ P2,
+                                                    int ld2, int W1, int W, int64_t rows, int rpb,
+                                                    float* __restrict__ partials, const GroupSeg* segs,
+                                                    int64_t pstride) {
+  constexpr int EB = BF ? 2 : 4;
+  if (segs) {
+    const GroupSeg g = segs[blockIdx.z];
+    if ((int)blockIdx.x >= g.nb) return;
+    P = reinterpret_cast<const char*>(P) + (size_t)g.row0 * ld * EB;
+    rows = g.rows;
+    rpb = g.rpb;
+    partials += (int64_t)blockIdx.z * pstride;
+  }
+  // tile pair y -> (I, J) in row-major order of the upper triangle of the slice grid
+  const int ns = W / 64;
+  int I = 0, rem = blockIdx.y;
+  while (rem >= ns - I) {
+    rem -= ns - I;
+    ++I;
+  }
+  const int J = I + rem;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lrow = lane >> 4, lcol = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = min(rows, r0 + rpb);
+  const int split = W1 / 64;
+  // the two slices' column bases and sources
+  const char* baseI = I < split ? reinterpret_cast<const char*>(P) + (size_t)(64 * I) * EB
+                                : reinterpret_cast<const char*>(P2 + 64 * (I - split));
+  const char* baseJ = J < split ? reinterpret_cast<const char*>(P) + (size_t)(64 * J) * EB
+                                : reinterpret_cast<const char*>(P2 + 64 * (J - split));
+  const bool bfI = BF && I < split, bfJ = BF && J < split;
+  const size_t pitchI = I < split ? (size_t)ld * EB : (size_t)ld2 * 4;
+  const size_t pitchJ = J < split ? (size_t)ld * EB : (size_t)ld2 * 4;
+  auto elem = [](const char* rowp, bool bf, int c) -> float {
+    if (bf) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(rowp)[c] << 16);
+    return reinterpret_cast<const float*>(rowp)[c];
+  };
+  floatx4 acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int D = 2;  // slabs in flight per wave
+  float fi[D][4], fj[D][4];
+  auto load = [&](int dd, int64_t k) {
+    const int64_t row = k + lrow;
+    const bool ok = row < r1;
+    const int64_t rr = ok ? row : 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      fi[dd][s] = ok ? elem(baseI + rr * pitchI, bfI, 16 * s + lcol) : 0.f;
+      fj[dd][s] = ok ? elem(baseJ + rr * pitchJ, bfJ, 16 * s + lcol) : 0.f;
+    }
+  };
+  const int64_t step = 16;  // four waves x 4 rows
+  int64_t k0 = r0 + 4 * wave;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) load(dd, k0 + dd * step);
+  for (; k0 < r1; k0 += D * step) {
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[4 * a + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fi[dd][a], fj[dd][b], acc[4 * a + b], 0, 0, 0);
+      load(dd, k0 + (dd + D) * step);
+    }
+  }
+  __shared__ float red[64 * 64];
+  for (int g2 = 0; g2 < 4; ++g2) {
+    if (wave == g2) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int e = (16 * a + 4 * lrow + v) * 64 + 16 * b + lcol;
+            red[e] = g2 == 0 ? acc[4 * a + b][v] : red[e] + acc[4 * a + b][v];
+          }
+    }
+    __syncthreads();
+  }
+  float* outp = partials + (int64_t)blockIdx.x * W * W;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    outp[(int64_t)(64 * I + i) * W + 64 * J + j] = red[e];
+  }
+}
+
 // W64[i][j] = sum over blocks of the upper-triangle partial (i <= j), mirrored, so W64 is exactly
 // symmetric.  A block owns 16 entries; sixteen thread groups sum interleaved sixteenths of the
 // partials (fixed order) and the group sums are added in group order.
@@ -503,6 +687,17 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
       k_xform_gram<64, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
     else
       k_xform_gram<64, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
+  } else if (L == 128) {
+    // transform in place, then the Gram of the stored result by 64 x 64 tiles
+    const dim3 gx((unsigned)nb, 1, (unsigned)K);
+    const dim3 gg((unsigned)nb, 3, (unsigned)K);
+    if (bf) {
+      k_xform_strips<128, true, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+      k_gram_tiles<true><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+    } else {
+      k_xform_strips<128, false, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+      k_gram_tiles<false><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+    }
   } else {
     return hipErrorInvalidValue;
   }
@@ -522,6 +717,11 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
     case 64:
       k_gram_partial<128, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
       break;
+    case 128:
+      // [P1 | P2] is 256 wide: 4 slices, 10 tile pairs
+      k_gram_tiles<false><<<dim3((unsigned)nb, 10, 1), 256, 0, st>>>(P1, ld1, P2, ld2, L, 2 * L, rows, rpb, partials,
+                                                                     nullptr, 0);
+      break;
     default: return hipErrorInvalidValue;
   }
   k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W, nullptr, 0);
@@ -532,12 +732,23 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
                         int ldo, int64_t rows, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const unsigned grid = grid_for(rows, 4, 8192);
-  if (L == 32)
+  if (L == 32) {
     k_panel_xform2<32><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
-  else if (L == 64)
+  } else if (L == 64) {
     k_panel_xform2<64><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
-  else
+  } else if (L == 128) {
+    // out = P1 T2[0:L] (out may be P1), then out += P2 T2[L:2L]
+    int64_t nb;
+    int rpb;
+    gram_grid(rows, nb, rpb);
+    rpb = (rpb + 15) & ~15;
+    nb = (rows + rpb - 1) / rpb;
+    k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+    k_xform_strips<128, false, true><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+                                                                   nullptr);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

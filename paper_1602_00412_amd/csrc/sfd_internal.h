@@ -7,7 +7,7 @@
 
 namespace sfd {
 
-constexpr int kMaxEll = 56;      // 2*ell <= 112 keeps the FP64 eigensolver in one CU's LDS
+constexpr int kMaxEll = 100;     // the packed 2 ell x 2 ell FP64 Jacobi matrix fills one CU's LDS
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
 constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
 
@@ -116,7 +116,7 @@ struct Schedule {
 // with s.bands > 1 the structure is a banded CSC of s.band_rows columns per band
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
 // Y[r, :] = sum_k val[k] X[idx[k], :] over the structure of schedule s (its entries idx, val);
-// rows of width L (32 or 64) with pitches ldx / ldy in elements; FP32 accumulation.  Panel
+// rows of width L (32, 64 or 128; banded: 32 or 64) with pitches ldx / ldy in elements; FP32 accumulation.  Panel
 // types: F32 -> F32, BF16 -> BF16 and BF16 -> F32.  For a banded schedule (F32 only) r runs over
 // the band_rows output rows and the bands are added in band order by spmm_finish.  This launches
 // the main kernel only; spmm_finish completes the product.
@@ -134,7 +134,7 @@ hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule
 // ---------------------------------------------------------------- dense panels (sfd_dense.hip)
 // partial buffers of the Gram kernels hold at most gram_max_blocks() blocks of 4*L*L floats
 int gram_max_blocks();
-// P <- P T in place (rows x L, L in {32, 64}, FP32 or BF16; T: L x L f32) and W = Gram of the
+// P <- P T in place (rows x L, L in {32, 64, 128}, FP32 or BF16; T: L x L f32) and W = Gram of the
 // result as stored (FP64, L x L)
 hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
                       hipStream_t st);
@@ -171,21 +171,26 @@ hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float*
 // H + k vstride -> M64 / M32 + k L L, sc + k
 hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
                           int64_t wstride, hipStream_t st);
+// (n > 112: work holds eig_work_bytes(n) bytes per buffer, wstride bytes apart)
 hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, hipStream_t st);
+                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st);
+int64_t eig_work_bytes(int n);
 hipError_t ssh_post_group(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
                           DevScalars* sc, int K, int64_t estride, int64_t vstride, hipStream_t st);
 // symmetric eigensolver (cyclic Jacobi, FP64) of the n x n matrix A (pitch lda), n <= 2*kMaxEll:
-// evals descending, evecs column i <-> evals[i], pitch n
-hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, hipStream_t st);
+// evals descending, evecs column i <-> evals[i], pitch n; work: eig_work_bytes(n) bytes (may be
+// null when that is 0)
+hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, void* work, hipStream_t st);
 // SparseShrink tail: from the eigenpairs of P P^T: M = H D (ell x ell, FP64 and f32 L x L),
 // ||B'||^2, S, Delta/2, lambda_ell^2
 hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
                     DevScalars* sc, hipStream_t st);
 // exact buffer: M = I
 hipError_t ssh_identity(int ell, int L, double* M64, float* M32, DevScalars* sc, hipStream_t st);
-// DenseShrink stack Gram: SS = diag(I, M^T) W2 diag(I, M) (2 ell x 2 ell) from W2 (2L x 2L)
-hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, double* SS, hipStream_t st);
+// DenseShrink stack Gram: SS = diag(I, M^T) W2 diag(I, M) (2 ell x 2 ell) from W2 (2L x 2L);
+// scratch: ell x ell doubles
+hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, double* SS, double* scratch,
+                        hipStream_t st);
 // DenseShrink factors: T2 (2L x L, f32) = diag(I, M) U_ell D; lossless: no shift
 hipError_t dsh_post(const double* evals, const double* U, int ell, int L, const double* M64, int lossless,
                     float* T2, DevScalars* sc, hipStream_t st);

@@ -10,7 +10,7 @@ namespace sfd {
 
 namespace {
 
-constexpr int kCholMax = 64;
+constexpr int kCholMax = 128;
 
 // 1/sqrt(x) for x > 0: the hardware estimate refined by one Newton step (relative error
 // about one unit in the last place).
@@ -29,7 +29,11 @@ __device__ inline double rcp_nr(double x) {
   e = fma(-x, y, 1.0);
   return fma(y, e, y);
 }
-constexpr int kEigMax = 2 * kMaxEll;
+// the Jacobi solver with V in LDS takes n <= kEigMax; the one that logs its rotations (V
+// accumulated afterwards) takes n <= kEigMaxLog (the packed upper triangle fills one CU's LDS)
+constexpr int kEigMax = 112;
+constexpr int kEigMaxLog = 2 * kMaxEll;
+constexpr int kJacobiLogSweeps = 30;
 
 __device__ inline double readlane_d(double v, int l) {
   const long long bits = __double_as_longlong(v);
@@ -39,99 +43,137 @@ __device__ inline double readlane_d(double v, int l) {
 }
 
 // Right-looking Cholesky W = R^T R of the n x n leading block with the matrix in registers:
-// thread (w, j) (wave w, lane j) holds column j, rows i = 4 s + w.  One pivot per step: the wave
-// owning row k scales it into row k of R and publishes it in LDS; after one barrier every thread
-// updates its rows below k, reading the published row as LDS broadcasts.  A pivot that has
-// fallen to tau * W_kk (the column's own squared norm) marks column k as dependent on the earlier
-// ones: its row of R is zero.  T = R^{-1} on the kept columns follows by right-looking back
-// substitution, last row first: the wave owning row i finishes row i of T and publishes it; the
-// rows above subtract R[l][i] T[i][:], R[l][i] being lane i's entry of row l (a readlane inside
-// the wave).  Steps are unrolled, so register indices are static; the published rows alternate
-// between two LDS buffers, so one barrier per step suffices.  panel * T then has orthonormal kept
-// columns spanning the panel's numerical column space.
+// thread (w, j) (wave w of NW, lane j) holds columns j + 64 u (u < CPL), rows i = NW s + w.  One
+// pivot per step: the wave owning row k scales it into row k of R and publishes it in LDS; after
+// one barrier every thread updates its rows below k, reading the published row as LDS
+// broadcasts.  A pivot that has fallen to tau * W_kk (the column's own squared norm) marks column
+// k as dependent on the earlier ones: its row of R is zero.  T = R^{-1} on the kept columns
+// follows by right-looking back substitution, last row first: the wave owning row i finishes row
+// i of T and publishes it; the rows above subtract R[l][i] T[i][:], R[l][i] being an entry of
+// row l held in the same wave (a readlane).  Steps are unrolled, so register indices are static;
+// the published rows alternate between two LDS buffers, so one barrier per step suffices.
+// panel * T then has orthonormal kept columns spanning the panel's numerical column space.
 // (a group launch runs one workgroup per buffer k = blockIdx.x on W + k wstride, T + k L L, sc + k)
-__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ W, int ldw, int n, int L, double tau,
-                                                  float* __restrict__ T, DevScalars* sc, int64_t wstride) {
+template <int NW, int CPL>
+__global__ __launch_bounds__(64 * NW) void k_chol_inv(const double* __restrict__ W, int ldw, int n, int L, double tau,
+                                                      float* __restrict__ T, DevScalars* sc, int64_t wstride) {
   W += blockIdx.x * wstride;
   T += (int64_t)blockIdx.x * L * L;
   sc += blockIdx.x;
-  constexpr int S = kCholMax / 4;  // row slots per thread
-  __shared__ double pub[2][kCholMax];
-  __shared__ int ndrop[4];
+  constexpr int NMAX = 64 * CPL;
+  constexpr int S = NMAX / NW;  // row slots per thread
+  __shared__ double pub[2][NMAX];
+  __shared__ int ndrop[NW];
   const int j = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const bool jn = j < n;
-  double a[S], t[S], iv[S];
+  int col[CPL];
+  bool cn[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    col[u] = j + 64 * u;
+    cn[u] = col[u] < n;
+  }
+  double a[S][CPL], t[S][CPL], iv[S], d0[CPL];
   {
     // unconditional loads from clamped indices (all in flight together), then masked
-    const int jc = jn ? j : 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int i = 4 * s + w;
-      const double x = W[(i < n ? i : 0) * ldw + jc];
-      a[s] = (i < n && jn) ? x : 0.0;
-      t[s] = 0.0;
+      const int i = NW * s + w;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const double x = W[(i < n ? i : 0) * ldw + (cn[u] ? col[u] : 0)];
+        a[s][u] = (i < n && cn[u]) ? x : 0.0;
+        t[s][u] = 0.0;
+      }
       iv[s] = 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) d0[u] = W[(cn[u] ? col[u] : 0) * ldw + (cn[u] ? col[u] : 0)];  // W_jj
   }
-  const double d0 = W[(jn ? j : 0) * ldw + (jn ? j : 0)];  // W_jj
   int drops = 0;
+  // step k = NW sk + wk: the slot loop is unrolled (static register indices; the column half of
+  // the pivot, k / 64 = NW sk / 64, is static too because NW divides 64), the wave loop is not
 #pragma unroll
-  for (int k = 0; k < kCholMax; ++k) {
-    if (k >= n) break;
-    const int wk = k & 3, sk = k >> 2;
-    if (w == wk) {
-      const double p = readlane_d(a[sk], k);
-      const double dk = readlane_d(d0, k);
-      const bool keep = (dk > 0.0) && (p > tau * dk);
-      const double is = keep ? rsqrt_nr(p) : 0.0;
-      iv[sk] = is;
-      drops += keep ? 0 : 1;
-      const double r = (j >= k && jn) ? a[sk] * is : 0.0;
-      a[sk] = r;  // row k of R
-      pub[k & 1][j] = r;
-    }
-    __syncthreads();
-    // branch-free update (masked multipliers), so the broadcast reads are issued together
-    const double rkj = pub[k & 1][j];
+  for (int sk = 0; sk < S; ++sk) {
+    const int uk = (NW * sk) / 64;
+    for (int wk = 0; wk < NW; ++wk) {
+      const int k = NW * sk + wk;
+      if (k >= n) break;
+      const int lk = k % 64;
+      if (w == wk) {
+        const double p = readlane_d(a[sk][uk], lk);
+        const double dk = readlane_d(d0[uk], lk);
+        const bool keep = (dk > 0.0) && (p > tau * dk);
+        const double is = keep ? rsqrt_nr(p) : 0.0;
+        iv[sk] = is;
+        drops += keep ? 0 : 1;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s < sk) continue;  // rows 4 s + w <= k
-      const int i = 4 * s + w;
-      const double f = (i > k && i < n) ? pub[k & 1][i] : 0.0;
-      a[s] = fma(-f, rkj, a[s]);
+        for (int u = 0; u < CPL; ++u) {
+          const double r = (col[u] >= k && cn[u]) ? a[sk][u] * is : 0.0;
+          a[sk][u] = r;  // row k of R
+          pub[k & 1][col[u]] = r;
+        }
+      }
+      __syncthreads();
+      // branch-free update (masked multipliers), so the broadcast reads are issued together
+      double rkj[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) rkj[u] = pub[k & 1][col[u]];
+#pragma unroll
+      for (int s = sk; s < S; ++s) {  // rows NW s + w > k
+        const int i = NW * s + w;
+        const double f = (i > k && i < n) ? pub[k & 1][i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) a[s][u] = fma(-f, rkj[u], a[s][u]);
+      }
     }
   }
-  // T = R^{-1}: t[s] accumulates row i = 4 s + w of T (column j)
+  // T = R^{-1}: t[s][u] accumulates row i = NW s + w of T (column col[u]); rows i = NW si + wi
+  // from the last
 #pragma unroll
-  for (int i = kCholMax - 1; i >= 0; --i) {
-    if (i >= n) continue;
-    const int wi = i & 3, si = i >> 2;
-    if (w == wi) {
-      const double x = ((i == j) ? 1.0 : 0.0) - t[si];
-      const double ti = jn ? x * iv[si] : 0.0;
-      t[si] = ti;
-      pub[i & 1][j] = ti;
-    }
-    __syncthreads();
-    const double tij = pub[i & 1][j];
+  for (int si = S - 1; si >= 0; --si) {
+    const int ui = (NW * si) / 64;
+    for (int wi = NW - 1; wi >= 0; --wi) {
+      const int i = NW * si + wi;
+      if (i >= n) continue;
+      const int li = i % 64;
+      if (w == wi) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s > si) continue;  // rows 4 s + w >= i
-      const int l = 4 * s + w;
-      const double r = readlane_d(a[s], i);
-      t[s] = fma(l < i ? r : 0.0, tij, t[s]);
+        for (int u = 0; u < CPL; ++u) {
+          const double x = ((i == col[u]) ? 1.0 : 0.0) - t[si][u];
+          const double ti = cn[u] ? x * iv[si] : 0.0;
+          t[si][u] = ti;
+          pub[i & 1][col[u]] = ti;
+        }
+      }
+      __syncthreads();
+      double tij[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) tij[u] = pub[i & 1][col[u]];
+#pragma unroll
+      for (int s = 0; s <= si; ++s) {  // rows NW s + w <= i
+        const int l = NW * s + w;
+        const double r = readlane_d(a[s][ui], li);  // R[l][i]
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) t[s][u] = fma(l < i ? r : 0.0, tij[u], t[s][u]);
+      }
     }
   }
   // T (L x L, zero-padded)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int i = 4 * s + w;
-    if (i < L && j < L) T[i * L + j] = (i < n && jn) ? (float)t[s] : 0.f;
+    const int i = NW * s + w;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (i < L && col[u] < L) T[i * L + col[u]] = (i < n && cn[u]) ? (float)t[s][u] : 0.f;
   }
   if (j == 0) ndrop[w] = drops;
   __syncthreads();
-  if (threadIdx.x == 0) sc->dropped = ndrop[0] + ndrop[1] + ndrop[2] + ndrop[3];
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int q = 0; q < NW; ++q) tot += ndrop[q];
+    sc->dropped = tot;
+  }
 }
 
 __device__ inline int packed_index(int i, int j, int N) {
@@ -142,6 +184,7 @@ __device__ inline int packed_index(int i, int j, int N) {
 
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxBlocksPerThread = (kEigMax / 2) * (kEigMax / 2 + 1) / 2 / kJacobiThreads + 1;
+constexpr int kJacobiMaxBlocksPerThreadLog = (kEigMaxLog / 2) * (kEigMaxLog / 2 + 1) / 2 / kJacobiThreads + 1;
 
 // Cyclic Jacobi with the round-robin ordering: in each round the N/2 index pairs are disjoint,
 // so every thread updates whole 2 x 2 blocks of A (packed upper triangle in LDS) and pairs of
@@ -293,6 +336,199 @@ __global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __r
   }
 }
 
+// The same cyclic Jacobi for larger n (up to kEigMaxLog): only the packed upper triangle of A
+// stays in LDS; the rotations are not applied to V here but logged, round by round, to global
+// memory (c, s of pair k of round r at log[r P + k]; the pairs follow from r), and k_eig_replay
+// accumulates V from the log afterwards.  Writes the eigenvalues descending (ties by index), the
+// column of V each belongs to (perm) and the number of logged rounds.
+__global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi_log(const double* __restrict__ Ain, int lda, int n,
+                                                        double* __restrict__ evals, double2* __restrict__ rlog,
+                                                        int* __restrict__ perm, int* __restrict__ nrounds,
+                                                        int64_t astride, int64_t estride, int64_t logstride,
+                                                        int64_t pstride) {
+  extern __shared__ double lds[];
+  Ain += blockIdx.x * astride;
+  evals += blockIdx.x * estride;
+  rlog += blockIdx.x * logstride;
+  perm += blockIdx.x * pstride;
+  nrounds += blockIdx.x * pstride;
+  const int N = n + (n & 1);
+  const int P = N / 2;
+  double* A = lds;                    // N (N + 1) / 2
+  double* rc = A + (N * (N + 1)) / 2;  // P
+  double* rs = rc + P;                 // P
+  __shared__ int flag;
+  __shared__ double scale;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N * N; e += kJacobiThreads) {
+    const int i = e / N, j = e - (e / N) * N;
+    if (i <= j) A[packed_index(i, j, N)] = (i < n && j < n) ? Ain[i * lda + j] : 0.0;
+  }
+  int nblk = 0;
+  int bk1[kJacobiMaxBlocksPerThreadLog], bk2[kJacobiMaxBlocksPerThreadLog];
+  {
+    const int total = P * (P + 1) / 2;
+    int k1 = 0, base = 0;
+    for (int b = tid; b < total; b += kJacobiThreads) {
+      while (b >= base + (P - k1)) {
+        base += P - k1;
+        ++k1;
+      }
+#pragma unroll
+      for (int r = 0; r < kJacobiMaxBlocksPerThreadLog; ++r)
+        if (r == nblk) {
+          bk1[r] = k1;
+          bk2[r] = k1 + (b - base);
+        }
+      ++nblk;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, fabs(A[packed_index(i, i, N)]));
+    scale = m;
+  }
+  __syncthreads();
+  const double abs_tol = 1e-18 * scale;
+  int rounds = 0;
+  for (int sweep = 0; sweep < kJacobiLogSweeps; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r, ++rounds) {
+      if (tid < P) {
+        const int k = tid;
+        int p = k == 0 ? 0 : 1 + (k - 1 + r) % (N - 1);
+        int q = 1 + (N - 2 - k + r) % (N - 1);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double app = A[packed_index(p, p, N)], aqq = A[packed_index(q, q, N)];
+        const double apq = A[packed_index(p, q, N)];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+          const double theta = (aqq - app) * rcp_nr(2.0 * apq);
+          const double h2 = fma(theta, theta, 1.0);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + h2 * rsqrt_nr(h2));
+          c = rsqrt_nr(fma(t, t, 1.0));
+          s = t * c;
+          flag = 1;
+        }
+        rc[k] = c;
+        rs[k] = s;
+        rlog[(int64_t)rounds * P + k] = make_double2(c, s);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < kJacobiMaxBlocksPerThreadLog; ++rr) {
+        if (rr >= nblk) break;
+        const int k1 = bk1[rr], k2 = bk2[rr];
+        const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1 = k1 == 0 ? 0 : 1 + (k1 - 1 + r) % (N - 1), q1 = 1 + (N - 2 - k1 + r) % (N - 1);
+        int p2 = k2 == 0 ? 0 : 1 + (k2 - 1 + r) % (N - 1), q2 = 1 + (N - 2 - k2 + r) % (N - 1);
+        if (p1 > q1) {
+          const int t = p1;
+          p1 = q1;
+          q1 = t;
+        }
+        if (p2 > q2) {
+          const int t = p2;
+          p2 = q2;
+          q2 = t;
+        }
+        if (k1 == k2) {
+          const int ipp = packed_index(p1, p1, N), iqq = packed_index(q1, q1, N), ipq = packed_index(p1, q1, N);
+          const double t = s1 / c1;
+          const double apq = A[ipq];
+          A[ipp] = A[ipp] - t * apq;
+          A[iqq] = A[iqq] + t * apq;
+          A[ipq] = 0.0;
+        } else {
+          const int i_pp = packed_index(p1, p2, N), i_pq = packed_index(p1, q2, N);
+          const int i_qp = packed_index(q1, p2, N), i_qq = packed_index(q1, q2, N);
+          const double a_pp = A[i_pp], a_pq = A[i_pq], a_qp = A[i_qp], a_qq = A[i_qq];
+          const double up = c2 * a_pp - s2 * a_pq, uq = s2 * a_pp + c2 * a_pq;
+          const double wp = c2 * a_qp - s2 * a_qq, wq = s2 * a_qp + c2 * a_qq;
+          A[i_pp] = c1 * up - s1 * wp;
+          A[i_pq] = c1 * uq - s1 * wq;
+          A[i_qp] = s1 * up + c1 * wp;
+          A[i_qq] = s1 * uq + c1 * wq;
+        }
+      }
+      __syncthreads();
+    }
+    const int done = (flag == 0);
+    __syncthreads();
+    if (done) break;
+  }
+  if (tid == 0) *nrounds = rounds;
+  for (int i = tid; i < n; i += kJacobiThreads) {
+    const double li = A[packed_index(i, i, N)];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A[packed_index(j, j, N)];
+      rank += (lj > li) || (lj == li && j < i);
+    }
+    evals[rank] = li;
+    perm[rank] = i;
+  }
+}
+
+// V from the rotation log of k_eig_jacobi_log: rows of V are independent under the column
+// rotations, so block x owns kReplayRows rows (in LDS, starting as rows of I) and applies every
+// logged round in order (one barrier per round; rounds whose rotation is the identity are
+// skipped per pair).  evecs column c (pitch n) <- V column perm[c].
+constexpr int kReplayRows = 16;
+__global__ __launch_bounds__(256) void k_eig_replay(const double2* __restrict__ rlog, const int* __restrict__ nrounds,
+                                                    const int* __restrict__ perm, int n,
+                                                    double* __restrict__ evecs, int64_t logstride, int64_t pstride,
+                                                    int64_t evstride) {
+  extern __shared__ double vr[];  // kReplayRows x N
+  rlog += blockIdx.y * logstride;
+  nrounds += blockIdx.y * pstride;
+  perm += blockIdx.y * pstride;
+  evecs += blockIdx.y * evstride;
+  const int N = n + (n & 1);
+  const int P = N / 2;
+  const int row0 = blockIdx.x * kReplayRows;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kReplayRows * N; e += 256) {
+    const int i = e / N, j = e % N;
+    vr[e] = (row0 + i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int R = *nrounds;
+  const int items = kReplayRows * P;
+  for (int r = 0; r < R; ++r) {
+    const int rm = r % (N - 1);
+    for (int it = tid; it < items; it += 256) {
+      const int k = it % P, i = it / P;
+      const double2 cs = rlog[(int64_t)r * P + k];
+      if (cs.y != 0.0) {
+        int p = k == 0 ? 0 : 1 + (k - 1 + rm) % (N - 1);
+        int q = 1 + (N - 2 - k + rm) % (N - 1);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double vp = vr[i * N + p], vq = vr[i * N + q];
+        vr[i * N + p] = cs.x * vp - cs.y * vq;
+        vr[i * N + q] = cs.y * vp + cs.x * vq;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kReplayRows * n; e += 256) {
+    const int i = e / n, c = e % n;
+    const int row = row0 + i;
+    if (row < n) evecs[(int64_t)row * n + c] = vr[i * N + perm[c]];
+  }
+}
+
 // (a group launch: buffer k = blockIdx.x on evals + k estride, H + k vstride, M64 / M32 + k L L,
 // sc + k)
 __global__ __launch_bounds__(256) void k_ssh_post(const double* __restrict__ evals, const double* __restrict__ H,
@@ -347,22 +583,26 @@ __global__ void k_ssh_identity(int ell, int L, double* __restrict__ M64, float* 
   }
 }
 
-// SS = [[W_BB, W_BP M], [M^T W_PB, M^T W_PP M]] with W2 = [[W_BB, W_BP], [W_PB, W_PP]] the Gram
-// of [B^T | P^T] (pitch 2L): the Gram of the stack [B; B'] with B' = M^T P.
-__global__ __launch_bounds__(256) void k_dsh_assemble(const double* __restrict__ W2, int L, int ell,
-                                                      const double* __restrict__ M, double* __restrict__ SS) {
-  __shared__ double Q[kMaxEll][kMaxEll + 1];  // W_PP M
-  const int tid = threadIdx.x;
+// Q = W_PP M (ell x ell, into scratch), W_PP the lower-right block of W2 (pitch 2L)
+__global__ __launch_bounds__(256) void k_dsh_q(const double* __restrict__ W2, int L, int ell,
+                                               const double* __restrict__ M, double* __restrict__ Q) {
   const int ld = 2 * L;
-  const int n = 2 * ell;
-  for (int e = tid; e < ell * ell; e += 256) {
-    int i = e / ell, j = e % ell;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < ell * ell; e += gridDim.x * 256) {
+    const int i = e / ell, j = e % ell;
     double s = 0.0;
     for (int k = 0; k < ell; ++k) s += W2[(L + i) * ld + L + k] * M[k * ell + j];
-    Q[i][j] = s;
+    Q[e] = s;
   }
-  __syncthreads();
-  for (int e = tid; e < ell * ell; e += 256) {
+}
+
+// SS = [[W_BB, W_BP M], [M^T W_PB, M^T W_PP M]] with W2 = [[W_BB, W_BP], [W_PB, W_PP]] the Gram
+// of [B^T | P^T] (pitch 2L): the Gram of the stack [B; B'] with B' = M^T P.  Q = W_PP M.
+__global__ __launch_bounds__(256) void k_dsh_assemble(const double* __restrict__ W2, int L, int ell,
+                                                      const double* __restrict__ M, const double* __restrict__ Q,
+                                                      double* __restrict__ SS) {
+  const int ld = 2 * L;
+  const int n = 2 * ell;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < ell * ell; e += gridDim.x * 256) {
     int i = e / ell, j = e % ell;
     SS[i * n + j] = W2[i * ld + j];
     double s = 0.0;
@@ -371,7 +611,7 @@ __global__ __launch_bounds__(256) void k_dsh_assemble(const double* __restrict__
     SS[(ell + j) * n + i] = s;
     if (i <= j) {
       double t = 0.0;
-      for (int k = 0; k < ell; ++k) t += M[k * ell + i] * Q[k][j];
+      for (int k = 0; k < ell; ++k) t += M[k * ell + i] * Q[k * ell + j];
       SS[(ell + i) * n + ell + j] = t;
       SS[(ell + j) * n + ell + i] = t;
     }
@@ -413,9 +653,13 @@ __global__ __launch_bounds__(256) void k_dsh_post(const double* __restrict__ eva
 
 hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
                     hipStream_t st) {
-  if (ell > kCholMax || L > kCholMax) return hipErrorInvalidValue;
-  k_chol_inv<<<1, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, 0);
-  return hipGetLastError();
+  return chol_inv_group(W, ldw, ell, L, tau, T, sc, 1, 0, st);
+}
+
+// dynamic LDS of the logging Jacobi solver: packed upper A, rotation pair (c, s)
+size_t eig_log_lds_bytes(int n) {
+  const int N = n + (n & 1);
+  return sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N);
 }
 
 // dynamic LDS of the Jacobi solver for an n x n problem: packed upper A, V, pair lists
@@ -425,22 +669,48 @@ size_t eig_lds_bytes(int n) {
   return sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N * N + 2 * P) + sizeof(int) * 2 * P;
 }
 
+int64_t eig_work_bytes(int n) {
+  if (n <= kEigMax) return 0;
+  const int64_t N = n + (n & 1), P = N / 2;
+  const int64_t logb = (int64_t)kJacobiLogSweeps * (N - 1) * P * 16;
+  return logb + (((int64_t)n + 1) * 4 + 255) / 256 * 256;
+}
+
 hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, hipStream_t st) {
-  if (n < 1 || n > kEigMax || K < 1) return hipErrorInvalidValue;
+                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st) {
+  if (n < 1 || n > kEigMaxLog || K < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
-    // allow the largest problem's dynamic LDS (more than the default 64 KiB; gfx950 has 160 KiB)
+    // allow the largest problems' dynamic LDS (more than the default 64 KiB; gfx950 has 160 KiB)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(kEigMax));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_log),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_log_lds_bytes(kEigMaxLog));
     attr_set = true;
   }
-  k_eig_jacobi<<<K, kJacobiThreads, eig_lds_bytes(n), st>>>(A, lda, n, evals, evecs, astride, estride, vstride);
+  if (n <= kEigMax) {
+    k_eig_jacobi<<<K, kJacobiThreads, eig_lds_bytes(n), st>>>(A, lda, n, evals, evecs, astride, estride, vstride);
+    return hipGetLastError();
+  }
+  if (!work) return hipErrorInvalidValue;
+  // workspace of buffer k: rotation log, then n + 1 ints (perm, round count)
+  const int64_t N = n + (n & 1), P = N / 2;
+  const int64_t logb = (int64_t)kJacobiLogSweeps * (N - 1) * P * 16;
+  double2* rlog = reinterpret_cast<double2*>(work);
+  int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + logb);
+  // per-buffer strides in elements of each array (wstride bytes apart)
+  if (wstride % 16 != 0) return hipErrorInvalidValue;
+  const int64_t ls = wstride / 16, ps = wstride / 4;
+  // the round counts of the K buffers sit after each perm (perm + n)
+  k_eig_jacobi_log<<<K, kJacobiThreads, eig_log_lds_bytes(n), st>>>(A, lda, n, evals, rlog, perm, perm + n, astride,
+                                                                    estride, ls, ps);
+  k_eig_replay<<<dim3((unsigned)((n + kReplayRows - 1) / kReplayRows), (unsigned)K), 256,
+                 sizeof(double) * kReplayRows * N, st>>>(rlog, perm + n, perm, n, evecs, ls, ps, vstride);
   return hipGetLastError();
 }
 
-hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, hipStream_t st) {
-  return eig_sym_group(A, lda, n, evals, evecs, 1, 0, 0, 0, st);
+hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, void* work, hipStream_t st) {
+  return eig_sym_group(A, lda, n, evals, evecs, 1, 0, 0, 0, work, eig_work_bytes(n), st);
 }
 
 hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
@@ -452,7 +722,10 @@ hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double
 hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
                           int64_t wstride, hipStream_t st) {
   if (ell > kCholMax || L > kCholMax) return hipErrorInvalidValue;
-  k_chol_inv<<<K, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
+  if (ell <= 64 && L <= 64)
+    k_chol_inv<4, 1><<<K, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
+  else
+    k_chol_inv<16, 2><<<K, 1024, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
   return hipGetLastError();
 }
 
@@ -467,8 +740,11 @@ hipError_t ssh_identity(int ell, int L, double* M64, float* M32, DevScalars* sc,
   return hipGetLastError();
 }
 
-hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, double* SS, hipStream_t st) {
-  k_dsh_assemble<<<1, 256, 0, st>>>(W2, L, ell, M64, SS);
+hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, double* SS, double* scratch,
+                        hipStream_t st) {
+  const unsigned g = (unsigned)std::min(64, (ell * ell + 255) / 256);
+  k_dsh_q<<<g, 256, 0, st>>>(W2, L, ell, M64, scratch);
+  k_dsh_assemble<<<g, 256, 0, st>>>(W2, L, ell, M64, scratch, SS);
   return hipGetLastError();
 }
 

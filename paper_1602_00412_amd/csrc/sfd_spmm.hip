@@ -63,13 +63,18 @@ __device__ inline uint32_t f32_to_bf16(float f) {
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// value of lane J of this lane's LPR-lane group (LPR = 4, 8 or 16; groups never straddle a
-// 32-lane half): ds_swizzle in bit-mask mode, source = (lane & 31 & ~(LPR - 1)) | J
+// value of lane J of this lane's LPR-lane group: for LPR = 4 .. 32 (groups never straddle a
+// 32-lane half) ds_swizzle in bit-mask mode, source = (lane & 31 & ~(LPR - 1)) | J; for LPR = 64
+// (the whole wave) a readlane
 template <int LPR, int J>
 __device__ inline int bcast_i(int v) {
-  static_assert(LPR == 4 || LPR == 8 || LPR == 16, "group width");
-  constexpr int and_mask = 0x1F & ~(LPR - 1);
-  return __builtin_amdgcn_ds_swizzle(v, and_mask | (J << 5));
+  static_assert(LPR == 4 || LPR == 8 || LPR == 16 || LPR == 32 || LPR == 64, "group width");
+  if constexpr (LPR == 64) {
+    return __builtin_amdgcn_readlane(v, J);
+  } else {
+    constexpr int and_mask = 0x1F & ~(LPR - 1);
+    return __builtin_amdgcn_ds_swizzle(v, and_mask | (J << 5));
+  }
 }
 template <int LPR, int J>
 __device__ inline float bcast_f(float v) {
@@ -208,16 +213,9 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
     }
     // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
     const int cnt = min(LPR, dc.z - p);
-    if (cnt > 0) gather_block<LPR, U, 0, BIN>(ci, vi, Xs, lds, sub, acc);
-    if constexpr (LPR > U) {
-      if (cnt > U) gather_block<LPR, U, U, BIN>(ci, vi, Xs, lds, sub, acc);
-    }
-    if constexpr (LPR > 2 * U) {
-      if (cnt > 2 * U) gather_block<LPR, U, 2 * U, BIN>(ci, vi, Xs, lds, sub, acc);
-    }
-    if constexpr (LPR > 3 * U) {
-      if (cnt > 3 * U) gather_block<LPR, U, 3 * U, BIN>(ci, vi, Xs, lds, sub, acc);
-    }
+    [&]<int... b>(std::integer_sequence<int, b...>) {
+      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN>(ci, vi, Xs, lds, sub, acc) : void()), ...);
+    }(std::make_integer_sequence<int, LPR / U>{});
     if (!same) {
       float o[VEC];
 #pragma unroll
@@ -487,37 +485,45 @@ hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void*
                 PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
   if (L == 32) return spmm_l<32>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   if (L == 64) return spmm_l<64>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 128 && s.bands == 1) return spmm_l<128>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   return hipErrorInvalidValue;
 }
 
+namespace {
+
+template <int L>
+void launch_fixup(const Schedule& s, float* partial, void* Y, bool yb, int ldy, hipStream_t st) {
+  if (yb)
+    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+  else
+    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+}
+
+}  // namespace
+
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st) {
-  const float* T = nullptr;
-  if (L != 32 && L != 64) return hipErrorInvalidValue;
-  const int* nlong = s.counters;
-  const unsigned gfix = 256;
   const bool yb = yt == PanelType::BF16;
   if (s.bands > 1) {
-    if (yb) return hipErrorInvalidValue;
+    // long rows fixed up in place in the band buffer, then the bands added
+    if (yb || (L != 32 && L != 64)) return hipErrorInvalidValue;
     const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((s.band_rows + 3) / 4, 8192));
     if (L == 32) {
-      k_spmm_fixup<32, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 32);
-      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, reinterpret_cast<float*>(Y),
-                                            ldy);
+      launch_fixup<32>(s, partial, s.bandbuf, false, 32, st);
+      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, nullptr,
+                                            reinterpret_cast<float*>(Y), ldy);
     } else {
-      k_spmm_fixup<64, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, s.bandbuf, 64);
-      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, T, reinterpret_cast<float*>(Y),
-                                            ldy);
+      launch_fixup<64>(s, partial, s.bandbuf, false, 64, st);
+      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, nullptr,
+                                            reinterpret_cast<float*>(Y), ldy);
     }
   } else if (L == 32) {
-    if (yb)
-      k_spmm_fixup<32, true><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
-    else
-      k_spmm_fixup<32, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    launch_fixup<32>(s, partial, Y, yb, ldy, st);
+  } else if (L == 64) {
+    launch_fixup<64>(s, partial, Y, yb, ldy, st);
+  } else if (L == 128) {
+    launch_fixup<128>(s, partial, Y, yb, ldy, st);
   } else {
-    if (yb)
-      k_spmm_fixup<64, true><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
-    else
-      k_spmm_fixup<64, false><<<gfix, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, nlong, partial, Y, ldy);
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

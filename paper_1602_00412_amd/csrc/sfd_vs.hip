@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_vs_init(const double* __restrict__ part
 __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ part, int nb,
                                                    const double* __restrict__ M, int ell, int L,
                                                    float* __restrict__ c2) {
-  __shared__ double red[16][64];
+  __shared__ double red[16][128];
   part += (int64_t)blockIdx.x * nb * L;
   M += (int64_t)blockIdx.x * L * L;
   c2 += (int64_t)blockIdx.x * 2 * L;
@@ -71,20 +71,23 @@ __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ par
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  {
+  // columns lane and lane + 64 (L <= 128)
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int cc = lane + 64 * h;
+    if (cc >= L) break;
     double s = 0.0;
-    const int col = lane < L ? lane : 0;
     int b = wave;
     for (; b + 48 < nb; b += 64) {
-      const float v0 = part[(int64_t)b * L + col], v1 = part[(int64_t)(b + 16) * L + col];
-      const float v2 = part[(int64_t)(b + 32) * L + col], v3 = part[(int64_t)(b + 48) * L + col];
+      const float v0 = part[(int64_t)b * L + cc], v1 = part[(int64_t)(b + 16) * L + cc];
+      const float v2 = part[(int64_t)(b + 32) * L + cc], v3 = part[(int64_t)(b + 48) * L + cc];
       s += v0;
       s += v1;
       s += v2;
       s += v3;
     }
-    for (; b < nb; b += 16) s += part[(int64_t)b * L + col];
-    red[wave][lane] = s;
+    for (; b < nb; b += 16) s += part[(int64_t)b * L + cc];
+    red[wave][cc] = s;
   }
   __syncthreads();
   if (tid < ell) {

@@ -41,11 +41,11 @@ def _single(sfd, st, d, ell, sid, **opts):
     return sk, sk.sketch().cpu().numpy()
 
 
-@pytest.mark.parametrize("device", [True, False])
-def test_batch_equals_single_streams(gpu_lib, device):
+@pytest.mark.parametrize("device,ell", [(True, 12), (False, 12), (True, 80)])
+def test_batch_equals_single_streams(gpu_lib, device, ell):
     import torch
 
-    d, ell = 300, 12
+    d = 300
     lens = [0, 40, 700, 1500, 9, 620]
     streams = [small_random_csr(n, d, 8, 100 + s, dist="lognormal") for s, n in enumerate(lens)]
     indptr, idx, val, starts = _cat(streams)

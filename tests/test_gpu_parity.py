@@ -220,7 +220,7 @@ def test_errors_leave_state_unchanged(gpu_lib):
         gpu_lib.Sketch(10, 11)
 
 
-@pytest.mark.parametrize("n,d,ell,seed", [(300, 60, 8, 0), (1000, 200, 20, 1), (700, 150, 50, 2)])
+@pytest.mark.parametrize("n,d,ell,seed", [(300, 60, 8, 0), (1000, 200, 20, 1), (700, 150, 50, 2), (1000, 400, 100, 3)])
 def test_fd_mode_matches_fd_oracle(gpu_lib, n, d, ell, seed):
     # FrequentDirections (Sec. 2.1) in batches of ell rows through the same DenseShrink kernels
     from oracle import FDBatchOracle
@@ -259,3 +259,25 @@ def test_sharded_merge_tree_matches_oracle(gpu_lib):
     assert evaluate.gram_distance(B, os_[0].sketch()) <= TOL
     lmin, _ = evaluate.cov_extremes(st.to_scipy(), B)
     assert lmin >= -1e-5 * evaluate.fro2(st.to_scipy())
+
+
+@pytest.mark.parametrize("n,d,ell,lam,seed", [
+    (2500, 400, 100, 25, 6),  # ell = 100: 128-wide panels, 200 x 200 DenseShrink eigensolve
+    (1800, 300, 65, 30, 7),   # ell = 65: the smallest ell on 128-wide panels, ragged tail
+])
+def test_wide_panel_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
+    st = small_random_csr(n, d, lam, seed, dist="lognormal", dup_rate=0.02)
+    o = _oracle(st, ell)
+    sk, B = _gpu_sketch(gpu_lib, st, ell)
+    assert sk.stats()["flushes"] == o.flushes >= 4
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+    assert sk.last_live == o.query()[1]
+
+
+def test_wide_panel_large_buffer_matches_oracle(gpu_lib):
+    # one 3,000-row buffer at ell = 100 with Zipf-long CSC columns, then a pending tail
+    st = small_random_csr(4000, 3000, 40, 8, dist="lognormal")
+    o = _oracle(st, 100)
+    sk, B = _gpu_sketch(gpu_lib, st, 100)
+    assert sk.stats()["flushes"] == o.flushes == 1
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
