@@ -85,6 +85,80 @@ def cpu_baseline(st, ell: int, rows: int):
     }
 
 
+def run_batch_full(args) -> int:
+    """All 4,096 streams of the batching workload (d = 2e4, ell = 32, Poisson(30) entries per row,
+    Zipf(1.1) columns, lognormal(0,1) values, 1e3..1e5 rows per stream), generated on the device,
+    resident in HBM, appended in one batch call and queried; a few streams are checked against
+    single-stream handles (bit for bit) and the shortest one against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1602_00412_amd import sfd
+    from workloads.device import config4_batch
+
+    t0 = time.perf_counter()
+    ptr, idx, val, starts = config4_batch("cuda", streams=args.c4_streams)
+    torch.cuda.synchronize()
+    S, d, ell = len(starts) - 1, 20_000, 32
+    nnz = int(ptr[-1].item())
+    log(f"generated {S} streams, {starts[-1]} rows, {nnz} nnz in {time.perf_counter() - t0:.1f} s")
+    bat = sfd.Batch(S, d, ell)
+    b_out = torch.empty((S, ell, d), dtype=torch.float32, device="cuda")
+    sos = np.arange(S, dtype=np.int32)
+
+    def step():
+        bat.reset()
+        bat.append_csr(sos, starts, ptr, idx, val)
+        bat.sketch(out=b_out)
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / args.steps
+    flushes = sum(bat.stats(s)["flushes"] for s in range(S))
+    log(f"{1e3 * el:.1f} ms/step, {nnz / el:.3e} nnz/s, {flushes} buffer steps")
+    # samples: streams 0, 1 and the shortest against single-stream handles, the shortest against
+    # the oracle
+    from oracle import SFDOracle, evaluate
+
+    lens = np.diff(starts)
+    short = int(np.argmin(lens))
+    bitwise = True
+    for s_ in sorted({0, 1, short}):
+        one = sfd.Sketch(d, ell, 0.25, 0, stream_id=s_)
+        lo, hi = int(starts[s_]), int(starts[s_ + 1])
+        one.append_csr(ptr[lo:hi + 1], idx, val)
+        bitwise = bitwise and torch.equal(one.sketch(), b_out[s_])
+    lo, hi = int(starts[short]), int(starts[short + 1])
+    a, b = int(ptr[lo].item()), int(ptr[hi].item())
+    o = SFDOracle(d, ell, 0.25, 0, stream_id=short, unit_roundoff=2.0 ** -24)
+    o.append_csr((ptr[lo:hi + 1] - a).cpu().numpy(), idx[a:b].cpu().numpy(), val[a:b].cpu().numpy())
+    parity = evaluate.gram_distance(b_out[short].cpu().numpy().astype(np.float64), o.sketch())
+    log(f"samples: bitwise equal to single-stream handles: {bitwise}; stream {short} ({hi - lo} rows) vs oracle "
+        f"{parity:.2e}")
+    line = {
+        "metric": METRIC, "value": nnz / el, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{S} independent zipf-poisson streams, {starts[-1]} rows, d={d}, lambda=30, s=1.1, "
+                               f"lognormal, ell={ell} eps=1/4, generated on the device, one batch call",
+                   "nnz": nnz, "ell": ell, "buffers_per_step": flushes, "parallelism": "1 GPU"},
+        "roofline": None, "cpu_baseline": None,
+        "samples": {"bitwise_equal_to_single_stream": bool(bitwise), "oracle_stream": short,
+                    "oracle_rel_frobenius": parity},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +178,11 @@ def main() -> int:
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workload", choices=["config2", "config5", "config4"], default="config2",
+                    help="config2: the 1e6-row stream at ell=50 (default); config5: the 1e7-row, d=1e6 stream "
+                         "at ell=100, generated on the device, FP32 and BF16; config4: all 4,096 batch streams, "
+                         "generated on the device, one batch call")
+    ap.add_argument("--c4-streams", type=int, default=4096, help="config4: the first this many streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
@@ -130,15 +209,36 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
         return 0
+    if args.workload == "config4":
+        return run_batch_full(args)
     t0 = time.perf_counter()
-    st = config2_plain_fp32(seed=0, n=args.rows)
-    ell = 50
-    log(f"generated n={st.n} d={st.d} nnz={st.nnz} in {time.perf_counter() - t0:.1f} s")
-    indptr = torch.from_numpy(st.indptr).cuda()
-    indices = torch.from_numpy(st.indices).cuda()
-    values = torch.from_numpy(st.values).cuda()
-    out = torch.empty((ell, st.d), dtype=torch.float32, device="cuda")
-    sk = sfd.Sketch(st.d, ell, 0.25, 0, csc_bands=args.csc_bands or None, precision=args.precision)
+    if args.workload == "config5":
+        from workloads.device import config5_large
+        from workloads import CsrStream
+
+        n5 = args.rows if args.rows != 1_000_000 else 10_000_000
+        indptr, indices, values = config5_large("cuda", n=n5)
+        torch.cuda.synchronize()
+        ell = 100
+        # host copy of a prefix: the sample the oracle checks
+        pre = min(args.cpu_sample_rows, n5)
+        ppre = indptr[:pre + 1].cpu().numpy()
+        st = CsrStream(ppre, indices[:int(ppre[-1])].cpu().numpy(), values[:int(ppre[-1])].cpu().numpy(),
+                       1_000_000, dict(name="config5_large prefix"))
+        st_n, st_d, st_nnz = n5, 1_000_000, int(indptr[-1].item())
+        desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=100 s=1.0 lognormal+planted rank-100 (30%), "
+                f"ell={ell} eps=1/4, generated on the device")
+    else:
+        st = config2_plain_fp32(seed=0, n=args.rows)
+        ell = 50
+        indptr = torch.from_numpy(st.indptr).cuda()
+        indices = torch.from_numpy(st.indices).cuda()
+        values = torch.from_numpy(st.values).cuda()
+        st_n, st_d, st_nnz = st.n, st.d, st.nnz
+        desc = f"zipf-poisson stream n={st.n} d={st.d} lambda=50 s=1.0 lognormal+planted rank-20 (30%), ell={ell} eps=1/4"
+    log(f"generated n={st_n} d={st_d} nnz={st_nnz} in {time.perf_counter() - t0:.1f} s")
+    out = torch.empty((ell, st_d), dtype=torch.float32, device="cuda")
+    sk = sfd.Sketch(st_d, ell, 0.25, 0, csc_bands=args.csc_bands or None, precision=args.precision)
 
     def step():
         sk.reset()
@@ -161,7 +261,7 @@ def main() -> int:
         elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
     stats = sk.stats()
-    value = st.nnz / (elapsed / args.steps)
+    value = st_nnz / (elapsed / args.steps)
     log(f"{ms_per_step:.1f} ms/step, {value:.3e} nnz/s, flushes/step={stats['flushes']}")
 
     # Per-kernel-class pass (after the timed steps): one more step with HIP events around every
@@ -195,9 +295,10 @@ def main() -> int:
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
         bfk = args.precision == "bf16"
-        roof["kernel"] = {"spmm_csc": f"k_spmm<64, true, {4 if bfk else 8}, true, {str(bfk).lower()}, "
+        Lw = 64 if ell <= 64 else 128
+        roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {str(bfk).lower()}, "
                                       f"{str(bfk).lower()}> (X = A'^T Y, CSC)",
-                          "spmm_csr": f"k_spmm<64, true, {4 if bfk else 8}, false, {str(bfk).lower()}, "
+                          "spmm_csr": f"k_spmm<{Lw}, {4 if bfk else 8}, false, {str(bfk).lower()}, "
                                       f"{str(bfk).lower()}> (Y = A' X, CSR)"}.get(dom, dom)
         roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["calls"]
         roof["avg_launch_us"] = avg_s * 1e6
@@ -210,7 +311,7 @@ def main() -> int:
     forms = {}
     sk_bf = None
     if not args.no_forms and not args.profile_only and args.precision == "fp32":
-        sk_bf = sfd.Sketch(st.d, ell, 0.25, 0, precision="bf16")
+        sk_bf = sfd.Sketch(st_d, ell, 0.25, 0, precision="bf16")
         out_bf = torch.empty_like(out)
 
         def step_bf():
@@ -228,7 +329,7 @@ def main() -> int:
         el_bf = time.perf_counter() - t_start
         from oracle import evaluate as _ev
 
-        forms["bf16"] = {"value": st.nnz / (el_bf / args.steps), "unit": "nnz/s",
+        forms["bf16"] = {"value": st_nnz / (el_bf / args.steps), "unit": "nnz/s",
                          "ms_per_step": 1e3 * el_bf / args.steps,
                          "speedup_vs_fp32": elapsed / el_bf,
                          "rel_frobenius_vs_fp32": _ev.gram_distance(out_bf.cpu().numpy().astype(np.float64),
@@ -239,7 +340,8 @@ def main() -> int:
     # The batched form: the first `batch_streams` streams of the 4,096-stream recipe (d = 2e4,
     # ell = 32, log-uniform lengths 1e3..1e5 rows), resident in HBM, appended in one call and
     # queried; compared with the same streams fed one at a time through a single-stream handle.
-    if not args.no_forms and not args.profile_only and args.precision == "fp32" and args.batch_streams > 0:
+    if (not args.no_forms and not args.profile_only and args.precision == "fp32" and args.batch_streams > 0
+            and args.workload == "config2"):
         from workloads import config4_batch_stream
 
         t = time.perf_counter()
@@ -300,7 +402,23 @@ def main() -> int:
 
     cpu = None
     parity = None
-    if not args.no_cpu_baseline:
+    if args.workload == "config5":
+        # The oracle at d = 1e6 costs a 1e6 x 100 Householder QR per product (about a second
+        # each), so it checks the device path on the prefix with q = 3 (the same kernels and
+        # shapes; the q of the method is only shortened) and is not timed as a baseline.
+        from oracle import SFDOracle, evaluate
+
+        t = time.perf_counter()
+        o = SFDOracle(st.d, ell, 0.25, 0, q=3, unit_roundoff=2.0 ** -24)
+        o.append_csr(st.indptr, st.indices, st.values)
+        Bo = o.sketch()
+        sk2 = sfd.Sketch(st.d, ell, 0.25, 0, q=3)
+        sk2.append_csr(torch.from_numpy(st.indptr).cuda(), torch.from_numpy(st.indices).cuda(),
+                       torch.from_numpy(st.values).cuda())
+        parity = evaluate.gram_distance(sk2.sketch().cpu().numpy().astype(np.float64), Bo)
+        log(f"prefix parity ({st.n} rows, q=3) vs oracle: {parity:.2e} in {time.perf_counter() - t:.1f} s")
+        cpu = None
+    elif not args.no_cpu_baseline:
         t = time.perf_counter()
         sub, B_oracle, cpu = cpu_baseline(st, ell, min(args.cpu_sample_rows, st.n))
         log(f"cpu baseline: {cpu['value']:.3e} nnz/s in {time.perf_counter() - t:.1f} s")
@@ -327,9 +445,8 @@ def main() -> int:
         "dtype": "f32" if args.precision == "fp32" else "bf16 panels, f32 accumulate",
         "data": "synthetic",
         "config": {
-            "workload": f"zipf-poisson stream n={st.n} d={st.d} lambda=50 s=1.0 lognormal+planted rank-20 (30%), "
-                        f"ell={ell} eps=1/4 fp32",
-            "nnz": st.nnz,
+            "workload": desc,
+            "nnz": st_nnz,
             "ell": ell,
             "buffers_per_step": stats["flushes"],
             "q_last": stats["last_q"],
