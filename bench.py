@@ -32,8 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # product's kernels.  Valid only for the kernel source it was taken with (sha256 prefix).
 MEASURED_TRAFFIC = {
     # class: (bytes per call, source file, sha256 prefix of that file, summary under profiles/)
-    "spmm_csc": (1.2201e+09, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "518854583c222958",
-                 "profiles/sfd_spmm_csc_2e5rows_hbm_traffic.txt"),
+    "spmm_csc": (1.2191e+09, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "7cec4e3fc9376d98",
+                 "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
 }
 
 
