@@ -159,6 +159,61 @@ def run_batch_full(args) -> int:
     return 0
 
 
+def run_paper_sweep(args) -> int:
+    """The paper's own synthetic workload (Sec. 4: n = 10,000 rows of z distinct +-1 entries,
+    90% of them in the first 1.5 z columns, ell = 50) swept over z (d = 1,000) and over d
+    (z = 100), with three algorithms on the GPU: SFD (Alg 2 with BoostedSparseShrink), SFD with
+    SparseShrink alone (VerifySpectral off, as in the paper's experiments) and FrequentDirections
+    (Sec. 2.1, DenseShrink of ell-row batches).  Reports ms per pass and cov-err (Sec. 4) of each;
+    the paper reports SFD faster than FD on sparse inputs and not on dense ones."""
+    import numpy as np
+    import torch
+
+    from oracle import evaluate
+    from paper_1602_00412_amd import sfd
+    from workloads import paper_head_tail
+
+    n, ell = 10_000, 50
+    points = [(1000, z) for z in (5, 10, 20, 50, 100, 200, 500)] + [(d, 100) for d in (2000, 4000, 6000)]
+    algos = (("sfd", {}), ("sfd_noverify", {"verify": 0}), ("fd", {"algorithm": "fd"}))
+    rows = []
+    for d, z in points:
+        st = paper_head_tail(n=n, d=d, z=z)
+        A = st.to_scipy()
+        ptr = torch.from_numpy(st.indptr).cuda()
+        idx = torch.from_numpy(st.indices).cuda()
+        val = torch.from_numpy(st.values).cuda()
+        out = torch.empty((ell, d), dtype=torch.float32, device="cuda")
+        rec = {"d": d, "z": z, "nnz": st.nnz}
+        for name, opts in algos:
+            sk = sfd.Sketch(d, ell, 0.25, 0, **opts)
+
+            def step():
+                sk.reset()
+                sk.append_csr(ptr, idx, val)
+                sk.sketch(out=out)
+
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t) / args.steps
+            rec[name] = {"ms": ms, "cov_err": evaluate.cov_err(A, out.cpu().numpy().astype(np.float64)),
+                         "buffers": sk.stats()["flushes"]}
+            sk.close()
+        rec["fd_over_sfd_time"] = rec["fd"]["ms"] / rec["sfd_noverify"]["ms"]
+        rows.append(rec)
+        log(f"d={d} z={z}: sfd {rec['sfd']['ms']:.1f} ms, sfd w/o verify {rec['sfd_noverify']['ms']:.1f} ms, "
+            f"fd {rec['fd']['ms']:.1f} ms; cov-err {rec['sfd']['cov_err']:.4f} / {rec['sfd_noverify']['cov_err']:.4f} "
+            f"/ {rec['fd']['cov_err']:.4f}")
+    print(json.dumps({"workload": f"paper head/tail generator, n={n}, ell={ell}, eps=1/4", "steps": args.steps,
+                      "warmup": args.warmup, "points": rows}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,10 +233,12 @@ def main() -> int:
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", choices=["config2", "config5", "config4"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "config5", "config4", "paper"], default="config2",
                     help="config2: the 1e6-row stream at ell=50 (default); config5: the 1e7-row, d=1e6 stream "
                          "at ell=100, generated on the device, FP32 and BF16; config4: all 4,096 batch streams, "
-                         "generated on the device, one batch call")
+                         "generated on the device, one batch call; paper: the paper's head/tail +-1 generator "
+                         "swept over entries per row and over d, SFD (with and without VerifySpectral) "
+                         "against FrequentDirections on the GPU")
     ap.add_argument("--c4-streams", type=int, default=4096, help="config4: the first this many streams")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -211,6 +268,8 @@ def main() -> int:
         return 0
     if args.workload == "config4":
         return run_batch_full(args)
+    if args.workload == "paper":
+        return run_paper_sweep(args)
     t0 = time.perf_counter()
     if args.workload == "config5":
         from workloads.device import config5_large
@@ -304,6 +363,16 @@ def main() -> int:
         roof["avg_launch_us"] = avg_s * 1e6
         roof["launches"] = p["calls"]
         roof["timing"] = "HIP events on the lane stream, one-lane pass after the timed steps"
+        g = prof.get("gram")
+        if g and g["calls"]:
+            # the panel transform + Gram class on MFMA: achieved FP32 TFLOP/s against the peak and
+            # against min(peak, intensity x HBM bandwidth) for its algorithmic bytes
+            tf = g["flops"] / (g["ms"] / 1e3) / 1e12
+            ai = g["flops"] / max(g["bytes"], 1.0)
+            attainable = min(FP32_MFMA_PEAK_TFS, ai * HBM_PEAK_GBS / 1e3)
+            roof["gram_mfma"] = {"achieved_tflops": tf, "peak_tflops": FP32_MFMA_PEAK_TFS,
+                                 "frac_of_peak": tf / FP32_MFMA_PEAK_TFS, "flop_per_byte": ai,
+                                 "attainable_tflops": attainable, "frac_of_attainable": tf / attainable}
         log(f"roofline: {dom} {roof['avg_launch_us']:.1f} us/launch, {achieved:.1f} {roof['unit']}")
 
     # The BF16 precision form on the same resident stream: same q, same random blocks, panels of
@@ -450,6 +519,8 @@ def main() -> int:
             "ell": ell,
             "buffers_per_step": stats["flushes"],
             "q_last": stats["last_q"],
+            "attempts_per_step": stats["attempts"],
+            "vs_rejects_per_step": stats["vs_rejects"],
             "parallelism": "1 GPU",
         },
         "roofline": roof,

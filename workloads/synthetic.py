@@ -238,25 +238,32 @@ def config4_batch_stream(stream_id: int, seed: int = 0, n: int | None = None) ->
 
 def paper_head_tail(n: int = 10_000, d: int = 1000, z: int = 100, seed: int = 0) -> CsrStream:
     """The paper's synthetic generator (Sec. 4, "Datasets"): each row gets exactly z distinct
-    non-zeros of value +1 or -1; each placement picks the head (first 1.5 z columns) with
-    probability 0.9, else the tail, and a column uniformly inside it, without duplicates."""
+    non-zeros of value +1 or -1; each placement picks the head (the first 1.5 z columns) with
+    probability 0.9, else the tail, and a column uniformly inside it; a placement that repeats a
+    column of the row is drawn again (rows are generated with vectorised draws: the first z
+    distinct placements of each row's draw sequence)."""
     rng = np.random.default_rng([seed, 0x4EAD])
-    head = int(1.5 * z)
-    indptr = np.arange(n + 1, dtype=np.int64) * z
-    idx = np.empty(n * z, dtype=np.int32)
-    for i in range(n):
-        chosen: list[int] = []
-        seen = set()
-        while len(chosen) < z:
-            if rng.random() < 0.9:
-                c = int(rng.integers(0, head))
-            else:
-                c = int(rng.integers(head, d))
-            if c not in seen:
-                seen.add(c)
-                chosen.append(c)
-        idx[i * z:(i + 1) * z] = np.sort(chosen)
-    vals = rng.choice(np.array([-1.0, 1.0], dtype=np.float32), size=n * z)
+    head = min(int(1.5 * z), d)
+    k = np.full(n, min(z, d), dtype=np.int64)
+    cols = [None] * n
+    todo = np.arange(n)
+    W = 2 * z + 16
+    while todo.size:
+        R = todo.size
+        in_head = rng.random((R, W)) < 0.9
+        if head >= d:
+            in_head[:] = True
+        hc = rng.integers(0, head, size=(R, W))
+        tc = rng.integers(head, d, size=(R, W)) if head < d else hc
+        cand = np.where(in_head, hc, tc)
+        keep, enough = _first_distinct(cand, k[todo])
+        for j in np.nonzero(enough)[0]:
+            cols[todo[j]] = np.sort(cand[j][keep[j]])
+        todo = todo[~enough]
+        W *= 2
+    indptr = np.arange(n + 1, dtype=np.int64) * int(k[0])
+    idx = np.concatenate(cols).astype(np.int32) if n else np.zeros(0, np.int32)
+    vals = rng.choice(np.array([-1.0, 1.0], dtype=np.float32), size=len(idx))
     return CsrStream(indptr, idx, vals, d, dict(name="paper_head_tail", ell=50, k=10, seed=seed, z=z))
 
 
