@@ -233,8 +233,10 @@ def main() -> int:
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", choices=["config2", "config5", "config4", "paper"], default="config2",
-                    help="config2: the 1e6-row stream at ell=50 (default); config5: the 1e7-row, d=1e6 stream "
+    ap.add_argument("--workload", choices=["config2", "config3", "config5", "config4", "paper"], default="config2",
+                    help="config2: the 1e6-row stream at ell=50 (default); config3: the 2e6-row, d=5e4 stream "
+                         "at ell=200 (N(0,1) values), generated on the device, FP32 and BF16; "
+                         "config5: the 1e7-row, d=1e6 stream "
                          "at ell=100, generated on the device, FP32 and BF16; config4: all 4,096 batch streams, "
                          "generated on the device, one batch call; paper: the paper's head/tail +-1 generator "
                          "swept over entries per row and over d, SFD (with and without VerifySpectral) "
@@ -271,22 +273,28 @@ def main() -> int:
     if args.workload == "paper":
         return run_paper_sweep(args)
     t0 = time.perf_counter()
-    if args.workload == "config5":
-        from workloads.device import config5_large
+    if args.workload in ("config5", "config3"):
+        from workloads.device import config3_precision, config5_large
         from workloads import CsrStream
 
-        n5 = args.rows if args.rows != 1_000_000 else 10_000_000
-        indptr, indices, values = config5_large("cuda", n=n5)
+        big = args.workload == "config5"
+        n5 = args.rows if args.rows != 1_000_000 else (10_000_000 if big else 2_000_000)
+        d5 = 1_000_000 if big else 50_000
+        indptr, indices, values = (config5_large if big else config3_precision)("cuda", n=n5)
         torch.cuda.synchronize()
-        ell = 100
+        ell = 100 if big else 200
         # host copy of a prefix: the sample the oracle checks
         pre = min(args.cpu_sample_rows, n5)
         ppre = indptr[:pre + 1].cpu().numpy()
         st = CsrStream(ppre, indices[:int(ppre[-1])].cpu().numpy(), values[:int(ppre[-1])].cpu().numpy(),
-                       1_000_000, dict(name="config5_large prefix"))
-        st_n, st_d, st_nnz = n5, 1_000_000, int(indptr[-1].item())
-        desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=100 s=1.0 lognormal+planted rank-100 (30%), "
-                f"ell={ell} eps=1/4, generated on the device")
+                       d5, dict(name=f"{args.workload} prefix"))
+        st_n, st_d, st_nnz = n5, d5, int(indptr[-1].item())
+        if big:
+            desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=100 s=1.0 lognormal+planted rank-100 (30%), "
+                    f"ell={ell} eps=1/4, generated on the device")
+        else:
+            desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=80 s=1.1 N(0,1)+planted rank-50 (sigma_i=1/i), "
+                    f"ell={ell} eps=1/4, generated on the device")
     else:
         st = config2_plain_fp32(seed=0, n=args.rows)
         ell = 50
@@ -354,7 +362,7 @@ def main() -> int:
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
         bfk = args.precision == "bf16"
-        Lw = 64 if ell <= 64 else 128
+        Lw = 32 if ell <= 32 else 64 if ell <= 64 else 128 if ell <= 128 else 256
         roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {str(bfk).lower()}, "
                                       f"{str(bfk).lower()}> (X = A'^T Y, CSC)",
                           "spmm_csr": f"k_spmm<{Lw}, {4 if bfk else 8}, false, {str(bfk).lower()}, "
@@ -471,9 +479,9 @@ def main() -> int:
 
     cpu = None
     parity = None
-    if args.workload == "config5":
-        # The oracle at d = 1e6 costs a 1e6 x 100 Householder QR per product (about a second
-        # each), so it checks the device path on the prefix with q = 3 (the same kernels and
+    if args.workload in ("config5", "config3"):
+        # The oracle costs a d x ell Householder QR per product (about a second each at d = 1e6,
+        # ell = 100), so it checks the device path on the prefix with q = 3 (the same kernels and
         # shapes; the q of the method is only shortened) and is not timed as a baseline.
         from oracle import SFDOracle, evaluate
 

@@ -19,7 +19,7 @@
  *    every call but sfd_reset/sfd_destroy/sfd_get_stats returns SFD_E_STATE.
  *  - Threads: a handle must not be used by two threads at once.  Different handles are
  *    independent.
- *  - Sizes: 1 <= ell <= min(d, 100) in this build; ell*d + d < 2^31 (int32 buffer indices).
+ *  - Sizes: 1 <= ell <= min(d, 256) in this build; ell*d + d < 2^31 (int32 buffer indices).
  *  - Streams: an sfd_t is one stream; an sfd_batch_t holds many (see the end of this file).
  */
 #ifndef SFD_H
@@ -128,7 +128,7 @@ typedef struct {
  * eps is the accuracy of SimultaneousIteration (Alg 1; SparseShrink uses 1/4) and sets the
  * power count q = ceil(ln(m/eps)/eps) for an m-row buffer; seed is the first word of the
  * random key.  B starts at 0 (Alg 2).  Allocates all device memory the handle uses.
- * Errors: SFD_E_ARG (ell < 1, ell > min(d, 100), ell*d + d >= 2^31, eps not in (0,1),
+ * Errors: SFD_E_ARG (ell < 1, ell > min(d, 256), ell*d + d >= 2^31, eps not in (0,1),
  * out == NULL), SFD_E_NOMEM, SFD_E_DEVICE. */
 int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t **out);
 

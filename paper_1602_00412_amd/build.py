@@ -35,6 +35,7 @@ SOURCES = [
     "sfd_spmm.hip",
     "sfd_dense.hip",
     "sfd_small.hip",
+    "sfd_eig_tri.hip",
     "sfd_vs.hip",
     "sfd_api.cpp",
 ]

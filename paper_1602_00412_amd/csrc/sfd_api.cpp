@@ -2,7 +2,7 @@
 // conventions in include/sfd.h).
 //
 // Device state of a handle: per stream (one for sfd_t, nstreams for sfd_batch_t) the sketch B
-// stored transposed as a d x L panel (row-major, L = 32, 64 or 128 >= ell, zero-padded) and the
+// stored transposed as a d x L panel (row-major, L = 32, 64, 128 or 256 >= ell, zero-padded) and the
 // pending buffer A' as CSR; and up to kLanes "lanes" shared by the streams.
 // A lane is the workspace of one buffer step with its own HIP stream: a CSR view of the buffer,
 // its CSC copy and chunk schedules, the SimultaneousIteration panels X (d x L) and Y (m x L),
@@ -80,7 +80,8 @@ struct Lane {
   float* gram_part = nullptr;
   double *W = nullptr, *W2 = nullptr;
   double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
-  char* eig_work = nullptr;  // the 2 ell x 2 ell eigensolver's rotation log (2 ell > 112)
+  char* eig_work = nullptr;  // workspace of the larger eigensolves (ell or 2 ell > 112)
+  double* cholw = nullptr;   // the Cholesky factor between its two passes (ell > 128)
   float *M32 = nullptr, *T = nullptr, *T2 = nullptr;
   float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
   double* vs_npart = nullptr;
@@ -111,6 +112,8 @@ struct GroupWork {
   float* T = nullptr;
   double *evals = nullptr, *evecs = nullptr, *M64 = nullptr;
   float* M32 = nullptr;
+  char* eig_work = nullptr;  // per buffer: workspace of the ell x ell eigensolve (ell > 112)
+  double* cholw = nullptr;   // per buffer: the Cholesky factor between its passes (ell > 128)
   DevScalars* sc = nullptr;
   DevScalars* sc_host = nullptr;  // pinned
   GroupSeg *segs_x = nullptr, *segs_y = nullptr;
@@ -356,7 +359,8 @@ int alloc_state(sfd_t* h) {
     ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
          dalloc(h, &ln.W2, 4 * L * L);
     ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
-    ok = ok && dalloc(h, &ln.eig_work, eig_work_bytes(2 * h->ell));
+    ok = ok && dalloc(h, &ln.eig_work, std::max(eig_work_bytes(h->ell), eig_work_bytes(2 * h->ell)));
+    ok = ok && dalloc(h, &ln.cholw, chol_work_doubles(h->L));
     ok = ok && dalloc(h, &ln.M64, L * L) && dalloc(h, &ln.M32, L * L) && dalloc(h, &ln.T, L * L) &&
          dalloc(h, &ln.T2, 2 * L * L);
     ok = ok && dalloc(h, &ln.vs_w, d) && dalloc(h, &ln.vs_wraw, d) && dalloc(h, &ln.vs_z, d) &&
@@ -432,7 +436,7 @@ int orth_out(sfd_t* h, Lane& ln, void* panel, PanelType pt, int64_t rows) {
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_CHOL, 8.0 * ell * ell, ell * ell * ell, 1);
-    CK(chol_inv(ln.W, L, h->ell, L, kCholDropTol, ln.T, ln.sc, ln.st));
+    CK(chol_inv(ln.W, L, h->ell, L, kCholDropTol, ln.T, ln.sc, ln.cholw, ln.st));
   }
   return SFD_OK;
 }
@@ -699,6 +703,8 @@ int alloc_group(sfd_t* h, int kmax) {
   ok = ok && dalloc(h, &g.W, kmax * L * L) && dalloc(h, &g.Wp, kmax * L * L) && dalloc(h, &g.T, kmax * L * L);
   ok = ok && dalloc(h, &g.evals, kmax * 2 * L) && dalloc(h, &g.evecs, kmax * 4 * L * L);
   ok = ok && dalloc(h, &g.M64, kmax * L * L) && dalloc(h, &g.M32, kmax * L * L) && dalloc(h, &g.sc, kmax);
+  ok = ok && dalloc(h, &g.eig_work, kmax * eig_work_bytes(h->ell)) &&
+       dalloc(h, &g.cholw, kmax * chol_work_doubles((int)L));
   ok = ok && dalloc(h, &g.segs_x, kmax) && dalloc(h, &g.segs_y, kmax) && dalloc(h, &g.seg_rows, kmax + 1) &&
        dalloc(h, &g.tsteps, kmax);
   ok = ok && dalloc(h, &g.vs_w, kmax * d) && dalloc(h, &g.vs_wraw, kmax * d) && dalloc(h, &g.vs_z, g.cap_rows) &&
@@ -869,12 +875,12 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
   }
   CK(set_identity(g.T, L, K, st));
   CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
-  CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+  CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
   for (int iter = 0; iter <= qmax; ++iter) {
     CK(spmm(g.sr, g.colidx, g.val, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, st));
     CK(spmm_finish(g.sr, g.partial, g.Y, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.Y, PanelType::F32, L, 0, 0, nby, g.segs_y, K, L, g.T, g.gram_part, g.W, st));
-    CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+    CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
     CK(spmm(g.scs, g.cscrow, g.cscval, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, st));
     CK(spmm_finish(g.scs, g.partial, g.X, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
@@ -884,10 +890,10 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
       CK(hipMemcpyAsync(g.Pt + k * d * L, g.X + k * d * L, sizeof(float) * d * L, hipMemcpyDeviceToDevice, st));
       CK(hipMemcpyAsync(g.Wp + k * LL, g.W + k * LL, sizeof(double) * LL, hipMemcpyDeviceToDevice, st));
     }
-    if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, st));
+    if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
   }
   // ---- SparseShrink (Alg 3): eig of P P^T, M = H D, the scalars of Alg 4
-  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, nullptr, 0, st));
+  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, g.eig_work, eig_work_bytes(ell), st));
   CK(ssh_post_group(g.evals, g.evecs, ell, L, kAlpha, g.M64, g.M32, g.sc, K, 2 * L, 4 * LL, st));
   CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1254,7 +1260,7 @@ int create_handle(int64_t d, int32_t ell, double eps, uint64_t seed, int nstream
   if (!h) return SFD_E_NOMEM;
   h->d = d;
   h->ell = ell;
-  h->L = ell <= 32 ? 32 : ell <= 64 ? 64 : 128;
+  h->L = ell <= 32 ? 32 : ell <= 64 ? 64 : ell <= 128 ? 128 : 256;
   h->eps = eps;
   h->seed = seed;
   h->lanes_alloc = lanes;

@@ -3,7 +3,7 @@
 // transforms panel * T, the panel-transpose matrix-vector product of VerifySpectral, and the
 // counter-based start block G of Alg 1.
 //
-// Panels are row-major and tall (d x L or m x L, L = 32, 64 or 128 >= ell, zero-padded), so
+// Panels are row-major and tall (d x L or m x L, L = 32, 64, 128 or 256 >= ell, zero-padded), so
 // every Gram has its contraction along the tall axis.
 #include <type_traits>
 #include <utility>
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   }
 }
 
-// Wide panels (L = 128): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), FP32 or BF16 panels,
+// Wide panels (L = 128 or 256): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), FP32 or BF16 panels,
 // and with ACC out <- out + Pin T (FP32 only; used for [P1 | P2] T2 as two passes).  Wave w of a
 // block computes output strip w (columns 16 w .. 16 w + 15) and keeps its strip of T as MFMA B
 // operands in registers (lane l: T[4 ks + l / 16][16 w + l % 16]); the 16-row input tile is loaded
@@ -286,7 +286,7 @@ template <int L, bool BF, bool ACC>
 __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi, void* out, int ldo, int64_t rows,
                                                         int rpb, const float* __restrict__ T, int ldt,
                                                         const GroupSeg* segs) {
-  static_assert(L == 128, "strip-per-wave transform");
+  static_assert(L == 128 || L == 256, "strip-per-wave transform");
   static_assert(!(BF && ACC), "accumulation is FP32 only");
   constexpr int NT = L * 4;  // threads: one wave per 16-column strip
   constexpr int KS = L / 4;
@@ -535,11 +535,12 @@ __global__ __launch_bounds__(256) void k_panel_xform2(const float* P1, int ld1, 
 
 // Groups: buffer k = blockIdx.y has panel P + k rows ld, vector y + k rows, scale
 // scale_ptr + k sstride and partials part + k gridDim.x L.
+template <int CPL>
 __global__ __launch_bounds__(256) void k_panel_gemv_t(const float* __restrict__ P, int ld, int L, int64_t rows,
                                                       int rpb, const float* __restrict__ y,
                                                       const double* __restrict__ scale_ptr, float* __restrict__ part,
                                                       int sstride) {
-  __shared__ float red[4][128];
+  __shared__ float red[4][64 * CPL];
   {
     const int64_t k = blockIdx.y;
     P += k * rows * ld;
@@ -551,37 +552,40 @@ __global__ __launch_bounds__(256) void k_panel_gemv_t(const float* __restrict__ 
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = min(rows, r0 + rpb);
-  float a0 = 0.f, a1 = 0.f;
-  const int c0 = lane < L ? lane : 0;
-  const int c1 = 64 + lane < L ? 64 + lane : 0;
-  const float m0 = lane < L ? 1.f : 0.f, m1 = 64 + lane < L ? 1.f : 0.f;
+  float a[CPL], m[CPL];
+  int c[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    a[q] = 0.f;
+    c[q] = 64 * q + lane < L ? 64 * q + lane : 0;
+    m[q] = 64 * q + lane < L ? 1.f : 0.f;
+  }
   int64_t r = r0 + wave;
   for (; r + 12 < r1; r += 16) {
-    float yv[4], p0[4], p1[4];
+    float yv[4], pv[4][CPL];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       yv[u] = y[r + 4 * u];
-      p0[u] = P[(r + 4 * u) * ld + c0];
-      p1[u] = P[(r + 4 * u) * ld + c1];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) pv[u][q] = P[(r + 4 * u) * ld + c[q]];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a0 = fmaf(p0[u] * m0, yv[u], a0);
-      a1 = fmaf(p1[u] * m1, yv[u], a1);
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) a[q] = fmaf(pv[u][q] * m[q], yv[u], a[q]);
   }
   for (; r < r1; r += 4) {
     const float yv = y[r];
-    a0 = fmaf(P[r * ld + c0] * m0, yv, a0);
-    a1 = fmaf(P[r * ld + c1] * m1, yv, a1);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) a[q] = fmaf(P[r * ld + c[q]] * m[q], yv, a[q]);
   }
-  red[wave][lane] = a0;
-  red[wave][64 + lane] = a1;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) red[wave][64 * q + lane] = a[q];
   __syncthreads();
-  if (threadIdx.x < 128 && threadIdx.x < L) {
-    float s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  for (int col = threadIdx.x; col < 64 * CPL && col < L; col += 256) {
+    float s = red[0][col] + red[1][col] + red[2][col] + red[3][col];
     float sc = scale_ptr ? (float)(*scale_ptr) : 1.f;
-    part[(int64_t)blockIdx.x * L + threadIdx.x] = s * sc;
+    part[(int64_t)blockIdx.x * L + col] = s * sc;
   }
 }
 
@@ -687,17 +691,26 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
       k_xform_gram<64, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
     else
       k_xform_gram<64, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
-  } else if (L == 128) {
+  } else if (L == 128 || L == 256) {
     // transform in place, then the Gram of the stored result by 64 x 64 tiles
     const dim3 gx((unsigned)nb, 1, (unsigned)K);
-    const dim3 gg((unsigned)nb, 3, (unsigned)K);
-    if (bf) {
-      k_xform_strips<128, true, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-      k_gram_tiles<true><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+    const int ns = L / 64;
+    const dim3 gg((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), (unsigned)K);
+    if (L == 128) {
+      if (bf)
+        k_xform_strips<128, true, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+      else
+        k_xform_strips<128, false, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
     } else {
-      k_xform_strips<128, false, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-      k_gram_tiles<false><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+      if (bf)
+        k_xform_strips<256, true, false><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+      else
+        k_xform_strips<256, false, false><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
     }
+    if (bf)
+      k_gram_tiles<true><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+    else
+      k_gram_tiles<false><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
   } else {
     return hipErrorInvalidValue;
   }
@@ -718,10 +731,13 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
       k_gram_partial<128, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
       break;
     case 128:
-      // [P1 | P2] is 256 wide: 4 slices, 10 tile pairs
-      k_gram_tiles<false><<<dim3((unsigned)nb, 10, 1), 256, 0, st>>>(P1, ld1, P2, ld2, L, 2 * L, rows, rpb, partials,
-                                                                     nullptr, 0);
+    case 256: {
+      // [P1 | P2] is 2L wide: 2L / 64 slices and their upper tile pairs
+      const int ns = 2 * L / 64;
+      k_gram_tiles<false><<<dim3((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), 1), 256, 0, st>>>(
+          P1, ld1, P2, ld2, L, 2 * L, rows, rpb, partials, nullptr, 0);
       break;
+    }
     default: return hipErrorInvalidValue;
   }
   k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W, nullptr, 0);
@@ -736,16 +752,22 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
     k_panel_xform2<32><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
   } else if (L == 64) {
     k_panel_xform2<64><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
-  } else if (L == 128) {
+  } else if (L == 128 || L == 256) {
     // out = P1 T2[0:L] (out may be P1), then out += P2 T2[L:2L]
     int64_t nb;
     int rpb;
     gram_grid(rows, nb, rpb);
     rpb = (rpb + 15) & ~15;
     nb = (rows + rpb - 1) / rpb;
-    k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-    k_xform_strips<128, false, true><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
-                                                                   nullptr);
+    if (L == 128) {
+      k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<128, false, true><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+                                                                     nullptr);
+    } else {
+      k_xform_strips<256, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<256, false, true><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+                                                                      nullptr);
+    }
   } else {
     return hipErrorInvalidValue;
   }
@@ -763,7 +785,10 @@ hipError_t panel_gemv_t(const float* P, int ld, int L, int64_t rows, const float
                         float* part, hipStream_t st, int K, int sstride) {
   int nb = gemv_blocks(rows);
   int rpb = (int)((rows + nb - 1) / nb);
-  k_panel_gemv_t<<<dim3((unsigned)nb, (unsigned)K), 256, 0, st>>>(P, ld, L, rows, rpb, y, scale_ptr, part, sstride);
+  if (L <= 128)
+    k_panel_gemv_t<2><<<dim3((unsigned)nb, (unsigned)K), 256, 0, st>>>(P, ld, L, rows, rpb, y, scale_ptr, part, sstride);
+  else
+    k_panel_gemv_t<4><<<dim3((unsigned)nb, (unsigned)K), 256, 0, st>>>(P, ld, L, rows, rpb, y, scale_ptr, part, sstride);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 
 namespace sfd {
 
-constexpr int kMaxEll = 100;     // the packed 2 ell x 2 ell FP64 Jacobi matrix fills one CU's LDS
+constexpr int kMaxEll = 256;     // panels up to 256 wide; FP64 eigensolves up to 512 x 512
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
 constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
 
@@ -164,17 +164,23 @@ hipError_t start_block(uint64_t seed, uint64_t stream_id, uint64_t buffer, uint6
 // ---------------------------------------------------------------- small FP64 solvers (sfd_small.hip)
 // pivoted Cholesky of the ell x ell Gram W (pitch ldw) and the inverse of its factor, T (L x L,
 // f32, zero-padded); columns whose residual falls to tau * (their norm^2) are dropped
-hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
+// (ell > 128: Rw holds chol_work_doubles(L) doubles per buffer, the factor between the passes)
+hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, double* Rw,
                     hipStream_t st);
+int64_t chol_work_doubles(int L);
 // group launches (one workgroup per buffer k): chol_inv on W + k wstride -> T + k L L, sc + k;
 // eig_sym on A + k astride -> evals + k estride, evecs + k vstride; ssh_post on evals + k estride,
 // H + k vstride -> M64 / M32 + k L L, sc + k
 hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
-                          int64_t wstride, hipStream_t st);
-// (n > 112: work holds eig_work_bytes(n) bytes per buffer, wstride bytes apart)
+                          int64_t wstride, double* Rw, hipStream_t st);
+// (n > 112: work holds eig_work_bytes(n) bytes per buffer, wstride bytes apart; n <= 512)
 hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
                          int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st);
 int64_t eig_work_bytes(int n);
+// the tridiagonal solver (sfd_eig_tri.hip) behind eig_sym_group for 112 < n <= 512
+hipError_t eig_tri_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
+                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st);
+int64_t eig_tri_work_bytes(int n);
 hipError_t ssh_post_group(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
                           DevScalars* sc, int K, int64_t estride, int64_t vstride, hipStream_t st);
 // symmetric eigensolver (cyclic Jacobi, FP64) of the n x n matrix A (pitch lda), n <= 2*kMaxEll:

@@ -10,7 +10,8 @@ namespace sfd {
 
 namespace {
 
-constexpr int kCholMax = 128;
+constexpr int kCholMax = 128;      // register-resident factor and inverse together
+constexpr int kCholMaxWide = 256;  // factor and inverse in two passes (8 and 16 waves: what their registers hold)
 
 // 1/sqrt(x) for x > 0: the hardware estimate refined by one Newton step (relative error
 // about one unit in the last place).
@@ -29,11 +30,9 @@ __device__ inline double rcp_nr(double x) {
   e = fma(-x, y, 1.0);
   return fma(y, e, y);
 }
-// the Jacobi solver with V in LDS takes n <= kEigMax; the one that logs its rotations (V
-// accumulated afterwards) takes n <= kEigMaxLog (the packed upper triangle fills one CU's LDS)
+// the Jacobi solver (A and V in LDS) takes n <= kEigMax; larger problems go to the tridiagonal
+// solver (sfd_eig_tri.hip)
 constexpr int kEigMax = 112;
-constexpr int kEigMaxLog = 2 * kMaxEll;
-constexpr int kJacobiLogSweeps = 30;
 
 __device__ inline double readlane_d(double v, int l) {
   const long long bits = __double_as_longlong(v);
@@ -176,6 +175,173 @@ __global__ __launch_bounds__(64 * NW) void k_chol_inv(const double* __restrict__
   }
 }
 
+// The same Cholesky for 128 < n <= 256 in two passes, because the factor and its inverse no
+// longer fit the registers together.  Thread (w, j) of NW waves holds columns c = j + 64 u
+// (u < 4) and, of rows i = NW s + w, only the slots that can be on or above the diagonal of
+// its column group (s < (64 / NW) (u + 1)).
+// Pass 1 factors W = R^T R (dropping dependent columns as above) and writes R (pitch 256, zero
+// below the diagonal) and 1 / R_kk to Rw, Rw + 256 * 256.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_chol_factor_wide(const double* __restrict__ W, int ldw, int n, double tau,
+                                                              double* __restrict__ Rw, DevScalars* sc,
+                                                              int64_t wstride, int64_t rstride) {
+  W += blockIdx.x * wstride;
+  Rw += blockIdx.x * rstride;
+  sc += blockIdx.x;
+  constexpr int CPL = 4, S = 256 / NW, LD = 256, SG = 64 / NW;  // SG: slots per column group
+  __shared__ double pub[2][256];
+  __shared__ int ndrop[NW];
+  const int j = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int col[CPL];
+  bool cn[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    col[u] = j + 64 * u;
+    cn[u] = col[u] < n;
+  }
+  double a[S][CPL], d0[CPL];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = NW * s + w;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      if (s >= SG * (u + 1)) continue;
+      const double x = W[(i < n ? i : 0) * ldw + (cn[u] ? col[u] : 0)];
+      a[s][u] = (i < n && cn[u]) ? x : 0.0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) d0[u] = W[(cn[u] ? col[u] : 0) * ldw + (cn[u] ? col[u] : 0)];
+  int drops = 0;
+#pragma unroll
+  for (int sk = 0; sk < S; ++sk) {
+    const int uk = sk / SG;
+    for (int wk = 0; wk < NW; ++wk) {
+      const int k = NW * sk + wk;
+      if (k >= n) break;
+      const int lk = k % 64;
+      if (w == wk) {
+        const double p = readlane_d(a[sk][uk], lk);
+        const double dk = readlane_d(d0[uk], lk);
+        const bool keep = (dk > 0.0) && (p > tau * dk);
+        const double is = keep ? rsqrt_nr(p) : 0.0;
+        drops += keep ? 0 : 1;
+        if (j == 0) Rw[LD * LD + k] = is;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          double r = 0.0;
+          if (sk < SG * (u + 1)) {
+            r = (col[u] >= k && cn[u]) ? a[sk][u] * is : 0.0;
+            a[sk][u] = r;  // row k of R
+          }
+          pub[k & 1][col[u]] = r;
+        }
+      }
+      __syncthreads();
+      double rkj[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) rkj[u] = pub[k & 1][col[u]];
+#pragma unroll
+      for (int s = sk; s < S; ++s) {
+        const int i = NW * s + w;
+        const double f = (i > k && i < n) ? pub[k & 1][i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          if (s < SG * (u + 1)) a[s][u] = fma(-f, rkj[u], a[s][u]);
+      }
+    }
+  }
+  // R (rows of this thread's slots; below-diagonal entries and untracked slots are zero)
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = NW * s + w;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      double r = 0.0;
+      if (s < SG * (u + 1)) r = (i <= col[u] && i < n && cn[u]) ? a[s][u] : 0.0;
+      Rw[i * LD + col[u]] = r;
+    }
+  }
+  if (j == 0) ndrop[w] = drops;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int q = 0; q < NW; ++q) tot += ndrop[q];
+    sc->dropped = tot;
+  }
+}
+
+// Pass 2: T = R^{-1} by right-looking back substitution as in k_chol_inv; R[l][i] is read from
+// Rw (one address per wave and slot).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_chol_inverse_wide(const double* __restrict__ Rw, int n, int L,
+                                                               float* __restrict__ T, int64_t rstride) {
+  Rw += blockIdx.x * rstride;
+  T += (int64_t)blockIdx.x * L * L;
+  constexpr int CPL = 4, S = 256 / NW, LD = 256, SG = 64 / NW;
+  __shared__ double pub[2][256];
+  const int j = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int col[CPL];
+  bool cn[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    col[u] = j + 64 * u;
+    cn[u] = col[u] < n;
+  }
+  double t[S][CPL];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (s < SG * (u + 1)) t[s][u] = 0.0;
+  const double* ivd = Rw + LD * LD;
+#pragma unroll
+  for (int si = S - 1; si >= 0; --si) {
+    for (int wi = NW - 1; wi >= 0; --wi) {
+      const int i = NW * si + wi;
+      if (i >= n) continue;
+      if (w == wi) {
+        const double iv = ivd[i];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          double ti = 0.0;
+          if (si < SG * (u + 1)) {
+            const double x = ((i == col[u]) ? 1.0 : 0.0) - t[si][u];
+            ti = cn[u] ? x * iv : 0.0;
+            t[si][u] = ti;
+          }
+          pub[i & 1][col[u]] = ti;
+        }
+      }
+      __syncthreads();
+      double tij[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) tij[u] = pub[i & 1][col[u]];
+#pragma unroll
+      for (int s = 0; s <= si; ++s) {
+        const int l = NW * s + w;
+        const double r = l < i ? Rw[l * LD + i] : 0.0;  // R[l][i]
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          if (s < SG * (u + 1)) t[s][u] = fma(r, tij[u], t[s][u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = NW * s + w;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      if (i >= L || col[u] >= L) continue;
+      float v = 0.f;
+      if (s < SG * (u + 1)) v = (i < n && cn[u]) ? (float)t[s][u] : 0.f;
+      T[i * L + col[u]] = v;
+    }
+  }
+}
+
 __device__ inline int packed_index(int i, int j, int N) {
   const int a = i < j ? i : j;
   const int b = i < j ? j : i;
@@ -184,7 +350,6 @@ __device__ inline int packed_index(int i, int j, int N) {
 
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxBlocksPerThread = (kEigMax / 2) * (kEigMax / 2 + 1) / 2 / kJacobiThreads + 1;
-constexpr int kJacobiMaxBlocksPerThreadLog = (kEigMaxLog / 2) * (kEigMaxLog / 2 + 1) / 2 / kJacobiThreads + 1;
 
 // Cyclic Jacobi with the round-robin ordering: in each round the N/2 index pairs are disjoint,
 // so every thread updates whole 2 x 2 blocks of A (packed upper triangle in LDS) and pairs of
@@ -336,199 +501,6 @@ __global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi(const double* __r
   }
 }
 
-// The same cyclic Jacobi for larger n (up to kEigMaxLog): only the packed upper triangle of A
-// stays in LDS; the rotations are not applied to V here but logged, round by round, to global
-// memory (c, s of pair k of round r at log[r P + k]; the pairs follow from r), and k_eig_replay
-// accumulates V from the log afterwards.  Writes the eigenvalues descending (ties by index), the
-// column of V each belongs to (perm) and the number of logged rounds.
-__global__ __launch_bounds__(kJacobiThreads) void k_eig_jacobi_log(const double* __restrict__ Ain, int lda, int n,
-                                                        double* __restrict__ evals, double2* __restrict__ rlog,
-                                                        int* __restrict__ perm, int* __restrict__ nrounds,
-                                                        int64_t astride, int64_t estride, int64_t logstride,
-                                                        int64_t pstride) {
-  extern __shared__ double lds[];
-  Ain += blockIdx.x * astride;
-  evals += blockIdx.x * estride;
-  rlog += blockIdx.x * logstride;
-  perm += blockIdx.x * pstride;
-  nrounds += blockIdx.x * pstride;
-  const int N = n + (n & 1);
-  const int P = N / 2;
-  double* A = lds;                    // N (N + 1) / 2
-  double* rc = A + (N * (N + 1)) / 2;  // P
-  double* rs = rc + P;                 // P
-  __shared__ int flag;
-  __shared__ double scale;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < N * N; e += kJacobiThreads) {
-    const int i = e / N, j = e - (e / N) * N;
-    if (i <= j) A[packed_index(i, j, N)] = (i < n && j < n) ? Ain[i * lda + j] : 0.0;
-  }
-  int nblk = 0;
-  int bk1[kJacobiMaxBlocksPerThreadLog], bk2[kJacobiMaxBlocksPerThreadLog];
-  {
-    const int total = P * (P + 1) / 2;
-    int k1 = 0, base = 0;
-    for (int b = tid; b < total; b += kJacobiThreads) {
-      while (b >= base + (P - k1)) {
-        base += P - k1;
-        ++k1;
-      }
-#pragma unroll
-      for (int r = 0; r < kJacobiMaxBlocksPerThreadLog; ++r)
-        if (r == nblk) {
-          bk1[r] = k1;
-          bk2[r] = k1 + (b - base);
-        }
-      ++nblk;
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, fabs(A[packed_index(i, i, N)]));
-    scale = m;
-  }
-  __syncthreads();
-  const double abs_tol = 1e-18 * scale;
-  int rounds = 0;
-  for (int sweep = 0; sweep < kJacobiLogSweeps; ++sweep) {
-    if (tid == 0) flag = 0;
-    __syncthreads();
-    for (int r = 0; r < N - 1; ++r, ++rounds) {
-      if (tid < P) {
-        const int k = tid;
-        int p = k == 0 ? 0 : 1 + (k - 1 + r) % (N - 1);
-        int q = 1 + (N - 2 - k + r) % (N - 1);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        const double app = A[packed_index(p, p, N)], aqq = A[packed_index(q, q, N)];
-        const double apq = A[packed_index(p, q, N)];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > abs_tol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-          const double theta = (aqq - app) * rcp_nr(2.0 * apq);
-          const double h2 = fma(theta, theta, 1.0);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(theta) + h2 * rsqrt_nr(h2));
-          c = rsqrt_nr(fma(t, t, 1.0));
-          s = t * c;
-          flag = 1;
-        }
-        rc[k] = c;
-        rs[k] = s;
-        rlog[(int64_t)rounds * P + k] = make_double2(c, s);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int rr = 0; rr < kJacobiMaxBlocksPerThreadLog; ++rr) {
-        if (rr >= nblk) break;
-        const int k1 = bk1[rr], k2 = bk2[rr];
-        const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        int p1 = k1 == 0 ? 0 : 1 + (k1 - 1 + r) % (N - 1), q1 = 1 + (N - 2 - k1 + r) % (N - 1);
-        int p2 = k2 == 0 ? 0 : 1 + (k2 - 1 + r) % (N - 1), q2 = 1 + (N - 2 - k2 + r) % (N - 1);
-        if (p1 > q1) {
-          const int t = p1;
-          p1 = q1;
-          q1 = t;
-        }
-        if (p2 > q2) {
-          const int t = p2;
-          p2 = q2;
-          q2 = t;
-        }
-        if (k1 == k2) {
-          const int ipp = packed_index(p1, p1, N), iqq = packed_index(q1, q1, N), ipq = packed_index(p1, q1, N);
-          const double t = s1 / c1;
-          const double apq = A[ipq];
-          A[ipp] = A[ipp] - t * apq;
-          A[iqq] = A[iqq] + t * apq;
-          A[ipq] = 0.0;
-        } else {
-          const int i_pp = packed_index(p1, p2, N), i_pq = packed_index(p1, q2, N);
-          const int i_qp = packed_index(q1, p2, N), i_qq = packed_index(q1, q2, N);
-          const double a_pp = A[i_pp], a_pq = A[i_pq], a_qp = A[i_qp], a_qq = A[i_qq];
-          const double up = c2 * a_pp - s2 * a_pq, uq = s2 * a_pp + c2 * a_pq;
-          const double wp = c2 * a_qp - s2 * a_qq, wq = s2 * a_qp + c2 * a_qq;
-          A[i_pp] = c1 * up - s1 * wp;
-          A[i_pq] = c1 * uq - s1 * wq;
-          A[i_qp] = s1 * up + c1 * wp;
-          A[i_qq] = s1 * uq + c1 * wq;
-        }
-      }
-      __syncthreads();
-    }
-    const int done = (flag == 0);
-    __syncthreads();
-    if (done) break;
-  }
-  if (tid == 0) *nrounds = rounds;
-  for (int i = tid; i < n; i += kJacobiThreads) {
-    const double li = A[packed_index(i, i, N)];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = A[packed_index(j, j, N)];
-      rank += (lj > li) || (lj == li && j < i);
-    }
-    evals[rank] = li;
-    perm[rank] = i;
-  }
-}
-
-// V from the rotation log of k_eig_jacobi_log: rows of V are independent under the column
-// rotations, so block x owns kReplayRows rows (in LDS, starting as rows of I) and applies every
-// logged round in order (one barrier per round; rounds whose rotation is the identity are
-// skipped per pair).  evecs column c (pitch n) <- V column perm[c].
-constexpr int kReplayRows = 16;
-__global__ __launch_bounds__(256) void k_eig_replay(const double2* __restrict__ rlog, const int* __restrict__ nrounds,
-                                                    const int* __restrict__ perm, int n,
-                                                    double* __restrict__ evecs, int64_t logstride, int64_t pstride,
-                                                    int64_t evstride) {
-  extern __shared__ double vr[];  // kReplayRows x N
-  rlog += blockIdx.y * logstride;
-  nrounds += blockIdx.y * pstride;
-  perm += blockIdx.y * pstride;
-  evecs += blockIdx.y * evstride;
-  const int N = n + (n & 1);
-  const int P = N / 2;
-  const int row0 = blockIdx.x * kReplayRows;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kReplayRows * N; e += 256) {
-    const int i = e / N, j = e % N;
-    vr[e] = (row0 + i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int R = *nrounds;
-  const int items = kReplayRows * P;
-  for (int r = 0; r < R; ++r) {
-    const int rm = r % (N - 1);
-    for (int it = tid; it < items; it += 256) {
-      const int k = it % P, i = it / P;
-      const double2 cs = rlog[(int64_t)r * P + k];
-      if (cs.y != 0.0) {
-        int p = k == 0 ? 0 : 1 + (k - 1 + rm) % (N - 1);
-        int q = 1 + (N - 2 - k + rm) % (N - 1);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        const double vp = vr[i * N + p], vq = vr[i * N + q];
-        vr[i * N + p] = cs.x * vp - cs.y * vq;
-        vr[i * N + q] = cs.y * vp + cs.x * vq;
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kReplayRows * n; e += 256) {
-    const int i = e / n, c = e % n;
-    const int row = row0 + i;
-    if (row < n) evecs[(int64_t)row * n + c] = vr[i * N + perm[c]];
-  }
-}
-
 // (a group launch: buffer k = blockIdx.x on evals + k estride, H + k vstride, M64 / M32 + k L L,
 // sc + k)
 __global__ __launch_bounds__(256) void k_ssh_post(const double* __restrict__ evals, const double* __restrict__ H,
@@ -618,6 +590,7 @@ __global__ __launch_bounds__(256) void k_dsh_assemble(const double* __restrict__
   }
 }
 
+// (a grid of blocks over the entries of T2; every block derives the shrink factors itself)
 __global__ __launch_bounds__(256) void k_dsh_post(const double* __restrict__ evals, const double* __restrict__ U,
                                                   int ell, int L, const double* __restrict__ M, int lossless,
                                                   float* __restrict__ T2, DevScalars* sc) {
@@ -627,12 +600,12 @@ __global__ __launch_bounds__(256) void k_dsh_post(const double* __restrict__ eva
   const int n = 2 * ell;
   if (tid == 0) shift = lossless ? 0.0 : fmax(evals[ell - 1], 0.0);
   __syncthreads();
-  if (tid < ell) {
-    double mu = evals[tid];
-    D[tid] = (mu > 0.0 && mu > shift) ? sqrt((mu - shift) / mu) : 0.0;
+  for (int i = tid; i < ell; i += 256) {
+    double mu = evals[i];
+    D[i] = (mu > 0.0 && mu > shift) ? sqrt((mu - shift) / mu) : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < 2 * L * L; e += 256) {
+  for (int e = blockIdx.x * 256 + tid; e < 2 * L * L; e += gridDim.x * 256) {
     int r = e / L, i = e % L;
     double v = 0.0;
     if (i < ell) {
@@ -646,20 +619,14 @@ __global__ __launch_bounds__(256) void k_dsh_post(const double* __restrict__ eva
     }
     T2[e] = (float)v;
   }
-  if (tid == 0) sc->mu_ell = shift;
+  if (blockIdx.x == 0 && tid == 0) sc->mu_ell = shift;
 }
 
 }  // namespace
 
-hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc,
+hipError_t chol_inv(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, double* Rw,
                     hipStream_t st) {
-  return chol_inv_group(W, ldw, ell, L, tau, T, sc, 1, 0, st);
-}
-
-// dynamic LDS of the logging Jacobi solver: packed upper A, rotation pair (c, s)
-size_t eig_log_lds_bytes(int n) {
-  const int N = n + (n & 1);
-  return sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N);
+  return chol_inv_group(W, ldw, ell, L, tau, T, sc, 1, 0, Rw, st);
 }
 
 // dynamic LDS of the Jacobi solver for an n x n problem: packed upper A, V, pair lists
@@ -669,43 +636,20 @@ size_t eig_lds_bytes(int n) {
   return sizeof(double) * ((size_t)N * (N + 1) / 2 + (size_t)N * N + 2 * P) + sizeof(int) * 2 * P;
 }
 
-int64_t eig_work_bytes(int n) {
-  if (n <= kEigMax) return 0;
-  const int64_t N = n + (n & 1), P = N / 2;
-  const int64_t logb = (int64_t)kJacobiLogSweeps * (N - 1) * P * 16;
-  return logb + (((int64_t)n + 1) * 4 + 255) / 256 * 256;
-}
+int64_t eig_work_bytes(int n) { return n <= kEigMax ? 0 : eig_tri_work_bytes(n); }
 
 hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
                          int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st) {
-  if (n < 1 || n > kEigMaxLog || K < 1) return hipErrorInvalidValue;
+  if (n > kEigMax) return eig_tri_group(A, lda, n, evals, evecs, K, astride, estride, vstride, work, wstride, st);
+  if (n < 1 || K < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
-    // allow the largest problems' dynamic LDS (more than the default 64 KiB; gfx950 has 160 KiB)
+    // allow the largest problem's dynamic LDS (more than the default 64 KiB; gfx950 has 160 KiB)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(kEigMax));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eig_jacobi_log),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_log_lds_bytes(kEigMaxLog));
     attr_set = true;
   }
-  if (n <= kEigMax) {
-    k_eig_jacobi<<<K, kJacobiThreads, eig_lds_bytes(n), st>>>(A, lda, n, evals, evecs, astride, estride, vstride);
-    return hipGetLastError();
-  }
-  if (!work) return hipErrorInvalidValue;
-  // workspace of buffer k: rotation log, then n + 1 ints (perm, round count)
-  const int64_t N = n + (n & 1), P = N / 2;
-  const int64_t logb = (int64_t)kJacobiLogSweeps * (N - 1) * P * 16;
-  double2* rlog = reinterpret_cast<double2*>(work);
-  int* perm = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + logb);
-  // per-buffer strides in elements of each array (wstride bytes apart)
-  if (wstride % 16 != 0) return hipErrorInvalidValue;
-  const int64_t ls = wstride / 16, ps = wstride / 4;
-  // the round counts of the K buffers sit after each perm (perm + n)
-  k_eig_jacobi_log<<<K, kJacobiThreads, eig_log_lds_bytes(n), st>>>(A, lda, n, evals, rlog, perm, perm + n, astride,
-                                                                    estride, ls, ps);
-  k_eig_replay<<<dim3((unsigned)((n + kReplayRows - 1) / kReplayRows), (unsigned)K), 256,
-                 sizeof(double) * kReplayRows * N, st>>>(rlog, perm + n, perm, n, evecs, ls, ps, vstride);
+  k_eig_jacobi<<<K, kJacobiThreads, eig_lds_bytes(n), st>>>(A, lda, n, evals, evecs, astride, estride, vstride);
   return hipGetLastError();
 }
 
@@ -719,13 +663,20 @@ hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double
   return hipGetLastError();
 }
 
+int64_t chol_work_doubles(int L) { return L > kCholMax ? 256 * 256 + 256 : 0; }
+
 hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
-                          int64_t wstride, hipStream_t st) {
-  if (ell > kCholMax || L > kCholMax) return hipErrorInvalidValue;
-  if (ell <= 64 && L <= 64)
+                          int64_t wstride, double* Rw, hipStream_t st) {
+  if (ell > kCholMaxWide || L > kCholMaxWide) return hipErrorInvalidValue;
+  if (ell <= 64 && L <= 64) {
     k_chol_inv<4, 1><<<K, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
-  else
+  } else if (ell <= kCholMax && L <= kCholMax) {
     k_chol_inv<16, 2><<<K, 1024, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
+  } else {
+    if (!Rw) return hipErrorInvalidValue;
+    k_chol_factor_wide<8><<<K, 512, 0, st>>>(W, ldw, ell, tau, Rw, sc, wstride, chol_work_doubles(L));
+    k_chol_inverse_wide<16><<<K, 1024, 0, st>>>(Rw, ell, L, T, chol_work_doubles(L));
+  }
   return hipGetLastError();
 }
 
@@ -750,7 +701,7 @@ hipError_t dsh_assemble(const double* W2, int L, int ell, const double* M64, dou
 
 hipError_t dsh_post(const double* evals, const double* U, int ell, int L, const double* M64, int lossless,
                     float* T2, DevScalars* sc, hipStream_t st) {
-  k_dsh_post<<<1, 256, 0, st>>>(evals, U, ell, L, M64, lossless, T2, sc);
+  k_dsh_post<<<(unsigned)std::min(64, (2 * L * L + 255) / 256), 256, 0, st>>>(evals, U, ell, L, M64, lossless, T2, sc);
   return hipGetLastError();
 }
 

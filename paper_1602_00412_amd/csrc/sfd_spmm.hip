@@ -486,6 +486,7 @@ hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void*
   if (L == 32) return spmm_l<32>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   if (L == 64) return spmm_l<64>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   if (L == 128 && s.bands == 1) return spmm_l<128>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 256 && s.bands == 1) return spmm_l<256>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   return hipErrorInvalidValue;
 }
 
@@ -522,6 +523,8 @@ hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt,
     launch_fixup<64>(s, partial, Y, yb, ldy, st);
   } else if (L == 128) {
     launch_fixup<128>(s, partial, Y, yb, ldy, st);
+  } else if (L == 256) {
+    launch_fixup<256>(s, partial, Y, yb, ldy, st);
   } else {
     return hipErrorInvalidValue;
   }

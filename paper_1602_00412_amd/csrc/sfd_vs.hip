@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_vs_init(const double* __restrict__ part
 __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ part, int nb,
                                                    const double* __restrict__ M, int ell, int L,
                                                    float* __restrict__ c2) {
-  __shared__ double red[16][128];
+  __shared__ double red[16][256];
   part += (int64_t)blockIdx.x * nb * L;
   M += (int64_t)blockIdx.x * L * L;
   c2 += (int64_t)blockIdx.x * 2 * L;
@@ -71,9 +71,9 @@ __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ par
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  // columns lane and lane + 64 (L <= 128)
+  // columns lane + 64 h (L <= 256)
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < 4; ++h) {
     const int cc = lane + 64 * h;
     if (cc >= L) break;
     double s = 0.0;
@@ -126,12 +126,14 @@ __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_r
   }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const float cA = lane < L ? c2[lane] : 0.f;
-  const float cB = 64 + lane < L ? c2[64 + lane] : 0.f;
+  float cc[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) cc[h] = 64 * h + lane < L ? c2[64 * h + lane] : 0.f;
   double acc = 0.0;
   for (int64_t j = ((int64_t)blockIdx.x * 4 + wave); j < d; j += (int64_t)gridDim.x * 4) {
     const float* pr = P + j * ld;
-    float v = (lane < L ? pr[lane] * cA : 0.f) + (64 + lane < L ? pr[64 + lane] * cB : 0.f);
+    float v = (lane < L ? pr[lane] * cc[0] : 0.f) + (64 + lane < L ? pr[64 + lane] * cc[1] : 0.f);
+    if (L > 128) v += (128 + lane < L ? pr[128 + lane] * cc[2] : 0.f) + (192 + lane < L ? pr[192 + lane] * cc[3] : 0.f);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) {

@@ -44,6 +44,7 @@ def _check_form(sfd, st, ell):
     (1500, 90, 50, 20, 3),    # L = 64
     (3000, 1200, 40, 15, 4),  # long CSC columns, several flushes
     (2500, 400, 100, 25, 6),  # L = 128
+    (2400, 700, 200, 40, 10),  # L = 256
 ])
 def test_bf16_form_keeps_property1_and_cov_err(gpu_lib, n, d, ell, lam, seed):
     st = small_random_csr(n, d, lam, seed, dist="lognormal")

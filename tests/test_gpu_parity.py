@@ -220,7 +220,8 @@ def test_errors_leave_state_unchanged(gpu_lib):
         gpu_lib.Sketch(10, 11)
 
 
-@pytest.mark.parametrize("n,d,ell,seed", [(300, 60, 8, 0), (1000, 200, 20, 1), (700, 150, 50, 2), (1000, 400, 100, 3)])
+@pytest.mark.parametrize("n,d,ell,seed", [(300, 60, 8, 0), (1000, 200, 20, 1), (700, 150, 50, 2), (1000, 400, 100, 3),
+                                          (1000, 500, 200, 4)])
 def test_fd_mode_matches_fd_oracle(gpu_lib, n, d, ell, seed):
     # FrequentDirections (Sec. 2.1) in batches of ell rows through the same DenseShrink kernels
     from oracle import FDBatchOracle
@@ -281,3 +282,17 @@ def test_wide_panel_large_buffer_matches_oracle(gpu_lib):
     sk, B = _gpu_sketch(gpu_lib, st, 100)
     assert sk.stats()["flushes"] == o.flushes == 1
     assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+@pytest.mark.parametrize("n,d,ell,lam,seed", [
+    (2000, 600, 150, 40, 9),    # 256-wide panels; two-pass Cholesky; 300 x 300 eigensolve (tridiagonal)
+    (2400, 700, 200, 40, 10),   # ell = 200: 200 x 200 Jacobi with logged rotations, 400 x 400 tridiagonal
+    (1800, 520, 256, 50, 11),   # the widest: both eigensolves tridiagonal (256 and 512)
+])
+def test_widest_panel_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
+    st = small_random_csr(n, d, lam, seed, dist="lognormal", dup_rate=0.02 if ell == 150 else 0.0)
+    o = _oracle(st, ell)
+    sk, B = _gpu_sketch(gpu_lib, st, ell)
+    assert sk.stats()["flushes"] == o.flushes == 3
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+    assert sk.last_live == o.query()[1]

@@ -151,15 +151,16 @@ def gen_rows(keys, d: int, lam: float, cdf_zipf, cdf_pois, perm):
     return lens, cols[o], out_rows[o]
 
 
-def gen_csr(keys, d: int, lam: float, s: float, perm_key: int, *, r: int = 0, share: float = 0.0,
-            n_total: int = 1, chunk: int = 1 << 17):
+def gen_csr(keys, d: int, lam: float, s: float, perm_key: int, *, r: int = 0, share: float | None = 0.0,
+            n_total: int = 1, chunk: int = 1 << 17, base: str = "lognormal"):
     """CSR (indptr int64, indices int32, values float32) of the rows with the given keys, on
     their device.
 
-    Values: lognormal(0, 1) plus, for r > 0, a planted rank-r component U diag(sigma) V^T at the
-    stored positions with sigma_i = 1/i, U[i, :] ~ N(0, 1/n_total) per entry (near-orthonormal,
-    keyed by row), V a Gaussian d x r block orthonormalised by CholeskyQR2 in FP64, scaled so
-    its expected share of the energy is ``share``.
+    Values: lognormal(0, 1) (base="lognormal") or N(0, 1) (base="normal") plus, for r > 0, a
+    planted rank-r component U diag(sigma) V^T at the stored positions with sigma_i = 1/i,
+    U[i, :] ~ N(0, 1/n_total) per entry (near-orthonormal, keyed by row), V a Gaussian d x r
+    block orthonormalised by CholeskyQR2 in FP64, scaled so its expected share of the energy is
+    ``share`` (share=None: unscaled).
     """
     import torch
 
@@ -179,7 +180,8 @@ def gen_csr(keys, d: int, lam: float, s: float, perm_key: int, *, r: int = 0, sh
         V = G
         sigma = 1.0 / torch.arange(1, r + 1, dtype=torch.float64, device=device)
         e_pl = float((sigma ** 2).sum()) / (n_total * d)
-        scale = math.sqrt(share * math.exp(2.0) / ((1.0 - share) * e_pl))
+        e_base = math.exp(2.0) if base == "lognormal" else 1.0
+        scale = 1.0 if share is None else math.sqrt(share * e_base / ((1.0 - share) * e_pl))
     ptr_parts, idx_parts, val_parts = [torch.zeros(1, dtype=torch.int64, device=device)], [], []
     base_nnz = 0
     for c0 in range(0, n, chunk):
@@ -188,7 +190,9 @@ def gen_csr(keys, d: int, lam: float, s: float, perm_key: int, *, r: int = 0, sh
         # position of each entry inside its row (the draw counter of its value)
         starts = torch.cumsum(lens, 0) - lens
         pos = torch.arange(cols.numel(), device=device) - starts[rows]
-        vals = torch.exp(_normal(ck[rows], pos, P_VAL))
+        vals = _normal(ck[rows], pos, P_VAL)
+        if base == "lognormal":
+            vals = torch.exp(vals)
         if r:
             U = torch.stack([_normal(ck, torch.full_like(ck, c), P_U) for c in range(r)], dim=1)
             U = U * (sigma[None, :] / math.sqrt(n_total))
@@ -214,6 +218,16 @@ def config5_large(device, seed: int = 0, n: int = 10_000_000):
     key = stream_key(seed, 5)
     return gen_csr(row_keys(key, n, torch.device(device)), 1_000_000, 100.0, 1.0, key, r=100, share=0.3,
                    n_total=10_000_000)
+
+
+def config3_precision(device, seed: int = 0, n: int = 2_000_000):
+    """n=2e6, d=5e4, Poisson(80), Zipf(1.1) columns, N(0,1) values plus a planted rank-50
+    component with sigma_i = 1/i taken literally (unscaled); ell = 200."""
+    import torch
+
+    key = stream_key(seed, 3)
+    return gen_csr(row_keys(key, n, torch.device(device)), 50_000, 80.0, 1.1, key, r=50, share=None,
+                   n_total=2_000_000, base="normal")
 
 
 def config4_lengths(seed: int = 0, streams: int = 4096) -> np.ndarray:
