@@ -542,7 +542,7 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 16.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(ln.W, L, ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
+    CK(eig_sym(ln.W, L, ell, ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
@@ -606,7 +606,8 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_EIG, 64.0 * ell * ell, 0.0, 1);
-    CK(eig_sym(ln.SS, 2 * ell, 2 * ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
+    // only the ell leading eigenvectors enter the new sketch
+    CK(eig_sym(ln.SS, 2 * ell, 2 * ell, ell, ln.evals, ln.evecs, ln.eig_work, ln.st));
   }
   {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 1);
@@ -893,7 +894,7 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
   }
   // ---- SparseShrink (Alg 3): eig of P P^T, M = H D, the scalars of Alg 4
-  CK(eig_sym_group(g.Wp, L, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, g.eig_work, eig_work_bytes(ell), st));
+  CK(eig_sym_group(g.Wp, L, ell, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, g.eig_work, eig_work_bytes(ell), st));
   CK(ssh_post_group(g.evals, g.evecs, ell, L, kAlpha, g.M64, g.M32, g.sc, K, 2 * L, 4 * LL, st));
   CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));

@@ -10,7 +10,8 @@
 //     orthonormal inside clusters of close eigenvalues by modified Gram-Schmidt over the block;
 //  3. the eigenvectors of A = Q z, applying the reflectors in reverse order (one wave per
 //     eigenvector).
-// Output as the Jacobi solvers': eigenvalues descending, eigenvector columns (pitch n).
+// Output as the Jacobi solvers': eigenvalues descending, eigenvector columns (pitch n); only
+// the columns of the nvec largest eigenvalues are computed, the others are returned as zeros.
 #include <hip/hip_runtime.h>
 
 #include "sfd_internal.h"
@@ -123,7 +124,18 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_reduce(const double* __rest
       double s = 0.0;
       if (i < m) {
         const double* col = A + (int64_t)(k + 1) * n + k + 1 + i;
-        for (int j = h; j < m; j += 2) s = fma(col[(int64_t)j * n], v[j], s);
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = h;
+        for (; j + 6 < m; j += 8) {  // four loads in flight
+          const double a0 = col[(int64_t)j * n], a1 = col[(int64_t)(j + 2) * n];
+          const double a2 = col[(int64_t)(j + 4) * n], a3 = col[(int64_t)(j + 6) * n];
+          s = fma(a0, v[j], s);
+          s1 = fma(a1, v[j + 2], s1);
+          s2 = fma(a2, v[j + 4], s2);
+          s3 = fma(a3, v[j + 6], s3);
+        }
+        for (; j < m; j += 2) s = fma(col[(int64_t)j * n], v[j], s);
+        s = (s + s1) + (s2 + s3);
       }
       if (h == 1) ph[i] = s;
       __syncthreads();
@@ -134,11 +146,20 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_reduce(const double* __rest
     const double Kc = 0.5 * b * block_sum_d(pv, red);
     if (tid < m) p[tid] = p[tid] - Kc * v[tid];  // w
     __syncthreads();
-    // A_sub -= v w^T + w v^T
-    for (int64_t q = tid; q < (int64_t)m * m; q += kTriThreads) {
-      const int r = (int)(q / m), c = (int)(q % m);
-      double* a = A + (int64_t)(k + 1 + r) * n + k + 1 + c;
-      *a = *a - v[r] * p[c] - p[r] * v[c];
+    // A_sub -= v w^T + w v^T: wave wv takes rows wv, wv + 16, ..., its lanes the columns
+    {
+      const int lane = tid & 63, wv = tid >> 6;
+      for (int r = wv; r < m; r += kTriThreads / 64) {
+        double* arow = A + (int64_t)(k + 1 + r) * n + k + 1;
+        const double vr = v[r], pr = p[r];
+        int c = lane;
+        for (; c + 64 < m; c += 128) {
+          const double a0 = arow[c], a1 = arow[c + 64];
+          arow[c] = a0 - vr * p[c] - pr * v[c];
+          arow[c + 64] = a1 - vr * p[c + 64] - pr * v[c + 64];
+        }
+        if (c < m) arow[c] = arow[c] - vr * p[c] - pr * v[c];
+      }
     }
     __syncthreads();
   }
@@ -161,7 +182,7 @@ __device__ inline int sturm_below(const double* d, const double* e2, int n, doub
 }
 
 // 2. eigenvalues (bisection) and eigenvectors (inverse iteration) of T
-__global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, char* work, int64_t wstride,
+__global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, int nvec, char* work, int64_t wstride,
                                                          double* __restrict__ evals, int64_t estride) {
   TriWork w = tri_work(work + blockIdx.x * wstride, n);
   evals += blockIdx.x * estride;
@@ -213,7 +234,9 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, char* work, int6
     evals[t] = ev[t];
   }
   __syncthreads();
-  // inverse iteration, every eigenvalue on its own thread
+  // inverse iteration, every wanted eigenvalue (the nvec largest) on its own thread; the
+  // recurrences carry their running values in registers, so the loads of the stored factors are
+  // independent of the chain
   const double tiny = eps * tnorm + pivmin;
   double* dd = w.lu;
   double* du = w.lu + (int64_t)n * kBisThreads;
@@ -222,61 +245,67 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, char* work, int6
   double* y = w.y;
   unsigned char* piv = w.piv;
 #define LU(a, i) a[(int64_t)(i) * kBisThreads + t]
-  if (t < n) {
+  if (t < nvec) {
     const double lam = ev[t];
-    // factor T - lam I = P L U
-    for (int i = 0; i < n; ++i) {
-      LU(dd, i) = d[i] - lam;
-      LU(du, i) = e[i];
-      LU(dl, i) = e[i];
-      LU(du2, i) = 0.0;
-    }
+    // T - lam I = P L U (partial pivoting): dd = U's diagonal, du / du2 its first / second
+    // superdiagonal, dl the multipliers, piv the row interchanges
+    double dcur = d[0] - lam, ucur = n > 1 ? e[0] : 0.0;
     for (int i = 0; i + 1 < n; ++i) {
-      double di = LU(dd, i), li = LU(dl, i);
-      if (fabs(di) >= fabs(li)) {
-        if (fabs(di) < tiny) di = di >= 0.0 ? tiny : -tiny;
-        const double f = li / di;
-        LU(dd, i) = di;
+      const double li = e[i];
+      double dnext = d[i + 1] - lam;
+      double unext = i + 2 < n ? e[i + 1] : 0.0;
+      if (fabs(dcur) >= fabs(li)) {
+        if (fabs(dcur) < tiny) dcur = dcur >= 0.0 ? tiny : -tiny;
+        const double f = li / dcur;
+        LU(dd, i) = dcur;
         LU(dl, i) = f;
-        LU(dd, i + 1) = LU(dd, i + 1) - f * LU(du, i);
+        LU(du, i) = ucur;
+        LU(du2, i) = 0.0;
         LU(piv, i) = 0;
+        dnext = dnext - f * ucur;
       } else {
-        const double f = di / li;
+        const double f = dcur / li;
         LU(dd, i) = li;
         LU(dl, i) = f;
-        const double tmp = LU(du, i);
-        const double dn = LU(dd, i + 1);
-        LU(du, i) = dn;
-        LU(dd, i + 1) = tmp - f * dn;
-        if (i + 2 < n) {
-          const double un = LU(du, i + 1);
-          LU(du2, i) = un;
-          LU(du, i + 1) = -f * un;
-        }
+        LU(du, i) = dnext;
         LU(piv, i) = 1;
+        const double nd = ucur - f * dnext;
+        LU(du2, i) = unext;
+        unext = -f * unext;
+        dnext = nd;
       }
+      dcur = dnext;
+      ucur = unext;
     }
-    {
-      const double dn = LU(dd, n - 1);
-      if (fabs(dn) < tiny) LU(dd, n - 1) = dn >= 0.0 ? tiny : -tiny;
-    }
+    if (fabs(dcur) < tiny) dcur = dcur >= 0.0 ? tiny : -tiny;
+    LU(dd, n - 1) = dcur;
     // start vector (deterministic, spread over all components), three solves
     for (int i = 0; i < n; ++i) LU(y, i) = cos((double)i * (1.0 + t) * 0.6180339887498949 + t);
     for (int it = 0; it < 3; ++it) {
+      double ycur = LU(y, 0);
       for (int i = 0; i + 1 < n; ++i) {
         const double f = LU(dl, i);
+        const double yn = LU(y, i + 1);
         if (LU(piv, i) == 0) {
-          LU(y, i + 1) = LU(y, i + 1) - f * LU(y, i);
+          LU(y, i) = ycur;
+          ycur = yn - f * ycur;
         } else {
-          const double yi = LU(y, i), yn = LU(y, i + 1);
           LU(y, i) = yn;
-          LU(y, i + 1) = yi - f * yn;
+          ycur = ycur - f * yn;
         }
       }
-      LU(y, n - 1) = LU(y, n - 1) / LU(dd, n - 1);
-      if (n >= 2) LU(y, n - 2) = (LU(y, n - 2) - LU(du, n - 2) * LU(y, n - 1)) / LU(dd, n - 2);
-      for (int i = n - 3; i >= 0; --i)
-        LU(y, i) = (LU(y, i) - LU(du, i) * LU(y, i + 1) - LU(du2, i) * LU(y, i + 2)) / LU(dd, i);
+      double x1 = ycur / LU(dd, n - 1);
+      LU(y, n - 1) = x1;
+      if (n >= 2) {
+        double x0 = (LU(y, n - 2) - LU(du, n - 2) * x1) / LU(dd, n - 2);
+        LU(y, n - 2) = x0;
+        for (int i = n - 3; i >= 0; --i) {
+          const double xi = (LU(y, i) - LU(du, i) * x0 - LU(du2, i) * x1) / LU(dd, i);
+          LU(y, i) = xi;
+          x1 = x0;
+          x0 = xi;
+        }
+      }
       double mx = 0.0;
       for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(LU(y, i)));
       const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
@@ -303,9 +332,9 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, char* work, int6
   const int lane = t & 63, wave = t >> 6;
   constexpr int NWB = kBisThreads / 64;
   int c0 = 0;
-  while (c0 < n) {
+  while (c0 < nvec) {
     int c1 = c0 + 1;
-    while (c1 < n && ev[c1 - 1] - ev[c1] <= ortol) ++c1;
+    while (c1 < nvec && ev[c1 - 1] - ev[c1] <= ortol) ++c1;
     for (int j = c0; c1 - c0 > 1 && j < c1; ++j) {
       double* zj = w.Zt + (int64_t)j * n;
       // normalise z_j
@@ -344,13 +373,17 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_eig(int n, char* work, int6
 
 // 3. eigenvector j of A = H_0 H_1 ... H_{n-3} z_j: one wave per eigenvector, z in registers
 // (lane l holds components l + 64 r)
-__global__ __launch_bounds__(64) void k_tri_back(int n, const char* work, int64_t wstride, double* __restrict__ evecs,
-                                                 int64_t vstride) {
+__global__ __launch_bounds__(64) void k_tri_back(int n, int nvec, const char* work, int64_t wstride,
+                                                 double* __restrict__ evecs, int64_t vstride) {
   const TriWork w = tri_work(const_cast<char*>(work) + blockIdx.y * wstride, n);
   evecs += blockIdx.y * vstride;
   constexpr int R = kTriMax / 64;
   const int lane = threadIdx.x;
   const int j = blockIdx.x;
+  if (j >= nvec) {  // eigenvectors not asked for are returned as zero columns
+    for (int i = lane; i < n; i += 64) evecs[(int64_t)i * n + j] = 0.0;
+    return;
+  }
   double z[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -386,13 +419,15 @@ __global__ __launch_bounds__(64) void k_tri_back(int n, const char* work, int64_
 
 int64_t eig_tri_work_bytes(int n) { return n > 0 ? tri_work_doubles(n) * 8 + 256 : 0; }
 
-hipError_t eig_tri_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st) {
+hipError_t eig_tri_group(const double* A, int lda, int n, int nvec, double* evals, double* evecs, int K,
+                         int64_t astride, int64_t estride, int64_t vstride, void* work, int64_t wstride,
+                         hipStream_t st) {
   if (n < 1 || n > kTriMax || K < 1 || !work) return hipErrorInvalidValue;
+  nvec = nvec < 1 || nvec > n ? n : nvec;
   char* wk = reinterpret_cast<char*>(work);
   k_tri_reduce<<<K, kTriThreads, 0, st>>>(A, lda, n, astride, wk, wstride);
-  k_tri_eig<<<K, kBisThreads, 0, st>>>(n, wk, wstride, evals, estride);
-  k_tri_back<<<dim3((unsigned)n, (unsigned)K), 64, 0, st>>>(n, wk, wstride, evecs, vstride);
+  k_tri_eig<<<K, kBisThreads, 0, st>>>(n, nvec, wk, wstride, evals, estride);
+  k_tri_back<<<dim3((unsigned)n, (unsigned)K), 64, 0, st>>>(n, nvec, wk, wstride, evecs, vstride);
   return hipGetLastError();
 }
 

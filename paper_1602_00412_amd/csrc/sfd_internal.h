@@ -173,20 +173,24 @@ int64_t chol_work_doubles(int L);
 // H + k vstride -> M64 / M32 + k L L, sc + k
 hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, float* T, DevScalars* sc, int K,
                           int64_t wstride, double* Rw, hipStream_t st);
-// (n > 112: work holds eig_work_bytes(n) bytes per buffer, wstride bytes apart; n <= 512)
-hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st);
+// (n > 112: work holds eig_work_bytes(n) bytes per buffer, wstride bytes apart; n <= 512; the
+// eigenvectors of the nvec largest eigenvalues are computed, the other columns may be zero)
+hipError_t eig_sym_group(const double* A, int lda, int n, int nvec, double* evals, double* evecs, int K,
+                         int64_t astride, int64_t estride, int64_t vstride, void* work, int64_t wstride,
+                         hipStream_t st);
 int64_t eig_work_bytes(int n);
 // the tridiagonal solver (sfd_eig_tri.hip) behind eig_sym_group for 112 < n <= 512
-hipError_t eig_tri_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st);
+hipError_t eig_tri_group(const double* A, int lda, int n, int nvec, double* evals, double* evecs, int K,
+                         int64_t astride, int64_t estride, int64_t vstride, void* work, int64_t wstride,
+                         hipStream_t st);
 int64_t eig_tri_work_bytes(int n);
 hipError_t ssh_post_group(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
                           DevScalars* sc, int K, int64_t estride, int64_t vstride, hipStream_t st);
 // symmetric eigensolver (cyclic Jacobi, FP64) of the n x n matrix A (pitch lda), n <= 2*kMaxEll:
-// evals descending, evecs column i <-> evals[i], pitch n; work: eig_work_bytes(n) bytes (may be
-// null when that is 0)
-hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, void* work, hipStream_t st);
+// evals descending, evecs column i <-> evals[i], pitch n (columns beyond the nvec largest may
+// be zero); work: eig_work_bytes(n) bytes (may be null when that is 0)
+hipError_t eig_sym(const double* A, int lda, int n, int nvec, double* evals, double* evecs, void* work,
+                   hipStream_t st);
 // SparseShrink tail: from the eigenpairs of P P^T: M = H D (ell x ell, FP64 and f32 L x L),
 // ||B'||^2, S, Delta/2, lambda_ell^2
 hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,

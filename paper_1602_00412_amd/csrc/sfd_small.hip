@@ -638,9 +638,11 @@ size_t eig_lds_bytes(int n) {
 
 int64_t eig_work_bytes(int n) { return n <= kEigMax ? 0 : eig_tri_work_bytes(n); }
 
-hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double* evecs, int K, int64_t astride,
-                         int64_t estride, int64_t vstride, void* work, int64_t wstride, hipStream_t st) {
-  if (n > kEigMax) return eig_tri_group(A, lda, n, evals, evecs, K, astride, estride, vstride, work, wstride, st);
+hipError_t eig_sym_group(const double* A, int lda, int n, int nvec, double* evals, double* evecs, int K,
+                         int64_t astride, int64_t estride, int64_t vstride, void* work, int64_t wstride,
+                         hipStream_t st) {
+  if (n > kEigMax)
+    return eig_tri_group(A, lda, n, nvec, evals, evecs, K, astride, estride, vstride, work, wstride, st);
   if (n < 1 || K < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
@@ -653,8 +655,9 @@ hipError_t eig_sym_group(const double* A, int lda, int n, double* evals, double*
   return hipGetLastError();
 }
 
-hipError_t eig_sym(const double* A, int lda, int n, double* evals, double* evecs, void* work, hipStream_t st) {
-  return eig_sym_group(A, lda, n, evals, evecs, 1, 0, 0, 0, work, eig_work_bytes(n), st);
+hipError_t eig_sym(const double* A, int lda, int n, int nvec, double* evals, double* evecs, void* work,
+                   hipStream_t st) {
+  return eig_sym_group(A, lda, n, nvec, evals, evecs, 1, 0, 0, 0, work, eig_work_bytes(n), st);
 }
 
 hipError_t ssh_post(const double* evals, const double* H, int ell, int L, double alpha, double* M64, float* M32,
