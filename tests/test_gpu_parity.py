@@ -296,3 +296,33 @@ def test_widest_panel_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
     assert sk.stats()["flushes"] == o.flushes == 3
     assert evaluate.gram_distance(B, o.sketch()) <= TOL
     assert sk.last_live == o.query()[1]
+
+
+def test_widest_panels_exact_buffers_and_ell_equal_d(gpu_lib):
+    # ell = d = 200: every buffer (rows = d = ell) is kept exactly (dense rows on 256-wide
+    # panels), the first fold is lossless and the later ones shrink a 400 x 400 stack
+    st = small_random_csr(600, 200, 12, 12, dist="lognormal")
+    o = _oracle(st, 200)
+    sk, B = _gpu_sketch(gpu_lib, st, 200)
+    assert sk.stats()["flushes"] == o.flushes == 3
+    assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+def test_widest_panels_merge_and_verify_off(gpu_lib):
+    # ell = 180 without VerifySpectral, sketched in two shards and merged (Sec. 2.1)
+    st = small_random_csr(1800, 500, 30, 13, dist="lognormal")
+    shards = [(0, 1100), (1100, 1800)]
+    gs, os_ = [], []
+    for k, (lo, hi) in enumerate(shards):
+        sub = st.rows(lo, hi)
+        g = gpu_lib.Sketch(st.d, 180, stream_id=k, verify=0)
+        g.append_csr(*_dev(sub))
+        gs.append(g)
+        o = SFDOracle(st.d, 180, 0.25, 0, stream_id=k, unit_roundoff=U32, verify=False)
+        o.append_csr(sub.indptr, sub.indices, sub.values)
+        os_.append(o)
+    gs[0].merge(gs[1])
+    os_[0].merge(os_[1])
+    B = gs[0].sketch().cpu().numpy().astype(np.float64)
+    assert evaluate.gram_distance(B, os_[0].sketch()) <= TOL
+    assert gs[0].stats()["vs_calls"] == 0
