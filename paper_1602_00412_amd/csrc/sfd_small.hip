@@ -11,7 +11,7 @@ namespace sfd {
 namespace {
 
 constexpr int kCholMax = 128;      // register-resident factor and inverse together
-constexpr int kCholMaxWide = 256;  // factor and inverse in two passes (8 and 16 waves: what their registers hold)
+constexpr int kCholMaxWide = 256;  // factor and inverse in two passes of 8 waves each
 
 // 1/sqrt(x) for x > 0: the hardware estimate refined by one Newton step (relative error
 // about one unit in the last place).
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * NW) void k_chol_factor_wide(const double* __re
 #pragma unroll
   for (int u = 0; u < CPL; ++u) d0[u] = W[(cn[u] ? col[u] : 0) * ldw + (cn[u] ? col[u] : 0)];
   int drops = 0;
-#pragma unroll
+#pragma clang loop unroll(full)  // static register indices need the whole loop unrolled
   for (int sk = 0; sk < S; ++sk) {
     const int uk = sk / SG;
     for (int wk = 0; wk < NW; ++wk) {
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(64 * NW) void k_chol_inverse_wide(const double* __r
     for (int u = 0; u < CPL; ++u)
       if (s < SG * (u + 1)) t[s][u] = 0.0;
   const double* ivd = Rw + LD * LD;
-#pragma unroll
+#pragma clang loop unroll(full)  // static register indices need the whole loop unrolled
   for (int si = S - 1; si >= 0; --si) {
     for (int wi = NW - 1; wi >= 0; --wi) {
       const int i = NW * si + wi;
@@ -678,7 +678,7 @@ hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, 
   } else {
     if (!Rw) return hipErrorInvalidValue;
     k_chol_factor_wide<8><<<K, 512, 0, st>>>(W, ldw, ell, tau, Rw, sc, wstride, chol_work_doubles(L));
-    k_chol_inverse_wide<16><<<K, 1024, 0, st>>>(Rw, ell, L, T, chol_work_doubles(L));
+    k_chol_inverse_wide<8><<<K, 512, 0, st>>>(Rw, ell, L, T, chol_work_doubles(L));
   }
   return hipGetLastError();
 }
