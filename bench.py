@@ -246,8 +246,14 @@ def main() -> int:
     # HIP maps streams onto a per-process pool of hardware queues (4 by default): with 8 (16 for
     # the batch's 16 lanes) every lane stream and torch's stream get a queue of their own, so
     # concurrent buffer steps do not serialise behind one another.  Set before HIP starts; a
-    # value already in the environment is kept.
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16" if args.workload == "config4" else "8")
+    # larger value already in the environment is kept.
+    want = 16 if args.workload == "config4" else 8
+    try:
+        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        have = 0
+    if have < want:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(want)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
               f"one merge at the end, which this build does not run across GPUs", file=sys.stderr)
