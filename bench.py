@@ -29,18 +29,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # HBM traffic of one product measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # per dispatch, the factors that make a plain 1 GiB copy read as 1 GiB each way), summed over the
-# product's kernels.  Valid only for the kernel source it was taken with (sha256 prefix).
+# product's kernels.  Valid only for the workload, panel precision and kernel source it was taken
+# with (sha256 prefix).
 MEASURED_TRAFFIC = {
-    # class: (bytes per call, source file, sha256 prefix of that file, summary under profiles/)
-    "spmm_csc": (1.2192e+09, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "cf72d36e6ce4cb3c",
+    # (class, workload, precision): (bytes per call, source file, sha256 prefix, summary)
+    ("spmm_csc", "config2", "fp32"): (1.2192e+09, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "cf72d36e6ce4cb3c",
                  "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
 }
 
 
-def measured_traffic(cls: str):
+def measured_traffic(cls: str, workload: str, precision: str):
     import hashlib
 
-    ent = MEASURED_TRAFFIC.get(cls)
+    ent = MEASURED_TRAFFIC.get((cls, workload, precision))
     if not ent:
         return None
     nbytes, src, sha, _ = ent
@@ -229,6 +230,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
     ap.add_argument("--batch-streams", type=int, default=64,
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
+    ap.add_argument("--hw-queues", type=int, default=0, choices=[0, 1, 2, 4, 8, 16, 32],
+                    help="HIP hardware queues for this process (0: at least 16)")
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -243,17 +246,21 @@ def main() -> int:
                          "against FrequentDirections on the GPU")
     ap.add_argument("--c4-streams", type=int, default=4096, help="config4: the first this many streams")
     args = ap.parse_args()
-    # HIP maps streams onto a per-process pool of hardware queues (4 by default): with 8 (16 for
-    # the batch's 16 lanes) every lane stream and torch's stream get a queue of their own, so
-    # concurrent buffer steps do not serialise behind one another.  Set before HIP starts; a
-    # larger value already in the environment is kept.
-    want = 16 if args.workload == "config4" else 8
-    try:
-        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
-    except ValueError:
-        have = 0
-    if have < want:
-        os.environ["GPU_MAX_HW_QUEUES"] = str(want)
+    # HIP maps streams onto a per-process pool of hardware queues (4 by default) and streams
+    # beyond it share queues: with 16, torch's stream and the lane and main streams of both
+    # handles created here (FP32 line, BF16 form; or the batch's 16 lanes) get queues of their
+    # own, so concurrent buffer steps do not serialise behind one another.  Set before HIP
+    # starts; a larger value already in the environment is kept.
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    else:
+        want = 16
+        try:
+            have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+        except ValueError:
+            have = 0
+        if have < want:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(want)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
               f"one merge at the end, which this build does not run across GPUs", file=sys.stderr)
@@ -374,7 +381,7 @@ def main() -> int:
         else:
             achieved = p["bytes"] / p["calls"] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None if args.csc_bands else measured_traffic(dom, args.workload, args.precision)}
         bfk = args.precision == "bf16"
         Lw = 32 if ell <= 32 else 64 if ell <= 64 else 128 if ell <= 128 else 256
         roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {str(bfk).lower()}, "

@@ -1,8 +1,9 @@
 """The large single-stream workload (d = 1e6, ell = 100, 128-wide panels) at its full shapes.
 
-The oracle costs a 1e6 x 100 Householder QR per product, so it is run on a prefix of the
-device-generated stream (one buffer folded by the query) with a shortened iteration count
-q = 3 on both sides: every kernel runs at the workload's d and panel width.
+The oracle costs a 1e6 x 100 Householder QR per product and two SVDs of 1e6-wide stacks, so it
+is run once, on a prefix of the device-generated stream (one buffer folded by the query), with a
+shortened iteration count q = 3 on both sides: every kernel runs at the workload's d and panel
+width.
 """
 
 import numpy as np
@@ -13,6 +14,7 @@ from oracle import SFDOracle, evaluate
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.timeout(170)
 def test_large_stream_prefix_matches_oracle(gpu_lib):
     import torch
 
@@ -26,8 +28,9 @@ def test_large_stream_prefix_matches_oracle(gpu_lib):
     sk = gpu_lib.Sketch(d, ell, 0.25, 0, q=3)
     sk.append_csr(ptr, idx, val)
     B = sk.sketch().cpu().numpy().astype(np.float64)
-    assert sk.stats()["flushes"] == 0 and sk.last_live == o.query()[1] == ell - 1
-    assert evaluate.gram_distance(B, o.sketch()) <= 1e-4
+    Bo, live_o, _ = o.query()  # about a minute of FP64 work at d = 1e6: queried once
+    assert sk.stats()["flushes"] == 0 and sk.last_live == live_o == ell - 1
+    assert evaluate.gram_distance(B, Bo) <= 1e-4
 
 
 def test_batch_streams_from_the_device_generator(gpu_lib):
