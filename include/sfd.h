@@ -60,10 +60,13 @@ enum {
   SFD_OPT_STREAM_ID = 5,    /* second word of the random key; default 0 */
   SFD_OPT_PROFILE = 6,      /* 1: time every kernel class with HIP events and clear the
                                counters; 0: stop timing.  Default 0. */
-  SFD_OPT_CSC_BANDS = 7,    /* row bands of the transposed products A'^T Y (0..8): with k > 1 the
-                               buffer's rows are cut into k bands gathered by different XCDs and
-                               the bands' sums added afterwards; 0 or 1 = one band (default).
-                               Results agree to rounding. */
+  SFD_OPT_CSC_BANDS = 7,    /* XCD-local pieces in the transposed products A'^T Y: 0 automatic
+                               (default: on when the gathered panel, rows(A') x panel width, is
+                               4-64 MB), 1 off, 8 on.  On: the buffer's rows are cut into 8 bands
+                               of about nnz/8 entries, every column with at least
+                               SFD_OPT_CSC_HOT_MIN entries is cut at the band boundaries, and the
+                               pieces of band b run on the workgroups dispatched to XCD b (its L2
+                               then holds that band's rows of Y).  Results agree to rounding. */
   SFD_OPT_LANES = 8,        /* lanes (HIP streams) that run successive buffers' SparseShrink
                                concurrently, 1..4; default 4.  Results do not depend on it. */
   SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
@@ -72,11 +75,15 @@ enum {
                                takes its transform from that Y's own Gram and writes FP32, so
                                B'^T B' <= A'^T A' (Property 1) still holds for the FP32 values.
                                Only the subspace quality changes (cov-err, Sec. 4). */
-  SFD_OPT_ALGORITHM = 10    /* SFD_ALGO_SFD (default): Alg 2's flush rule (rows(A') = d or
+  SFD_OPT_ALGORITHM = 10,   /* SFD_ALGO_SFD (default): Alg 2's flush rule (rows(A') = d or
                                nnz(A') >= ell*d) and BoostedSparseShrink; SFD_ALGO_FD: the
                                paper's comparator FrequentDirections (Sec. 2.1) in batches of
                                ell rows -- the buffer flushes at ell rows and is folded exactly
                                by DenseShrink (Alg 5).  Applies to the flushes that follow. */
+  SFD_OPT_CSC_HOT_MIN = 11  /* entries from which a column is cut into XCD-local pieces
+                               (SFD_OPT_CSC_BANDS), >= 1; default 64.  Raised to
+                               ceil(nnz(A') / 32768) for a buffer, so at most 32768 columns are
+                               cut. */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */
@@ -90,7 +97,7 @@ enum {
   SFD_PROF_EIG = 6,       /* FP64 symmetric eigensolves */
   SFD_PROF_VS = 7,        /* VerifySpectral power steps (Alg 6) */
   SFD_PROF_OTHER = 8,     /* start blocks, shrink factors, copies */
-  SFD_PROF_FIXUP = 9,     /* long-row fix-ups (and band sums) that complete a sparse product */
+  SFD_PROF_FIXUP = 9,     /* long-row and hot-column fix-ups that complete a sparse product */
   SFD_PROF_COUNT = 10
 };
 

@@ -38,6 +38,7 @@ constexpr double kCholDropTol = 1e-5;                 // relative residual^2 bel
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
 constexpr int kLanes = 16;        // lanes of a batch handle; a single-stream handle uses 4
 constexpr int kLanesSingle = 4;
+constexpr int kHotMinDefault = 64;  // entries from which a column is cut into XCD-local pieces
 
 // State of one stream (Alg 2): the sketch B (stored transposed, d x L), the pending buffer A'
 // (CSR), the flush index b, the persistent VerifySpectral counter i and the structural count
@@ -73,7 +74,6 @@ struct Lane {
   int* scan_tmp = nullptr;
   Schedule sr{}, scs{};
   float* partial = nullptr;
-  float* bandbuf = nullptr;  // per-band output rows of the banded CSC products (kMaxBands * d x L)
   // panels and small work
   float *X = nullptr, *Y = nullptr, *Pt = nullptr;
   uint16_t *Xb = nullptr, *Yb = nullptr;  // BF16 panels of the precision form
@@ -139,7 +139,8 @@ struct sfd_s {
   int q_override = 0;
   int max_attempts = 16;
   int verify = 1;
-  int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic
+  int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic, 1 off, kXcdBands on
+  int hot_min = kHotMinDefault;  // SFD_OPT_CSC_HOT_MIN
   int lanes_alloc = kLanesSingle;  // lanes with workspaces
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
@@ -321,11 +322,12 @@ int alloc_state(sfd_t* h) {
   const int64_t cap = h->ell * d + d;
   h->cap = cap;
   const int64_t tiles = (cap + 2047) / 2048;
-  // chunk capacity: one per row of the unbanded CSC (empty rows included), or one per
-  // non-empty row of the banded CSC, plus the extra chunks of long rows
-  const int64_t max_chunks = std::max<int64_t>(d, std::min<int64_t>(kMaxBands * d, cap)) + cap / kSpmmChunk + 2;
-  const int64_t slots = 2 * cap / kSpmmChunk + 16;
-  const int64_t band_rows = kMaxBands * d + 1;
+  // chunk capacity: one per row (empty rows included) plus the extra chunks of long rows, and
+  // for the CSC with XCD-local pieces up to kXcdBands pieces of each of at most kHotCap hot
+  // columns; partial slots likewise
+  const int64_t max_chunks = d + 2 * cap / kSpmmChunk + (int64_t)kXcdBands * kHotCap + 2;
+  const int64_t slots = 2 * cap / kSpmmChunk + 16 + (int64_t)kXcdBands * kHotCap;
+  const int64_t vrows = (int64_t)(kXcdBands + 1) * d + 1;  // chunk-count rows of the hot schedule
   bool ok = true;
   for (StreamState& ss : h->streams) {
     ok = ok && dalloc(h, &ss.B, d * L);
@@ -337,22 +339,20 @@ int alloc_state(sfd_t* h) {
   for (int li = 0; li < h->lanes_alloc; ++li) {
     Lane& ln = h->lanes[li];
     ok = ok && dalloc(h, &ln.own_rowptr, d + 1) && dalloc(h, &ln.Bq, d * L);
-    ok = ok && dalloc(h, &ln.cscptr, band_rows) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
+    ok = ok && dalloc(h, &ln.cscptr, d + 1) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
     ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
     ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
     ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
     ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
-    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, band_rows)) + 16);
+    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, vrows)) + 16);
     ln.csc.scan_tmp = ln.scan_tmp;
     for (Schedule* s : {&ln.sr, &ln.scs}) {
-      const int64_t rows = (s == &ln.scs) ? band_rows : d + 1;
-      ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, rows) && dalloc(h, &s->desc, max_chunks) &&
-           dalloc(h, &s->long_rows, rows) && dalloc(h, &s->counters, 4);
+      const int64_t rows = (s == &ln.scs) ? vrows : d + 1;
+      ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->desc, max_chunks) &&
+           dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4) && dalloc(h, &s->regions, kXcdBands + 2);
       s->max_chunks = max_chunks;
     }
-    // the banded CSC is offered for L <= 64 only
-    ok = ok && dalloc(h, &ln.partial, slots * L) && dalloc(h, &ln.bandbuf, L <= 64 ? kMaxBands * d * L : 1);
-    ln.scs.bandbuf = ln.bandbuf;
+    ok = ok && dalloc(h, &ln.partial, slots * L);
     ln.scs.transposed = true;
     ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
     ok = ok && dalloc(h, &ln.Xb, d * L) && dalloc(h, &ln.Yb, d * L);
@@ -460,43 +460,46 @@ int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType
                  2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 1);
     CK(spmm(ln.scs, ln.cscrow, ln.cscval, Y, yt, h->L, X, xt, h->L, h->L, ln.partial, ln.st));
   }
-  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, ln.scs.bands > 1 ? 2 : 1);
+  ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
   CK(spmm_finish(ln.scs, ln.partial, X, xt, h->L, h->L, ln.st));
   return SFD_OK;
 }
 
-// Buffer set-up on the lane: CSC (with ||A'||_F^2) and, for m > ell, the chunk schedules.
-// Row bands of the buffer's CSC (SFD_OPT_CSC_BANDS): the transposed products gather rows of the
-// m x L panel Y; with k bands, band b's rows are gathered by the blocks dispatched to XCD b
-// (mod 8) only, and the bands' sums are added afterwards.  Off unless asked for: on a 1e5-row
-// buffer it cuts the product's L2 misses about 4x, but the band reduction costs more than the
-// product saves.
-int csc_bands(const sfd_t* h, const Lane& ln) {
-  if (ln.m <= h->ell || ln.nnz == 0 || h->precision != SFD_PRECISION_FP32 || h->L > 64) return 1;
-  if ((int64_t)kMaxBands * h->d + 1 >= ((int64_t)1 << 31)) return 1;  // int32 keys and row ids
-  return h->bands_opt > 0 ? std::min(h->bands_opt, kMaxBands) : 1;
+// XCD-local pieces of the hot columns for the transposed products of a buffer of m rows
+// (SFD_OPT_CSC_BANDS): automatic when the gathered panel (m rows of the panel width) is larger
+// than one XCD's L2 (4 MB) and one band of it (an eighth) still fits in twice that; the lockstep
+// groups of a batch handle build plain schedules, so such buffers take the lanes there.
+bool csc_hot(const sfd_t* h, int64_t m, int64_t nnz) {
+  if (m <= h->ell || nnz == 0 || h->bands_opt == 1) return false;
+  if (h->bands_opt == kXcdBands) return true;
+  const int64_t bytes = m * h->L * (h->precision == SFD_PRECISION_BF16 ? 2 : 4);
+  return bytes > ((int64_t)4 << 20) && bytes <= ((int64_t)64 << 20);
 }
 
+// Buffer set-up on the lane: CSC (with ||A'||_F^2) and, for m > ell, the chunk schedules.
 int prepare(sfd_t* h, Lane& ln) {
   const int64_t d = h->d;
-  const int bands = csc_bands(h, ln);
   {
     ProfScope ps(h, ln.st, SFD_PROF_CSC_BUILD, 16.0 * ln.nnz + 4.0 * (ln.m + d), 0.0, 1);
     const int* keys = nullptr;
-    CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, bands, ln.cscptr, ln.cscrow, ln.cscval, ln.csc,
-                 &keys, ln.st));
-    CK(fro2_segments(ln.cscptr, keys, ln.cscrow, ln.cscval, bands * d, 1, ln.csc.part, ln.sc, ln.st));
+    CK(build_csc(ln.rowptr, ln.colidx, ln.val, ln.m, ln.nnz, d, ln.cscptr, ln.cscrow, ln.cscval, ln.csc, &keys,
+                 ln.st));
+    CK(fro2_segments(ln.cscptr, keys, ln.cscrow, ln.cscval, d, 1, ln.csc.part, ln.sc, ln.st));
   }
-  ln.scs.bands = bands;
-  ln.scs.band_rows = (int)d;
   if (ln.m > h->ell) {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 2);
-    const int64_t cap_chunks = std::max<int64_t>(d, std::min<int64_t>(kMaxBands * d, h->cap)) + h->cap / kSpmmChunk + 2;
-    ln.sr.max_chunks = std::min<int64_t>(cap_chunks, (int64_t)ln.m + ln.nnz / kSpmmChunk + 2);
-    ln.scs.max_chunks = std::min<int64_t>(
-        cap_chunks, (bands > 1 ? std::min<int64_t>(bands * d, ln.nnz) : d) + ln.nnz / kSpmmChunk + 2);
+    ln.sr.max_chunks = (int64_t)ln.m + (int64_t)ln.nnz / kSpmmChunk + 2;
     CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
-    CK(schedule_build(ln.cscptr, (int)(bands * d), ln.scs, ln.scan_tmp, ln.st));
+    if (csc_hot(h, ln.m, ln.nnz)) {
+      // at most nnz / hot columns reach `hot`, so at most kHotCap
+      const int64_t hot = std::max<int64_t>(h->hot_min, (ln.nnz + kHotCap - 1) / kHotCap);
+      ln.scs.max_chunks = d + 2 * (int64_t)ln.nnz / kSpmmChunk + kXcdBands * std::min<int64_t>(d, ln.nnz / hot) + 2;
+      CK(schedule_build_hot(ln.cscptr, ln.cscrow, (int)d, ln.rowptr, ln.m, ln.nnz, (int)hot, ln.scs, ln.scan_tmp,
+                            ln.st));
+    } else {
+      ln.scs.max_chunks = d + (int64_t)ln.nnz / kSpmmChunk + 2;
+      CK(schedule_build(ln.cscptr, (int)d, ln.scs, ln.scan_tmp, ln.st));
+    }
   }
   return SFD_OK;
 }
@@ -558,7 +561,7 @@ int verify_spectral(sfd_t* h, Lane& ln, int attempt, int t) {
   const int64_t d = h->d;
   const int m = ln.m;
   ProfScope ps(h, ln.st, SFD_PROF_VS, t * (16.0 * ln.nnz + 8.0 * d * ell + 4.0 * (2.0 * m + 6.0 * d)),
-               t * (4.0 * ln.nnz + 4.0 * d * ell), (ln.scs.bands > 1 ? 9 : 8) * t + 3);
+               t * (4.0 * ln.nnz + 4.0 * d * ell), 8 * t + 3);
   CK(start_block(h->seed, ln.ss->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w,
                  1, ln.st));
   CK(vs_init(ln.vs_w, d, ln.vs_npart, ln.sc, ln.st));
@@ -694,7 +697,7 @@ int alloc_group(sfd_t* h, int kmax) {
   for (Schedule* sch : {&g.sr, &g.scs}) {
     const int64_t rows = g.cap_rows + 1;
     ok = ok && dalloc(h, &sch->nch, rows) && dalloc(h, &sch->pslot, rows) && dalloc(h, &sch->desc, max_chunks) &&
-         dalloc(h, &sch->long_rows, rows) && dalloc(h, &sch->counters, 4);
+         dalloc(h, &sch->long_rows, rows) && dalloc(h, &sch->counters, 4) && dalloc(h, &sch->regions, kXcdBands + 2);
     sch->max_chunks = max_chunks;
   }
   g.scs.transposed = true;
@@ -836,7 +839,7 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
       CK(hipMemcpyAsync(g.val + E[(size_t)k], v.val, sizeof(float) * v.nnz, hipMemcpyDeviceToDevice, st));
   }
   const int* keys = nullptr;
-  CK(build_csc(g.rowptr, g.colidx, g.val, (int)M, (int)NNZ, (int64_t)K * d, 1, g.cscptr, g.cscrow, g.cscval, g.csc,
+  CK(build_csc(g.rowptr, g.colidx, g.val, (int)M, (int)NNZ, (int64_t)K * d, g.cscptr, g.cscrow, g.cscval, g.csc,
                &keys, st));
   CK(fro2_segments(g.cscptr, keys, g.cscrow, g.cscval, d, K, g.fro_part, g.sc, st));
   g.sr.max_chunks = M + NNZ / kSpmmChunk + 2;
@@ -997,7 +1000,7 @@ int run_batched(sfd_t* h, const std::vector<BufferView>& views) {
     std::vector<BufferView> small;
     std::vector<GroupItem> items;
     for (auto& e : round) {
-      if (e.first.m <= h->ell || h->grp.kmax == 0) {
+      if (e.first.m <= h->ell || h->grp.kmax == 0 || csc_hot(h, e.first.m, e.first.nnz)) {
         small.push_back(e.first);
         continue;
       }
@@ -1376,8 +1379,12 @@ int sfd_set_option(sfd_t* h, int key, double value) {
       h->algorithm = (int)value;
       return SFD_OK;
     case SFD_OPT_CSC_BANDS:
-      if (!(value >= 0 && value <= kMaxBands) || value != std::floor(value)) return SFD_E_ARG;
+      if (value != 0 && value != 1 && value != kXcdBands) return SFD_E_ARG;
       h->bands_opt = (int)value;
+      return SFD_OK;
+    case SFD_OPT_CSC_HOT_MIN:
+      if (!(value >= 1 && value <= (double)(1 << 30)) || value != std::floor(value)) return SFD_E_ARG;
+      h->hot_min = (int)value;
       return SFD_OK;
     default:
       return SFD_E_ARG;
@@ -1617,13 +1624,13 @@ int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
     return SFD_OK;
   };
   // streams without pending rows: B itself; pending buffers of more than ell rows: lockstep
-  // groups (purposes 2/3, nothing stored); the others: the lanes
+  // groups (purposes 2/3, nothing stored) unless they take XCD-local pieces; the others: the lanes
   std::vector<int32_t> lane_q, grp_q;
   for (int32_t s = 0; s < (int32_t)h->streams.size(); ++s) {
     StreamState& ss = h->streams[(size_t)s];
     if (ss.pm == 0) {
       if ((rc = emit(ss.B, s, l0.st, l0.X))) return rc;
-    } else if (ss.pm > h->ell && h->grp.kmax > 0) {
+    } else if (ss.pm > h->ell && h->grp.kmax > 0 && !csc_hot(h, ss.pm, ss.pnnz)) {
       grp_q.push_back(s);
     } else {
       lane_q.push_back(s);

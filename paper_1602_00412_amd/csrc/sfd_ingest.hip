@@ -83,20 +83,13 @@ __global__ void k_colptr_from_sorted(const int* keys, int nnz, int64_t d, int* c
   }
 }
 
-// rowid[k] = row of entry k; with bands > 1 also keys[k] = band(row) * d + column, the band of
-// a row being floor(rowptr[row] * bands / nnz) (contiguous bands of about nnz / bands entries)
-__global__ void k_expand_rowid(const int* rowptr, int m, int* rowid, const int* colidx, int nnz, int bands, int d,
-                               int* keys) {
+// rowid[k] = row of entry k
+__global__ void k_expand_rowid(const int* rowptr, int m, int* rowid) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   int stride = gridDim.x * blockDim.x;
   for (; r < m; r += stride) {
     int a = rowptr[r], b = rowptr[r + 1];
     for (int k = a; k < b; ++k) rowid[k] = r;
-    if (keys) {
-      int band = (int)(((int64_t)a * bands) / nnz);
-      if (band > bands - 1) band = bands - 1;
-      for (int k = a; k < b; ++k) keys[k] = band * d + colidx[k];
-    }
   }
 }
 
@@ -264,20 +257,19 @@ hipError_t append_rowptr(const int64_t* indptr, int64_t r0, int64_t cnt, int* ro
   return hipGetLastError();
 }
 
-hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, const int** sorted_keys, hipStream_t st) {
   hipError_t e;
-  const int64_t rows = d * bands;
+  const int64_t rows = d;
   *sorted_keys = w.keys0;
   if (nnz == 0) return fill_i32(cscptr, rows + 1, 0, st);
-  k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid, colidx, nnz, bands, (int)d,
-                                                         bands > 1 ? w.keys1 : nullptr);
-  // stable LSD radix sort of the (band, column) keys, payload = entry index
+  k_expand_rowid<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, w.rowid);
+  // stable LSD radix sort of the column ids, payload = entry index
   int bits = 1;
   while ((int64_t(1) << bits) < rows) ++bits;
   int passes = (bits + 7) / 8;
   int ntiles = (nnz + kRsTile - 1) / kRsTile;
-  const int* kin = bands > 1 ? w.keys1 : colidx;
+  const int* kin = colidx;
   const int* vin = nullptr;
   int* kout = w.keys0;
   int* vout = w.vals0;

@@ -9,7 +9,8 @@ namespace sfd {
 
 constexpr int kMaxEll = 256;     // panels up to 256 wide; FP64 eigensolves up to 512 x 512
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
-constexpr int kMaxBands = 8;     // row bands of the banded CSC (one per XCD)
+constexpr int kXcdBands = 8;     // row bands of the hot-column pieces (one per XCD)
+constexpr int kHotCap = 32768;   // hot columns a transposed-product schedule holds at most
 
 // One buffer of a lockstep group (buffers of several streams running their SimultaneousIteration
 // together, one launch per step for all of them): its segment of a stacked panel (first row,
@@ -76,12 +77,8 @@ struct CscWork {
   int* hist;      // 256 * tiles
   double* part;   // reduction partials
 };
-// With bands > 1 the buffer's rows are split into `bands` contiguous bands of about nnz/bands
-// entries (row r is in band floor(rowptr[r] * bands / nnz)) and the structure becomes the
-// concatenation of the bands' CSCs: "row" b*d + c of cscptr (bands*d + 1 entries) holds the
-// entries of column c in band b.  Rows stay ascending inside every column.
-// *sorted_keys: the entries' sorted keys (band * d + column), in one of w's arrays
-hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d, int bands,
+// *sorted_keys: the entries' sorted column ids, in one of w's arrays
+hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int m, int nnz, int64_t d,
                      int* cscptr, int* cscrow, float* cscval, CscWork& w, const int** sorted_keys, hipStream_t st);
 // ||A'||_F^2 with repeated (row, column) entries summed, for each of K column segments of d
 // columns of a CSC (keys: its entries' sorted column ids, from build_csc) (the buffers of a group; K = 1 for one buffer) into sc[k].fro2A; part holds
@@ -98,31 +95,39 @@ hipError_t dense_from_csc(const int* cscptr, const int* cscrow, const float* csc
 // ---------------------------------------------------------------- sparse products (sfd_spmm.hip)
 struct Schedule {
   int* nch;          // rows + 1 : chunks per row -> scanned chunk start; nch[rows] = number of chunks
-  int* pslot;        // rows + 1 : partial slots per long row -> scanned slot start
-  int4* desc;        // chunk -> {row, first entry, end entry, partial slot or -1 (whole row)}
-  int* long_rows;    // rows split into several chunks
+  int* pslot;        // output rows + 1 : partial slots per long output row -> scanned slot start
+  int4* desc;        // chunk -> {output row, first entry, end entry, partial slot or -1 (whole row)}
+  int* long_rows;    // output rows whose chunks write partial slots
   int* counters;     // [0] = number of long rows
+  int* regions;      // kXcdBands + 2 chunk offsets: the chunk ranges the product kernels walk
   int rows;          // rows of the structure the schedule was built for
   int64_t max_chunks;  // capacity of desc (bounds the grid)
-  // banded CSC (build_csc with bands > 1): rows = bands * band_rows; empty rows get no chunk;
-  // products write raw per-band rows into bandbuf (rows x L floats) and a reduction adds the
-  // bands of each output row
-  int bands = 1;
-  int band_rows = 0;
-  float* bandbuf = nullptr;
+  // 0: one chunk range [regions[0], regions[1]) walked by every block.  kXcdBands (hot-column
+  // pieces of a CSC, schedule_build_hot): range b < kXcdBands holds the pieces of the hot
+  // columns whose entries lie in row band b, walked by the blocks with blockIdx % kXcdBands == b
+  // (dispatched to XCD b, so the rows they gather stay in that XCD's L2); range kXcdBands holds
+  // the other columns, walked by every block.
+  int nlocal = 0;
   bool transposed = false;  // the CSC of a buffer (A'^T products); only names the kernels apart
 };
-// builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation);
-// with s.bands > 1 the structure is a banded CSC of s.band_rows columns per band
+// builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
+// The schedule of a buffer's CSC (d columns, rows ascending in every column) with XCD-local
+// pieces: the rows of the buffer (CSR rowptr, m rows, nnz entries) are cut into kXcdBands
+// contiguous bands of about nnz / kXcdBands entries (row r in band floor(rowptr[r] kXcdBands /
+// nnz)); a column of at least hot_min entries is cut at the band boundaries, and its pieces'
+// chunks all write partial slots that the fix-up adds in band order, then chunk order.  s.nch
+// holds (kXcdBands + 1) d + 1 ints, s.pslot d + 1, s.desc d + 2 nnz / kSpmmChunk + kXcdBands
+// hot columns + 2 (hot_min >= nnz / kHotCap keeps the hot columns within kHotCap).
+hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const int* rowptr, int m, int nnz,
+                              int hot_min, Schedule& s, int* scan_tmp, hipStream_t st);
 // Y[r, :] = sum_k val[k] X[idx[k], :] over the structure of schedule s (its entries idx, val);
-// rows of width L (32, 64 or 128; banded: 32 or 64) with pitches ldx / ldy in elements; FP32 accumulation.  Panel
-// types: F32 -> F32, BF16 -> BF16 and BF16 -> F32.  For a banded schedule (F32 only) r runs over
-// the band_rows output rows and the bands are added in band order by spmm_finish.  This launches
-// the main kernel only; spmm_finish completes the product.
+// rows of width L (32, 64, 128 or 256) with pitches ldx / ldy in elements; FP32 accumulation.
+// Panel types: F32 -> F32, BF16 -> BF16 and BF16 -> F32.  This launches the main kernel only;
+// spmm_finish completes the product.
 hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
                 PanelType yt, int ldy, int L, float* partial, hipStream_t st);
-// the long rows' fix-up of a product (and for a banded schedule the band sums)
+// the long rows' fix-up of a product
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1); for a group's stacked
 // structure (seg_rows: K + 1 row offsets, device) row r of buffer k is scaled by

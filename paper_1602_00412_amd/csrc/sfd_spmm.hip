@@ -5,8 +5,16 @@
 // kSpmmChunk stored entries, each described by {row, first entry, end entry, partial slot}.
 // Short rows are one chunk and are written directly; the chunks of a long row (Zipf-hot
 // columns in the CSC) write partial rows that a fix-up pass adds in chunk order, so results do
-// not depend on scheduling.  In the dense products an L/4-lane group owns one chunk at a time
-// and reads each dense row of width L as float4 (lane s: columns 4s..4s+3).
+// not depend on scheduling.  In the dense products an L/VEC-lane group owns one chunk at a time
+// and reads each dense row of width L as 16-byte segments (lane s: columns VEC s .. VEC s +
+// VEC - 1).
+//
+// XCD-local pieces (transposed products of large buffers): the gathered panel Y (m x L) is
+// larger than one XCD's L2, and a gather of a random row of it runs at the Infinity-Cache /
+// HBM rate.  The buffer's rows are cut into one band per XCD, and the hot columns (at least
+// hot_min entries) are cut at the band boundaries: the pieces of band b run only on the blocks
+// dispatched to XCD b, whose L2 then holds that band's rows of Y.  Short columns would pay
+// more for the pieces' partial rows than they save and keep one chunk range for all blocks.
 #include <algorithm>
 #include <utility>
 
@@ -26,13 +34,13 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
 }
 
 // chunks per row: one for a short row (also an empty one, whose output row is then written as
-// zeros, unless skip_empty), ceil(len / kSpmmChunk) for a long row
-__global__ void k_sched_counts(const int* ptr, int rows, int skip_empty, int* nch, int* pslot) {
+// zeros), ceil(len / kSpmmChunk) for a long row
+__global__ void k_sched_counts(const int* ptr, int rows, int* nch, int* pslot) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   int stride = gridDim.x * blockDim.x;
   for (; r < rows; r += stride) {
     int len = ptr[r + 1] - ptr[r];
-    int c = len <= kSpmmChunk ? (len > 0 || !skip_empty ? 1 : 0) : (len + kSpmmChunk - 1) / kSpmmChunk;
+    int c = len <= kSpmmChunk ? 1 : (len + kSpmmChunk - 1) / kSpmmChunk;
     nch[r] = c;
     pslot[r] = c > 1 ? c : 0;
   }
@@ -51,6 +59,104 @@ __global__ void k_sched_desc(const int* ptr, int rows, const int* chunk_start, c
       desc[c] = make_int4(r, bb, min(e, bb + kSpmmChunk), c1 - c0 > 1 ? slot_start[r] + k : -1);
     }
     if (c1 - c0 > 1) long_rows[atomicAdd(&counters[0], 1)] = r;
+  }
+}
+
+// regions[k] = chunk_start[k * span], k = 0 .. nreg (the chunk ranges of a schedule)
+__global__ void k_sched_regions(const int* chunk_start, int64_t span, int nreg, int* regions) {
+  const int k = threadIdx.x;
+  if (k <= nreg) regions[k] = chunk_start[(int64_t)k * span];
+}
+
+// rb[b] = first row of row band b (b = 0 .. kXcdBands; rb[kXcdBands] = m); row r is in band
+// min(kXcdBands - 1, floor(rowptr[r] kXcdBands / nnz)), so the bands are contiguous and hold
+// about nnz / kXcdBands entries each (a band may be empty).
+__global__ void k_band_rows(const int* rowptr, int m, int nnz, int* rb) {
+  auto band_of = [&](int r) {
+    const int b = (int)(((int64_t)rowptr[r] * kXcdBands) / nnz);
+    return b < kXcdBands - 1 ? b : kXcdBands - 1;
+  };
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (; r < m; r += stride) {
+    const int br = band_of(r);
+    const int bp = r > 0 ? band_of(r - 1) : -1;
+    for (int b = bp + 1; b <= br; ++b) rb[b] = r;
+    if (r == m - 1)
+      for (int b = br + 1; b <= kXcdBands; ++b) rb[b] = m;
+  }
+}
+
+// first position in [lo, hi) of the ascending rows a[] whose row is >= key
+__device__ inline int lower_row(const int* a, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Chunk counts of the CSC with XCD-local pieces: "row" b d + j (b < kXcdBands) holds the chunks
+// of hot column j's piece in row band b, "row" kXcdBands d + j those of a short column j (one
+// at least, so an empty column is written as zeros).  pslot[j] = partial slots of column j.
+__global__ void k_hot_counts(const int* ptr, const int* rowid, int d, int hot_min, const int* rb, int* nch,
+                             int* pslot) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (; j < d; j += stride) {
+    const int b = ptr[j], e = ptr[j + 1], len = e - b;
+    if (len >= hot_min) {
+      int lo = b, tot = 0;
+      for (int k = 0; k < kXcdBands; ++k) {
+        const int hi = k == kXcdBands - 1 ? e : lower_row(rowid, lo, e, rb[k + 1]);
+        const int c = (hi - lo + kSpmmChunk - 1) / kSpmmChunk;
+        nch[(int64_t)k * d + j] = c;
+        tot += c;
+        lo = hi;
+      }
+      nch[(int64_t)kXcdBands * d + j] = 0;
+      pslot[j] = tot > 1 ? tot : 0;
+    } else {
+      for (int k = 0; k < kXcdBands; ++k) nch[(int64_t)k * d + j] = 0;
+      const int c = len <= kSpmmChunk ? 1 : (len + kSpmmChunk - 1) / kSpmmChunk;
+      nch[(int64_t)kXcdBands * d + j] = c;
+      pslot[j] = c > 1 ? c : 0;
+    }
+  }
+}
+
+// Descriptors of the CSC with XCD-local pieces: a hot column's chunks take its partial slots in
+// band order, then chunk order (the order the fix-up adds them).
+__global__ void k_hot_desc(const int* ptr, const int* rowid, int d, int hot_min, const int* rb,
+                           const int* chunk_start, const int* slot_start, int4* desc, int* long_rows,
+                           int* counters) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (; j < d; j += stride) {
+    const int b = ptr[j], e = ptr[j + 1], len = e - b;
+    const int s0 = slot_start[j];
+    const bool split = slot_start[j + 1] > s0;  // the column's chunks write partial slots
+    if (len >= hot_min) {
+      int lo = b, done = 0;
+      for (int k = 0; k < kXcdBands; ++k) {
+        const int hi = k == kXcdBands - 1 ? e : lower_row(rowid, lo, e, rb[k + 1]);
+        const int c0 = chunk_start[(int64_t)k * d + j], c1 = chunk_start[(int64_t)k * d + j + 1];
+        for (int c = c0; c < c1; ++c) {
+          const int first = lo + (c - c0) * kSpmmChunk;
+          desc[c] = make_int4(j, first, min(hi, first + kSpmmChunk), split ? s0 + done + (c - c0) : -1);
+        }
+        done += c1 - c0;
+        lo = hi;
+      }
+    } else {
+      const int64_t v = (int64_t)kXcdBands * d + j;
+      const int c0 = chunk_start[v], c1 = chunk_start[v + 1];
+      for (int c = c0; c < c1; ++c) {
+        const int first = b + (c - c0) * kSpmmChunk;
+        desc[c] = make_int4(j, first, min(e, first + kSpmmChunk), split ? s0 + (c - c0) : -1);
+      }
+    }
+    if (split) long_rows[atomicAdd(&counters[0], 1)] = j;
   }
 }
 
@@ -151,42 +257,28 @@ __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::ra
   for (int u = 0; u < U; ++u) Seg<BF>::fma(v[u], x[u], acc);
 }
 
-// Y[r, :] = sum_k val[k] X[idx[k], :] over chunk descriptors, X and Y FP32 or BF16
-// panels (BIN / BOUT), FP32 accumulation.  A group of L/VEC lanes owns a chunk at a time (lane s
+// Y[r, :] = sum_k val[k] X[idx[k], :] over the chunk descriptors [c0, c1): this lane's group
+// takes chunks c0 + first, + stride, ...  A group of L/VEC lanes owns a chunk at a time (lane s
 // holds columns VEC s .. VEC s + VEC - 1) and walks it in blocks of L/VEC entries: lane s of the
 // group loads entry s of the block (coalesced), then the entries are broadcast inside the group
 // and their dense row segments gathered.  The next block's ids and values, and the next chunk's
 // descriptor, are loaded before the current block's gathers, so one memory latency per block is
-// exposed instead of three.  A group's chunks are c, c + S, c + 2S, ... in its band's chunk
-// range (S = all groups of the band).
-// Bands (bands > 1, banded CSC): band b's chunks run on the blocks with blockIdx % bands == b;
-// workgroups are dispatched round-robin over the 8 XCDs, so with 8 bands each XCD gathers from
-// its own band's rows of X only.
+// exposed instead of three.
 // Output: a whole row goes to out[r], the chunks of a long row to their FP32 partial slots (the
-// fix-up adds them in chunk order).  The inverse Cholesky factor of the input panel is applied to
-// the output afterwards (xform_gram), together with the output's Gram.
-template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT>
-__global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ chunk_start,
-                                              int bands, int band_rows, const int* __restrict__ idx,
-                                              const float* __restrict__ val, const void* __restrict__ X, int ldx,
-                                              void* __restrict__ out, int ldo, float* __restrict__ partial) {
+// fix-up adds them in slot order).
+template <int L, int U, bool BIN, bool BOUT>
+__device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_t c0, int64_t c1, int64_t first,
+                                           int64_t stride, const int* __restrict__ idx,
+                                           const float* __restrict__ val, const void* __restrict__ X, int ldx,
+                                           void* __restrict__ out, int ldo, float* __restrict__ partial) {
   using S = Seg<BIN>;
   constexpr int VEC = S::VEC;
   constexpr int LPR = L / VEC;  // lanes per group
-  constexpr int G = 64 / LPR;   // groups per wave
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int sub = lane % LPR;
-  const int grp = lane / LPR;
-  const int band = blockIdx.x % bands;
-  const int slot = blockIdx.x / bands;
-  const int c0 = chunk_start[(int64_t)band * band_rows];
-  const int c1 = chunk_start[(int64_t)(band + 1) * band_rows];
-  const int64_t stride = (int64_t)(gridDim.x / bands) * 4 * G;
+  const int sub = (threadIdx.x & 63) % LPR;
   const typename S::raw* Xs = reinterpret_cast<const typename S::raw*>(X);
   const int lds = ldx / VEC;  // row pitch in segments
   const size_t out_row_bytes = (size_t)ldo * (BOUT ? 2 : 4);
-  int64_t cc = c0 + ((int64_t)slot * 4 + wave) * G + grp;
+  int64_t cc = c0 + first;
   int4 dc = cc < c1 ? desc[cc] : make_int4(0, 0, 0, -1);
   int64_t ncc = cc + stride;
   int4 dn = ncc < c1 ? desc[ncc] : make_int4(0, 0, 0, -1);
@@ -243,11 +335,33 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
   }
 }
 
-// One block per long row: wave w adds the row's partials w, w + 4, ... (in order), then the
-// four wave sums are added in wave order.
+// The product over a schedule's chunk ranges.  nlocal = 0: every block walks [regions[0],
+// regions[1]).  nlocal = kXcdBands: a block first walks the pieces of its XCD's row band
+// (range blockIdx % nlocal, shared with the other blocks of that XCD), then its share of the
+// short columns' range (range nlocal, shared with all blocks); gridDim.x is a multiple of nlocal.
+template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT>
+__global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ regions,
+                                              int nlocal, const int* __restrict__ idx,
+                                              const float* __restrict__ val, const void* __restrict__ X, int ldx,
+                                              void* __restrict__ out, int ldo, float* __restrict__ partial) {
+  constexpr int G = 64 / (L / Seg<BIN>::VEC);  // groups per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int grp = lane / (L / Seg<BIN>::VEC);
+  if (nlocal > 0) {
+    const int band = blockIdx.x % nlocal;
+    const int64_t slot = blockIdx.x / nlocal;
+    spmm_range<L, U, BIN, BOUT>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
+                                (int64_t)(gridDim.x / nlocal) * 4 * G, idx, val, X, ldx, out, ldo, partial);
+  }
+  spmm_range<L, U, BIN, BOUT>(desc, regions[nlocal], regions[nlocal + 1], ((int64_t)blockIdx.x * 4 + wave) * G + grp,
+                              (int64_t)gridDim.x * 4 * G, idx, val, X, ldx, out, ldo, partial);
+}
+
+// One block per long row: wave w adds the row's partials w, w + 4, ... (in slot order), then
+// the four wave sums are added in wave order.
 template <int L, bool BOUT>
-__global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ chunk_start,
-                                                    const int* __restrict__ slot_start,
+__global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ slot_start,
                                                     const int* __restrict__ long_rows, const int* __restrict__ nlong_ptr,
                                                     const float* __restrict__ partial, void* __restrict__ Y,
                                                     int ldy) {
@@ -258,7 +372,7 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ chun
   const int nlong = *nlong_ptr;
   for (int li = blockIdx.x; li < nlong; li += gridDim.x) {
   const int r = long_rows[li];
-  const int n = chunk_start[r + 1] - chunk_start[r];
+  const int n = slot_start[r + 1] - slot_start[r];
   const float* base = partial + (int64_t)slot_start[r] * L;
   float acc[CPL];
 #pragma unroll
@@ -349,8 +463,7 @@ __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, con
 }
 
 // One wave per long row: lane j adds partials j, j + 64, ...; then an xor-tree over the wave.
-__global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ chunk_start,
-                                                    const int* __restrict__ slot_start,
+__global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ slot_start,
                                                     const int* __restrict__ long_rows, const int* __restrict__ nlong_ptr,
                                                     const float* __restrict__ partial, float* __restrict__ z) {
   const int nlong = *nlong_ptr;
@@ -359,7 +472,7 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ chun
   for (int64_t ii = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; ii < nlong; ii += nwaves) {
     const int i = (int)ii;
     const int r = long_rows[i];
-    const int n = chunk_start[r + 1] - chunk_start[r];
+    const int n = slot_start[r + 1] - slot_start[r];
     const int s0 = slot_start[r];
     float s = 0.f;
     for (int j = lane; j < n; j += 64) s += partial[s0 + j];
@@ -369,91 +482,29 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ chun
   }
 }
 
-// Y[j, :] = (sum over bands b, in order, of part[b * band_rows + j, :]) * T; a band in which
-// row j has no entries (no chunk) adds nothing.  One wave per output row; lane c < L holds
-// column c, lanes 0..bands-1 fetch the bands' chunk counts.
-template <int L>
-__global__ __launch_bounds__(256) void k_band_reduce(const int* __restrict__ chunk_start, int bands, int band_rows,
-                                                     const float* __restrict__ part, const float* __restrict__ T,
-                                                     float* __restrict__ Y, int ldy) {
-  static_assert(L <= 64, "one lane per column");
-  __shared__ float tl[L * L];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (T) {
-    for (int e = threadIdx.x; e < L * L; e += 256) tl[e] = T[e];
-  }
-  __syncthreads();
-  const int col = lane < L ? lane : 0;
-  for (int64_t j = (int64_t)blockIdx.x * 4 + wave; j < band_rows; j += (int64_t)gridDim.x * 4) {
-    int n = 0;
-    if (lane < bands) {
-      const int64_t r = (int64_t)lane * band_rows + j;
-      n = chunk_start[r + 1] - chunk_start[r];
-    }
-    float v[kMaxBands];
-#pragma unroll
-    for (int b = 0; b < kMaxBands; ++b) {
-      const int nb = b < bands ? __builtin_amdgcn_readlane(n, b) : 0;
-      v[b] = nb > 0 ? part[((int64_t)b * band_rows + j) * L + col] : 0.f;
-    }
-    float acc = 0.f;
-#pragma unroll
-    for (int b = 0; b < kMaxBands; ++b) acc += v[b];
-    float o = acc;
-    if (T) {
-      o = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < L; ++kk)
-        o = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), kk)), tl[kk * L + col], o);
-    }
-    if (lane < L) Y[j * ldy + lane] = o;
-  }
-}
-
-// z[j] = sum over bands b, in order, of zpart[b * band_rows + j] (bands with no entry in row j
-// add nothing)
-__global__ __launch_bounds__(256) void k_band_reduce_vec(const int* __restrict__ chunk_start, int bands,
-                                                         int band_rows, const float* __restrict__ zpart,
-                                                         float* __restrict__ z) {
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < band_rows; j += (int64_t)gridDim.x * 256) {
-    float acc = 0.f;
-    for (int b = 0; b < bands; ++b) {
-      const int64_t r = (int64_t)b * band_rows + j;
-      if (chunk_start[r + 1] > chunk_start[r]) acc += zpart[r];
-    }
-    z[j] = acc;
-  }
-}
-
 template <int L, int U, bool BIN, bool BOUT>
 void launch_spmm(const Schedule& s, const int* idx, const float* val, const void* X, int ldx, void* out, int ldo,
                  float* partial, hipStream_t st) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);
   // about four chunks per group; the grid is not persistent (finished blocks make room for
-  // waiting ones, which balances uneven chunks), and a multiple of the band count
-  int64_t per = ((int64_t)s.max_chunks / s.bands + 16 * G - 1) / (16 * G);
-  per = std::max<int64_t>(1, std::min<int64_t>(per, kSpmmMaxBlocks / s.bands));
-  const unsigned grid = (unsigned)(per * s.bands);
-  const int band_rows = s.bands > 1 ? s.band_rows : s.rows;
+  // waiting ones, which balances uneven chunks), and a multiple of the XCD count for pieces
+  int64_t grid = ((int64_t)s.max_chunks + 16 * G - 1) / (16 * G);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, kSpmmMaxBlocks));
+  if (s.nlocal > 0) grid = (grid + s.nlocal - 1) / s.nlocal * s.nlocal;
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
-    k_spmm<L, U, true, BIN, BOUT><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out,
-                                                        ldo, partial);
+    k_spmm<L, U, true, BIN, BOUT><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx, out,
+                                                                  ldo, partial);
   else
-    k_spmm<L, U, false, BIN, BOUT><<<grid, 256, 0, st>>>(s.desc, s.nch, s.bands, band_rows, idx, val, X, ldx, out,
-                                                         ldo, partial);
+    k_spmm<L, U, false, BIN, BOUT><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx, out,
+                                                                   ldo, partial);
 }
 
 template <int L>
 hipError_t spmm_l(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
                   PanelType yt, int ldy, float* partial, hipStream_t st) {
   const bool xb = xt == PanelType::BF16, yb = yt == PanelType::BF16;
-  if (s.bands > 1) {
-    // FP32 per-band rows; spmm_finish fixes up long rows in place and adds the bands
-    if (xb || yb) return hipErrorInvalidValue;
-    launch_spmm<L, 4, false, false>(s, idx, val, X, ldx, s.bandbuf, L, partial, st);
-  } else if (!xb && !yb) {
+  if (!xb && !yb) {
     launch_spmm<L, 8, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
   } else if (xb && yb) {
     launch_spmm<L, 4, true, true>(s, idx, val, X, ldx, Y, ldy, partial, st);
@@ -465,19 +516,48 @@ hipError_t spmm_l(const Schedule& s, const int* idx, const float* val, const voi
   return hipGetLastError();
 }
 
+template <int L>
+void launch_fixup(const Schedule& s, float* partial, void* Y, bool yb, int ldy, hipStream_t st) {
+  if (yb)
+    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+  else
+    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+}
+
 }  // namespace
 
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st) {
   hipError_t e;
-  if (rows > 0)
-    k_sched_counts<<<grid_for(rows, 256, 8192), 256, 0, st>>>(ptr, rows, s.bands > 1 ? 1 : 0, s.nch, s.pslot);
+  if (rows > 0) k_sched_counts<<<grid_for(rows, 256, 8192), 256, 0, st>>>(ptr, rows, s.nch, s.pslot);
   if ((e = scan_exclusive(s.nch, s.nch, rows, scan_tmp, st)) != hipSuccess) return e;
   if ((e = scan_exclusive(s.pslot, s.pslot, rows, scan_tmp, st)) != hipSuccess) return e;
   if ((e = fill_i32(s.counters, 1, 0, st)) != hipSuccess) return e;
   if (rows > 0)
     k_sched_desc<<<grid_for(rows, 256, 8192), 256, 0, st>>>(ptr, rows, s.nch, s.pslot, s.desc, s.long_rows,
                                                              s.counters);
+  k_sched_regions<<<1, 64, 0, st>>>(s.nch, rows, 1, s.regions);
   s.rows = rows;
+  s.nlocal = 0;
+  return hipGetLastError();
+}
+
+hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const int* rowptr, int m, int nnz,
+                              int hot_min, Schedule& s, int* scan_tmp, hipStream_t st) {
+  if (d <= 0 || m <= 0 || nnz <= 0 || hot_min < 1) return hipErrorInvalidValue;
+  hipError_t e;
+  const int64_t vrows = (int64_t)(kXcdBands + 1) * d;
+  // the band boundaries live in the regions array until the regions are written last
+  int* rb = s.regions;
+  k_band_rows<<<grid_for(m, 256, 8192), 256, 0, st>>>(rowptr, m, nnz, rb);
+  k_hot_counts<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, d, hot_min, rb, s.nch, s.pslot);
+  if ((e = scan_exclusive(s.nch, s.nch, vrows, scan_tmp, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(s.pslot, s.pslot, d, scan_tmp, st)) != hipSuccess) return e;
+  if ((e = fill_i32(s.counters, 1, 0, st)) != hipSuccess) return e;
+  k_hot_desc<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, d, hot_min, rb, s.nch, s.pslot, s.desc,
+                                                      s.long_rows, s.counters);
+  k_sched_regions<<<1, 64, 0, st>>>(s.nch, d, kXcdBands + 1, s.regions);
+  s.rows = d;
+  s.nlocal = kXcdBands;
   return hipGetLastError();
 }
 
@@ -485,39 +565,14 @@ hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void*
                 PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
   if (L == 32) return spmm_l<32>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   if (L == 64) return spmm_l<64>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 128 && s.bands == 1) return spmm_l<128>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 256 && s.bands == 1) return spmm_l<256>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 128) return spmm_l<128>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 256) return spmm_l<256>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
   return hipErrorInvalidValue;
 }
 
-namespace {
-
-template <int L>
-void launch_fixup(const Schedule& s, float* partial, void* Y, bool yb, int ldy, hipStream_t st) {
-  if (yb)
-    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, Y, ldy);
-  else
-    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, Y, ldy);
-}
-
-}  // namespace
-
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st) {
   const bool yb = yt == PanelType::BF16;
-  if (s.bands > 1) {
-    // long rows fixed up in place in the band buffer, then the bands added
-    if (yb || (L != 32 && L != 64)) return hipErrorInvalidValue;
-    const unsigned gr = (unsigned)std::max<int64_t>(1, std::min<int64_t>((s.band_rows + 3) / 4, 8192));
-    if (L == 32) {
-      launch_fixup<32>(s, partial, s.bandbuf, false, 32, st);
-      k_band_reduce<32><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, nullptr,
-                                            reinterpret_cast<float*>(Y), ldy);
-    } else {
-      launch_fixup<64>(s, partial, s.bandbuf, false, 64, st);
-      k_band_reduce<64><<<gr, 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, nullptr,
-                                            reinterpret_cast<float*>(Y), ldy);
-    }
-  } else if (L == 32) {
+  if (L == 32) {
     launch_fixup<32>(s, partial, Y, yb, ldy, st);
   } else if (L == 64) {
     launch_fixup<64>(s, partial, Y, yb, ldy, st);
@@ -535,15 +590,13 @@ hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule
                 const double* scale_ptr, float* z, float* partial, hipStream_t st, const int64_t* seg_rows, int K,
                 int sstride) {
   (void)ptr;
-  const int* nchunks = s.nch + s.rows;
+  // every chunk of the schedule, in descriptor order: [regions[0], regions[nlocal + 1])
+  const int* nchunks = s.regions + s.nlocal + 1;
   int64_t g = ((int64_t)s.max_chunks + 15) / 16;
   if (g > kSpmmMaxBlocks) g = kSpmmMaxBlocks;
   if (g < 1) g = 1;
-  float* zo = s.bands > 1 ? s.bandbuf : z;
-  k_spmv<<<(unsigned)g, 256, 0, st>>>(s.desc, nchunks, idx, val, y, scale_ptr, zo, partial, seg_rows, K, sstride);
-  k_spmv_fixup<<<64, 256, 0, st>>>(s.nch, s.pslot, s.long_rows, s.counters, partial, zo);
-  if (s.bands > 1)
-    k_band_reduce_vec<<<grid_for(s.band_rows, 256, 4096), 256, 0, st>>>(s.nch, s.bands, s.band_rows, s.bandbuf, z);
+  k_spmv<<<(unsigned)g, 256, 0, st>>>(s.desc, nchunks, idx, val, y, scale_ptr, z, partial, seg_rows, K, sstride);
+  k_spmv_fixup<<<64, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, z);
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ OPT_PRECISION = 9
 PRECISION_FP32 = 0
 PRECISION_BF16 = 1
 OPT_ALGORITHM = 10
+OPT_CSC_HOT_MIN = 11
 ALGO_SFD = 0
 ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
@@ -190,8 +191,8 @@ class Sketch:
     """A Sparse Frequent Directions stream (sfd_create ... sfd_destroy)."""
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
-                 max_attempts=None, verify=None, stream_id=None, csc_bands=None, precision=None,
-                 algorithm=None, use_torch_stream: bool = True):
+                 max_attempts=None, verify=None, stream_id=None, csc_bands=None, csc_hot_min=None,
+                 precision=None, algorithm=None, use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
@@ -199,7 +200,7 @@ class Sketch:
         self.d, self.ell = int(d), int(ell)
         for key, val in ((OPT_DELTA, delta), (OPT_Q, q), (OPT_MAX_ATTEMPTS, max_attempts),
                          (OPT_VERIFY, None if verify is None else float(bool(verify))), (OPT_STREAM_ID, stream_id),
-                         (OPT_CSC_BANDS, csc_bands),
+                         (OPT_CSC_BANDS, csc_bands), (OPT_CSC_HOT_MIN, csc_hot_min),
                          (OPT_PRECISION, None if precision is None else
                           {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision)),
                          (OPT_ALGORITHM, None if algorithm is None else

@@ -60,3 +60,17 @@ def test_batch_argument_errors_without_a_gpu():
     assert lib.sfd_batch_sketch(None, None, 0) == sfd.SFD_E_ARG
     assert lib.sfd_batch_append_csr(None, 0, None, None, None, None, None, 0) == sfd.SFD_E_ARG
     assert lib.sfd_batch_set_option(None, sfd.OPT_DELTA, 0.1) == sfd.SFD_E_ARG
+
+
+def test_binding_constants_match_the_header():
+    # every option / precision / algorithm / memory constant of the binding has the header's value
+    from paper_1602_00412_amd import sfd
+
+    with open(os.path.join(ROOT, "include", "sfd.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    values = {name: int(v) for name, v in re.findall(r"\bSFD_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    for prefix in ("OPT_", "PRECISION_", "ALGO_", "MEM_"):
+        names = [n for n in values if n.startswith(prefix)]
+        assert names
+        for n in names:
+            assert getattr(sfd, n) == values[n], n

@@ -41,8 +41,9 @@ def _single(sfd, st, d, ell, sid, **opts):
     return sk, sk.sketch().cpu().numpy()
 
 
-@pytest.mark.parametrize("device,ell", [(True, 12), (False, 12), (True, 80)])
-def test_batch_equals_single_streams(gpu_lib, device, ell):
+@pytest.mark.parametrize("device,ell,bands", [(True, 12, None), (False, 12, None), (True, 80, None), (True, 12, 8)])
+def test_batch_equals_single_streams(gpu_lib, device, ell, bands):
+    # bands = 8: XCD-local pieces forced, so every buffer takes the lanes (as single handles do)
     import torch
 
     d = 300
@@ -50,6 +51,11 @@ def test_batch_equals_single_streams(gpu_lib, device, ell):
     streams = [small_random_csr(n, d, 8, 100 + s, dist="lognormal") for s, n in enumerate(lens)]
     indptr, idx, val, starts = _cat(streams)
     b = gpu_lib.Batch(len(streams), d, ell)
+    opts = {}
+    if bands is not None:
+        b.set_option(gpu_lib.OPT_CSC_BANDS, bands)
+        b.set_option(gpu_lib.OPT_CSC_HOT_MIN, 4)
+        opts = dict(csc_bands=bands, csc_hot_min=4)
     order = [3, 0, 5, 1, 4, 2]  # segments in any stream order
     seg_starts = []
     block_ptr, block_idx, block_val = [np.zeros(1, np.int64)], [], []
@@ -70,7 +76,7 @@ def test_batch_equals_single_streams(gpu_lib, device, ell):
         b.append_csr(order, seg_starts, bp, bi, bv)
     B = b.sketch().cpu().numpy()
     for s, st in enumerate(streams):
-        sk, Bs = _single(gpu_lib, st, d, ell, s)
+        sk, Bs = _single(gpu_lib, st, d, ell, s, **opts)
         np.testing.assert_array_equal(B[s], Bs)
         assert b.stats(s)["flushes"] == sk.stats()["flushes"]
         assert b.stats(s)["vs_calls"] == sk.stats()["vs_calls"]

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import SFDOracle, evaluate
 from oracle.rng import start_block as oracle_start_block
-from workloads import config1_fp64_reference, small_random_csr
+from workloads import CsrStream, config1_fp64_reference, small_random_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -73,25 +73,47 @@ def test_small_streams_match_oracle(gpu_lib, n, d, ell, lam, seed):
     assert sk.last_live == o.query()[1]
 
 
-@pytest.mark.parametrize("bands", [2, 8])
-def test_banded_csc_matches_oracle(gpu_lib, bands):
-    # transposed products through the row-banded CSC (forced on small buffers)
+@pytest.mark.parametrize("hot_min", [1, 16])
+def test_xcd_pieces_match_oracle(gpu_lib, hot_min):
+    # transposed products with the hot columns cut into per-XCD row-band pieces (forced on small
+    # buffers; hot_min = 1 cuts every non-empty column, 16 a mix of cut and whole columns)
     st = small_random_csr(1500, 90, 20, 3, dist="lognormal", dup_rate=0.05)
     o = _oracle(st, 50)
-    sk, B = _gpu_sketch(gpu_lib, st, 50, csc_bands=bands)
+    sk, B = _gpu_sketch(gpu_lib, st, 50, csc_bands=8, csc_hot_min=hot_min)
     assert sk.stats()["flushes"] == o.flushes
     assert evaluate.gram_distance(B, o.sketch()) <= TOL
     _, B1 = _gpu_sketch(gpu_lib, st, 50, csc_bands=1)
     assert evaluate.gram_distance(B, B1) <= 1e-5
 
 
-@pytest.mark.parametrize("bands", [1, 8])
-def test_large_buffer_matches_oracle(gpu_lib, bands):
-    # one 20,000-row buffer (flushed by the rows rule: 6e5 stored entries, long CSC columns)
-    # and a 4,000-row pending buffer folded by the query
+def test_xcd_pieces_with_empty_bands(gpu_lib):
+    # one row holds most of the buffer's entries, so several row bands are empty and the
+    # others hold few rows; plus empty rows and empty columns
+    d, ell = 400, 20
+    rng = np.random.default_rng(11)
+    lens = rng.poisson(3, 300)
+    lens[7] = 360  # about 30% of the entries: row 7's band is followed by an empty one
+    lens[rng.random(300) < 0.1] = 0
+    rows = [np.sort(rng.choice(d - 40, size=k, replace=False)) for k in lens]
+    indptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([len(r) for r in rows], out=indptr[1:])
+    indices = np.concatenate(rows).astype(np.int32)
+    values = rng.standard_normal(len(indices)).astype(np.float32)
+    st = CsrStream(indptr, indices, values, d, dict(name="empty bands"))
+    o = _oracle(st, ell)
+    for hot_min in (1, 4):
+        sk, B = _gpu_sketch(gpu_lib, st, ell, csc_bands=8, csc_hot_min=hot_min)
+        assert sk.stats()["flushes"] == o.flushes
+        assert evaluate.gram_distance(B, o.sketch()) <= TOL
+
+
+@pytest.mark.parametrize("bands,hot_min", [(1, None), (8, None), (8, 2)])
+def test_large_buffer_matches_oracle(gpu_lib, bands, hot_min):
+    # one 20,000-row buffer (flushed by the rows rule: 6e5 stored entries, long CSC columns whose
+    # band pieces span several chunks) and a 4,000-row pending buffer folded by the query
     st = small_random_csr(24000, 20000, 30, 5, dist="lognormal")
     o = _oracle(st, 40)
-    sk, B = _gpu_sketch(gpu_lib, st, 40, csc_bands=bands)
+    sk, B = _gpu_sketch(gpu_lib, st, 40, csc_bands=bands, csc_hot_min=hot_min)
     assert sk.stats()["flushes"] == o.flushes == 1
     assert evaluate.gram_distance(B, o.sketch()) <= TOL
 
