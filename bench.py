@@ -29,25 +29,33 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # HBM traffic of one product measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # per dispatch, the factors that make a plain 1 GiB copy read as 1 GiB each way), summed over the
-# product's kernels.  Valid only for the workload, panel precision and kernel source it was taken
-# with (sha256 prefix).
+# product's kernels.  Valid only for the workload, panel precision and kernel sources it was taken
+# with (sha256 prefix of the sources, concatenated in the order listed).
+TRAFFIC_SOURCES = ("paper_1602_00412_amd/csrc/sfd_spmm.hip", "paper_1602_00412_amd/csrc/sfd_internal.h")
 MEASURED_TRAFFIC = {
-    # (class, workload, precision): (bytes per call, source file, sha256 prefix, summary)
-    ("spmm_csc", "config2", "fp32"): (6.4242e+08, "paper_1602_00412_amd/csrc/sfd_spmm.hip", "e8f3b672f33f459e",
-                 "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
+    # (class, workload, precision): (bytes per call, sha256 prefix of TRAFFIC_SOURCES, summary)
+    ("spmm_csc", "config2", "fp32"): (6.3923e+08, "a2b96265373c624c",
+                                      "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
 }
 
 
-def measured_traffic(cls: str, workload: str, precision: str):
+def traffic_sources_sha() -> str:
     import hashlib
 
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(HERE, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls: str, workload: str, precision: str):
     ent = MEASURED_TRAFFIC.get((cls, workload, precision))
     if not ent:
         return None
-    nbytes, src, sha, _ = ent
+    nbytes, sha, _ = ent
     try:
-        with open(os.path.join(HERE, src), "rb") as f:
-            cur = hashlib.sha256(f.read()).hexdigest()
+        cur = traffic_sources_sha()
     except OSError:
         return None
     return nbytes if cur.startswith(sha) else None
@@ -226,7 +234,10 @@ def main() -> int:
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up and the per-kernel-class pass only (no timed steps; for rocprofv3 runs)")
     ap.add_argument("--rows", type=int, default=1_000_000, help="stream length (default: the full workload)")
-    ap.add_argument("--csc-bands", type=int, default=0, help="row bands of the transposed products (0: default)")
+    ap.add_argument("--csc-bands", type=int, default=0, choices=[0, 1, 8],
+                    help="XCD-local pieces of the transposed products: 0 automatic, 1 off, 8 on")
+    ap.add_argument("--csc-hot-min", type=int, default=0,
+                    help="entries from which a CSC column is cut into XCD-local pieces (0: the library's default)")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
     ap.add_argument("--batch-streams", type=int, default=64,
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
@@ -323,7 +334,8 @@ def main() -> int:
         desc = f"zipf-poisson stream n={st.n} d={st.d} lambda=50 s=1.0 lognormal+planted rank-20 (30%), ell={ell} eps=1/4"
     log(f"generated n={st_n} d={st_d} nnz={st_nnz} in {time.perf_counter() - t0:.1f} s")
     out = torch.empty((ell, st_d), dtype=torch.float32, device="cuda")
-    sk = sfd.Sketch(st_d, ell, 0.25, 0, csc_bands=args.csc_bands or None, precision=args.precision)
+    sk = sfd.Sketch(st_d, ell, 0.25, 0, csc_bands=args.csc_bands or None, csc_hot_min=args.csc_hot_min or None,
+                    precision=args.precision)
 
     def step():
         sk.reset()
@@ -381,7 +393,7 @@ def main() -> int:
         else:
             achieved = p["bytes"] / p["calls"] / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None if args.csc_bands else measured_traffic(dom, args.workload, args.precision)}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None if (args.csc_bands or args.csc_hot_min) else measured_traffic(dom, args.workload, args.precision)}
         bfk = args.precision == "bf16"
         Lw = 32 if ell <= 32 else 64 if ell <= 64 else 128 if ell <= 128 else 256
         roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {str(bfk).lower()}, "

@@ -81,9 +81,9 @@ enum {
                                ell rows -- the buffer flushes at ell rows and is folded exactly
                                by DenseShrink (Alg 5).  Applies to the flushes that follow. */
   SFD_OPT_CSC_HOT_MIN = 11  /* entries from which a column is cut into XCD-local pieces
-                               (SFD_OPT_CSC_BANDS), >= 1; default 64.  Raised to
-                               ceil(nnz(A') / 32768) for a buffer, so at most 32768 columns are
-                               cut. */
+                               (SFD_OPT_CSC_BANDS), >= 1; default 160.  Raised to
+                               ceil(nnz(A') / min(d, 32768)) for a buffer, so at most
+                               min(d, 32768) columns are cut. */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */

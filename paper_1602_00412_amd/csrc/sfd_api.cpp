@@ -38,7 +38,6 @@ constexpr double kCholDropTol = 1e-5;                 // relative residual^2 bel
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
 constexpr int kLanes = 16;        // lanes of a batch handle; a single-stream handle uses 4
 constexpr int kLanesSingle = 4;
-constexpr int kHotMinDefault = 64;  // entries from which a column is cut into XCD-local pieces
 
 // State of one stream (Alg 2): the sketch B (stored transposed, d x L), the pending buffer A'
 // (CSR), the flush index b, the persistent VerifySpectral counter i and the structural count
@@ -141,6 +140,7 @@ struct sfd_s {
   int verify = 1;
   int bands_opt = 0;      // SFD_OPT_CSC_BANDS: 0 automatic, 1 off, kXcdBands on
   int hot_min = kHotMinDefault;  // SFD_OPT_CSC_HOT_MIN
+  int64_t hot_cap = 0;           // hot columns a schedule with XCD-local pieces holds: min(d, kHotCap)
   int lanes_alloc = kLanesSingle;  // lanes with workspaces
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
@@ -323,10 +323,11 @@ int alloc_state(sfd_t* h) {
   h->cap = cap;
   const int64_t tiles = (cap + 2047) / 2048;
   // chunk capacity: one per row (empty rows included) plus the extra chunks of long rows, and
-  // for the CSC with XCD-local pieces up to kXcdBands pieces of each of at most kHotCap hot
+  // for the CSC with XCD-local pieces up to kXcdBands pieces of each of at most hot_cap hot
   // columns; partial slots likewise
-  const int64_t max_chunks = d + 2 * cap / kSpmmChunk + (int64_t)kXcdBands * kHotCap + 2;
-  const int64_t slots = 2 * cap / kSpmmChunk + 16 + (int64_t)kXcdBands * kHotCap;
+  h->hot_cap = std::min<int64_t>(d, kHotCap);
+  const int64_t max_chunks = d + 2 * cap / kSpmmChunk + kXcdBands * h->hot_cap + 2;
+  const int64_t slots = 2 * cap / kSpmmChunk + 16 + kXcdBands * h->hot_cap;
   const int64_t vrows = (int64_t)(kXcdBands + 1) * d + 1;  // chunk-count rows of the hot schedule
   bool ok = true;
   for (StreamState& ss : h->streams) {
@@ -491,8 +492,8 @@ int prepare(sfd_t* h, Lane& ln) {
     ln.sr.max_chunks = (int64_t)ln.m + (int64_t)ln.nnz / kSpmmChunk + 2;
     CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
     if (csc_hot(h, ln.m, ln.nnz)) {
-      // at most nnz / hot columns reach `hot`, so at most kHotCap
-      const int64_t hot = std::max<int64_t>(h->hot_min, (ln.nnz + kHotCap - 1) / kHotCap);
+      // at most nnz / hot columns reach `hot`, so at most hot_cap
+      const int64_t hot = std::max<int64_t>(h->hot_min, (ln.nnz + h->hot_cap - 1) / h->hot_cap);
       ln.scs.max_chunks = d + 2 * (int64_t)ln.nnz / kSpmmChunk + kXcdBands * std::min<int64_t>(d, ln.nnz / hot) + 2;
       CK(schedule_build_hot(ln.cscptr, ln.cscrow, (int)d, ln.rowptr, ln.m, ln.nnz, (int)hot, ln.scs, ln.scan_tmp,
                             ln.st));

@@ -10,7 +10,8 @@ namespace sfd {
 constexpr int kMaxEll = 256;     // panels up to 256 wide; FP64 eigensolves up to 512 x 512
 constexpr int kSpmmChunk = 256;  // entries per wave in the sparse products; longer rows are split
 constexpr int kXcdBands = 8;     // row bands of the hot-column pieces (one per XCD)
-constexpr int kHotCap = 32768;   // hot columns a transposed-product schedule holds at most
+constexpr int kHotCap = 32768;   // hot columns a transposed-product schedule holds at most (and <= d)
+constexpr int kHotMinDefault = 160;  // entries from which a CSC column is cut into XCD-local pieces
 
 // One buffer of a lockstep group (buffers of several streams running their SimultaneousIteration
 // together, one launch per step for all of them): its segment of a stacked panel (first row,
@@ -118,7 +119,7 @@ hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, 
 // nnz)); a column of at least hot_min entries is cut at the band boundaries, and its pieces'
 // chunks all write partial slots that the fix-up adds in band order, then chunk order.  s.nch
 // holds (kXcdBands + 1) d + 1 ints, s.pslot d + 1, s.desc d + 2 nnz / kSpmmChunk + kXcdBands
-// hot columns + 2 (hot_min >= nnz / kHotCap keeps the hot columns within kHotCap).
+// hot columns + 2 (hot_min >= nnz / H keeps the hot columns within H).
 hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const int* rowptr, int m, int nnz,
                               int hot_min, Schedule& s, int* scan_tmp, hipStream_t st);
 // Y[r, :] = sum_k val[k] X[idx[k], :] over the structure of schedule s (its entries idx, val);
