@@ -241,6 +241,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
     ap.add_argument("--batch-streams", type=int, default=64,
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes of the timed FP32 line (0: the library's default)")
     ap.add_argument("--hw-queues", type=int, default=0, choices=[0, 1, 2, 4, 8, 16, 32],
                     help="HIP hardware queues for this process (0: at least 16)")
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
@@ -336,6 +337,9 @@ def main() -> int:
     out = torch.empty((ell, st_d), dtype=torch.float32, device="cuda")
     sk = sfd.Sketch(st_d, ell, 0.25, 0, csc_bands=args.csc_bands or None, csc_hot_min=args.csc_hot_min or None,
                     precision=args.precision)
+    if args.lanes:
+        sk.set_option(sfd.OPT_LANES, args.lanes)
+    lanes_main = args.lanes or (8 if ell > 128 else 4)  # the library's default lanes
 
     def step():
         sk.reset()
@@ -375,7 +379,7 @@ def main() -> int:
         torch.cuda.synchronize()
         prof = sk.profile()
         sk.set_option(sfd.OPT_PROFILE, 0)
-        sk.set_option(sfd.OPT_LANES, 4)
+        sk.set_option(sfd.OPT_LANES, lanes_main)
         for name, p in prof.items():
             if p["calls"]:
                 phases[name] = {"ms": p["ms"], "calls": p["calls"], "launches": p["launches"],
@@ -565,6 +569,7 @@ def main() -> int:
             "q_last": stats["last_q"],
             "attempts_per_step": stats["attempts"],
             "vs_rejects_per_step": stats["vs_rejects"],
+            "lanes": lanes_main,
             "parallelism": "1 GPU",
         },
         "roofline": roof,

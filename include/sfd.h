@@ -68,7 +68,11 @@ enum {
                                pieces of band b run on the workgroups dispatched to XCD b (its L2
                                then holds that band's rows of Y).  Results agree to rounding. */
   SFD_OPT_LANES = 8,        /* lanes (HIP streams) that run successive buffers' SparseShrink
-                               concurrently, 1..4; default 4.  Results do not depend on it. */
+                               concurrently, 1..16; default 4 (8 for ell > 128, where a buffer
+                               step is paced by its one-workgroup FP64 solvers).  A lane beyond
+                               those allocated gets its workspaces (one buffer's CSC, schedules
+                               and panels) when first asked for, after the work in flight.
+                               Results do not depend on it. */
   SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
                                SimultaneousIteration (Alg 1) stored in BF16 with FP32 accumulation;
                                the last product P^T = A'^T Y (Alg 3) reads the stored BF16 Y,

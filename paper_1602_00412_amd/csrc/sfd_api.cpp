@@ -38,6 +38,7 @@ constexpr double kCholDropTol = 1e-5;                 // relative residual^2 bel
 constexpr int kPurposeSI = 0, kPurposeVS = 1, kPurposeQuerySI = 2, kPurposeQueryVS = 3;
 constexpr int kLanes = 16;        // lanes of a batch handle; a single-stream handle uses 4
 constexpr int kLanesSingle = 4;
+constexpr int kLanesWide = 8;  // a single-stream handle with ell > 128
 
 // State of one stream (Alg 2): the sketch B (stored transposed, d x L), the pending buffer A'
 // (CSR), the flush index b, the persistent VerifySpectral counter i and the structural count
@@ -317,18 +318,57 @@ int read_scalars(sfd_t* h, Lane& ln) {
   return sync_lane(h, ln);
 }
 
-int alloc_state(sfd_t* h) {
-  const int64_t d = h->d, L = h->L;
-  const int64_t cap = h->ell * d + d;
-  h->cap = cap;
+// Workspaces and stream of one lane (a buffer step in flight).
+int alloc_lane(sfd_t* h, Lane& ln) {
+  const int64_t d = h->d, L = h->L, cap = h->cap;
   const int64_t tiles = (cap + 2047) / 2048;
   // chunk capacity: one per row (empty rows included) plus the extra chunks of long rows, and
   // for the CSC with XCD-local pieces up to kXcdBands pieces of each of at most hot_cap hot
   // columns; partial slots likewise
-  h->hot_cap = std::min<int64_t>(d, kHotCap);
   const int64_t max_chunks = d + 2 * cap / kSpmmChunk + kXcdBands * h->hot_cap + 2;
   const int64_t slots = 2 * cap / kSpmmChunk + 16 + kXcdBands * h->hot_cap;
   const int64_t vrows = (int64_t)(kXcdBands + 1) * d + 1;  // chunk-count rows of the hot schedule
+  bool ok = true;
+  ok = ok && dalloc(h, &ln.own_rowptr, d + 1) && dalloc(h, &ln.Bq, d * L);
+  ok = ok && dalloc(h, &ln.cscptr, d + 1) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
+  ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
+  ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
+  ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
+  ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
+  ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, vrows)) + 16);
+  ln.csc.scan_tmp = ln.scan_tmp;
+  for (Schedule* s : {&ln.sr, &ln.scs}) {
+    const int64_t rows = (s == &ln.scs) ? vrows : d + 1;
+    ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->desc, max_chunks) &&
+         dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4) && dalloc(h, &s->regions, kXcdBands + 2);
+    s->max_chunks = max_chunks;
+  }
+  ok = ok && dalloc(h, &ln.partial, slots * L);
+  ln.scs.transposed = true;
+  ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
+  ok = ok && dalloc(h, &ln.Xb, d * L) && dalloc(h, &ln.Yb, d * L);
+  ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
+       dalloc(h, &ln.W2, 4 * L * L);
+  ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
+  ok = ok && dalloc(h, &ln.eig_work, std::max(eig_work_bytes(h->ell), eig_work_bytes(2 * h->ell)));
+  ok = ok && dalloc(h, &ln.cholw, chol_work_doubles(h->L));
+  ok = ok && dalloc(h, &ln.M64, L * L) && dalloc(h, &ln.M32, L * L) && dalloc(h, &ln.T, L * L) &&
+       dalloc(h, &ln.T2, 2 * L * L);
+  ok = ok && dalloc(h, &ln.vs_w, d) && dalloc(h, &ln.vs_wraw, d) && dalloc(h, &ln.vs_z, d) &&
+       dalloc(h, &ln.vs_c2, 2 * L) && dalloc(h, &ln.vs_gpart, (int64_t)gemv_blocks(d) * L) &&
+       dalloc(h, &ln.vs_npart, 2048);
+  ok = ok && dalloc(h, &ln.sc, 1);
+  if (!ok) return SFD_E_NOMEM;
+  if (hipHostMalloc((void**)&ln.sc_host, sizeof(DevScalars)) != hipSuccess) return SFD_E_NOMEM;
+  if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess) return SFD_E_DEVICE;
+  return SFD_OK;
+}
+
+int alloc_state(sfd_t* h) {
+  const int64_t d = h->d, L = h->L;
+  const int64_t cap = h->ell * d + d;
+  h->cap = cap;
+  h->hot_cap = std::min<int64_t>(d, kHotCap);
   bool ok = true;
   for (StreamState& ss : h->streams) {
     ok = ok && dalloc(h, &ss.B, d * L);
@@ -337,42 +377,11 @@ int alloc_state(sfd_t* h) {
     if (hipEventCreateWithFlags(&ss.ev_dsh, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   }
   ok = ok && dalloc(h, &h->err_dev, 4);
-  for (int li = 0; li < h->lanes_alloc; ++li) {
-    Lane& ln = h->lanes[li];
-    ok = ok && dalloc(h, &ln.own_rowptr, d + 1) && dalloc(h, &ln.Bq, d * L);
-    ok = ok && dalloc(h, &ln.cscptr, d + 1) && dalloc(h, &ln.cscrow, cap) && dalloc(h, &ln.cscval, cap);
-    ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
-    ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
-    ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
-    ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
-    ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, vrows)) + 16);
-    ln.csc.scan_tmp = ln.scan_tmp;
-    for (Schedule* s : {&ln.sr, &ln.scs}) {
-      const int64_t rows = (s == &ln.scs) ? vrows : d + 1;
-      ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->desc, max_chunks) &&
-           dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4) && dalloc(h, &s->regions, kXcdBands + 2);
-      s->max_chunks = max_chunks;
-    }
-    ok = ok && dalloc(h, &ln.partial, slots * L);
-    ln.scs.transposed = true;
-    ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
-    ok = ok && dalloc(h, &ln.Xb, d * L) && dalloc(h, &ln.Yb, d * L);
-    ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
-         dalloc(h, &ln.W2, 4 * L * L);
-    ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
-    ok = ok && dalloc(h, &ln.eig_work, std::max(eig_work_bytes(h->ell), eig_work_bytes(2 * h->ell)));
-    ok = ok && dalloc(h, &ln.cholw, chol_work_doubles(h->L));
-    ok = ok && dalloc(h, &ln.M64, L * L) && dalloc(h, &ln.M32, L * L) && dalloc(h, &ln.T, L * L) &&
-         dalloc(h, &ln.T2, 2 * L * L);
-    ok = ok && dalloc(h, &ln.vs_w, d) && dalloc(h, &ln.vs_wraw, d) && dalloc(h, &ln.vs_z, d) &&
-         dalloc(h, &ln.vs_c2, 2 * L) && dalloc(h, &ln.vs_gpart, (int64_t)gemv_blocks(d) * L) &&
-         dalloc(h, &ln.vs_npart, 2048);
-    ok = ok && dalloc(h, &ln.sc, 1);
-    if (!ok) return SFD_E_NOMEM;
-    if (hipHostMalloc((void**)&ln.sc_host, sizeof(DevScalars)) != hipSuccess) return SFD_E_NOMEM;
-    if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess) return SFD_E_DEVICE;
-  }
   if (!ok) return SFD_E_NOMEM;
+  for (int li = 0; li < h->lanes_alloc; ++li) {
+    int rc = alloc_lane(h, h->lanes[li]);
+    if (rc) return rc;
+  }
   if (hipHostMalloc((void**)&h->i64_host, sizeof(int64_t) * 16) != hipSuccess) return SFD_E_NOMEM;
   if (hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   return SFD_OK;
@@ -1319,7 +1328,9 @@ const char* sfd_strerror(int code) {
 }
 
 int sfd_create(int64_t d, int32_t ell, double eps, uint64_t seed, sfd_t** out) {
-  return create_handle(d, ell, eps, seed, 1, kLanesSingle, out);
+  // past ell = 128 the FP64 Cholesky and eigensolves of a buffer step (one workgroup each) set its
+  // pace, so more buffer steps run side by side
+  return create_handle(d, ell, eps, seed, 1, ell > 128 ? kLanesWide : kLanesSingle, out);
 }
 
 int sfd_destroy(sfd_t* h) {
@@ -1371,10 +1382,21 @@ int sfd_set_option(sfd_t* h, int key, double value) {
       if (value != SFD_PRECISION_FP32 && value != SFD_PRECISION_BF16) return SFD_E_ARG;
       h->precision = (int)value;
       return SFD_OK;
-    case SFD_OPT_LANES:
-      if (!(value >= 1 && value <= h->lanes_alloc) || value != std::floor(value)) return SFD_E_ARG;
+    case SFD_OPT_LANES: {
+      if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;
+      // lanes beyond those allocated get their workspaces now (after the work in flight)
+      if ((int)value > h->lanes_alloc) {
+        DeviceGuard g(h->device);
+        int rc = sync_all(h);
+        if (rc) return rc;
+        for (int li = h->lanes_alloc; li < (int)value; ++li) {
+          if ((rc = alloc_lane(h, h->lanes[li]))) return rc;
+          h->lanes_alloc = li + 1;
+        }
+      }
       h->nlanes = (int)value;
       return SFD_OK;
+    }
     case SFD_OPT_ALGORITHM:
       if (value != SFD_ALGO_SFD && value != SFD_ALGO_FD) return SFD_E_ARG;
       h->algorithm = (int)value;

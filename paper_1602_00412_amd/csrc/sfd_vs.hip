@@ -111,10 +111,18 @@ __global__ __launch_bounds__(1024) void k_vs_small(const float* __restrict__ par
   }
 }
 
-// w[j] = w_raw[j] - P[j, :] . c2, one wave per row, and the block's sum of w^2 in FP64.
+// w[j] = w_raw[j] - P[j, :] . c2 and the block's partial of sum_j w[j]^2 (FP64), for j < d.  A row
+// is read by L/4 lanes (one float4 each) and reduced over them with xor shuffles; a wave takes
+// 64/(L/4) rows per pass and kVsUnroll passes at once, so that many rows' loads are in flight.
+// Groups: buffer k = blockIdx.y (its w_raw, P, c2, w and partials at offsets k d, k d ld,
+// k 2 L, k d, k gridDim.x).
+constexpr int kVsUnroll = 4;
+template <int L>
 __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_raw, const float* __restrict__ P,
-                                                   int ld, int L, const float* __restrict__ c2, int64_t d,
+                                                   int ld, const float* __restrict__ c2, int64_t d,
                                                    float* __restrict__ w, double* __restrict__ part) {
+  constexpr int LPR = L / 4;     // lanes per row
+  constexpr int RPW = 64 / LPR;  // rows per wave and pass
   __shared__ double s[4];
   {
     const int64_t k = blockIdx.y;
@@ -126,22 +134,40 @@ __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_r
   }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  float cc[4];
-#pragma unroll
-  for (int h = 0; h < 4; ++h) cc[h] = 64 * h + lane < L ? c2[64 * h + lane] : 0.f;
+  const int sub = lane % LPR, rw = lane / LPR;
+  const float4 cc = reinterpret_cast<const float4*>(c2)[sub];
   double acc = 0.0;
-  for (int64_t j = ((int64_t)blockIdx.x * 4 + wave); j < d; j += (int64_t)gridDim.x * 4) {
-    const float* pr = P + j * ld;
-    float v = (lane < L ? pr[lane] * cc[0] : 0.f) + (64 + lane < L ? pr[64 + lane] * cc[1] : 0.f);
-    if (L > 128) v += (128 + lane < L ? pr[128 + lane] * cc[2] : 0.f) + (192 + lane < L ? pr[192 + lane] * cc[3] : 0.f);
+  const int64_t step = (int64_t)gridDim.x * 4 * RPW * kVsUnroll;
+  for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * RPW * kVsUnroll; j0 < d; j0 += step) {
+    float4 p[kVsUnroll];
+    float wr[kVsUnroll];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) {
-      float r = w_raw[j] - v;
-      w[j] = r;
-      acc += (double)r * (double)r;
+    for (int u = 0; u < kVsUnroll; ++u) {
+      const int64_t j = j0 + u * RPW + rw;
+      p[u] = j < d ? reinterpret_cast<const float4*>(P + j * ld)[sub] : make_float4(0.f, 0.f, 0.f, 0.f);
+      wr[u] = (sub == 0 && j < d) ? w_raw[j] : 0.f;
+    }
+    float v[kVsUnroll];
+#pragma unroll
+    for (int u = 0; u < kVsUnroll; ++u) v[u] = ((p[u].x * cc.x + p[u].y * cc.y) + p[u].z * cc.z) + p[u].w * cc.w;
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int u = 0; u < kVsUnroll; ++u) v[u] += __shfl_xor(v[u], o, 64);
+    if (sub == 0) {
+#pragma unroll
+      for (int u = 0; u < kVsUnroll; ++u) {
+        const int64_t j = j0 + u * RPW + rw;
+        if (j < d) {
+          const float r = wr[u] - v[u];
+          w[j] = r;
+          acc += (double)r * (double)r;
+        }
+      }
     }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (lane == 0) s[wave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
@@ -194,7 +220,17 @@ int vs_finish_blocks(int64_t d) {
 hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
                      float* w, double* part, hipStream_t st, int K) {
   (void)ell;
-  k_vs_finish<<<dim3(vs_finish_blocks(d), K), 256, 0, st>>>(w_raw, P, ld, L, c2, d, w, part);
+  const dim3 grid(vs_finish_blocks(d), K);
+  if (L == 32)
+    k_vs_finish<32><<<grid, 256, 0, st>>>(w_raw, P, ld, c2, d, w, part);
+  else if (L == 64)
+    k_vs_finish<64><<<grid, 256, 0, st>>>(w_raw, P, ld, c2, d, w, part);
+  else if (L == 128)
+    k_vs_finish<128><<<grid, 256, 0, st>>>(w_raw, P, ld, c2, d, w, part);
+  else if (L == 256)
+    k_vs_finish<256><<<grid, 256, 0, st>>>(w_raw, P, ld, c2, d, w, part);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
