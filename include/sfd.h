@@ -230,6 +230,40 @@ int sfd_batch_append_csr(sfd_batch_t *h, int32_t nseg, const int32_t *stream_of_
  * ell x d row-major sketches, caller-owned, in memory of kind mem. */
 int sfd_batch_sketch(sfd_batch_t *h, float *B_out, int mem);
 
+/* ------------------------------------------------------------------ accuracy of a sketch
+ * The measures of the paper's experiments (Sec. 4, "Measurements"), in FP64 on the GPU:
+ *   cov-err  = ||A^T A - B^T B||_2 / ||A||_F^2;
+ *   proj-err = ||A - A V_k V_k^T||_F^2 / ||A - A_k||_F^2, V_k the top-k right singular vectors of
+ *              B, A_k the best rank-k approximation of A (Sec. 1.1 notation). */
+typedef struct {
+  double fro2A;        /* ||A||_F^2, repeated (row, column) entries summed */
+  double cov_min;      /* smallest and largest eigenvalue of A^T A - B^T B (Lanczos Ritz values) */
+  double cov_max;
+  double cov_err;      /* max(|cov_min|, |cov_max|) / fro2A (+inf or NaN when A = 0) */
+  double top_k_energy; /* sum of the k largest eigenvalues of A^T A = sum_{i<=k} sigma_i(A)^2 */
+  double proj_num;     /* ||A - A V_k V_k^T||_F^2 = fro2A - ||A V_k||_F^2 */
+  double proj_err;     /* proj_num / (fro2A - top_k_energy); the three are NaN when k = 0 */
+  int32_t steps;       /* Lanczos steps taken for cov-err (fewer than asked when the Krylov
+                          space of the operator closes) */
+  int32_t pad;
+} sfd_eval_t;
+
+/* Evaluate the ell x d sketch B against the n x d matrix A it summarises.
+ * A: CSR in device memory as in sfd_append_csr (int64 indptr[n + 1], rows read from
+ * indices/values positions indptr[0] .. indptr[n]); B: ell x d FP32 row-major in device memory
+ * (ell = 0: no sketch, B may be NULL).  k: rank of proj-err, 0 <= k <= ell (0 skips it).
+ * steps: Lanczos steps per operator, 1..512, at most d (<= 0: min(d, 160)).  The extreme
+ * eigenvalues of A^T A - B^T B come from Lanczos with full reorthogonalisation on
+ * x -> A^T(Ax) - B^T(Bx) from a start vector keyed by seed, the k largest of A^T A likewise on
+ * x -> A^T(Ax); A is never densified (a CSC copy is built for A^T y).  Work memory is allocated
+ * and freed inside the call (about 28 bytes per stored entry plus (steps + 1) d doubles); the
+ * work runs on hip_stream (NULL: the null stream) and the call returns when it is done.
+ * Errors: SFD_E_ARG (bad sizes or row pointers), SFD_E_INDEX (a column id outside [0, d)),
+ * SFD_E_NOMEM, SFD_E_DEVICE; *out is written only on success. */
+int sfd_evaluate(int64_t n, int64_t d, const int64_t *indptr, const int32_t *indices, const float *values,
+                 const float *B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void *hip_stream,
+                 sfd_eval_t *out);
+
 #ifdef __cplusplus
 }
 #endif

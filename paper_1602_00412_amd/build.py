@@ -37,6 +37,7 @@ SOURCES = [
     "sfd_small.hip",
     "sfd_eig_tri.hip",
     "sfd_vs.hip",
+    "sfd_eval.hip",
     "sfd_api.cpp",
 ]
 

@@ -1,0 +1,438 @@
+// Accuracy of a sketch against its input on the GPU, in FP64: the measures of the paper's
+// experiments (Sec. 4, "Measurements").
+//   cov-err  = ||A^T A - B^T B||_2 / ||A||_F^2.  The extreme eigenvalues of the d x d matrix
+//              A^T A - B^T B come from Lanczos with full reorthogonalisation on the operator
+//              x -> A^T (A x) - B^T (B x); the matrix is never formed.
+//   proj-err = ||A - A V_k V_k^T||_F^2 / ||A - A_k||_F^2 (Sec. 1.1 notation): V_k holds the top-k
+//              right singular vectors of B (from the FP64 eig of the ell x ell Gram B B^T), the
+//              numerator is ||A||_F^2 - ||A V_k||_F^2, and ||A - A_k||_F^2 = ||A||_F^2 minus the
+//              sum of the k largest eigenvalues of A^T A (Lanczos on x -> A^T (A x)).
+// A x runs over the input CSR, A^T y over a CSC built once (FP32 values, FP64 accumulation);
+// B stays FP32 and is read in FP64 arithmetic.  Every reduction has a fixed order, so results
+// are reproducible run to run.
+#include <cmath>
+#include <cstdint>
+#include <limits>
+#include <vector>
+
+#include "sfd.h"
+#include "sfd_internal.h"
+
+namespace sfd {
+namespace {
+
+constexpr int kEvalBlocks = 512;       // partial sums of the FP64 reductions
+constexpr int kEvalMaxSteps = 512;     // Lanczos steps per operator
+constexpr int kEvalDefaultSteps = 160;
+
+inline unsigned grid_for(int64_t n, int threads, int64_t cap = 8192) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// rowptr[r] = indptr[r] - indptr[0], r <= n (int32 offsets of the input CSR)
+__global__ void k_rebase(const int64_t* __restrict__ indptr, int64_t n, int* __restrict__ rowptr) {
+  const int64_t base = indptr[0];
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += (int64_t)gridDim.x * blockDim.x)
+    rowptr[r] = (int)(indptr[r] - base);
+}
+
+// y[r] = sum_k val[k] x[idx[k]] over the rows r < rows of (ptr, idx, val): a 16-lane group per
+// row, lane s adding entries s, s + 16, ... then a fixed xor tree.
+__global__ __launch_bounds__(256) void k_spmv64(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                const float* __restrict__ val, int64_t rows,
+                                                const double* __restrict__ x, double* __restrict__ y) {
+  const int sub = threadIdx.x & 15;
+  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) >> 4;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; r < rows; r += ng) {
+    const int a = ptr[r], b = ptr[r + 1];
+    double acc = 0.0;
+    for (int p = a + sub; p < b; p += 16) acc = fma((double)val[p], x[idx[p]], acc);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (sub == 0) y[r] = acc;
+  }
+}
+
+// block sum of v over 256 threads, fixed tree; the result is valid in thread 0
+__device__ inline double block_sum256(double v, double* s) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  return s[0];
+}
+
+// part[v nb + b] = block b's share of <Q[v], w> (rows of Q pitch ld), v = blockIdx.y
+__global__ __launch_bounds__(256) void k_multi_dot(const double* __restrict__ Q, int64_t ld,
+                                                   const double* __restrict__ w, int64_t d,
+                                                   double* __restrict__ part) {
+  __shared__ double s[256];
+  const double* q = Q + (int64_t)blockIdx.y * ld;
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256)
+    acc = fma(q[t], w[t], acc);
+  const double tot = block_sum256(acc, s);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+// out[v] = sum of part[v nb .. v nb + nb), v = blockIdx.x
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[(int64_t)blockIdx.x * nb + b];
+  const double tot = block_sum256(acc, s);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+// u[i] = sum_t B[i][t] x[t] (B: rows x d FP32, row-major), one block per row
+__global__ __launch_bounds__(256) void k_rows_dot(const float* __restrict__ B, int64_t d,
+                                                  const double* __restrict__ x, double* __restrict__ u) {
+  __shared__ double s[256];
+  const float* row = B + (int64_t)blockIdx.x * d;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < d; t += 256) acc = fma((double)row[t], x[t], acc);
+  const double tot = block_sum256(acc, s);
+  if (threadIdx.x == 0) u[blockIdx.x] = tot;
+}
+
+// w[t] -= sum_i B[i][t] u[i], i < rows
+__global__ __launch_bounds__(256) void k_sub_bt(const float* __restrict__ B, int rows, int64_t d,
+                                                const double* __restrict__ u, double* __restrict__ w) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int i = 0; i < rows; ++i) acc = fma((double)B[(int64_t)i * d + t], u[i], acc);
+    w[t] -= acc;
+  }
+}
+
+// w -= alpha[j] q_j + beta[j] q_{j-1}  (beta[0] = 0: q_{-1} is not read)
+__global__ __launch_bounds__(256) void k_three_term(double* __restrict__ w, const double* __restrict__ qj,
+                                                    const double* __restrict__ qm, const double* __restrict__ alpha,
+                                                    const double* __restrict__ beta, int j, int64_t d) {
+  const double a = alpha[j], b = j > 0 ? beta[j] : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) {
+    double v = fma(-a, qj[t], w[t]);
+    if (j > 0) v = fma(-b, qm[t], v);
+    w[t] = v;
+  }
+}
+
+// w -= sum_{i < nv} h[i] Q[i]  (one classical Gram-Schmidt sweep against the Lanczos basis)
+__global__ __launch_bounds__(256) void k_reorth(const double* __restrict__ Q, int64_t ld, int nv,
+                                                const double* __restrict__ h, double* __restrict__ w, int64_t d) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) acc = fma(Q[(int64_t)i * ld + t], h[i], acc);
+    w[t] -= acc;
+  }
+}
+
+// q = w / sqrt(*nrm2) (q = 0 when the norm is 0); *beta_out = the norm
+__global__ __launch_bounds__(256) void k_normalize(const double* __restrict__ w, const double* __restrict__ nrm2,
+                                                   double* __restrict__ q, double* __restrict__ beta_out, int64_t d) {
+  const double b = sqrt(fmax(*nrm2, 0.0));
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && beta_out) *beta_out = b;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) q[t] = w[t] * inv;
+}
+
+// start vector: q[t] uniform in [-1, 1) from a splitmix64 hash of (seed, t)
+__global__ __launch_bounds__(256) void k_start(uint64_t seed, double* __restrict__ q, int64_t d) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(t + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    q[t] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+// G[i][j] = G[j][i] = sum_t B[i][t] B[j][t] for i <= j (one block per pair, fixed order)
+__global__ __launch_bounds__(256) void k_gram64(const float* __restrict__ B, int rows, int64_t d,
+                                                double* __restrict__ G) {
+  __shared__ double s[256];
+  const int i = blockIdx.x, j = blockIdx.y;
+  if (i > j) return;
+  const float* bi = B + (int64_t)i * d;
+  const float* bj = B + (int64_t)j * d;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < d; t += 256) acc = fma((double)bi[t], (double)bj[t], acc);
+  const double tot = block_sum256(acc, s);
+  if (threadIdx.x == 0) {
+    G[(int64_t)i * rows + j] = tot;
+    G[(int64_t)j * rows + i] = tot;
+  }
+}
+
+// V[c][t] = (sum_l B[l][t] U[l][c]) / sigma_c for c < k (U: rows x rows eigenvectors, column c
+// <-> the c-th largest eigenvalue ev[c] = sigma_c^2; a zero sigma gives a zero row)
+__global__ __launch_bounds__(256) void k_right_vectors(const float* __restrict__ B, int rows, int64_t d,
+                                                       const double* __restrict__ U, const double* __restrict__ ev,
+                                                       int k, double* __restrict__ V) {
+  const int c = blockIdx.y;
+  const double sig = sqrt(fmax(ev[c], 0.0));
+  const double inv = sig > 0.0 ? 1.0 / sig : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < d; t += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int l = 0; l < rows; ++l) acc = fma((double)B[(int64_t)l * d + t], U[(int64_t)l * rows + c], acc);
+    V[(int64_t)c * d + t] = acc * inv;
+  }
+}
+
+// The k-th smallest (k = 0 ..) eigenvalue of the symmetric tridiagonal matrix with diagonal a
+// and off-diagonal b (b[i] couples i - 1 and i, b[0] unused), by bisection on Sturm counts.
+double tri_kth(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  const int m = (int)a.size();
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < m ? std::fabs(b[i + 1]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  const double tiny = std::numeric_limits<double>::min() / std::numeric_limits<double>::epsilon();
+  // number of eigenvalues below x
+  auto below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      q = a[i] - x - (i > 0 ? b[i] * b[i] / q : 0.0);
+      if (q == 0.0) q = -tiny;
+      if (q < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 2.0 * std::numeric_limits<double>::epsilon() * scale; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) > k) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+struct Allocs {
+  std::vector<void*> p;
+  template <class T>
+  bool get(T** out, int64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) return false;
+    p.push_back(q);
+    *out = static_cast<T*>(q);
+    return true;
+  }
+  ~Allocs() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+struct EvalCtx {
+  int64_t n, d;
+  const int* rowptr;
+  const int* colidx;
+  const float* val;
+  const int *cscptr, *cscrow;
+  const float* cscval;
+  const float* B;
+  int ell;
+  double *y, *w, *u, *part, *scal, *Q, *alpha, *beta;
+  hipStream_t st;
+};
+
+// w = A^T (A x) (- B^T (B x))
+hipError_t apply_op(EvalCtx& c, const double* x, bool withB) {
+  k_spmv64<<<grid_for(c.n * 16, 256), 256, 0, c.st>>>(c.rowptr, c.colidx, c.val, c.n, x, c.y);
+  k_spmv64<<<grid_for(c.d * 16, 256), 256, 0, c.st>>>(c.cscptr, c.cscrow, c.cscval, c.d, c.y, c.w);
+  if (withB && c.ell > 0) {
+    k_rows_dot<<<c.ell, 256, 0, c.st>>>(c.B, c.d, x, c.u);
+    k_sub_bt<<<grid_for(c.d, 256), 256, 0, c.st>>>(c.B, c.ell, c.d, c.u, c.w);
+  }
+  return hipGetLastError();
+}
+
+// <Q[v], w> for v < nv into out[v]
+hipError_t multi_dot(EvalCtx& c, const double* Q, int nv, const double* w, double* out) {
+  const unsigned nb = grid_for(c.d, 256, kEvalBlocks);
+  k_multi_dot<<<dim3(nb, nv), 256, 0, c.st>>>(Q, c.d, w, c.d, c.part);
+  k_sum_parts<<<nv, 256, 0, c.st>>>(c.part, (int)nb, out);
+  return hipGetLastError();
+}
+
+// Lanczos with full reorthogonalisation (two classical Gram-Schmidt sweeps per step) on the
+// operator: the tridiagonal coefficients of `steps` steps (fewer when the Krylov space closes).
+hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector<double>& a, std::vector<double>& b) {
+  hipError_t e;
+  const int64_t d = c.d;
+  const unsigned gd = grid_for(d, 256);
+  double* h = c.scal + 2;  // kEvalMaxSteps + 1 reorthogonalisation coefficients
+  double* nrm2 = c.scal;
+  k_start<<<gd, 256, 0, c.st>>>(seed, c.w, d);
+  if ((e = multi_dot(c, c.w, 1, c.w, nrm2)) != hipSuccess) return e;
+  k_normalize<<<gd, 256, 0, c.st>>>(c.w, nrm2, c.Q, nullptr, d);
+  for (int j = 0; j < steps; ++j) {
+    const double* qj = c.Q + (int64_t)j * d;
+    if ((e = apply_op(c, qj, withB)) != hipSuccess) return e;
+    if ((e = multi_dot(c, qj, 1, c.w, c.alpha + j)) != hipSuccess) return e;
+    k_three_term<<<gd, 256, 0, c.st>>>(c.w, qj, j > 0 ? qj - d : qj, c.alpha, c.beta, j, d);
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((e = multi_dot(c, c.Q, j + 1, c.w, h)) != hipSuccess) return e;
+      k_reorth<<<gd, 256, 0, c.st>>>(c.Q, d, j + 1, h, c.w, d);
+    }
+    if ((e = multi_dot(c, c.w, 1, c.w, nrm2)) != hipSuccess) return e;
+    k_normalize<<<gd, 256, 0, c.st>>>(c.w, nrm2, c.Q + (int64_t)(j + 1) * d, c.beta + j + 1, d);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<double> ha((size_t)steps), hb((size_t)steps + 1);
+  if ((e = hipMemcpyAsync(ha.data(), c.alpha, sizeof(double) * steps, hipMemcpyDeviceToHost, c.st)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(hb.data(), c.beta, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, c.st)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
+  // the Krylov space closes at the first coupling that vanishes against the coefficients seen so
+  // far (the steps after it start from rounding noise and are dropped: their coefficients are
+  // meaningless and can grow without bound)
+  double scale = 0.0;
+  a.clear();
+  b.assign(1, 0.0);
+  for (int j = 0; j < steps; ++j) {
+    a.push_back(ha[(size_t)j]);
+    scale = std::max(scale, std::fabs(ha[(size_t)j]) + b.back());
+    if (j + 1 < steps) {
+      if (!(hb[(size_t)j + 1] > 1e-12 * scale)) break;
+      b.push_back(hb[(size_t)j + 1]);
+    }
+  }
+  return hipSuccess;
+}
+
+int hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? SFD_E_NOMEM : SFD_E_DEVICE; }
+
+}  // namespace
+}  // namespace sfd
+
+extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const int32_t* indices, const float* values,
+                            const float* B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void* hip_stream,
+                            sfd_eval_t* out) {
+  using namespace sfd;
+  if (!out || !indptr || n < 0 || d < 1 || ell < 0 || k < 0 || k > ell || (ell > 0 && !B)) return SFD_E_ARG;
+  if (ell > 2 * kMaxEll || steps > kEvalMaxSteps || d >= ((int64_t)1 << 31)) return SFD_E_ARG;
+  const int m = (int)std::min<int64_t>(d, steps > 0 ? steps : kEvalDefaultSteps);
+  if (k > m) return SFD_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  Allocs al;
+  // the input: rows, then the stored-entry count from the row pointers
+  int* err = nullptr;
+  if (!al.get(&err, 1)) return SFD_E_NOMEM;
+  int64_t ends[2] = {0, 0};
+  if (hipMemcpyAsync(&ends[0], indptr, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&ends[1], indptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SFD_E_DEVICE;
+  const int64_t nnz = ends[1] - ends[0];
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31) || (nnz > 0 && (!indices || !values))) return SFD_E_ARG;
+  int herr = 0;
+  if (fill_i32(err, 1, 0, st) != hipSuccess || validate_rows(indptr, n, d, err, st) != hipSuccess ||
+      validate_indices(indices, ends[0], ends[1], d, err, st) != hipSuccess ||
+      hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SFD_E_DEVICE;
+  if (herr & 1) return SFD_E_ARG;
+  if (herr & 2) return SFD_E_INDEX;
+  const int* colidx = indices + ends[0];
+  const float* vals = values + ends[0];
+  // workspaces
+  EvalCtx c{};
+  c.n = n;
+  c.d = d;
+  c.B = B;
+  c.ell = ell;
+  c.st = st;
+  int *rowptr = nullptr, *cscptr = nullptr, *cscrow = nullptr;
+  float* cscval = nullptr;
+  CscWork w{};
+  const int64_t tiles = (nnz + 2047) / 2048;
+  DevScalars* sc = nullptr;
+  bool ok = al.get(&rowptr, n + 1) && al.get(&cscptr, d + 1) && al.get(&cscrow, nnz) && al.get(&cscval, nnz);
+  ok = ok && al.get(&w.counts, 1) && al.get(&w.rowid, nnz) && al.get(&w.keys0, nnz) && al.get(&w.keys1, nnz) &&
+       al.get(&w.vals0, nnz) && al.get(&w.vals1, nnz) && al.get(&w.hist, 256 * tiles + 1) &&
+       al.get(&w.part, fro2_part_doubles(1)) && al.get(&w.scan_tmp, scan_tmp_ints(256 * tiles + 1) + 16) &&
+       al.get(&sc, 1);
+  ok = ok && al.get(&c.y, n) && al.get(&c.w, d) && al.get(&c.u, std::max(ell, 1)) &&
+       al.get(&c.part, (int64_t)kEvalBlocks * (kEvalMaxSteps + 1)) && al.get(&c.scal, kEvalMaxSteps + 8) &&
+       al.get(&c.Q, (int64_t)(m + 1) * d) && al.get(&c.alpha, m) && al.get(&c.beta, m + 1);
+  double *G = nullptr, *ev = nullptr, *U = nullptr, *V = nullptr, *kd = nullptr;
+  void* ework = nullptr;
+  if (k > 0) {
+    ok = ok && al.get(&G, (int64_t)ell * ell) && al.get(&ev, ell) && al.get(&U, (int64_t)ell * ell) &&
+         al.get(&V, (int64_t)k * d) && al.get(&kd, k) &&
+         al.get(reinterpret_cast<char**>(&ework), std::max<int64_t>(eig_work_bytes(ell), 1));
+  }
+  if (!ok) return SFD_E_NOMEM;
+  hipError_t e;
+  // CSR offsets, CSC (and ||A||_F^2 with repeated entries summed, from the sorted column ids)
+  k_rebase<<<grid_for(n + 1, 256), 256, 0, st>>>(indptr, n, rowptr);
+  const int* keys = nullptr;
+  if ((e = build_csc(rowptr, colidx, vals, (int)n, (int)nnz, d, cscptr, cscrow, cscval, w, &keys, st)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = fill_f32(reinterpret_cast<float*>(sc), sizeof(DevScalars) / 4, 0.f, st)) != hipSuccess) return hip_fail(e);
+  if (nnz > 0 && (e = fro2_segments(cscptr, keys, cscrow, cscval, d, 1, w.part, sc, st)) != hipSuccess)
+    return hip_fail(e);
+  c.rowptr = rowptr;
+  c.colidx = colidx;
+  c.val = vals;
+  c.cscptr = cscptr;
+  c.cscrow = cscrow;
+  c.cscval = cscval;
+  DevScalars hsc{};
+  if (hipMemcpyAsync(&hsc, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SFD_E_DEVICE;
+  const double fro2A = nnz > 0 ? hsc.fro2A : 0.0;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  sfd_eval_t r{};
+  r.fro2A = fro2A;
+  // cov-err: extreme eigenvalues of A^T A - B^T B
+  std::vector<double> ta, tb;
+  if ((e = lanczos(c, true, m, seed, ta, tb)) != hipSuccess) return hip_fail(e);
+  r.cov_min = tri_kth(ta, tb, 0);
+  r.cov_max = tri_kth(ta, tb, (int)ta.size() - 1);
+  r.cov_err = std::max(std::fabs(r.cov_min), std::fabs(r.cov_max)) / fro2A;
+  r.steps = (int32_t)ta.size();
+  r.top_k_energy = nan;
+  r.proj_num = nan;
+  r.proj_err = nan;
+  if (k > 0) {
+    // ||A - A_k||_F^2 from the k largest eigenvalues of A^T A
+    if ((e = lanczos(c, false, m, seed ^ 0x5DEECE66Dull, ta, tb)) != hipSuccess) return hip_fail(e);
+    const int mm = (int)ta.size();
+    double topk = 0.0;
+    for (int i = 0; i < k && i < mm; ++i) topk += tri_kth(ta, tb, mm - 1 - i);
+    r.top_k_energy = topk;
+    // V_k from the eig of B B^T, then ||A V_k||_F^2 = sum_c ||A v_c||^2
+    k_gram64<<<dim3(ell, ell), 256, 0, st>>>(B, ell, d, G);
+    if ((e = eig_sym(G, ell, ell, ell, ev, U, ework, st)) != hipSuccess) return hip_fail(e);
+    k_right_vectors<<<dim3(grid_for(d, 256), k), 256, 0, st>>>(B, ell, d, U, ev, k, V);
+    for (int cc = 0; cc < k; ++cc) {
+      k_spmv64<<<grid_for(n * 16, 256), 256, 0, st>>>(rowptr, colidx, vals, n, V + (int64_t)cc * d, c.y);
+      const unsigned nb = grid_for(n, 256, kEvalBlocks);
+      k_multi_dot<<<dim3(nb, 1), 256, 0, st>>>(c.y, n, c.y, n, c.part);
+      k_sum_parts<<<1, 256, 0, st>>>(c.part, (int)nb, kd + cc);
+    }
+    std::vector<double> hk((size_t)k);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+    if (hipMemcpyAsync(hk.data(), kd, sizeof(double) * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SFD_E_DEVICE;
+    double av = 0.0;
+    for (double x : hk) av += x;
+    r.proj_num = fro2A - av;
+    r.proj_err = r.proj_num / (fro2A - topk);
+  }
+  *out = r;
+  return SFD_OK;
+}

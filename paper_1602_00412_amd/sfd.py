@@ -62,6 +62,7 @@ EXPORTS = [
     "sfd_batch_get_stats",
     "sfd_batch_append_csr",
     "sfd_batch_sketch",
+    "sfd_evaluate",
 ]
 
 
@@ -92,6 +93,24 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class EvalResult(ctypes.Structure):
+    """sfd_eval_t: the accuracy measures of a sketch (Sec. 4)."""
+    _fields_ = [
+        ("fro2A", ctypes.c_double),
+        ("cov_min", ctypes.c_double),
+        ("cov_max", ctypes.c_double),
+        ("cov_err", ctypes.c_double),
+        ("top_k_energy", ctypes.c_double),
+        ("proj_num", ctypes.c_double),
+        ("proj_err", ctypes.c_double),
+        ("steps", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
 
 class Profile(ctypes.Structure):
@@ -142,6 +161,7 @@ def load(path: str = LIB_PATH):
         "sfd_batch_get_stats": (i, [vp, i32, ctypes.POINTER(Stats)]),
         "sfd_batch_append_csr": (i, [vp, i32, vp, vp, vp, vp, vp, i]),
         "sfd_batch_sketch": (i, [vp, vp, i]),
+        "sfd_evaluate": (i, [i64, i64, vp, vp, vp, vp, i32, i32, i32, u64, vp, ctypes.POINTER(EvalResult)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -352,3 +372,24 @@ def start_block(seed: int, stream_id: int, buffer: int, attempt: int, purpose: i
     torch.cuda.synchronize()
     _check(load().sfd_start_block(seed, stream_id, buffer, attempt, purpose, d, ell, out.data_ptr()), "sfd_start_block")
     return out
+
+
+def evaluate(indptr, indices, values, d: int, B=None, k: int = 0, steps: int = 0, seed: int = 0) -> dict:
+    """cov-err and proj-err of the sketch B (ell x d) against the CSR matrix A (sfd_evaluate, FP64 on
+    the GPU).  indptr/indices/values and B are torch CUDA tensors (int64, int32, float32, float32)."""
+    import torch
+
+    n = int(indptr.numel()) - 1
+    for t, dt in ((indptr, torch.int64), (indices, torch.int32), (values, torch.float32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError("indptr / indices / values must be contiguous CUDA int64 / int32 / float32 tensors")
+    ell, bp = 0, None
+    if B is not None:
+        if not (B.is_cuda and B.dtype == torch.float32 and B.is_contiguous() and B.dim() == 2 and B.shape[1] == d):
+            raise TypeError("B must be a contiguous CUDA float32 tensor of shape (ell, d)")
+        ell, bp = int(B.shape[0]), B.data_ptr()
+    res = EvalResult()
+    _check(load().sfd_evaluate(n, int(d), indptr.data_ptr(), indices.data_ptr(), values.data_ptr(), bp, ell, int(k),
+                               int(steps), int(seed), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                               ctypes.byref(res)), "sfd_evaluate")
+    return res.as_dict()

@@ -46,6 +46,9 @@ def test_strerror_and_argument_errors_without_a_gpu():
     assert lib.sfd_create(1 << 30, 5, 0.25, 0, ctypes.byref(h)) == sfd.SFD_E_ARG
     assert lib.sfd_destroy(None) == sfd.SFD_OK
     assert lib.sfd_merge(None, None) == sfd.SFD_E_ARG
+    res = sfd.EvalResult()
+    assert lib.sfd_evaluate(10, 5, None, None, None, None, 0, 0, 0, 0, None, ctypes.byref(res)) == sfd.SFD_E_ARG
+    assert lib.sfd_evaluate(10, 0, None, None, None, None, 0, 0, 0, 0, None, None) == sfd.SFD_E_ARG
 
 
 def test_batch_argument_errors_without_a_gpu():
