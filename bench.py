@@ -517,8 +517,25 @@ def main() -> int:
             f"({res['single'] / res['batched']:.2f}x one stream at a time)")
         del bat, single
 
+    # The evaluator (sfd_evaluate, FP64 on the GPU): cov-err and proj-err (k = 10) of the timed
+    # line's sketch against the whole stream.  Not for the 10^9-entry stream (its 160-step
+    # Lanczos runs would take about a minute).
+    if not args.no_forms and not args.profile_only and args.workload in ("config2", "config3"):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ev = sfd.evaluate(indptr, indices, values, st_d, out, k=10, steps=160)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        forms["eval"] = {"seconds": dt, "cov_err": ev["cov_err"], "proj_err": ev["proj_err"], "k": 10,
+                         "lanczos_steps": ev["steps"], "rows": st_n, "nnz": st_nnz, "d": st_d, "ell": ell,
+                         "what": "sfd_evaluate of the sketch against the whole stream (two 160-step FP64 "
+                                 "Lanczos runs with full reorthogonalisation, CSC build included)"}
+        log(f"evaluator: cov-err {ev['cov_err']:.4e}, proj-err(k=10) {ev['proj_err']:.4f} of the sketch vs the "
+            f"whole stream in {dt:.2f} s")
+
     cpu = None
     parity = None
+    eval_check = None
     if args.workload in ("config5", "config3"):
         # The oracle costs a d x ell Householder QR per product (about a second each at d = 1e6,
         # ell = 100), so it checks the device path on the prefix with q = 3 (the same kernels and
@@ -548,6 +565,26 @@ def main() -> int:
         Bg = sk2.sketch().cpu().numpy().astype(np.float64)
         parity = evaluate.gram_distance(Bg, B_oracle)
         log(f"sample parity (rel. Frobenius of B^T B vs oracle): {parity:.2e}")
+        # the evaluator on the same sample against scipy's ARPACK on the evaluator's definitions
+        # (the sketch's residual A^T A - B^T B is positive semidefinite, so cov-err is its largest
+        # eigenvalue over ||A||_F^2)
+        if not args.no_forms:
+            import scipy.sparse as sps
+            import scipy.sparse.linalg as spla
+
+            A_s = sps.csr_matrix((sub.values.astype(np.float64), sub.indices, sub.indptr - sub.indptr[0]),
+                                 shape=(sub.n, st.d))
+            ev_s = sfd.evaluate(torch.from_numpy(sub.indptr).cuda(), torch.from_numpy(sub.indices).cuda(),
+                                torch.from_numpy(sub.values).cuda(), st.d,
+                                torch.from_numpy(Bg.astype(np.float32)).cuda(), k=10, steps=160)
+            op = spla.LinearOperator((st.d, st.d), dtype=np.float64,
+                                     matvec=lambda x: A_s.T @ (A_s @ np.ravel(x)) - Bg.T @ (Bg @ np.ravel(x)))
+            lmax = spla.eigsh(op, k=1, which="LA", tol=1e-10, return_eigenvectors=False)[0]
+            eval_check = {"cov_err_gpu": ev_s["cov_err"], "cov_err_arpack": float(lmax / evaluate.fro2(A_s)),
+                          "proj_err_gpu": ev_s["proj_err"], "proj_err_ref": evaluate.proj_err(A_s, Bg, 10),
+                          "sample": f"first {sub.n} rows, the GPU sketch of them (ell={ell}), k=10"}
+            log(f"evaluator on the sample: cov-err {ev_s['cov_err']:.6e} (ARPACK {eval_check['cov_err_arpack']:.6e}), "
+                f"proj-err {ev_s['proj_err']:.6f} (reference {eval_check['proj_err_ref']:.6f})")
     line = {
         "metric": METRIC,
         "value": value,
@@ -575,6 +612,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "sample_parity_rel_frobenius": parity,
+        "evaluator_check": eval_check,
         "forms": forms,
         "phases": phases,
     }

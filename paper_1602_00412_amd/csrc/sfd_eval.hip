@@ -39,20 +39,49 @@ __global__ void k_rebase(const int64_t* __restrict__ indptr, int64_t n, int* __r
     rowptr[r] = (int)(indptr[r] - base);
 }
 
-// y[r] = sum_k val[k] x[idx[k]] over the rows r < rows of (ptr, idx, val): a 16-lane group per
-// row, lane s adding entries s, s + 16, ... then a fixed xor tree.
-__global__ __launch_bounds__(256) void k_spmv64(const int* __restrict__ ptr, const int* __restrict__ idx,
-                                                const float* __restrict__ val, int64_t rows,
-                                                const double* __restrict__ x, double* __restrict__ y) {
+// y[r] = sum_k val[k] x[idx[k]] over the chunk schedule of a CSR / CSC structure (rows cut into
+// chunks of at most kSpmmChunk entries, so Zipf-long columns are spread over many groups): a
+// 16-lane group per chunk, lane s adding entries s, s + 16, ... then a fixed xor tree; a whole
+// row is written to y, the chunks of a long row to their partial slots (k_spmv64_fixup).
+__global__ __launch_bounds__(256) void k_spmv64(const int4* __restrict__ desc, const int* __restrict__ nchunks_ptr,
+                                                const int* __restrict__ idx, const float* __restrict__ val,
+                                                const double* __restrict__ x, double* __restrict__ y,
+                                                double* __restrict__ partial) {
   const int sub = threadIdx.x & 15;
+  const int64_t nchunks = *nchunks_ptr;
   const int64_t ng = ((int64_t)gridDim.x * blockDim.x) >> 4;
-  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; r < rows; r += ng) {
-    const int a = ptr[r], b = ptr[r + 1];
+  for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; c < nchunks; c += ng) {
+    const int4 dc = desc[c];
     double acc = 0.0;
-    for (int p = a + sub; p < b; p += 16) acc = fma((double)val[p], x[idx[p]], acc);
+    for (int p = dc.y + sub; p < dc.z; p += 16) acc = fma((double)val[p], x[idx[p]], acc);
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-    if (sub == 0) y[r] = acc;
+    if (sub == 0) {
+      if (dc.w < 0)
+        y[dc.x] = acc;
+      else
+        partial[dc.w] = acc;
+    }
+  }
+}
+
+// y[r] = sum of the partial slots of long row r, in slot order (lane j adds slots j, j + 64, ...,
+// then a fixed xor tree); one wave per long row
+__global__ __launch_bounds__(256) void k_spmv64_fixup(const int* __restrict__ slot_start,
+                                                      const int* __restrict__ long_rows,
+                                                      const int* __restrict__ nlong_ptr,
+                                                      const double* __restrict__ partial, double* __restrict__ y) {
+  const int nlong = *nlong_ptr;
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < nlong; i += nw) {
+    const int r = long_rows[i];
+    const int s0 = slot_start[r], n = slot_start[r + 1] - s0;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += partial[s0 + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) y[r] = acc;
   }
 }
 
@@ -232,21 +261,27 @@ struct Allocs {
 
 struct EvalCtx {
   int64_t n, d;
-  const int* rowptr;
   const int* colidx;
   const float* val;
-  const int *cscptr, *cscrow;
+  const int* cscrow;
   const float* cscval;
+  Schedule sr, sc;  // chunk schedules of the CSR and the CSC
   const float* B;
   int ell;
-  double *y, *w, *u, *part, *scal, *Q, *alpha, *beta;
+  double *y, *w, *u, *part, *scal, *Q, *alpha, *beta, *partial;
   hipStream_t st;
 };
 
+// y = the product of a scheduled structure with x
+void spmv_sched(EvalCtx& c, const Schedule& s, const int* idx, const float* val, const double* x, double* y) {
+  k_spmv64<<<grid_for(s.max_chunks * 16, 256), 256, 0, c.st>>>(s.desc, s.regions + 1, idx, val, x, y, c.partial);
+  k_spmv64_fixup<<<256, 256, 0, c.st>>>(s.pslot, s.long_rows, s.counters, c.partial, y);
+}
+
 // w = A^T (A x) (- B^T (B x))
 hipError_t apply_op(EvalCtx& c, const double* x, bool withB) {
-  k_spmv64<<<grid_for(c.n * 16, 256), 256, 0, c.st>>>(c.rowptr, c.colidx, c.val, c.n, x, c.y);
-  k_spmv64<<<grid_for(c.d * 16, 256), 256, 0, c.st>>>(c.cscptr, c.cscrow, c.cscval, c.d, c.y, c.w);
+  spmv_sched(c, c.sr, c.colidx, c.val, x, c.y);
+  spmv_sched(c, c.sc, c.cscrow, c.cscval, c.y, c.w);
   if (withB && c.ell > 0) {
     k_rows_dot<<<c.ell, 256, 0, c.st>>>(c.B, c.d, x, c.u);
     k_sub_bt<<<grid_for(c.d, 256), 256, 0, c.st>>>(c.B, c.ell, c.d, c.u, c.w);
@@ -360,8 +395,16 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
   bool ok = al.get(&rowptr, n + 1) && al.get(&cscptr, d + 1) && al.get(&cscrow, nnz) && al.get(&cscval, nnz);
   ok = ok && al.get(&w.counts, 1) && al.get(&w.rowid, nnz) && al.get(&w.keys0, nnz) && al.get(&w.keys1, nnz) &&
        al.get(&w.vals0, nnz) && al.get(&w.vals1, nnz) && al.get(&w.hist, 256 * tiles + 1) &&
-       al.get(&w.part, fro2_part_doubles(1)) && al.get(&w.scan_tmp, scan_tmp_ints(256 * tiles + 1) + 16) &&
+       al.get(&w.part, fro2_part_doubles(1)) &&
+       al.get(&w.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, std::max(n, d) + 1)) + 16) &&
        al.get(&sc, 1);
+  for (Schedule* sch : {&c.sr, &c.sc}) {
+    const int64_t rows = sch == &c.sr ? n : d;
+    sch->max_chunks = rows + nnz / kSpmmChunk + 2;
+    ok = ok && al.get(&sch->nch, rows + 1) && al.get(&sch->pslot, rows + 1) && al.get(&sch->desc, sch->max_chunks) &&
+         al.get(&sch->long_rows, rows + 1) && al.get(&sch->counters, 4) && al.get(&sch->regions, kXcdBands + 2);
+  }
+  ok = ok && al.get(&c.partial, 2 * nnz / kSpmmChunk + 16);
   ok = ok && al.get(&c.y, n) && al.get(&c.w, d) && al.get(&c.u, std::max(ell, 1)) &&
        al.get(&c.part, (int64_t)kEvalBlocks * (kEvalMaxSteps + 1)) && al.get(&c.scal, kEvalMaxSteps + 8) &&
        al.get(&c.Q, (int64_t)(m + 1) * d) && al.get(&c.alpha, m) && al.get(&c.beta, m + 1);
@@ -382,12 +425,12 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
   if ((e = fill_f32(reinterpret_cast<float*>(sc), sizeof(DevScalars) / 4, 0.f, st)) != hipSuccess) return hip_fail(e);
   if (nnz > 0 && (e = fro2_segments(cscptr, keys, cscrow, cscval, d, 1, w.part, sc, st)) != hipSuccess)
     return hip_fail(e);
-  c.rowptr = rowptr;
   c.colidx = colidx;
   c.val = vals;
-  c.cscptr = cscptr;
   c.cscrow = cscrow;
   c.cscval = cscval;
+  if ((e = schedule_build(rowptr, (int)n, c.sr, w.scan_tmp, st)) != hipSuccess) return hip_fail(e);
+  if ((e = schedule_build(cscptr, (int)d, c.sc, w.scan_tmp, st)) != hipSuccess) return hip_fail(e);
   DevScalars hsc{};
   if (hipMemcpyAsync(&hsc, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -418,7 +461,7 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
     if ((e = eig_sym(G, ell, ell, ell, ev, U, ework, st)) != hipSuccess) return hip_fail(e);
     k_right_vectors<<<dim3(grid_for(d, 256), k), 256, 0, st>>>(B, ell, d, U, ev, k, V);
     for (int cc = 0; cc < k; ++cc) {
-      k_spmv64<<<grid_for(n * 16, 256), 256, 0, st>>>(rowptr, colidx, vals, n, V + (int64_t)cc * d, c.y);
+      spmv_sched(c, c.sr, colidx, vals, V + (int64_t)cc * d, c.y);
       const unsigned nb = grid_for(n, 256, kEvalBlocks);
       k_multi_dot<<<dim3(nb, 1), 256, 0, st>>>(c.y, n, c.y, n, c.part);
       k_sum_parts<<<1, 256, 0, st>>>(c.part, (int)nb, kd + cc);
