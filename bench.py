@@ -243,7 +243,7 @@ def main() -> int:
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
     ap.add_argument("--lanes", type=int, default=0, help="lanes of the timed FP32 line (0: the library's default)")
     ap.add_argument("--hw-queues", type=int, default=0, choices=[0, 1, 2, 4, 8, 16, 32],
-                    help="HIP hardware queues for this process (0: at least 16)")
+                    help="HIP hardware queues for this process (0: at least 16, 32 for the ell = 200 workload)")
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -259,14 +259,16 @@ def main() -> int:
     ap.add_argument("--c4-streams", type=int, default=4096, help="config4: the first this many streams")
     args = ap.parse_args()
     # HIP maps streams onto a per-process pool of hardware queues (4 by default) and streams
-    # beyond it share queues: with 16, torch's stream and the lane and main streams of both
-    # handles created here (FP32 line, BF16 form; or the batch's 16 lanes) get queues of their
-    # own, so concurrent buffer steps do not serialise behind one another.  Set before HIP
-    # starts; a larger value already in the environment is kept.
+    # beyond it share queues: with 16 (32 when the handles run 8 lanes each), torch's stream and
+    # the lane and main streams of both handles created here (FP32 line, BF16 form; or the
+    # batch's 16 lanes) get queues of their own, so concurrent buffer steps do not serialise
+    # behind one another.  Set before HIP starts; a larger value already in the environment is
+    # kept.
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     else:
-        want = 16
+        # the ell = 200 workload's handles run 8 lanes each (FP32 line and BF16 form)
+        want = 32 if args.workload == "config3" else 16
         try:
             have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
         except ValueError:

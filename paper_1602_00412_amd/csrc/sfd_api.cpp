@@ -441,7 +441,8 @@ int orth_out(sfd_t* h, Lane& ln, void* panel, PanelType pt, int64_t rows) {
   const int L = h->L;
   const double ell = h->ell;
   {
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 2.0 * pbytes(pt) * rows * ell, 4.0 * rows * ell * ell, 2);
+    // flops the method needs: panel x triangular T and the symmetric Gram, rows ell (ell + 1) each
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 2.0 * pbytes(pt) * rows * ell, 2.0 * rows * ell * (ell + 1), 2);
     CK(xform_gram(panel, pt, L, rows, L, ln.T, ln.gram_part, ln.W, ln.st));
   }
   {
@@ -550,7 +551,7 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   if ((rc = spmm_csc(h, ln, Y, pt, ln.Pt, PanelType::F32))) return rc;
   {
     // P^T <- P^T T_y and W = P P^T
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 4.0 * d * ell * ell, 2);
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 2.0 * d * ell * (ell + 1), 2);
     CK(xform_gram(ln.Pt, PanelType::F32, L, d, L, ln.T, ln.gram_part, ln.W, ln.st));
   }
   {
@@ -610,7 +611,8 @@ int dense_shrink(sfd_t* h, Lane& ln, const float* Bin, const float* Pt, int loss
   if (!M64) M64 = ln.M64;
   CK(hipStreamWaitEvent(ln.st, ln.ss->ev_dsh, 0));
   {
-    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 8.0 * d * ell * ell, 2);
+    // the symmetric Gram of the d x 2 ell stack [B^T | P^T]
+    ProfScope ps(h, ln.st, SFD_PROF_GRAM, 8.0 * d * ell, 2.0 * d * ell * (2.0 * ell + 1), 2);
     CK(gram2(Bin, L, Pt, L, d, L, ln.gram_part, ln.W2, ln.st));
   }
   {

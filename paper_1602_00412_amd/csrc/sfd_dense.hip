@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __res
 //    below hit 64 distinct banks);
 //  * out (16 x L) = tile (16 x L) * T: k-step ks, strip n: A[m][k] = tile[m][4 ks + k] (lane l:
 //    m = l % 16, k = l / 16), B[k][n'] = T[4 ks + k][16 n + n'] (held in registers), C lane l:
-//    out[4 (l / 16) + v][16 n + l % 16];
+//    out[4 (l / 16) + v][16 n + l % 16]; T is upper triangular (an inverse Cholesky factor), so
+//    strip n needs the k-steps ks < 4 (n + 1) only;
 //  * the accumulator of strip n at fixed v is itself an A / B operand over the four rows
 //    4 k + v (k = l / 16), so Gram += out^T out is formed from the registers directly: for
 //    v = 0..3 and each upper tile (si, sj), MFMA(C_si[v], C_sj[v]).
@@ -224,8 +225,10 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const float a = my[lm * LP + 4 * ks + lk];
+      // T is upper triangular: rows 4 ks .. 4 ks + 3 of strip n are zero once ks >= 4 (n + 1)
 #pragma unroll
-      for (int n = 0; n < S; ++n) o[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tb[ks][n], o[n], 0, 0, 0);
+      for (int n = 0; n < S; ++n)
+        if (ks < 4 * (n + 1)) o[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tb[ks][n], o[n], 0, 0, 0);
     }
     // round to the stored precision, store, and add the stored values' Gram
 #pragma unroll
@@ -280,9 +283,10 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
 // operands in registers (lane l: T[4 ks + l / 16][16 w + l % 16]); the 16-row input tile is loaded
 // by the whole block (16 bytes per thread), staged in LDS as FP32 (pitch L + 4, two buffers, so
 // one barrier per tile), and read as A operands by every wave.  A tile is read completely before
-// any of it is written, so out may be Pin.
+// any of it is written, so out may be Pin.  UPPER: T is upper triangular (an inverse Cholesky
+// factor), so strip w needs the k-steps ks < 4 (w + 1) only.
 // Groups: buffer k = blockIdx.z owns rows [segs[k].row0, + segs[k].rows) with T + k L L.
-template <int L, bool BF, bool ACC>
+template <int L, bool BF, bool ACC, bool UPPER>
 __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi, void* out, int ldo, int64_t rows,
                                                         int rpb, const float* __restrict__ T, int ldt,
                                                         const GroupSeg* segs) {
@@ -344,7 +348,8 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi
     }
     const float* tl = tile[buf];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) o = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[lm * LP + 4 * ks + lk], tb[ks], o, 0, 0, 0);
+    for (int ks = 0; ks < KS; ++ks)
+      if (!UPPER || ks < 4 * (w + 1)) o = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[lm * LP + 4 * ks + lk], tb[ks], o, 0, 0, 0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = t0 + 4 * lk + v;
@@ -698,14 +703,14 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
     const dim3 gg((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), (unsigned)K);
     if (L == 128) {
       if (bf)
-        k_xform_strips<128, true, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+        k_xform_strips<128, true, false, true><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
       else
-        k_xform_strips<128, false, false><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+        k_xform_strips<128, false, false, true><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
     } else {
       if (bf)
-        k_xform_strips<256, true, false><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+        k_xform_strips<256, true, false, true><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
       else
-        k_xform_strips<256, false, false><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
+        k_xform_strips<256, false, false, true><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
     }
     if (bf)
       k_gram_tiles<true><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
@@ -760,12 +765,12 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
     rpb = (rpb + 15) & ~15;
     nb = (rows + rpb - 1) / rpb;
     if (L == 128) {
-      k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<128, false, true><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+      k_xform_strips<128, false, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<128, false, true, false><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
                                                                      nullptr);
     } else {
-      k_xform_strips<256, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<256, false, true><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+      k_xform_strips<256, false, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<256, false, true, false><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
                                                                       nullptr);
     }
   } else {

@@ -140,8 +140,9 @@ hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule
 // ---------------------------------------------------------------- dense panels (sfd_dense.hip)
 // partial buffers of the Gram kernels hold at most gram_max_blocks() blocks of 4*L*L floats
 int gram_max_blocks();
-// P <- P T in place (rows x L, L in {32, 64, 128}, FP32 or BF16; T: L x L f32) and W = Gram of the
-// result as stored (FP64, L x L)
+// P <- P T in place (rows x L, L in {32, 64, 128, 256}, FP32 or BF16; T: L x L f32, upper
+// triangular: its zero blocks below the diagonal are skipped) and W = Gram of the result as
+// stored (FP64, L x L)
 hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const float* T, float* partials, double* W,
                       hipStream_t st);
 // the same for the K buffers of a group: segs (device, K entries) give each buffer's rows of P;
