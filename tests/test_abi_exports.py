@@ -77,3 +77,18 @@ def test_binding_constants_match_the_header():
         assert names
         for n in names:
             assert getattr(sfd, n) == values[n], n
+
+
+def test_evaluate_binding_checks_its_arguments_without_a_gpu():
+    # host tensors and wrong dtypes are refused before the library is called
+    import torch
+
+    from paper_1602_00412_amd import sfd
+
+    p = torch.zeros(2, dtype=torch.int64)
+    i = torch.zeros(1, dtype=torch.int32)
+    v = torch.zeros(1, dtype=torch.float32)
+    with pytest.raises(TypeError):
+        sfd.evaluate(p, i, v, 4)
+    with pytest.raises(TypeError):
+        sfd.evaluate(p, i.to(torch.int64), v, 4)
