@@ -277,7 +277,7 @@ def main() -> int:
             os.environ["GPU_MAX_HW_QUEUES"] = str(want)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
-              f"one merge at the end, which this build does not run across GPUs", file=sys.stderr)
+              f"one merge at the end; runs across several GPUs are not implemented", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -19,7 +19,7 @@
  *    every call but sfd_reset/sfd_destroy/sfd_get_stats returns SFD_E_STATE.
  *  - Threads: a handle must not be used by two threads at once.  Different handles are
  *    independent.
- *  - Sizes: 1 <= ell <= min(d, 256) in this build; ell*d + d < 2^31 (int32 buffer indices).
+ *  - Sizes: 1 <= ell <= min(d, 256); ell*d + d < 2^31 (int32 buffer indices).
  *  - Streams: an sfd_t is one stream; an sfd_batch_t holds many (see the end of this file).
  */
 #ifndef SFD_H
