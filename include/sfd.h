@@ -71,8 +71,9 @@ enum {
                                concurrently, 1..16; default 4 (8 for ell > 128, where a buffer
                                step is paced by its one-workgroup FP64 solvers).  A lane beyond
                                those allocated gets its workspaces (one buffer's CSC, schedules
-                               and panels) when first asked for, after the work in flight.
-                               Results do not depend on it. */
+                               and panels: about 28 (ell d + d) + 20 d L bytes, L the panel
+                               width 32/64/128/256, e.g. 0.35 GB at d = 1e5, ell = 50) when first
+                               asked for, after the work in flight.  Results do not depend on it. */
   SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
                                SimultaneousIteration (Alg 1) stored in BF16 with FP32 accumulation;
                                the last product P^T = A'^T Y (Alg 3) reads the stored BF16 Y,
