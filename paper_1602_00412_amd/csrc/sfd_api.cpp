@@ -334,7 +334,7 @@ int alloc_lane(sfd_t* h, Lane& ln) {
   ok = ok && dalloc(h, &ln.csc.counts, 1) && dalloc(h, &ln.csc.rowid, cap);
   ok = ok && dalloc(h, &ln.csc.keys0, cap) && dalloc(h, &ln.csc.keys1, cap);
   ok = ok && dalloc(h, &ln.csc.vals0, cap) && dalloc(h, &ln.csc.vals1, cap);
-  ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, 1024);
+  ok = ok && dalloc(h, &ln.csc.hist, 256 * tiles + 1) && dalloc(h, &ln.csc.part, fro2_part_doubles(1));
   ok = ok && dalloc(h, &ln.scan_tmp, scan_tmp_ints(std::max<int64_t>(256 * tiles + 1, vrows)) + 16);
   ln.csc.scan_tmp = ln.scan_tmp;
   for (Schedule* s : {&ln.sr, &ln.scs}) {

@@ -187,7 +187,7 @@ __global__ void k_dense_from_csc(const int* cscptr, const int* cscrow, const flo
   }
 }
 
-constexpr int kFroBlocks = 64;  // blocks per column segment
+constexpr int kFroBlocks = 1024;  // blocks per column segment (four per CU for one buffer)
 
 // ||A'||_F^2 of each of K column segments of d columns (the buffers of a group, K = 1 for one
 // buffer), repeated (row, column) entries summed.  Entry-parallel over the segment's entries
@@ -217,11 +217,18 @@ __global__ __launch_bounds__(256) void k_fro2_cols(const int* __restrict__ cscpt
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s[0];
 }
 
-__global__ __launch_bounds__(64) void k_fro2_sum(const double* __restrict__ part, int nb, DevScalars* sc) {
-  if (threadIdx.x != 0) return;
+// sc[k].fro2A = sum of the nb block partials of segment k (fixed-order tree)
+__global__ __launch_bounds__(256) void k_fro2_sum(const double* __restrict__ part, int nb, DevScalars* sc) {
+  __shared__ double s[256];
   double t = 0.0;
-  for (int b = 0; b < nb; ++b) t += part[(int64_t)blockIdx.x * nb + b];
-  sc[blockIdx.x].fro2A = t;
+  for (int b = threadIdx.x; b < nb; b += 256) t += part[(int64_t)blockIdx.x * nb + b];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sc[blockIdx.x].fro2A = s[0];
 }
 
 // dst[i] = src[i] + add (column ids of buffer k moved to the group's columns k d ..)
@@ -297,7 +304,7 @@ hipError_t build_csc(const int* rowptr, const int* colidx, const float* val, int
 hipError_t fro2_segments(const int* cscptr, const int* keys, const int* cscrow, const float* cscval, int64_t d, int K,
                          double* part, DevScalars* sc, hipStream_t st) {
   k_fro2_cols<<<dim3(kFroBlocks, K), 256, 0, st>>>(cscptr, keys, cscrow, cscval, d, part);
-  k_fro2_sum<<<K, 64, 0, st>>>(part, kFroBlocks, sc);
+  k_fro2_sum<<<K, 256, 0, st>>>(part, kFroBlocks, sc);
   return hipGetLastError();
 }
 
