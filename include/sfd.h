@@ -252,7 +252,8 @@ typedef struct {
 /* Evaluate the ell x d sketch B against the n x d matrix A it summarises.
  * A: CSR in device memory as in sfd_append_csr (int64 indptr[n + 1], rows read from
  * indices/values positions indptr[0] .. indptr[n]); B: ell x d FP32 row-major in device memory
- * (ell = 0: no sketch, B may be NULL).  k: rank of proj-err, 0 <= k <= ell (0 skips it).
+ * (ell = 0: no sketch, B may be NULL; ell <= 512).  k: rank of proj-err, 0 <= k <= ell and
+ * k <= the steps taken (0 skips it).  n, d < 2^31, at most 2^31 - 1 stored entries.
  * steps: Lanczos steps per operator, 1..512, at most d (<= 0: min(d, 160)).  The extreme
  * eigenvalues of A^T A - B^T B come from Lanczos with full reorthogonalisation on
  * x -> A^T(Ax) - B^T(Bx) from a start vector keyed by seed, the k largest of A^T A likewise on

@@ -355,7 +355,7 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
                             sfd_eval_t* out) {
   using namespace sfd;
   if (!out || !indptr || n < 0 || d < 1 || ell < 0 || k < 0 || k > ell || (ell > 0 && !B)) return SFD_E_ARG;
-  if (ell > 2 * kMaxEll || steps > kEvalMaxSteps || d >= ((int64_t)1 << 31)) return SFD_E_ARG;
+  if (ell > 2 * kMaxEll || steps > kEvalMaxSteps || d >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31)) return SFD_E_ARG;
   const int m = (int)std::min<int64_t>(d, steps > 0 ? steps : kEvalDefaultSteps);
   if (k > m) return SFD_E_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
