@@ -342,6 +342,7 @@ def main() -> int:
     if args.lanes:
         sk.set_option(sfd.OPT_LANES, args.lanes)
     lanes_main = args.lanes or (8 if ell > 128 else 4)  # the library's default lanes
+    Lw_main = 32 if ell <= 32 else 64 if ell <= 64 else 128 if ell <= 128 else 256  # panel width
 
     def step():
         sk.reset()
@@ -409,6 +410,14 @@ def main() -> int:
         roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["calls"]
         roof["avg_launch_us"] = avg_s * 1e6
         roof["launches"] = p["calls"]
+        if dom in ("spmm_csc", "spmm_csr") and stats["flushes"]:
+            # what a sparse product actually moves: one panel row (L elements) gathered per stored
+            # entry, against the gather rates of 256-byte rows that fit an XCD's L2 (about 20 TB/s)
+            # or come from the Infinity Cache (about 8.6 TB/s)
+            row_bytes = Lw_main * (2 if args.precision == "bf16" else 4)
+            gathered = st_nnz / stats["flushes"] * row_bytes
+            roof["gathered_bytes_per_launch"] = gathered
+            roof["gathered_TBps"] = gathered / avg_s / 1e12
         roof["timing"] = "HIP events on the lane stream, one-lane pass after the timed steps"
         roof["latency_bound"] = {k: {"ms": prof[k]["ms"], "calls": prof[k]["calls"],
                                      "avg_call_us": 1e3 * prof[k]["ms"] / prof[k]["calls"]}
