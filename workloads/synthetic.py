@@ -177,8 +177,9 @@ def config1_fp64_reference(seed: int = 0, n: int = 10_000) -> CsrStream:
 def config2_plain_fp32(seed: int = 0, n: int = 1_000_000) -> CsrStream:
     """n=1e6, d=1e5, Poisson(50) per row, Zipf(1.0) columns; values lognormal(0,1) plus a planted
     rank-20 component (sigma_i = 1/i) scaled to 30% of the expected energy at the sampled
-    positions; ell = 50.  U is N(0, 1/n) per entry (near-orthonormal, generated per row chunk so
-    prefixes agree); V is Gaussian then QR-orthonormalised."""
+    positions; ell = 50.  U is N(0, 1/n) per entry with n = 1e6 (near-orthonormal, generated per
+    row chunk, so a shorter stream has the same rows of U); V is Gaussian then
+    QR-orthonormalised.  Whole 65,536-row chunks of a shorter stream equal those of the full one."""
     d, lam, s, r = 100_000, 50.0, 1.0, 20
     return _lognormal_planted(seed, 2, n, d, lam, s, r, share=0.3, ell=50, name="config2_plain_fp32", n_total=1_000_000)
 
