@@ -7,7 +7,7 @@ SimultaneousIteration, VerifySpectral, BoostedSparseShrink, DenseShrink) and que
 
 Workload: n = 1,000,000 rows, d = 100,000, Poisson(50) entries per row from Zipf(1.0) columns,
 lognormal(0,1) values plus a planted rank-20 component with 30% of the energy, ell = 50,
-eps = 1/4, FP32 (workloads.config2_plain_fp32).
+eps = 1/4, FP32 (workloads.stream_1e6_d1e5).
 
 Prints one JSON line (metric, value in nnz/s, roofline of the dominant kernel class measured
 with HIP events on the library's stream over the timed region, and the FP64 oracle's rate on
@@ -34,7 +34,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_SOURCES = ("paper_1602_00412_amd/csrc/sfd_spmm.hip", "paper_1602_00412_amd/csrc/sfd_internal.h")
 MEASURED_TRAFFIC = {
     # (class, workload, precision): (bytes per call, sha256 prefix of TRAFFIC_SOURCES, summary)
-    ("spmm_csc", "config2", "fp32"): (6.3926e+08, "c3650cf861b0983e",
+    ("spmm_csc", "stream1e6", "fp32"): (6.3926e+08, "c3650cf861b0983e",
                                       "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
 }
 
@@ -103,10 +103,10 @@ def run_batch_full(args) -> int:
     import torch
 
     from paper_1602_00412_amd import sfd
-    from workloads.device import config4_batch
+    from workloads.device import batch_streams_d2e4
 
     t0 = time.perf_counter()
-    ptr, idx, val, starts = config4_batch("cuda", streams=args.c4_streams)
+    ptr, idx, val, starts = batch_streams_d2e4("cuda", streams=args.batch_first_streams)
     torch.cuda.synchronize()
     S, d, ell = len(starts) - 1, 20_000, 32
     nnz = int(ptr[-1].item())
@@ -248,15 +248,15 @@ def main() -> int:
                     help="panel precision of the main (timed and profiled) form; the line's value is FP32's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", choices=["config2", "config3", "config5", "config4", "paper"], default="config2",
-                    help="config2: the 1e6-row stream at ell=50 (default); config3: the 2e6-row, d=5e4 stream "
+    ap.add_argument("--workload", choices=["stream1e6", "ell200", "d1e6", "batch4096", "paper"], default="stream1e6",
+                    help="stream1e6: the 1e6-row stream at ell=50 (default); ell200: the 2e6-row, d=5e4 stream "
                          "at ell=200 (N(0,1) values), generated on the device, FP32 and BF16; "
-                         "config5: the 1e7-row, d=1e6 stream "
-                         "at ell=100, generated on the device, FP32 and BF16; config4: all 4,096 batch streams, "
+                         "d1e6: the 1e7-row, d=1e6 stream "
+                         "at ell=100, generated on the device, FP32 and BF16; batch4096: all 4,096 batch streams, "
                          "generated on the device, one batch call; paper: the paper's head/tail +-1 generator "
                          "swept over entries per row and over d, SFD (with and without VerifySpectral) "
                          "against FrequentDirections on the GPU")
-    ap.add_argument("--c4-streams", type=int, default=4096, help="config4: the first this many streams")
+    ap.add_argument("--batch-first-streams", type=int, default=4096, help="batch4096: the first this many streams")
     args = ap.parse_args()
     # HIP maps streams onto a per-process pool of hardware queues (4 by default) and streams
     # beyond it share queues: with 16 (32 when the handles run 8 lanes each), torch's stream and
@@ -268,7 +268,7 @@ def main() -> int:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     else:
         # the ell = 200 workload's handles run 8 lanes each (FP32 line and BF16 form)
-        want = 32 if args.workload == "config3" else 16
+        want = 32 if args.workload == "ell200" else 16
         try:
             have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
         except ValueError:
@@ -284,7 +284,7 @@ def main() -> int:
     import torch
 
     from paper_1602_00412_amd import sfd
-    from workloads import config2_plain_fp32
+    from workloads import stream_1e6_d1e5
 
     sfd.load()
     if not torch.cuda.is_available():
@@ -300,27 +300,27 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
         return 0
-    if args.workload == "config4":
+    if args.workload == "batch4096":
         return run_batch_full(args)
     if args.workload == "paper":
         return run_paper_sweep(args)
     t0 = time.perf_counter()
-    if args.workload in ("config5", "config3"):
-        from workloads.device import config3_precision, config5_large
+    if args.workload in ("d1e6", "ell200"):
+        from workloads.device import stream_2e6_d5e4, stream_1e7_d1e6
         from workloads import CsrStream
 
-        big = args.workload == "config5"
-        n5 = args.rows if args.rows != 1_000_000 else (10_000_000 if big else 2_000_000)
-        d5 = 1_000_000 if big else 50_000
-        indptr, indices, values = (config5_large if big else config3_precision)("cuda", n=n5)
+        big = args.workload == "d1e6"
+        n_dev = args.rows if args.rows != 1_000_000 else (10_000_000 if big else 2_000_000)
+        d_dev = 1_000_000 if big else 50_000
+        indptr, indices, values = (stream_1e7_d1e6 if big else stream_2e6_d5e4)("cuda", n=n_dev)
         torch.cuda.synchronize()
         ell = 100 if big else 200
         # host copy of a prefix: the sample the oracle checks
-        pre = min(args.cpu_sample_rows, n5)
+        pre = min(args.cpu_sample_rows, n_dev)
         ppre = indptr[:pre + 1].cpu().numpy()
         st = CsrStream(ppre, indices[:int(ppre[-1])].cpu().numpy(), values[:int(ppre[-1])].cpu().numpy(),
-                       d5, dict(name=f"{args.workload} prefix"))
-        st_n, st_d, st_nnz = n5, d5, int(indptr[-1].item())
+                       d_dev, dict(name=f"{args.workload} prefix"))
+        st_n, st_d, st_nnz = n_dev, d_dev, int(indptr[-1].item())
         if big:
             desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=100 s=1.0 lognormal+planted rank-100 (30%), "
                     f"ell={ell} eps=1/4, generated on the device")
@@ -328,7 +328,7 @@ def main() -> int:
             desc = (f"zipf-poisson stream n={st_n} d={st_d} lambda=80 s=1.1 N(0,1)+planted rank-50 (sigma_i=1/i), "
                     f"ell={ell} eps=1/4, generated on the device")
     else:
-        st = config2_plain_fp32(seed=0, n=args.rows)
+        st = stream_1e6_d1e5(seed=0, n=args.rows)
         ell = 50
         indptr = torch.from_numpy(st.indptr).cuda()
         indices = torch.from_numpy(st.indices).cuda()
@@ -469,11 +469,11 @@ def main() -> int:
     # ell = 32, log-uniform lengths 1e3..1e5 rows), resident in HBM, appended in one call and
     # queried; compared with the same streams fed one at a time through a single-stream handle.
     if (not args.no_forms and not args.profile_only and args.precision == "fp32" and args.batch_streams > 0
-            and args.workload == "config2"):
-        from workloads import config4_batch_stream
+            and args.workload == "stream1e6"):
+        from workloads import batch_stream_d2e4
 
         t = time.perf_counter()
-        bst = [config4_batch_stream(s) for s in range(args.batch_streams)]
+        bst = [batch_stream_d2e4(s) for s in range(args.batch_streams)]
         bd, bell = bst[0].d, 32
         b_ptr = np.zeros(1 + sum(x.n for x in bst), dtype=np.int64)
         starts = np.zeros(len(bst) + 1, dtype=np.int64)
@@ -531,7 +531,7 @@ def main() -> int:
     # The evaluator (sfd_evaluate, FP64 on the GPU): cov-err and proj-err (k = 10) of the timed
     # line's sketch against the whole stream.  Not for the 10^9-entry stream (its 160-step
     # Lanczos runs would take about a minute).
-    if not args.no_forms and not args.profile_only and args.workload in ("config2", "config3"):
+    if not args.no_forms and not args.profile_only and args.workload in ("stream1e6", "ell200"):
         torch.cuda.synchronize()
         t = time.perf_counter()
         ev = sfd.evaluate(indptr, indices, values, st_d, out, k=10, steps=160)
@@ -547,7 +547,7 @@ def main() -> int:
     cpu = None
     parity = None
     eval_check = None
-    if args.workload in ("config5", "config3"):
+    if args.workload in ("d1e6", "ell200"):
         # The oracle costs a d x ell Householder QR per product (about a second each at d = 1e6,
         # ell = 100), so it checks the device path on the prefix with q = 3 (the same kernels and
         # shapes; the q of the method is only shortened) and is not timed as a baseline.

@@ -2,7 +2,7 @@
 
     python tests/golden/make_golden.py
 
-config1_oracle.json: the FP64 oracle on the 10,000 x 1,000 Zipf stream (ell = 20, seed 0):
+stream_1e4_d1e3_oracle.json: the FP64 oracle on the 10,000 x 1,000 Zipf stream (ell = 20, seed 0):
 squared singular values of B, per-buffer VerifySpectral log norms, cov-err and the
 FrequentDirections bound with k = 10.
 """
@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import SFDOracle, evaluate  # noqa: E402
-from workloads import config1_fp64_reference  # noqa: E402
+from workloads import stream_1e4_d1e3  # noqa: E402
 
 
-def config1_record():
-    st = config1_fp64_reference()
+def golden_record():
+    st = stream_1e4_d1e3()
     o = SFDOracle(st.d, 20, 0.25, 0)
     o.append_csr(st.indptr, st.indices, st.values)
     B = o.sketch()
@@ -39,5 +39,5 @@ def config1_record():
 
 
 if __name__ == "__main__":
-    with open(os.path.join(HERE, "config1_oracle.json"), "w") as f:
-        json.dump(config1_record(), f, indent=1)
+    with open(os.path.join(HERE, "stream_1e4_d1e3_oracle.json"), "w") as f:
+        json.dump(golden_record(), f, indent=1)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import evaluate
-from workloads import config1_fp64_reference, small_random_csr
+from workloads import stream_1e4_d1e3, small_random_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_bf16_form_keeps_property1_and_cov_err(gpu_lib, n, d, ell, lam, seed):
 
 
 def test_bf16_form_on_10k_rows(gpu_lib):
-    st = config1_fp64_reference()
+    st = stream_1e4_d1e3()
     sk, e16, e32 = _check_form(gpu_lib, st, 20)
     assert sk.stats()["flushes"] == 10
 

@@ -34,9 +34,9 @@ def test_million_row_stream_properties(gpu_lib):
     # 10^6 rows, d = 10^5, ell = 50 (ten buffers of 10^5 rows); host-generated like the bench
     import torch
 
-    from workloads import config2_plain_fp32
+    from workloads import stream_1e6_d1e5
 
-    st = config2_plain_fp32(seed=0)
+    st = stream_1e6_d1e5(seed=0)
     dev = [torch.from_numpy(a).cuda() for a in (st.indptr, st.indices, st.values)]
     r, bound = _check(gpu_lib, *dev, st.d, 50, 5)
     assert r["cov_err"] < 0.01
@@ -44,7 +44,7 @@ def test_million_row_stream_properties(gpu_lib):
 
 def test_ell200_stream_properties(gpu_lib):
     # 2x10^6 rows, d = 5x10^4, ell = 200 (forty buffers), generated on the device like the bench
-    from workloads.device import config3_precision
+    from workloads.device import stream_2e6_d5e4
 
-    indptr, indices, values = config3_precision("cuda")
+    indptr, indices, values = stream_2e6_d5e4("cuda")
     _check(gpu_lib, indptr, indices, values, 50_000, 200, 10)

@@ -18,9 +18,9 @@ pytestmark = pytest.mark.gpu
 def test_large_stream_prefix_matches_oracle(gpu_lib):
     import torch
 
-    from workloads.device import config5_large
+    from workloads.device import stream_1e7_d1e6
 
-    ptr, idx, val = config5_large("cuda", n=3000)
+    ptr, idx, val = stream_1e7_d1e6("cuda", n=3000)
     ptr_h, idx_h, val_h = ptr.cpu().numpy(), idx.cpu().numpy(), val.cpu().numpy()
     d, ell = 1_000_000, 100
     o = SFDOracle(d, ell, 0.25, 0, q=3, unit_roundoff=2.0 ** -24)
@@ -36,9 +36,9 @@ def test_large_stream_prefix_matches_oracle(gpu_lib):
 def test_batch_streams_from_the_device_generator(gpu_lib):
     import torch
 
-    from workloads.device import config4_batch
+    from workloads.device import batch_streams_d2e4
 
-    ptr, idx, val, starts = config4_batch("cuda", streams=3, first=40)
+    ptr, idx, val, starts = batch_streams_d2e4("cuda", streams=3, first=40)
     b = gpu_lib.Batch(3, 20_000, 32)
     b.append_csr(np.arange(3, dtype=np.int32), starts, ptr, idx, val)
     B = b.sketch()

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import SFDOracle, evaluate
 from oracle.rng import start_block as oracle_start_block
-from workloads import CsrStream, config1_fp64_reference, small_random_csr
+from workloads import CsrStream, stream_1e4_d1e3, small_random_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -118,8 +118,8 @@ def test_large_buffer_matches_oracle(gpu_lib, bands, hot_min):
     assert evaluate.gram_distance(B, o.sketch()) <= TOL
 
 
-def test_config1_matches_oracle_and_fd_bound(gpu_lib):
-    st = config1_fp64_reference()
+def test_1e4_row_stream_matches_oracle_and_fd_bound(gpu_lib):
+    st = stream_1e4_d1e3()
     o = _oracle(st, 20)
     sk, B = _gpu_sketch(gpu_lib, st, 20)
     stats = sk.stats()

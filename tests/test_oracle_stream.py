@@ -17,7 +17,7 @@ import oracle.stream as ost
 from oracle import FDBatchOracle, FDOracle, SFDOracle, evaluate
 from oracle.rng import PURPOSE_SI, PURPOSE_VS, sphere_vector, start_block
 from oracle.shrink import ALPHA, si_iterations, vs_steps
-from workloads import config1_fp64_reference, small_random_csr
+from workloads import stream_1e4_d1e3, small_random_csr
 
 pytestmark = pytest.mark.cpu
 
@@ -161,9 +161,9 @@ def test_sfd_property1_and_theorem(seed):
         assert lmax <= evaluate.sfd_bound(A, ell, k)
 
 
-def test_sfd_meets_fd_bound_on_config1():
+def test_sfd_meets_fd_bound_on_the_1e4_row_stream():
     """The empirical target: SFD's covariance error under FrequentDirections' bound (k = 10)."""
-    st = config1_fp64_reference()
+    st = stream_1e4_d1e3()
     o = _run_sfd(st, 20)
     A = st.to_scipy()
     B = o.sketch()

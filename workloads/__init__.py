@@ -9,10 +9,10 @@ from .synthetic import (
     zipf_cdf,
     poisson_zipf_pattern,
     small_random_csr,
-    config1_fp64_reference,
-    config2_plain_fp32,
-    config3_precision,
-    config4_batch_stream,
+    stream_1e4_d1e3,
+    stream_1e6_d1e5,
+    stream_2e6_d5e4,
+    batch_stream_d2e4,
     paper_head_tail,
 )
 
@@ -21,9 +21,9 @@ __all__ = [
     "zipf_cdf",
     "poisson_zipf_pattern",
     "small_random_csr",
-    "config1_fp64_reference",
-    "config2_plain_fp32",
-    "config3_precision",
-    "config4_batch_stream",
+    "stream_1e4_d1e3",
+    "stream_1e6_d1e5",
+    "stream_2e6_d5e4",
+    "batch_stream_d2e4",
     "paper_head_tail",
 ]

@@ -209,7 +209,7 @@ def gen_csr(keys, d: int, lam: float, s: float, perm_key: int, *, r: int = 0, sh
     return torch.cat(ptr_parts), torch.cat(idx_parts), torch.cat(val_parts)
 
 
-def config5_large(device, seed: int = 0, n: int = 10_000_000):
+def stream_1e7_d1e6(device, seed: int = 0, n: int = 10_000_000):
     """n=1e7, d=1e6, Poisson(100), Zipf(1.0) columns, lognormal(0,1) values plus a planted
     rank-100 component (sigma_i = 1/i) scaled to 30% of the expected energy; ell = 100.
     Rows 0..n-1 of the 1e7-row stream (a prefix for n < 1e7)."""
@@ -220,7 +220,7 @@ def config5_large(device, seed: int = 0, n: int = 10_000_000):
                    n_total=10_000_000)
 
 
-def config3_precision(device, seed: int = 0, n: int = 2_000_000):
+def stream_2e6_d5e4(device, seed: int = 0, n: int = 2_000_000):
     """n=2e6, d=5e4, Poisson(80), Zipf(1.1) columns, N(0,1) values plus a planted rank-50
     component with sigma_i = 1/i taken literally (unscaled); ell = 200."""
     import torch
@@ -230,7 +230,7 @@ def config3_precision(device, seed: int = 0, n: int = 2_000_000):
                    n_total=2_000_000, base="normal")
 
 
-def config4_lengths(seed: int = 0, streams: int = 4096) -> np.ndarray:
+def batch_stream_lengths(seed: int = 0, streams: int = 4096) -> np.ndarray:
     """Row counts of the 4,096 batch streams: round(exp(U(ln 1e3, ln 1e5))), U keyed by stream."""
     import torch
 
@@ -239,14 +239,14 @@ def config4_lengths(seed: int = 0, streams: int = 4096) -> np.ndarray:
     return np.rint(np.exp(np.log(1e3) + u * (np.log(1e5) - np.log(1e3)))).astype(np.int64)
 
 
-def config4_batch(device, seed: int = 0, streams: int = 4096, first: int = 0):
+def batch_streams_d2e4(device, seed: int = 0, streams: int = 4096, first: int = 0):
     """Streams first .. first + streams - 1 of the batching workload, one after another:
     (indptr, indices, values, row starts (streams + 1, int64 numpy)).  Stream s: n_s rows,
     d = 2e4, Poisson(30), Zipf(1.1) columns, lognormal(0,1) values; ell = 32."""
     import torch
 
     device = torch.device(device)
-    lens = config4_lengths(seed, 4096)[first:first + streams]
+    lens = batch_stream_lengths(seed, 4096)[first:first + streams]
     bases = torch.tensor([_s64(stream_key(seed, 4, 1000 + first + s)) for s in range(streams)], dtype=torch.int64,
                          device=device)
     lens_t = torch.from_numpy(lens).to(device)

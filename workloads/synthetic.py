@@ -156,7 +156,7 @@ def _chunk_gaussian_rows(seed_words, n_total, r):
     return rows_fn
 
 
-def config1_fp64_reference(seed: int = 0, n: int = 10_000) -> CsrStream:
+def stream_1e4_d1e3(seed: int = 0, n: int = 10_000) -> CsrStream:
     """n=10,000, d=1,000, Poisson(10) entries per row, Zipf(1.1) columns; values = entries of a
     planted rank-10 U diag(sigma) V^T (U, V Gaussian then QR-orthonormalised, sigma_i = 2^-i)
     plus N(0, 0.1^2) noise (0.1 read as the standard deviation); ell = 20, k = 10."""
@@ -170,18 +170,18 @@ def config1_fp64_reference(seed: int = 0, n: int = 10_000) -> CsrStream:
     planted = _planted_at(indptr, indices, lambda lo, hi: U[lo:hi], sigma, V)
     noise = np.random.default_rng(words + [0x401]).normal(0.0, 0.1, size=len(indices))
     vals = (planted + noise).astype(np.float32)
-    return CsrStream(indptr, indices, vals, d, dict(name="config1_fp64_reference", ell=20, k=10, seed=seed,
+    return CsrStream(indptr, indices, vals, d, dict(name="stream_1e4_d1e3", ell=20, k=10, seed=seed,
                                                     planted_energy_share=float(np.sum(planted ** 2) / np.sum((planted + noise) ** 2))))
 
 
-def config2_plain_fp32(seed: int = 0, n: int = 1_000_000) -> CsrStream:
+def stream_1e6_d1e5(seed: int = 0, n: int = 1_000_000) -> CsrStream:
     """n=1e6, d=1e5, Poisson(50) per row, Zipf(1.0) columns; values lognormal(0,1) plus a planted
     rank-20 component (sigma_i = 1/i) scaled to 30% of the expected energy at the sampled
     positions; ell = 50.  U is N(0, 1/n) per entry with n = 1e6 (near-orthonormal, generated per
     row chunk, so a shorter stream has the same rows of U); V is Gaussian then
     QR-orthonormalised.  Whole 65,536-row chunks of a shorter stream equal those of the full one."""
     d, lam, s, r = 100_000, 50.0, 1.0, 20
-    return _lognormal_planted(seed, 2, n, d, lam, s, r, share=0.3, ell=50, name="config2_plain_fp32", n_total=1_000_000)
+    return _lognormal_planted(seed, 2, n, d, lam, s, r, share=0.3, ell=50, name="stream_1e6_d1e5", n_total=1_000_000)
 
 
 def _lognormal_planted(seed, cid, n, d, lam, s, r, share, ell, name, n_total):
@@ -207,7 +207,7 @@ def _lognormal_planted(seed, cid, n, d, lam, s, r, share, ell, name, n_total):
     return CsrStream(indptr, indices, vals.astype(np.float32), d, meta)
 
 
-def config3_precision(seed: int = 0, n: int = 2_000_000) -> CsrStream:
+def stream_2e6_d5e4(seed: int = 0, n: int = 2_000_000) -> CsrStream:
     """n=2e6, d=5e4, Poisson(80), Zipf(1.1); N(0,1) values plus a planted rank-50 component with
     sigma_i = 1/i taken literally (unscaled, so its energy share is tiny); ell = 200."""
     d, lam, s, r = 50_000, 80.0, 1.1, 50
@@ -222,17 +222,17 @@ def config3_precision(seed: int = 0, n: int = 2_000_000) -> CsrStream:
         a, b = int(indptr[c]), int(indptr[hi])
         base[a:b] = np.random.default_rng(words + [0x401, c // CHUNK]).standard_normal(b - a)
     return CsrStream(indptr, indices, (base + planted).astype(np.float32), d,
-                     dict(name="config3_precision", ell=200, k=10, seed=seed))
+                     dict(name="stream_2e6_d5e4", ell=200, k=10, seed=seed))
 
 
-def config4_batch_stream(stream_id: int, seed: int = 0, n: int | None = None) -> CsrStream:
+def batch_stream_d2e4(stream_id: int, seed: int = 0, n: int | None = None) -> CsrStream:
     """Stream s of the 4,096-stream batch: n_s = round(exp(U(ln 1e3, ln 1e5))) rows, d = 2e4,
     Poisson(30), Zipf(1.1), lognormal(0,1) values; ell = 32."""
     d, lam, s = 20_000, 30.0, 1.1
     if n is None:
         u = np.random.default_rng([seed, 4, 0x1E9]).random(4096)[stream_id]
         n = int(round(np.exp(np.log(1e3) + u * (np.log(1e5) - np.log(1e3)))))
-    st = _lognormal_planted(seed, (4, 1000 + stream_id), n, d, lam, s, 0, 0.0, 32, "config4_batch_stream", n)
+    st = _lognormal_planted(seed, (4, 1000 + stream_id), n, d, lam, s, 0, 0.0, 32, "batch_stream_d2e4", n)
     st.meta["stream_id"] = stream_id
     return st
 
