@@ -199,6 +199,24 @@ def _ptr_kind(x, dtype):
     return a.ctypes.data, MEM_HOST, a
 
 
+def _out_ptr(out, shape, device: bool):
+    """Pointer to a caller-supplied FP32 output buffer of ``shape`` after checking it: a contiguous
+    CUDA tensor (device=True) or a C-contiguous writeable numpy array (device=False) with exactly
+    that many elements, so the library never writes past it."""
+    n = int(np.prod(shape))
+    if device:
+        import torch
+
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                and out.numel() == n):
+            raise TypeError(f"out must be a contiguous CUDA float32 tensor of {n} elements {tuple(shape)}")
+        return out.data_ptr()
+    if not (isinstance(out, np.ndarray) and out.dtype == np.float32 and out.flags.c_contiguous and out.flags.writeable
+            and out.size == n):
+        raise TypeError(f"out must be a C-contiguous writeable float32 numpy array of {n} elements {tuple(shape)}")
+    return out.ctypes.data
+
+
 def _torch_stream_handle():
     import torch
 
@@ -254,11 +272,13 @@ class Sketch:
 
             if out is None:
                 out = torch.empty((self.ell, self.d), dtype=torch.float32, device="cuda")
-            _check(load().sfd_sketch(self._h, out.data_ptr(), MEM_DEVICE, ctypes.byref(live)), "sfd_sketch")
+            ptr = _out_ptr(out, (self.ell, self.d), True)
+            _check(load().sfd_sketch(self._h, ptr, MEM_DEVICE, ctypes.byref(live)), "sfd_sketch")
         else:
             if out is None:
                 out = np.empty((self.ell, self.d), dtype=np.float32)
-            _check(load().sfd_sketch(self._h, out.ctypes.data, MEM_HOST, ctypes.byref(live)), "sfd_sketch")
+            ptr = _out_ptr(out, (self.ell, self.d), False)
+            _check(load().sfd_sketch(self._h, ptr, MEM_HOST, ctypes.byref(live)), "sfd_sketch")
         self.last_live = live.value
         return out
 
@@ -337,11 +357,11 @@ class Batch:
 
             if out is None:
                 out = torch.empty(shape, dtype=torch.float32, device="cuda")
-            _check(load().sfd_batch_sketch(self._h, out.data_ptr(), MEM_DEVICE), "sfd_batch_sketch")
+            _check(load().sfd_batch_sketch(self._h, _out_ptr(out, shape, True), MEM_DEVICE), "sfd_batch_sketch")
         else:
             if out is None:
                 out = np.empty(shape, dtype=np.float32)
-            _check(load().sfd_batch_sketch(self._h, out.ctypes.data, MEM_HOST), "sfd_batch_sketch")
+            _check(load().sfd_batch_sketch(self._h, _out_ptr(out, shape, False), MEM_HOST), "sfd_batch_sketch")
         return out
 
     def reset(self):

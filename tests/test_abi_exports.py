@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.cpu
@@ -92,3 +93,22 @@ def test_evaluate_binding_checks_its_arguments_without_a_gpu():
         sfd.evaluate(p, i, v, 4)
     with pytest.raises(TypeError):
         sfd.evaluate(p, i.to(torch.int64), v, 4)
+
+
+def test_output_buffers_are_checked_without_a_gpu():
+    # a caller-supplied output must hold exactly the sketch's FP32 values contiguously, in the
+    # memory kind asked for; anything else is refused before the library is called
+    import torch
+
+    from paper_1602_00412_amd import sfd
+
+    good = np.empty((3, 5), np.float32)
+    assert sfd._out_ptr(good, (3, 5), False) == good.ctypes.data
+    ro = np.empty((3, 5), np.float32)
+    ro.flags.writeable = False
+    for bad in (np.empty((3, 4), np.float32), np.empty((3, 5), np.float64), np.empty((5, 3), np.float32).T, ro,
+                torch.empty((3, 5))):
+        with pytest.raises(TypeError):
+            sfd._out_ptr(bad, (3, 5), False)
+    with pytest.raises(TypeError):
+        sfd._out_ptr(torch.empty((3, 5), dtype=torch.float32), (3, 5), True)  # host tensor, device asked
