@@ -241,7 +241,10 @@ typedef struct {
   double cov_min;      /* smallest and largest eigenvalue of A^T A - B^T B (Lanczos Ritz values) */
   double cov_max;
   double cov_err;      /* max(|cov_min|, |cov_max|) / fro2A (+inf or NaN when A = 0) */
-  double top_k_energy; /* sum of the k largest eigenvalues of A^T A = sum_{i<=k} sigma_i(A)^2 */
+  double top_k_energy; /* sum of the k largest eigenvalues of A^T A = sum_{i<=k} sigma_i(A)^2; when
+                          the Lanczos run on A^T A closes its Krylov space after j < k steps (the
+                          start vector meets fewer than k distinct eigenvalues, e.g. A = 0), the
+                          sum of the j it found */
   double proj_num;     /* ||A - A V_k V_k^T||_F^2 = fro2A - ||A V_k||_F^2 */
   double proj_err;     /* proj_num / (fro2A - top_k_energy); the three are NaN when k = 0 */
   int32_t steps;       /* Lanczos steps taken for cov-err (fewer than asked when the Krylov
@@ -253,7 +256,7 @@ typedef struct {
  * A: CSR in device memory as in sfd_append_csr (int64 indptr[n + 1], rows read from
  * indices/values positions indptr[0] .. indptr[n]); B: ell x d FP32 row-major in device memory
  * (ell = 0: no sketch, B may be NULL; ell <= 512).  k: rank of proj-err, 0 <= k <= ell and
- * k <= the steps taken (0 skips it).  n, d < 2^31, at most 2^31 - 1 stored entries.
+ * k <= min(d, steps) (0 skips it).  n, d < 2^31, at most 2^31 - 1 stored entries.
  * steps: Lanczos steps per operator, 1..512, at most d (<= 0: min(d, 160)).  The extreme
  * eigenvalues of A^T A - B^T B come from Lanczos with full reorthogonalisation on
  * x -> A^T(Ax) - B^T(Bx) from a start vector keyed by seed, the k largest of A^T A likewise on
