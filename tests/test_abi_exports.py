@@ -112,3 +112,14 @@ def test_output_buffers_are_checked_without_a_gpu():
             sfd._out_ptr(bad, (3, 5), False)
     with pytest.raises(TypeError):
         sfd._out_ptr(torch.empty((3, 5), dtype=torch.float32), (3, 5), True)  # host tensor, device asked
+
+
+def test_missing_library_fails_loudly():
+    # no fallback: without the built HIP library the binding raises instead of computing anything
+    import subprocess
+    import sys
+
+    code = ("import paper_1602_00412_amd.sfd as s\n"
+            "try:\n    s.load('/nonexistent/libsfd.so')\nexcept RuntimeError as e:\n    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("raised"), r.stdout + r.stderr
