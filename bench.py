@@ -81,15 +81,17 @@ def cpu_baseline(st, ell: int, rows: int):
     t0 = time.perf_counter()
     o = SFDOracle(st.d, ell, 0.25, 0)
     o.append_csr(sub.indptr, sub.indices, sub.values)
-    B = o.sketch()
+    rec = []
+    B, _, _ = o.query(log=rec)
     dt = time.perf_counter() - t0
+    qs = sorted({r["q"] for b in o.log for r in b["attempts"]} | {r["q"] for r in rec})
     return sub, B.astype(np.float64), {
         "value": sub.nnz / dt,
         "unit": "nnz/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"first {rows} rows ({sub.nnz} nnz) of the same stream, folded by one query "
-                  f"(m={rows}, q={o.log[-1]['attempts'][0]['q'] if o.log else 'n/a'}); {dt:.1f} s; "
+                  f"({o.flushes} flushes + the query's fold; q={','.join(map(str, qs)) or 'none'}); {dt:.1f} s; "
                   f"BLAS threads={threads}, scipy sparse products single-threaded",
     }
 
@@ -531,6 +533,7 @@ def main() -> int:
     # The evaluator (sfd_evaluate, FP64 on the GPU): cov-err and proj-err (k = 10) of the timed
     # line's sketch against the whole stream.  Not for the 10^9-entry stream (its 160-step
     # Lanczos runs would take about a minute).
+    cov_errs = {}
     if not args.no_forms and not args.profile_only and args.workload in ("stream1e6", "ell200"):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -538,11 +541,20 @@ def main() -> int:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         forms["eval"] = {"seconds": dt, "cov_err": ev["cov_err"], "proj_err": ev["proj_err"], "k": 10,
+                         "cov_max_ritz_residual": ev["cov_max_res"],
                          "lanczos_steps": ev["steps"], "rows": st_n, "nnz": st_nnz, "d": st_d, "ell": ell,
                          "what": "sfd_evaluate of the sketch against the whole stream (two 160-step FP64 "
                                  "Lanczos runs with full reorthogonalisation, CSC build included)"}
+        cov_errs["fp32"] = ev["cov_err"]
         log(f"evaluator: cov-err {ev['cov_err']:.4e}, proj-err(k=10) {ev['proj_err']:.4f} of the sketch vs the "
             f"whole stream in {dt:.2f} s")
+        if "bf16" in forms:
+            evb = sfd.evaluate(indptr, indices, values, st_d, out_bf, k=10, steps=160)
+            cov_errs["bf16"] = evb["cov_err"]
+            cov_errs["bf16_over_fp32"] = evb["cov_err"] / ev["cov_err"]
+            forms["bf16"]["cov_err"] = evb["cov_err"]
+            forms["bf16"]["proj_err"] = evb["proj_err"]
+            log(f"bf16 form: cov-err {evb['cov_err']:.4e} ({cov_errs['bf16_over_fp32']:.4f}x FP32)")
 
     cpu = None
     parity = None
@@ -594,6 +606,22 @@ def main() -> int:
             eval_check = {"cov_err_gpu": ev_s["cov_err"], "cov_err_arpack": float(lmax / evaluate.fro2(A_s)),
                           "proj_err_gpu": ev_s["proj_err"], "proj_err_ref": evaluate.proj_err(A_s, Bg, 10),
                           "sample": f"first {sub.n} rows, the GPU sketch of them (ell={ell}), k=10"}
+            # cov-err of each form's sketch of the sample against the FP64 oracle's sketch of it, all
+            # measured by the FP64 evaluator on the same rows
+            g_sub = [torch.from_numpy(a).cuda() for a in (sub.indptr, sub.indices, sub.values)]
+            sk3 = sfd.Sketch(st.d, ell, 0.25, 0, precision="bf16")
+            sk3.append_csr(*g_sub)
+            Bb = sk3.sketch()
+            sample_err = {"oracle_fp64": sfd.evaluate(*g_sub, st.d, torch.from_numpy(B_oracle.astype(np.float32)).cuda(),
+                                                      steps=160)["cov_err"],
+                          "fp32": ev_s["cov_err"],
+                          "bf16": sfd.evaluate(*g_sub, st.d, Bb, steps=160)["cov_err"]}
+            sample_err["fp32_over_oracle"] = sample_err["fp32"] / sample_err["oracle_fp64"]
+            sample_err["bf16_over_oracle"] = sample_err["bf16"] / sample_err["oracle_fp64"]
+            sample_err["rows"] = sub.n
+            cov_errs["sample"] = sample_err
+            log(f"sample cov-err: oracle {sample_err['oracle_fp64']:.6e}, fp32 {sample_err['fp32']:.6e}, "
+                f"bf16 {sample_err['bf16']:.6e}")
             log(f"evaluator on the sample: cov-err {ev_s['cov_err']:.6e} (ARPACK {eval_check['cov_err_arpack']:.6e}), "
                 f"proj-err {ev_s['proj_err']:.6f} (reference {eval_check['proj_err_ref']:.6f})")
     line = {
@@ -623,6 +651,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "sample_parity_rel_frobenius": parity,
+        "cov_err": cov_errs or None,
         "evaluator_check": eval_check,
         "forms": forms,
         "phases": phases,

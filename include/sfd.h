@@ -14,9 +14,12 @@
  *  - Synchronisation: work runs on the handle's HIP stream (sfd_set_stream); every call
  *    returns after that work has completed.
  *  - Errors: functions return SFD_OK (0) or a negative SFD_E_* code; sfd_strerror() names it.
- *    Argument and input-validation errors leave the handle unchanged.  A device error or an
- *    exhausted retry loop (SFD_E_NOCONVERGE) leaves the handle in an error state in which
- *    every call but sfd_reset/sfd_destroy/sfd_get_stats returns SFD_E_STATE.
+ *    Argument and input-validation errors leave the handle unchanged.  On an sfd_t, an
+ *    exhausted BoostedSparseShrink loop (SFD_E_NOCONVERGE) also leaves the handle as it was
+ *    before the call (sketch, buffer and counters; the stats' last_* figures then describe the
+ *    last rejected attempt).  A device error, and SFD_E_NOCONVERGE from sfd_batch_append_csr,
+ *    leave the handle in an error state in which every call but sfd_reset/sfd_destroy/
+ *    sfd_get_stats returns SFD_E_STATE.
  *  - Threads: a handle must not be used by two threads at once.  Different handles are
  *    independent.
  *  - Sizes: 1 <= ell <= min(d, 256); ell*d + d < 2^31 (int32 buffer indices).
@@ -85,10 +88,20 @@ enum {
                                paper's comparator FrequentDirections (Sec. 2.1) in batches of
                                ell rows -- the buffer flushes at ell rows and is folded exactly
                                by DenseShrink (Alg 5).  Applies to the flushes that follow. */
-  SFD_OPT_CSC_HOT_MIN = 11  /* entries from which a column is cut into XCD-local pieces
+  SFD_OPT_CSC_HOT_MIN = 11, /* entries from which a column is cut into XCD-local pieces
                                (SFD_OPT_CSC_BANDS), >= 1; default 160.  Raised to
                                ceil(nnz(A') / min(d, 32768)) for a buffer, so at most
                                min(d, 32768) columns are cut. */
+  SFD_OPT_TEST_ZERO_ROW = 12,      /* test hook, -1 (default) off: a column id j in [0, d) whose
+                                      row of the start block G of SimultaneousIteration (Alg 1)
+                                      is set to 0 in the attempts a < SFD_OPT_TEST_ZERO_ATTEMPTS
+                                      of every buffer step (flushes and queries).  A direction
+                                      that G misses stays out of span(Z) whatever q is, so a
+                                      buffer whose dominant direction is e_j gets a SparseShrink
+                                      that VerifySpectral (Alg 6) rejects: this runs the retry
+                                      loop of BoostedSparseShrink (Alg 4) on purpose. */
+  SFD_OPT_TEST_ZERO_ATTEMPTS = 13  /* attempts a < value that SFD_OPT_TEST_ZERO_ROW applies to,
+                                      >= 0; default 1 (the first attempt of each buffer). */
 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */
@@ -165,8 +178,10 @@ int sfd_set_stream(sfd_t *h, void *hip_stream);
  * rows(A') = d: B' = BoostedSparseShrink(A', ell, delta) (Alg 4), B = DenseShrink([B; B'], ell)
  * (Alg 5).  indptr/indices/values live in memory of kind `mem`.
  * Errors (state unchanged): SFD_E_ARG (nrows < 0, null pointer with nrows > 0, decreasing
- * indptr, a row with more than d entries), SFD_E_INDEX (column id outside [0, d)).
- * SFD_E_NOCONVERGE / SFD_E_DEVICE put the handle in its error state. */
+ * indptr, a row with more than d entries), SFD_E_INDEX (column id outside [0, d)),
+ * SFD_E_NOCONVERGE (a buffer's BoostedSparseShrink rejected SFD_OPT_MAX_ATTEMPTS SparseShrinks
+ * in a row: the sketch, the buffer and the counters are restored to their values before the
+ * call).  SFD_E_DEVICE puts the handle in its error state. */
 int sfd_append_csr(sfd_t *h, int64_t nrows, const int64_t *indptr, const int32_t *indices,
                    const float *values, int mem);
 
@@ -174,14 +189,17 @@ int sfd_append_csr(sfd_t *h, int64_t nrows, const int64_t *indptr, const int32_t
  * of kind `mem`.  Rows still in the buffer are folded into a copy of the state (Alg 2 returns
  * B; folding the pending rows keeps them), so the stream is unchanged and a repeated query
  * returns the same B.  *live_rows (may be NULL) receives the structural count of rows of
- * B_out that may be non-zero.  Errors: SFD_E_ARG (B_out == NULL), SFD_E_NOCONVERGE. */
+ * B_out that may be non-zero.  Errors: SFD_E_ARG (B_out == NULL), SFD_E_NOCONVERGE (the pending
+ * buffer's BoostedSparseShrink exhausted its attempts; the handle is unchanged). */
 int sfd_sketch(sfd_t *h, float *B_out, int mem, int32_t *live_rows);
 
 /* Merge src into dst (mergeability of Frequent Directions sketches, Sec. 2.1):
  * dst.B = DenseShrink([sketch(dst); sketch(src)], ell); dst's buffer is consumed; src is
- * unchanged.  Both handles must be on the same device.  Errors: SFD_E_SHAPE (different d or
- * ell), SFD_E_ARG (NULL or dst == src). */
-int sfd_merge(sfd_t *dst, sfd_t *src);
+ * unchanged (its sketch, buffer and counters; its query runs in src's own device workspaces,
+ * so src must not be in use by another thread).  Both handles must be on the same device.
+ * Errors: SFD_E_SHAPE (different d or ell), SFD_E_ARG (NULL, dst == src, a batch handle),
+ * SFD_E_NOCONVERGE (either query; both handles unchanged). */
+int sfd_merge(sfd_t *dst, const sfd_t *src);
 
 /* Copy the handle's counters into *out. */
 int sfd_get_stats(const sfd_t *h, sfd_stats_t *out);
@@ -250,6 +268,13 @@ typedef struct {
   int32_t steps;       /* Lanczos steps taken for cov-err (fewer than asked when the Krylov
                           space of the operator closes) */
   int32_t pad;
+  /* Ritz residual norms ||M y - theta y|| of the reported Ritz pairs (beta_{j+1} |s_j|, s the
+   * eigenvector of the Lanczos tridiagonal): each Ritz value lies within its residual of an
+   * eigenvalue of the operator, so a small residual certifies the extremes above.  0 when the
+   * Krylov space closed (the Ritz values are then exact eigenvalues). */
+  double cov_min_res;  /* of the pair giving cov_min */
+  double cov_max_res;  /* of the pair giving cov_max */
+  double top_k_res;    /* sum over the k pairs that give top_k_energy (NaN when k = 0) */
 } sfd_eval_t;
 
 /* Evaluate the ell x d sketch B against the n x d matrix A it summarises.

@@ -38,17 +38,27 @@ def normals(seed: int, stream_id: int, buffer_idx: int, attempt: int, purpose: i
     ctr[2] = np.uint64(buffer_idx)
     ctr[3] = np.uint64(purpose)
     words = philox4x64_10(ctr, (np.uint64(seed), np.uint64(stream_id)))
-    u = philox_uniform01(words)  # (4, nblocks)
+    return box_muller(words).reshape(-1)[:count]
+
+
+def box_muller(words: np.ndarray) -> np.ndarray:
+    """Four N(0,1) draws per block of four Philox words (shape (4, n) -> (n, 4)).
+
+    The words map to uniforms u0..u3 in (0, 1) (``philox_uniform01``); the Box-Muller transform
+    takes the pairs (u0, u1) and (u2, u3): radius sqrt(-2 ln u0), angle 2 pi u1, giving
+    (r cos, r sin), and the same for the second pair.
+    """
+    u = philox_uniform01(np.asarray(words, dtype=np.uint64).reshape(4, -1))
     r01 = np.sqrt(-2.0 * np.log(u[0]))
     r23 = np.sqrt(-2.0 * np.log(u[2]))
     t1 = 2.0 * np.pi * u[1]
     t3 = 2.0 * np.pi * u[3]
-    z = np.empty((nblocks, 4), dtype=np.float64)
+    z = np.empty((u.shape[1], 4), dtype=np.float64)
     z[:, 0] = r01 * np.cos(t1)
     z[:, 1] = r01 * np.sin(t1)
     z[:, 2] = r23 * np.cos(t3)
     z[:, 3] = r23 * np.sin(t3)
-    return z.reshape(-1)[:count]
+    return z
 
 
 def start_block(seed: int, stream_id: int, buffer_idx: int, attempt: int, purpose: int, d: int, ell: int) -> np.ndarray:

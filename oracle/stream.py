@@ -129,6 +129,11 @@ class SFDOracle:
                 self._flush()
 
     # -- the buffer step ---------------------------------------------------------------------
+    def draw_start_block(self, buffer_idx, attempt, purpose):
+        """G ~ N(0,1)^{d x ell} of SimultaneousIteration (Alg 1) for attempt ``attempt`` of buffer
+        ``buffer_idx`` (keyed as in ``oracle.rng``).  Tests override it to plant a start block."""
+        return start_block(self.seed, self.stream_id, buffer_idx, attempt, purpose, self.d, self.ell)
+
     def _fold(self, B, live, buffer_idx, vs_start, purpose_G, purpose_x, log):
         """Fold the pending buffer into (B, live); returns (B, live, VerifySpectral calls made)."""
         m = self.buf_rows
@@ -148,7 +153,7 @@ class SFDOracle:
 
             R = boosted_sparse_shrink(
                 A, self.ell,
-                lambda a: start_block(self.seed, self.stream_id, buffer_idx, a, purpose_G, self.d, self.ell),
+                lambda a: self.draw_start_block(buffer_idx, a, purpose_G),
                 lambda a: sphere_vector(self.seed, self.stream_id, buffer_idx, a, purpose_x, self.d),
                 next_i, q=q, delta=self.delta, max_attempts=self.max_attempts, verify=self.verify,
                 unit_roundoff=self.unit_roundoff, log=log)

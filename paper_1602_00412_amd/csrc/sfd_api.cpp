@@ -146,12 +146,20 @@ struct sfd_s {
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
+  int test_zero_row = -1;              // SFD_OPT_TEST_ZERO_ROW
+  int test_zero_attempts = 1;          // SFD_OPT_TEST_ZERO_ATTEMPTS
   // streams (one for an sfd_t handle, nstreams for a batch handle)
   std::vector<StreamState> streams;
   GroupWork grp;  // batch handles: lockstep groups of buffers (grp.kmax = 0: none)
   int error = 0;
   int64_t cap = 0;
   Lane lanes[kLanes];
+  // single-stream handles: the sketch and (when a host block could overwrite it) the pending
+  // buffer as they were before an append, restored when a BoostedSparseShrink loop is exhausted
+  float* Bsave = nullptr;
+  int* psave_row = nullptr;
+  int* psave_col = nullptr;
+  float* psave_val = nullptr;
   int* err_dev = nullptr;
   int64_t* cut_dev = nullptr;
   int64_t cut_cap = 0;
@@ -230,7 +238,7 @@ void free_all(sfd_t* h) {
 }
 
 int fail(sfd_t* h, int code) {
-  if (code == SFD_E_DEVICE || code == SFD_E_NOCONVERGE) h->error = code;
+  if (code == SFD_E_DEVICE) h->error = code;
   return code;
 }
 
@@ -376,6 +384,7 @@ int alloc_state(sfd_t* h) {
     if (!ok) return SFD_E_NOMEM;
     if (hipEventCreateWithFlags(&ss.ev_dsh, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
   }
+  if (h->streams.size() == 1) ok = ok && dalloc(h, &h->Bsave, d * L);
   ok = ok && dalloc(h, &h->err_dev, 4);
   if (!ok) return SFD_E_NOMEM;
   for (int li = 0; li < h->lanes_alloc; ++li) {
@@ -527,6 +536,8 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
     CK(fill_f32(ln.X, d * L, 0.f, ln.st));
     CK(start_block(h->seed, ln.ss->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.pg, d, ell, ln.X,
                    L, ln.st));
+    if (h->test_zero_row >= 0 && h->test_zero_row < d && attempt < h->test_zero_attempts)
+      CK(fill_f32(ln.X + (int64_t)h->test_zero_row * L, L, 0.f, ln.st));
   }
   // panels of the iteration: FP32, or BF16 in the precision form, where the products 1 .. 2q+1
   // read and write BF16 panels (FP32 accumulation) and the last one, P^T = A'^T Y T_y, reads
@@ -679,7 +690,7 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
       if (a + 1 >= h->max_attempts) break;
       if ((rc = sparse_shrink(h, ln, a + 1))) return rc;
     }
-    if (!accepted) return fail(h, SFD_E_NOCONVERGE);
+    if (!accepted) return SFD_E_NOCONVERGE;
     r_add = ell - 1;
   }
   const int lossless = (live_in + r_add <= ell) ? 1 : 0;
@@ -888,6 +899,8 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     const GroupItem& it = items[(size_t)k];
     CK(start_block(h->seed, it.v.ss->stream_id, (uint64_t)it.buffer, 0, (uint64_t)it.pg, d, ell, g.X + k * d * L, L,
                    st));
+    if (h->test_zero_row >= 0 && h->test_zero_row < d && h->test_zero_attempts > 0)
+      CK(fill_f32(g.X + k * d * L + (int64_t)h->test_zero_row * L, L, 0.f, st));
   }
   CK(set_identity(g.T, L, K, st));
   CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
@@ -984,7 +997,7 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
       if ((rc = dense_shrink(h, ln, ss.B, g.Pt + k * d * L, lossless, it.out, g.M64 + k * LL))) return rc;
       it.live = lossless ? ss.live + r_add : ell - 1;
     } else {
-      if (h->max_attempts <= 1) return fail(h, SFD_E_NOCONVERGE);
+      if (h->max_attempts <= 1) return SFD_E_NOCONVERGE;
       if ((rc = bind(h, ln, it.v, it.buffer, it.pg, it.px))) return rc;
       if ((rc = prepare(h, ln))) return rc;
       ln.q = q[(size_t)k];
@@ -1298,6 +1311,81 @@ int create_handle(int64_t d, int32_t ell, double eps, uint64_t seed, int nstream
   return SFD_OK;
 }
 
+// Counters of a stream restored to `old`; the last_* figures keep describing the last attempt made.
+void restore_counters(StreamState& ss, const sfd_stats_t& old) {
+  const sfd_stats_t cur = ss.stats;
+  ss.stats = old;
+  ss.stats.last_q = cur.last_q;
+  ss.stats.last_t = cur.last_t;
+  ss.stats.last_ln_norm = cur.last_ln_norm;
+  ss.stats.last_delta = cur.last_delta;
+  ss.stats.last_fro2_buffer = cur.last_fro2_buffer;
+  ss.stats.last_lambda_ell2 = cur.last_lambda_ell2;
+}
+
+// The state of a single stream before an append, for its rollback when a buffer's
+// BoostedSparseShrink exhausts its attempts (Alg 4): the host-side fields, the sketch (copied
+// to Bsave) and, when the append could overwrite them, the pending buffer's rows.
+struct StreamSnapshot {
+  int live = 0;
+  int64_t flushes = 0, vs_calls = 0;
+  sfd_stats_t stats{};
+  int pm = 0, pnnz = 0;
+  bool pending_saved = false;
+};
+
+int snapshot_stream(sfd_t* h, StreamState& ss, bool save_pending, StreamSnapshot* snap) {
+  Lane& l0 = h->lanes[0];
+  snap->live = ss.live;
+  snap->flushes = ss.flushes;
+  snap->vs_calls = ss.vs_calls;
+  snap->stats = ss.stats;
+  snap->pm = ss.pm;
+  snap->pnnz = ss.pnnz;
+  CK(hipMemcpyAsync(h->Bsave, ss.B, sizeof(float) * h->d * h->L, hipMemcpyDeviceToDevice, l0.st));
+  if (save_pending && ss.pm > 0) {
+    if (!h->psave_row) {
+      if (!dalloc(h, &h->psave_row, h->d + 1) || !dalloc(h, &h->psave_col, h->cap) ||
+          !dalloc(h, &h->psave_val, h->cap))
+        return SFD_E_NOMEM;
+    }
+    CK(hipMemcpyAsync(h->psave_row, ss.prow, sizeof(int) * (ss.pm + 1), hipMemcpyDeviceToDevice, l0.st));
+    if (ss.pnnz > 0) {
+      CK(hipMemcpyAsync(h->psave_col, ss.pcol, sizeof(int) * ss.pnnz, hipMemcpyDeviceToDevice, l0.st));
+      CK(hipMemcpyAsync(h->psave_val, ss.pval, sizeof(float) * ss.pnnz, hipMemcpyDeviceToDevice, l0.st));
+    }
+    snap->pending_saved = true;
+  }
+  // every DenseShrink of this append waits for the stream's last one: now the copy
+  CK(hipEventRecord(ss.ev_dsh, l0.st));
+  return SFD_OK;
+}
+
+// Undo an append after SFD_E_NOCONVERGE: wait for the buffer steps still in flight on the
+// lanes, then put back the sketch, the pending rows and the counters.
+int rollback_stream(sfd_t* h, StreamState& ss, const StreamSnapshot& snap) {
+  int rc = sync_all(h);
+  if (rc) return rc;
+  Lane& l0 = h->lanes[0];
+  CK(hipMemcpyAsync(ss.B, h->Bsave, sizeof(float) * h->d * h->L, hipMemcpyDeviceToDevice, l0.st));
+  if (snap.pending_saved) {
+    CK(hipMemcpyAsync(ss.prow, h->psave_row, sizeof(int) * (snap.pm + 1), hipMemcpyDeviceToDevice, l0.st));
+    if (snap.pnnz > 0) {
+      CK(hipMemcpyAsync(ss.pcol, h->psave_col, sizeof(int) * snap.pnnz, hipMemcpyDeviceToDevice, l0.st));
+      CK(hipMemcpyAsync(ss.pval, h->psave_val, sizeof(float) * snap.pnnz, hipMemcpyDeviceToDevice, l0.st));
+    }
+  }
+  CK(hipEventRecord(ss.ev_dsh, l0.st));
+  if ((rc = sync_lane(h, l0))) return rc;
+  ss.live = snap.live;
+  ss.flushes = snap.flushes;
+  ss.vs_calls = snap.vs_calls;
+  ss.pm = snap.pm;
+  ss.pnnz = snap.pnnz;
+  restore_counters(ss, snap.stats);
+  return SFD_E_NOCONVERGE;
+}
+
 void fill_stats(const StreamState& ss, sfd_stats_t* out) {
   *out = ss.stats;
   out->flushes = ss.flushes;
@@ -1312,6 +1400,11 @@ void fill_stats(const StreamState& ss, sfd_stats_t* out) {
 struct sfd_batch_s {
   sfd_t* core;
 };
+
+namespace {
+// the queries of every stream of a batch handle into B_out (sfd_batch_sketch)
+int batch_queries(sfd_t* h, float* B_out, int mem);
+}  // namespace
 
 extern "C" {
 
@@ -1411,6 +1504,14 @@ int sfd_set_option(sfd_t* h, int key, double value) {
       if (!(value >= 1 && value <= (double)(1 << 30)) || value != std::floor(value)) return SFD_E_ARG;
       h->hot_min = (int)value;
       return SFD_OK;
+    case SFD_OPT_TEST_ZERO_ROW:
+      if (!(value >= -1 && value < (double)h->d) || value != std::floor(value)) return SFD_E_ARG;
+      h->test_zero_row = (int)value;
+      return SFD_OK;
+    case SFD_OPT_TEST_ZERO_ATTEMPTS:
+      if (!(value >= 0 && value <= 1e6) || value != std::floor(value)) return SFD_E_ARG;
+      h->test_zero_attempts = (int)value;
+      return SFD_OK;
     default:
       return SFD_E_ARG;
   }
@@ -1455,10 +1556,18 @@ int sfd_append_csr(sfd_t* h, int64_t nrows, const int64_t* indptr, const int32_t
   sg.nrows = nrows;
   if (mem == SFD_MEM_HOST) {
     if ((rc = host_segment(h, sg))) return rc;
-    return append_host_segment(h, sg);
+  } else {
+    if ((rc = device_segment(h, sg))) return rc;
   }
-  if ((rc = device_segment(h, sg))) return rc;
-  return append_device_segments(h, segs);
+  // an append that flushes can end in SFD_E_NOCONVERGE: keep what it could change.  A host
+  // block stages each full buffer through the pending buffer, so from its second flush on it
+  // overwrites the rows pending before the call; a device block only appends after them.
+  StreamSnapshot snap;
+  const bool flushes = !sg.cuts.empty();
+  if (flushes && (rc = snapshot_stream(h, *sg.ss, mem == SFD_MEM_HOST && sg.cuts.size() >= 2, &snap))) return rc;
+  rc = mem == SFD_MEM_HOST ? append_host_segment(h, sg) : append_device_segments(h, segs);
+  if (rc == SFD_E_NOCONVERGE && flushes) return rollback_stream(h, *sg.ss, snap);
+  return rc;
 }
 
 int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
@@ -1471,7 +1580,11 @@ int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
   int live;
   int64_t calls;
   Lane& l0 = h->lanes[0];
-  if ((rc = query(h, h->streams[0], l0, &panel, &live, &calls))) return rc;
+  const sfd_stats_t before = h->streams[0].stats;
+  if ((rc = query(h, h->streams[0], l0, &panel, &live, &calls))) {
+    if (rc == SFD_E_NOCONVERGE) restore_counters(h->streams[0], before);
+    return rc;
+  }
   if (mem == SFD_MEM_DEVICE) {
     CK(transpose_out(panel, h->L, h->d, h->ell, B_out, l0.st));
   } else {
@@ -1483,8 +1596,11 @@ int sfd_sketch(sfd_t* h, float* B_out, int mem, int32_t* live_rows) {
   return SFD_OK;
 }
 
-int sfd_merge(sfd_t* dst, sfd_t* src) {
-  if (!dst || !src || dst == src) return SFD_E_ARG;
+int sfd_merge(sfd_t* dst, const sfd_t* src_c) {
+  if (!dst || !src_c || dst == src_c) return SFD_E_ARG;
+  // src's logical state (sketch, buffer, counters) is left as it was; its query runs in its own
+  // lane workspaces, which are scratch between calls
+  sfd_t* src = const_cast<sfd_t*>(src_c);
   int rc = check_handle(dst);
   if (rc) return rc;
   if ((rc = check_handle(src))) return rc;
@@ -1496,11 +1612,17 @@ int sfd_merge(sfd_t* dst, sfd_t* src) {
   if ((rc = order_after_caller(dst))) return rc;
   if ((rc = order_after_caller(src))) return rc;
   StreamState& sd = dst->streams[0];
+  const sfd_stats_t src_before = src->streams[0].stats, dst_before = sd.stats;
   const float *ps, *pd;
   int live_s, live_d;
   int64_t calls_s, calls_d;
-  if ((rc = query(src, src->streams[0], src->lanes[0], &ps, &live_s, &calls_s))) return rc;
-  if ((rc = query(dst, sd, dst->lanes[0], &pd, &live_d, &calls_d))) return rc;
+  rc = query(src, src->streams[0], src->lanes[0], &ps, &live_s, &calls_s);
+  src->streams[0].stats = src_before;
+  if (rc) return rc;
+  if ((rc = query(dst, sd, dst->lanes[0], &pd, &live_d, &calls_d))) {
+    if (rc == SFD_E_NOCONVERGE) restore_counters(sd, dst_before);
+    return rc;
+  }
   // stack [query(dst); query(src)], DenseShrink with M = I
   Lane& ln = h->lanes[0];
   ln.ss = &sd;
@@ -1609,8 +1731,12 @@ int sfd_batch_append_csr(sfd_batch_t* b, int32_t nseg, const int32_t* stream_of_
     // validate every segment before any state changes, then stage them one at a time
     for (Segment& sg : segs)
       if ((rc = host_segment(h, sg))) return rc;
-    for (Segment& sg : segs)
-      if (sg.nrows > 0 && (rc = append_host_segment(h, sg))) return rc;
+    for (Segment& sg : segs) {
+      if (sg.nrows > 0 && (rc = append_host_segment(h, sg))) {
+        if (rc == SFD_E_NOCONVERGE) h->error = rc;
+        return rc;
+      }
+    }
     return SFD_OK;
   }
   for (Segment& sg : segs) {
@@ -1623,7 +1749,11 @@ int sfd_batch_append_csr(sfd_batch_t* b, int32_t nseg, const int32_t* stream_of_
   std::vector<Segment> live_segs;
   for (Segment& sg : segs)
     if (sg.nrows > 0) live_segs.push_back(std::move(sg));
-  return append_device_segments(h, live_segs);
+  // the streams' buffer steps are interleaved, so a stream whose retries run out leaves the
+  // others partly advanced: the batch goes to its error state (no rollback)
+  rc = append_device_segments(h, live_segs);
+  if (rc == SFD_E_NOCONVERGE) h->error = rc;
+  return rc;
 }
 
 int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
@@ -1635,6 +1765,23 @@ int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
   DeviceGuard g(h->device);
   if ((rc = order_after_caller(h))) return rc;
   if ((rc = sync_all(h))) return rc;
+  std::vector<sfd_stats_t> before;
+  for (const StreamState& ss : h->streams) before.push_back(ss.stats);
+  rc = batch_queries(h, B_out, mem);
+  if (rc == SFD_E_NOCONVERGE) {
+    // queries change no state; their counters are put back (the streams' buffers are intact)
+    (void)sync_all(h);
+    for (size_t s = 0; s < h->streams.size(); ++s) restore_counters(h->streams[s], before[s]);
+  }
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_queries(sfd_t* h, float* B_out, int mem) {
+  int rc;
   const int64_t per = (int64_t)h->ell * h->d;
   const int nl = h->nlanes;
   Lane& l0 = h->lanes[0];
@@ -1691,4 +1838,4 @@ int sfd_batch_sketch(sfd_batch_t* b, float* B_out, int mem) {
   return sync_all(h);
 }
 
-}  // extern "C"
+}  // namespace

@@ -10,6 +10,7 @@
 // A x runs over the input CSR, A^T y over a CSC built once (FP32 values, FP64 accumulation);
 // B stays FP32 and is read in FP64 arithmetic.  Every reduction has a fixed order, so results
 // are reproducible run to run.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <limits>
@@ -244,6 +245,65 @@ double tri_kth(const std::vector<double>& a, const std::vector<double>& b, int k
   return 0.5 * (lo + hi);
 }
 
+// |last component| of the unit eigenvector of the symmetric tridiagonal (a, b) for its eigenvalue
+// theta, by inverse iteration: three solves with T - theta I, factored by Gaussian elimination
+// with partial pivoting (a row exchange brings in a second superdiagonal); a pivot that vanishes
+// is replaced by a tiny one, which only scales the solution along the eigenvector.
+double tri_evec_last(const std::vector<double>& a, const std::vector<double>& b, double theta) {
+  const int m = (int)a.size();
+  if (m == 1) return 1.0;
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(a[i]) + (i > 0 ? std::fabs(b[i]) : 0.0));
+  const double tiny = std::max(scale, std::numeric_limits<double>::min()) * std::numeric_limits<double>::epsilon();
+  std::vector<double> dg(m), up(m, 0.0), up2(m, 0.0), lo(m, 0.0);
+  std::vector<char> swp(m, 0);
+  for (int i = 0; i < m; ++i) dg[i] = a[i] - theta;
+  for (int i = 0; i + 1 < m; ++i) {
+    up[i] = b[i + 1];
+    lo[i] = b[i + 1];
+  }
+  for (int i = 0; i + 1 < m; ++i) {
+    if (std::fabs(dg[i]) >= std::fabs(lo[i])) {
+      if (dg[i] == 0.0) dg[i] = tiny;
+      const double f = lo[i] / dg[i];
+      lo[i] = f;
+      dg[i + 1] -= f * up[i];
+    } else {
+      // rows i and i + 1 exchanged
+      const double f = dg[i] / lo[i];
+      swp[i] = 1;
+      dg[i] = lo[i];
+      lo[i] = f;
+      const double t = up[i];
+      up[i] = dg[i + 1];
+      dg[i + 1] = t - f * dg[i + 1];
+      if (i + 2 < m) {
+        up2[i] = up[i + 1];
+        up[i + 1] = -f * up[i + 1];
+      }
+    }
+  }
+  if (dg[m - 1] == 0.0) dg[m - 1] = tiny;
+  std::vector<double> x(m, 1.0 / std::sqrt((double)m));
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i + 1 < m; ++i) {
+      if (swp[i]) std::swap(x[i], x[i + 1]);
+      x[i + 1] -= lo[i] * x[i];
+    }
+    x[m - 1] /= dg[m - 1];
+    x[m - 2] = (x[m - 2] - up[m - 2] * x[m - 1]) / dg[m - 2];
+    for (int i = m - 3; i >= 0; --i) x[i] = (x[i] - up[i] * x[i + 1] - up2[i] * x[i + 2]) / dg[i];
+    double nrm = 0.0;
+    for (double v : x) nrm = std::max(nrm, std::fabs(v));
+    for (double& v : x) v /= nrm;  // rescale first: the solve can overflow a plain 2-norm
+    nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (double& v : x) v /= nrm;
+  }
+  return std::fabs(x[m - 1]);
+}
+
 struct Allocs {
   std::vector<void*> p;
   template <class T>
@@ -299,7 +359,10 @@ hipError_t multi_dot(EvalCtx& c, const double* Q, int nv, const double* w, doubl
 
 // Lanczos with full reorthogonalisation (two classical Gram-Schmidt sweeps per step) on the
 // operator: the tridiagonal coefficients of `steps` steps (fewer when the Krylov space closes).
-hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector<double>& a, std::vector<double>& b) {
+// *beta_next: the coupling after the last kept step (0 when the Krylov space closed), which with
+// the eigenvectors of the tridiagonal gives the Ritz residuals.
+hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector<double>& a, std::vector<double>& b,
+                   double* beta_next) {
   hipError_t e;
   const int64_t d = c.d;
   const unsigned gd = grid_for(d, 256);
@@ -334,12 +397,16 @@ hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector
   double scale = 0.0;
   a.clear();
   b.assign(1, 0.0);
+  *beta_next = 0.0;
   for (int j = 0; j < steps; ++j) {
     a.push_back(ha[(size_t)j]);
     scale = std::max(scale, std::fabs(ha[(size_t)j]) + b.back());
+    const bool closed = !(hb[(size_t)j + 1] > 1e-12 * scale);
     if (j + 1 < steps) {
-      if (!(hb[(size_t)j + 1] > 1e-12 * scale)) break;
+      if (closed) break;
       b.push_back(hb[(size_t)j + 1]);
+    } else if (!closed) {
+      *beta_next = hb[(size_t)j + 1];
     }
   }
   return hipSuccess;
@@ -441,21 +508,30 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
   r.fro2A = fro2A;
   // cov-err: extreme eigenvalues of A^T A - B^T B
   std::vector<double> ta, tb;
-  if ((e = lanczos(c, true, m, seed, ta, tb)) != hipSuccess) return hip_fail(e);
+  double bn = 0.0;
+  if ((e = lanczos(c, true, m, seed, ta, tb, &bn)) != hipSuccess) return hip_fail(e);
   r.cov_min = tri_kth(ta, tb, 0);
   r.cov_max = tri_kth(ta, tb, (int)ta.size() - 1);
+  r.cov_min_res = bn > 0.0 ? bn * tri_evec_last(ta, tb, r.cov_min) : 0.0;
+  r.cov_max_res = bn > 0.0 ? bn * tri_evec_last(ta, tb, r.cov_max) : 0.0;
   r.cov_err = std::max(std::fabs(r.cov_min), std::fabs(r.cov_max)) / fro2A;
   r.steps = (int32_t)ta.size();
   r.top_k_energy = nan;
+  r.top_k_res = nan;
   r.proj_num = nan;
   r.proj_err = nan;
   if (k > 0) {
     // ||A - A_k||_F^2 from the k largest eigenvalues of A^T A
-    if ((e = lanczos(c, false, m, seed ^ 0x5DEECE66Dull, ta, tb)) != hipSuccess) return hip_fail(e);
+    if ((e = lanczos(c, false, m, seed ^ 0x5DEECE66Dull, ta, tb, &bn)) != hipSuccess) return hip_fail(e);
     const int mm = (int)ta.size();
-    double topk = 0.0;
-    for (int i = 0; i < k && i < mm; ++i) topk += tri_kth(ta, tb, mm - 1 - i);
+    double topk = 0.0, topk_res = 0.0;
+    for (int i = 0; i < k && i < mm; ++i) {
+      const double th = tri_kth(ta, tb, mm - 1 - i);
+      topk += th;
+      if (bn > 0.0) topk_res += bn * tri_evec_last(ta, tb, th);
+    }
     r.top_k_energy = topk;
+    r.top_k_res = topk_res;
     // V_k from the eig of B B^T, then ||A V_k||_F^2 = sum_c ||A v_c||^2
     k_gram64<<<dim3(ell, ell), 256, 0, st>>>(B, ell, d, G);
     if ((e = eig_sym(G, ell, ell, ell, ev, U, ework, st)) != hipSuccess) return hip_fail(e);

@@ -37,6 +37,8 @@ PRECISION_FP32 = 0
 PRECISION_BF16 = 1
 OPT_ALGORITHM = 10
 OPT_CSC_HOT_MIN = 11
+OPT_TEST_ZERO_ROW = 12
+OPT_TEST_ZERO_ATTEMPTS = 13
 ALGO_SFD = 0
 ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
@@ -107,6 +109,9 @@ class EvalResult(ctypes.Structure):
         ("proj_err", ctypes.c_double),
         ("steps", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("cov_min_res", ctypes.c_double),
+        ("cov_max_res", ctypes.c_double),
+        ("top_k_res", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -54,6 +54,29 @@ def test_small_cases_match_dense_oracle(gpu_lib, n, d, ell, k):
     assert r["proj_err"] == pytest.approx(evaluate.proj_err(A, Bh, k), rel=1e-7)
     # the FD property of the sketch (B^T B <= A^T A) shows as cov_min >= 0 up to FP32 rounding
     assert r["cov_min"] >= -1e-5 * r["fro2A"]
+    # the Krylov space is the whole space: the Ritz residuals vanish
+    assert r["cov_max_res"] <= 1e-6 * lmax and r["cov_min_res"] <= 1e-6 * lmax
+    assert r["top_k_res"] <= 1e-6 * r["top_k_energy"]
+
+
+@pytest.mark.parametrize("steps", [12, 30])
+def test_ritz_residuals_bound_the_distance_to_the_spectrum(gpu_lib, steps):
+    # fewer steps than d: each reported Ritz value lies within its residual of an eigenvalue of
+    # A^T A - B^T B (resp. A^T A), checked against the dense spectrum
+    st = small_random_csr(600, 300, 9, 17, dist="lognormal")
+    B = _sketch(gpu_lib, st, 20)
+    r = gpu_lib.evaluate(*_dev(st), st.d, B, k=4, steps=steps)
+    A, Bh = _csr(st), B.cpu().numpy().astype(np.float64)
+    G = (A.T @ A).toarray()
+    lam = np.linalg.eigvalsh(G - Bh.T @ Bh)
+    scale = np.abs(lam).max()
+    for th, res in ((r["cov_max"], r["cov_max_res"]), (r["cov_min"], r["cov_min_res"])):
+        assert np.min(np.abs(lam - th)) <= res * (1 + 1e-6) + 1e-10 * scale, (th, res)
+        assert 0.0 < res < scale  # a finite, informative certificate after a partial run
+    top = np.sort(np.linalg.eigvalsh(G))[::-1][:4]
+    # Ritz values interlace: the top-k Ritz sum is at most the true top-k energy
+    assert r["top_k_energy"] <= np.sum(top) * (1 + 1e-12)
+    assert r["top_k_res"] > 0.0
 
 
 def test_large_case_matches_arpack(gpu_lib):
@@ -72,6 +95,9 @@ def test_large_case_matches_arpack(gpu_lib):
     assert r["cov_min"] >= -1e-5 * r["fro2A"]
     assert r["cov_max"] == pytest.approx(lmax, rel=1e-5)
     assert r["cov_err"] == pytest.approx(lmax / evaluate.fro2(A), rel=1e-5)
+    # the residual certifies the extreme: ARPACK's value lies within it
+    assert abs(r["cov_max"] - lmax) <= r["cov_max_res"] + 1e-9 * lmax
+    assert r["cov_max_res"] <= 1e-3 * lmax
     assert r["proj_err"] == pytest.approx(evaluate.proj_err(A, Bh, 10), rel=1e-6)
     assert r["steps"] == 160
 

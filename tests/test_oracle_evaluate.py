@@ -40,3 +40,25 @@ def test_tail_energy_and_proj_err():
     assert np.isclose(evaluate.proj_err(A, B, 5), 1.0)
     with pytest.raises(ValueError):
         evaluate.sfd_bound(A, 20, 3)
+
+
+def test_top_singular_values_iterative_branch_matches_closed_form():
+    # min(n, d) > 2000 takes the iterative (ARPACK svds) branch: pinned against a matrix with
+    # known singular values, A = U diag(s) V^T with U, V orthonormal (Householder QR of Gaussian
+    # blocks), and against LAPACK's dense SVD of the same matrix
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(5)
+    n, d, r = 2600, 2100, 40
+    U, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((d, r)))
+    s = np.sort(rng.uniform(0.5, 20.0, r))[::-1]
+    s[3] = s[2] * (1 - 1e-3)  # a close pair in the top 10
+    A = sp.csr_matrix((U * s) @ V.T)
+    k = 10
+    got = evaluate.top_singular_values(A, k)
+    np.testing.assert_allclose(got, s[:k], rtol=1e-9)
+    dense = np.linalg.svd(A.toarray(), compute_uv=False)[:k]
+    np.testing.assert_allclose(got, dense, rtol=1e-9)
+    # and the tail energy it feeds: ||A - A_k||_F^2 = sum_{i > k} s_i^2
+    np.testing.assert_allclose(evaluate.tail_energy(A, k), np.sum(s[k:] ** 2), rtol=1e-9)

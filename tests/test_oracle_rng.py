@@ -82,3 +82,34 @@ def test_sphere_vector_uniform():
     # E[x] = 0 and E[x x^T] = I/d for the uniform law on the sphere
     assert np.abs(xs.mean(axis=0)).max() < 0.03
     np.testing.assert_allclose(xs.T @ xs / len(xs), np.eye(d) / d, atol=0.01)
+
+
+def test_box_muller_exact_values_for_hand_picked_words():
+    """Words whose uniforms have closed-form Box-Muller images, so the lane pairing (which uniform
+    is the radius, which the angle), the cos/sin order and the uniform map are each pinned."""
+    from oracle.rng import box_muller
+
+    top = lambda k: np.uint64(k << 12)  # a word whose top 52 bits are k: u = (k + 1/2) 2^-52
+    r_max = np.sqrt(106.0 * np.log(2.0))  # u = 2^-53 (k = 0): sqrt(-2 ln 2^-53)
+    # radius word k = 0; angle words at u = 1/4 + 2^-53 (k = 2^50) and u = 1/2 + 2^-53 (k = 2^51)
+    w = np.array([[top(0)], [top(1 << 50)], [top(0)], [top(1 << 51)]], dtype=np.uint64)
+    z = box_muller(w)[0]
+    eps = 2.0 * np.pi * 2.0 ** -53  # the angle's offset from pi/2 resp. pi
+    # (the zeros of cos / sin are only zero to the rounding of 2 pi u: |z| <= 1e-14 r)
+    assert abs(z[0]) <= 1e-14 * r_max                                       # cos(pi/2 + eps)
+    np.testing.assert_allclose(z[1], r_max, rtol=1e-15)                     # sin(pi/2 + eps)
+    np.testing.assert_allclose(z[2], -r_max, rtol=1e-15)                    # cos(pi + eps)
+    assert abs(z[3]) <= 1e-14 * r_max                                       # sin(pi + eps)
+    # radius word at u = 1 - 2^-53 (the largest word): r = sqrt(-2 ln(1 - 2^-53)) = 2^-26 (1 + ...)
+    # angle word 0: u = 2^-53, cos = 1, sin = 2 pi 2^-53
+    w = np.array([[np.uint64(2**64 - 1)], [np.uint64(0)], [np.uint64(2**64 - 1)], [top(3 << 50)]], dtype=np.uint64)
+    z = box_muller(w)[0]
+    np.testing.assert_allclose(z[0], 2.0 ** -26, rtol=1e-12)
+    np.testing.assert_allclose(z[1], 2.0 ** -26 * eps, rtol=1e-12)
+    assert abs(z[2]) <= 1e-14 * 2.0 ** -26                                 # cos(3 pi / 2 + eps)
+    np.testing.assert_allclose(z[3], -(2.0 ** -26), rtol=1e-12)           # sin(3 pi / 2 + eps)
+    # the start block is built from exactly these four lanes per Philox block, in this order
+    from oracle.philox import philox4x64_10
+
+    blk = philox4x64_10(np.array([0, 2, 3, 0], dtype=np.uint64), (5, 1))
+    np.testing.assert_array_equal(start_block(5, 1, 3, 2, 0, 1, 4)[0], box_muller(blk[:, None])[0])

@@ -392,3 +392,33 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
 
         monkeypatch.setattr(ost.SFDOracle, "_flush", flush_late)
     assert not _pins_hold()
+
+
+def test_planted_start_block_makes_every_buffer_reject_then_retry():
+    # the scenario of the GPU retry tests (Alg 4's loop), pinned on the oracle: on the spiked
+    # stream every buffer's dominant direction is e_0; with row 0 of attempt 0's start block zeroed
+    # (and q = 2, too few steps for rounding noise to regrow e_0) VerifySpectral rejects (Lemma 3.1:
+    # ||C|| >= 2 here), the next attempt's Gaussian block sees e_0 and is accepted
+    from oracle import NoConvergence
+    from tests.planted import ZeroRowOracle
+    from workloads import spiked_stream
+
+    st = spiked_stream(100, 40, 0)
+    o = ZeroRowOracle(40, 8, 0.25, 0, q=2, unit_roundoff=2.0 ** -24)
+    o.append_csr(st.indptr, st.indices, st.values)
+    assert o.flushes == 2
+    for b in o.log:
+        assert [r["accepted"] for r in b["attempts"]] == [False, True]
+        assert b["attempts"][0]["ln_norm"] > 5.0 and b["attempts"][1]["ln_norm"] < -10.0
+    assert [r["vs_index"] for b in o.log for r in b["attempts"]] == [1, 2, 3, 4]
+    rec = []
+    B, live, calls = o.query(log=rec)
+    assert [r["accepted"] for r in rec] == [False, True] and calls == 2
+    # the accepted sketch keeps Property 1 on the whole stream
+    A = st.to_scipy()
+    lmin, _ = evaluate.cov_extremes(A, B)
+    assert lmin >= -1e-9 * evaluate.fro2(A)
+    # every attempt planted: the loop gives up
+    bad = ZeroRowOracle(40, 8, 0.25, 0, q=2, max_attempts=3, zero_attempts=3, unit_roundoff=2.0 ** -24)
+    with pytest.raises(NoConvergence):
+        bad.append_csr(st.indptr, st.indices, st.values)

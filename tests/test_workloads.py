@@ -102,3 +102,59 @@ def test_device_generator_draws_do_not_depend_on_chunking():
     n1 = int(head[0][-1])
     assert torch.equal(head[0], whole[0][:1001])
     assert torch.equal(head[1], whole[1][:n1]) and torch.equal(head[2], whole[2][:n1])
+
+
+def _head_count_law(z, head, d, p_head=0.9):
+    """Exact distribution of the number of head columns in a row of the paper's generator (Sec. 4,
+    "Datasets"): a placement picks the head (first `head` columns) with probability p_head, else
+    the tail, a column uniformly inside it, and is drawn again when the row already holds that
+    column.  Conditioned on landing on a new column, the next new column is in the head with
+    probability p_head (H - h)/H / (p_head (H - h)/H + (1 - p_head)(T - t)/T)."""
+    H, T = head, d - head
+    P = np.zeros(z + 1)
+    P[0] = 1.0
+    for step in range(z):
+        Q = np.zeros(z + 1)
+        for h in range(step + 1):
+            if P[h] == 0.0:
+                continue
+            t = step - h
+            a = p_head * (H - h) / H if H else 0.0
+            b = (1 - p_head) * (T - t) / T if T else 0.0
+            Q[h + 1] += P[h] * a / (a + b)
+            Q[h] += P[h] * b / (a + b)
+        P = Q
+    return P
+
+
+@pytest.mark.parametrize("d,z", [(1000, 5), (1000, 100), (1000, 500), (6000, 100)])
+def test_paper_head_tail_follows_its_recipe(d, z):
+    # the paper's synthetic rows (Sec. 4, "Datasets"): exactly z distinct non-zeros of value +-1,
+    # head = the first 1.5 z columns, each placement in the head with probability 0.9, uniform
+    # inside the chosen part, repeats of a column drawn again
+    from workloads import paper_head_tail
+
+    n = 10_000 if z <= 100 else 2_000
+    st = paper_head_tail(n=n, d=d, z=z, seed=3)
+    _check_rows(st.indptr, st.indices, d)
+    assert np.all(np.diff(st.indptr) == z)
+    assert set(np.unique(st.values)) == {-1.0, 1.0}
+    plus = int(np.sum(st.values > 0))
+    assert abs(plus - st.nnz / 2) < 6 * math.sqrt(st.nnz / 4)  # a fair sign
+    head = int(1.5 * z)
+    in_head = (st.indices < head).reshape(n, z).sum(axis=1)
+    law = _head_count_law(z, head, d)
+    support = np.nonzero(law * n >= 5)[0]  # chi-square over the cells with enough mass
+    obs = np.array([np.sum(in_head == h) for h in support], dtype=np.float64)
+    exp = law[support] * n
+    obs = np.append(obs, n - obs.sum())
+    exp = np.append(exp, n - exp.sum())
+    keep = exp > 0
+    stat, p = scipy.stats.chisquare(obs[keep], exp[keep] * obs[keep].sum() / exp[keep].sum())
+    assert p > 1e-4, (stat, p, law[support][:5])
+    # uniform inside the head and inside the tail
+    cnt = np.bincount(st.indices, minlength=d).astype(np.float64)
+    for part in (cnt[:head], cnt[head:]):
+        if part.sum() > 20 * part.size:
+            stat, p = scipy.stats.chisquare(part)
+            assert p > 1e-4, (stat, p)

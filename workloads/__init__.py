@@ -14,6 +14,7 @@ from .synthetic import (
     stream_2e6_d5e4,
     batch_stream_d2e4,
     paper_head_tail,
+    spiked_stream,
 )
 
 __all__ = [
@@ -26,4 +27,5 @@ __all__ = [
     "stream_2e6_d5e4",
     "batch_stream_d2e4",
     "paper_head_tail",
+    "spiked_stream",
 ]

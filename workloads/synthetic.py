@@ -268,6 +268,29 @@ def paper_head_tail(n: int = 10_000, d: int = 1000, z: int = 100, seed: int = 0)
     return CsrStream(indptr, idx, vals, d, dict(name="paper_head_tail", ell=50, k=10, seed=seed, z=z))
 
 
+def spiked_stream(n: int, d: int, seed: int = 0, *, noise_nnz: int = 12, spike: float = 3.0,
+                  noise: float = 0.3) -> CsrStream:
+    """Rows that alternate between noise and a spike: even rows hold noise_nnz distinct columns of
+    1 .. d - 1 with N(0, noise^2) values, odd rows the single entry (column 0, spike).  Column 0 then
+    carries the dominant right singular direction e_0 of every buffer of consecutive rows, and
+    nothing else touches it: a start block whose row 0 is zero misses it."""
+    rng = np.random.default_rng([seed, 0x5B1E])
+    idx, val, lens = [], [], []
+    for r in range(n):
+        if r % 2:
+            idx.append(np.zeros(1, np.int64))
+            val.append(np.full(1, spike))
+        else:
+            idx.append(np.sort(rng.choice(np.arange(1, d), size=noise_nnz, replace=False)))
+            val.append(rng.standard_normal(noise_nnz) * noise)
+        lens.append(len(idx[-1]))
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    indices = np.concatenate(idx).astype(np.int32) if n else np.zeros(0, np.int32)
+    values = np.concatenate(val).astype(np.float32) if n else np.zeros(0, np.float32)
+    return CsrStream(indptr, indices, values, d, dict(name="spiked", seed=seed))
+
+
 def small_random_csr(n: int, d: int, lam: float, seed: int, *, s: float = 1.1, dup_rate: float = 0.0,
                      empty_rate: float = 0.0, dist: str = "normal") -> CsrStream:
     """A small Zipf-Poisson stream for tests, with optional empty rows and repeated column ids."""
