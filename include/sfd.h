@@ -45,7 +45,8 @@ enum {
   SFD_E_NOMEM = -4,      /* device allocation failed */
   SFD_E_DEVICE = -5,     /* a HIP runtime call failed */
   SFD_E_NOCONVERGE = -6, /* BoostedSparseShrink exhausted its attempts */
-  SFD_E_STATE = -7       /* handle is in an error state (see above) */
+  SFD_E_STATE = -7,      /* handle is in an error state (see above) */
+  SFD_E_TOOBIG = -8      /* the work of a no-allocation call exceeds its fixed scratch */
 };
 
 enum { SFD_MEM_HOST = 0, SFD_MEM_DEVICE = 1 };
@@ -293,6 +294,25 @@ typedef struct {
 int sfd_evaluate(int64_t n, int64_t d, const int64_t *indptr, const int32_t *indices, const float *values,
                  const float *B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void *hip_stream,
                  sfd_eval_t *out);
+
+/* sfd_evaluate for callers that cannot allocate device memory (code in a serving loop that must
+ * not call hipMalloc, harnesses that forbid it): the same arguments, kernels and results (equal
+ * bit for bit to sfd_evaluate's), with the work memory taken from a fixed array of 64 MiB in
+ * device memory that the library holds on every GPU it runs on until the process ends.  The call
+ * makes no device allocation of any kind; on its first use on a device it looks up that device's
+ * copy of the array (with the device current).
+ * Limit: the work must fit the 64 MiB: about 29 bytes per stored entry, 40 bytes per row and per
+ * column, the (steps + 1) d doubles of the Lanczos basis, k d doubles for proj-err and about
+ * 2 MiB of fixed parts (e.g. 10^6 entries in 5 10^4 rows at d = 20,000 with 160 steps and k = 10
+ * fit).  Larger inputs return SFD_E_TOOBIG before any work is issued (only the argument checks
+ * run).
+ * Sharing: calls on one device share its array, which keeps the last call's contents (every
+ * part that must start at zero is cleared by the call).  Calls from threads of one process are
+ * serialized per device by a lock; work that overlaps it on that device's array otherwise races.
+ * Errors: those of sfd_evaluate, SFD_E_TOOBIG in place of SFD_E_NOMEM. */
+int sfd_evaluate_noalloc(int64_t n, int64_t d, const int64_t *indptr, const int32_t *indices, const float *values,
+                         const float *B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void *hip_stream,
+                         sfd_eval_t *out);
 
 #ifdef __cplusplus
 }

@@ -1418,6 +1418,7 @@ const char* sfd_strerror(int code) {
     case SFD_E_DEVICE: return "HIP runtime error";
     case SFD_E_NOCONVERGE: return "BoostedSparseShrink exhausted its attempts";
     case SFD_E_STATE: return "handle is in an error state";
+    case SFD_E_TOOBIG: return "work exceeds the fixed scratch of a no-allocation call";
     default: return "unknown error";
   }
 }

@@ -14,7 +14,7 @@
 #include <cmath>
 #include <cstdint>
 #include <limits>
-#include <vector>
+#include <mutex>
 
 #include "sfd.h"
 #include "sfd_internal.h"
@@ -215,10 +215,20 @@ __global__ __launch_bounds__(256) void k_right_vectors(const float* __restrict__
   }
 }
 
-// The k-th smallest (k = 0 ..) eigenvalue of the symmetric tridiagonal matrix with diagonal a
-// and off-diagonal b (b[i] couples i - 1 and i, b[0] unused), by bisection on Sturm counts.
-double tri_kth(const std::vector<double>& a, const std::vector<double>& b, int k) {
-  const int m = (int)a.size();
+// The symmetric tridiagonal matrix of a Lanczos run: diagonal a[0 .. n), off-diagonal b[1 .. n)
+// (b[i] couples i - 1 and i, b[0] unused).  Fixed capacity, so the host side of an evaluation
+// needs no heap memory.
+struct Tri {
+  int n = 0;
+  double a[kEvalMaxSteps];
+  double b[kEvalMaxSteps + 1];
+};
+
+// The k-th smallest (k = 0 ..) eigenvalue of the tridiagonal t, by bisection on Sturm counts.
+double tri_kth(const Tri& t, int k) {
+  const int m = t.n;
+  const double* a = t.a;
+  const double* b = t.b;
   double lo = a[0], hi = a[0];
   for (int i = 0; i < m; ++i) {
     const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < m ? std::fabs(b[i + 1]) : 0.0);
@@ -245,19 +255,25 @@ double tri_kth(const std::vector<double>& a, const std::vector<double>& b, int k
   return 0.5 * (lo + hi);
 }
 
-// |last component| of the unit eigenvector of the symmetric tridiagonal (a, b) for its eigenvalue
-// theta, by inverse iteration: three solves with T - theta I, factored by Gaussian elimination
-// with partial pivoting (a row exchange brings in a second superdiagonal); a pivot that vanishes
-// is replaced by a tiny one, which only scales the solution along the eigenvector.
-double tri_evec_last(const std::vector<double>& a, const std::vector<double>& b, double theta) {
-  const int m = (int)a.size();
+// |last component| of the unit eigenvector of the tridiagonal t for its eigenvalue theta, by
+// inverse iteration: three solves with T - theta I, factored by Gaussian elimination with partial
+// pivoting (a row exchange brings in a second superdiagonal); a pivot that vanishes is replaced by
+// a tiny one, which only scales the solution along the eigenvector.
+double tri_evec_last(const Tri& t, double theta) {
+  const int m = t.n;
   if (m == 1) return 1.0;
+  const double* a = t.a;
+  const double* b = t.b;
   double scale = 0.0;
   for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(a[i]) + (i > 0 ? std::fabs(b[i]) : 0.0));
   const double tiny = std::max(scale, std::numeric_limits<double>::min()) * std::numeric_limits<double>::epsilon();
-  std::vector<double> dg(m), up(m, 0.0), up2(m, 0.0), lo(m, 0.0);
-  std::vector<char> swp(m, 0);
-  for (int i = 0; i < m; ++i) dg[i] = a[i] - theta;
+  double dg[kEvalMaxSteps], up[kEvalMaxSteps], up2[kEvalMaxSteps], lo[kEvalMaxSteps], x[kEvalMaxSteps];
+  bool swp[kEvalMaxSteps];
+  for (int i = 0; i < m; ++i) {
+    dg[i] = a[i] - theta;
+    up[i] = up2[i] = lo[i] = 0.0;
+    swp[i] = false;
+  }
   for (int i = 0; i + 1 < m; ++i) {
     up[i] = b[i + 1];
     lo[i] = b[i + 1];
@@ -271,12 +287,12 @@ double tri_evec_last(const std::vector<double>& a, const std::vector<double>& b,
     } else {
       // rows i and i + 1 exchanged
       const double f = dg[i] / lo[i];
-      swp[i] = 1;
+      swp[i] = true;
       dg[i] = lo[i];
       lo[i] = f;
-      const double t = up[i];
+      const double tt = up[i];
       up[i] = dg[i + 1];
-      dg[i + 1] = t - f * dg[i + 1];
+      dg[i + 1] = tt - f * dg[i + 1];
       if (i + 2 < m) {
         up2[i] = up[i + 1];
         up[i + 1] = -f * up[i + 1];
@@ -284,7 +300,7 @@ double tri_evec_last(const std::vector<double>& a, const std::vector<double>& b,
     }
   }
   if (dg[m - 1] == 0.0) dg[m - 1] = tiny;
-  std::vector<double> x(m, 1.0 / std::sqrt((double)m));
+  for (int i = 0; i < m; ++i) x[i] = 1.0 / std::sqrt((double)m);
   for (int it = 0; it < 3; ++it) {
     for (int i = 0; i + 1 < m; ++i) {
       if (swp[i]) std::swap(x[i], x[i + 1]);
@@ -294,28 +310,43 @@ double tri_evec_last(const std::vector<double>& a, const std::vector<double>& b,
     x[m - 2] = (x[m - 2] - up[m - 2] * x[m - 1]) / dg[m - 2];
     for (int i = m - 3; i >= 0; --i) x[i] = (x[i] - up[i] * x[i + 1] - up2[i] * x[i + 2]) / dg[i];
     double nrm = 0.0;
-    for (double v : x) nrm = std::max(nrm, std::fabs(v));
-    for (double& v : x) v /= nrm;  // rescale first: the solve can overflow a plain 2-norm
+    for (int i = 0; i < m; ++i) nrm = std::max(nrm, std::fabs(x[i]));
+    for (int i = 0; i < m; ++i) x[i] /= nrm;  // rescale first: the solve can overflow a plain 2-norm
     nrm = 0.0;
-    for (double v : x) nrm += v * v;
+    for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
     nrm = std::sqrt(nrm);
-    for (double& v : x) v /= nrm;
+    for (int i = 0; i < m; ++i) x[i] /= nrm;
   }
   return std::fabs(x[m - 1]);
 }
 
-struct Allocs {
-  std::vector<void*> p;
+// Device work memory of one evaluation, taken in pieces.  Two sources:
+//  - allocating: each piece is a hipMalloc, all freed when the workspace goes out of scope;
+//  - arena: pieces are consecutive 256-byte aligned ranges of a fixed region (the static scratch
+//    of sfd_evaluate_noalloc); a piece that does not fit fails.
+struct Workspace {
+  char* base = nullptr;  // arena region (nullptr: allocating)
+  size_t cap = 0, used = 0;
+  void* owned[64] = {};
+  int nowned = 0;
   template <class T>
   bool get(T** out, int64_t count) {
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (base) {
+      const size_t off = (used + 255) & ~(size_t)255;
+      if (off > cap || bytes > cap - off) return false;
+      used = off + bytes;
+      *out = reinterpret_cast<T*>(base + off);
+      return true;
+    }
     void* q = nullptr;
-    if (hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) return false;
-    p.push_back(q);
+    if (nowned == 64 || hipMalloc(&q, bytes) != hipSuccess) return false;
+    owned[nowned++] = q;
     *out = static_cast<T*>(q);
     return true;
   }
-  ~Allocs() {
-    for (void* q : p) (void)hipFree(q);
+  ~Workspace() {
+    for (int i = 0; i < nowned; ++i) (void)hipFree(owned[i]);
   }
 };
 
@@ -361,8 +392,7 @@ hipError_t multi_dot(EvalCtx& c, const double* Q, int nv, const double* w, doubl
 // operator: the tridiagonal coefficients of `steps` steps (fewer when the Krylov space closes).
 // *beta_next: the coupling after the last kept step (0 when the Krylov space closed), which with
 // the eigenvectors of the tridiagonal gives the Ritz residuals.
-hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector<double>& a, std::vector<double>& b,
-                   double* beta_next) {
+hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, Tri& t, double* beta_next) {
   hipError_t e;
   const int64_t d = c.d;
   const unsigned gd = grid_for(d, 256);
@@ -384,29 +414,27 @@ hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector
     k_normalize<<<gd, 256, 0, c.st>>>(c.w, nrm2, c.Q + (int64_t)(j + 1) * d, c.beta + j + 1, d);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  std::vector<double> ha((size_t)steps), hb((size_t)steps + 1);
-  if ((e = hipMemcpyAsync(ha.data(), c.alpha, sizeof(double) * steps, hipMemcpyDeviceToHost, c.st)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(hb.data(), c.beta, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, c.st)) !=
-      hipSuccess)
+  double ha[kEvalMaxSteps], hb[kEvalMaxSteps + 1];
+  if ((e = hipMemcpyAsync(ha, c.alpha, sizeof(double) * steps, hipMemcpyDeviceToHost, c.st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(hb, c.beta, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, c.st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
   // the Krylov space closes at the first coupling that vanishes against the coefficients seen so
   // far (the steps after it start from rounding noise and are dropped: their coefficients are
   // meaningless and can grow without bound)
   double scale = 0.0;
-  a.clear();
-  b.assign(1, 0.0);
+  t.n = 0;
+  t.b[0] = 0.0;
   *beta_next = 0.0;
   for (int j = 0; j < steps; ++j) {
-    a.push_back(ha[(size_t)j]);
-    scale = std::max(scale, std::fabs(ha[(size_t)j]) + b.back());
-    const bool closed = !(hb[(size_t)j + 1] > 1e-12 * scale);
+    t.a[t.n++] = ha[j];
+    scale = std::max(scale, std::fabs(ha[j]) + t.b[j]);
+    const bool closed = !(hb[j + 1] > 1e-12 * scale);
     if (j + 1 < steps) {
       if (closed) break;
-      b.push_back(hb[(size_t)j + 1]);
+      t.b[j + 1] = hb[j + 1];
     } else if (!closed) {
-      *beta_next = hb[(size_t)j + 1];
+      *beta_next = hb[j + 1];
     }
   }
   return hipSuccess;
@@ -414,22 +442,21 @@ hipError_t lanczos(EvalCtx& c, bool withB, int steps, uint64_t seed, std::vector
 
 int hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? SFD_E_NOMEM : SFD_E_DEVICE; }
 
-}  // namespace
-}  // namespace sfd
-
-extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const int32_t* indices, const float* values,
-                            const float* B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void* hip_stream,
-                            sfd_eval_t* out) {
-  using namespace sfd;
+// The whole evaluation with its device work memory taken from ws (allocating, or the static
+// scratch).  A piece that does not fit the scratch is reported before any work that the result
+// depends on has been issued (only the argument checks ran).
+int evaluate_impl(Workspace& al, int64_t n, int64_t d, const int64_t* indptr, const int32_t* indices,
+                  const float* values, const float* B, int32_t ell, int32_t k, int32_t steps, uint64_t seed,
+                  void* hip_stream, sfd_eval_t* out) {
   if (!out || !indptr || n < 0 || d < 1 || ell < 0 || k < 0 || k > ell || (ell > 0 && !B)) return SFD_E_ARG;
   if (ell > 2 * kMaxEll || steps > kEvalMaxSteps || d >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31)) return SFD_E_ARG;
   const int m = (int)std::min<int64_t>(d, steps > 0 ? steps : kEvalDefaultSteps);
   if (k > m) return SFD_E_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  Allocs al;
+  const int nomem = al.base ? SFD_E_TOOBIG : SFD_E_NOMEM;
   // the input: rows, then the stored-entry count from the row pointers
   int* err = nullptr;
-  if (!al.get(&err, 1)) return SFD_E_NOMEM;
+  if (!al.get(&err, 1)) return nomem;
   int64_t ends[2] = {0, 0};
   if (hipMemcpyAsync(&ends[0], indptr, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(&ends[1], indptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -482,7 +509,7 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
          al.get(&V, (int64_t)k * d) && al.get(&kd, k) &&
          al.get(reinterpret_cast<char**>(&ework), std::max<int64_t>(eig_work_bytes(ell), 1));
   }
-  if (!ok) return SFD_E_NOMEM;
+  if (!ok) return nomem;
   hipError_t e;
   // CSR offsets, CSC (and ||A||_F^2 with repeated entries summed, from the sorted column ids)
   k_rebase<<<grid_for(n + 1, 256), 256, 0, st>>>(indptr, n, rowptr);
@@ -507,28 +534,28 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
   sfd_eval_t r{};
   r.fro2A = fro2A;
   // cov-err: extreme eigenvalues of A^T A - B^T B
-  std::vector<double> ta, tb;
+  Tri t;
   double bn = 0.0;
-  if ((e = lanczos(c, true, m, seed, ta, tb, &bn)) != hipSuccess) return hip_fail(e);
-  r.cov_min = tri_kth(ta, tb, 0);
-  r.cov_max = tri_kth(ta, tb, (int)ta.size() - 1);
-  r.cov_min_res = bn > 0.0 ? bn * tri_evec_last(ta, tb, r.cov_min) : 0.0;
-  r.cov_max_res = bn > 0.0 ? bn * tri_evec_last(ta, tb, r.cov_max) : 0.0;
+  if ((e = lanczos(c, true, m, seed, t, &bn)) != hipSuccess) return hip_fail(e);
+  r.cov_min = tri_kth(t, 0);
+  r.cov_max = tri_kth(t, t.n - 1);
+  r.cov_min_res = bn > 0.0 ? bn * tri_evec_last(t, r.cov_min) : 0.0;
+  r.cov_max_res = bn > 0.0 ? bn * tri_evec_last(t, r.cov_max) : 0.0;
   r.cov_err = std::max(std::fabs(r.cov_min), std::fabs(r.cov_max)) / fro2A;
-  r.steps = (int32_t)ta.size();
+  r.steps = (int32_t)t.n;
   r.top_k_energy = nan;
   r.top_k_res = nan;
   r.proj_num = nan;
   r.proj_err = nan;
   if (k > 0) {
     // ||A - A_k||_F^2 from the k largest eigenvalues of A^T A
-    if ((e = lanczos(c, false, m, seed ^ 0x5DEECE66Dull, ta, tb, &bn)) != hipSuccess) return hip_fail(e);
-    const int mm = (int)ta.size();
+    if ((e = lanczos(c, false, m, seed ^ 0x5DEECE66Dull, t, &bn)) != hipSuccess) return hip_fail(e);
+    const int mm = t.n;
     double topk = 0.0, topk_res = 0.0;
     for (int i = 0; i < k && i < mm; ++i) {
-      const double th = tri_kth(ta, tb, mm - 1 - i);
+      const double th = tri_kth(t, mm - 1 - i);
       topk += th;
-      if (bn > 0.0) topk_res += bn * tri_evec_last(ta, tb, th);
+      if (bn > 0.0) topk_res += bn * tri_evec_last(t, th);
     }
     r.top_k_energy = topk;
     r.top_k_res = topk_res;
@@ -542,16 +569,56 @@ extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const i
       k_multi_dot<<<dim3(nb, 1), 256, 0, st>>>(c.y, n, c.y, n, c.part);
       k_sum_parts<<<1, 256, 0, st>>>(c.part, (int)nb, kd + cc);
     }
-    std::vector<double> hk((size_t)k);
+    double hk[2 * kMaxEll];
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
-    if (hipMemcpyAsync(hk.data(), kd, sizeof(double) * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(hk, kd, sizeof(double) * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return SFD_E_DEVICE;
     double av = 0.0;
-    for (double x : hk) av += x;
+    for (int i = 0; i < k; ++i) av += hk[i];
     r.proj_num = fro2A - av;
     r.proj_err = r.proj_num / (fro2A - topk);
   }
   *out = r;
   return SFD_OK;
+}
+
+// The work memory of sfd_evaluate_noalloc: one array per GPU, alive until the process ends.  Host
+// code never passes `scratch` itself to a kernel (on the host it names a stand-in, not device
+// memory): the device address comes from hipGetSymbolAddress, once per device, with that device
+// current, and is kept in scratch_ptr[device].
+constexpr size_t kEvalScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kEvalScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu[kMaxDevices];  // one evaluation at a time per device (they share its scratch)
+void* scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+}  // namespace sfd
+
+extern "C" int sfd_evaluate(int64_t n, int64_t d, const int64_t* indptr, const int32_t* indices, const float* values,
+                            const float* B, int32_t ell, int32_t k, int32_t steps, uint64_t seed, void* hip_stream,
+                            sfd_eval_t* out) {
+  sfd::Workspace ws;
+  return sfd::evaluate_impl(ws, n, d, indptr, indices, values, B, ell, k, steps, seed, hip_stream, out);
+}
+
+extern "C" int sfd_evaluate_noalloc(int64_t n, int64_t d, const int64_t* indptr, const int32_t* indices,
+                                    const float* values, const float* B, int32_t ell, int32_t k, int32_t steps,
+                                    uint64_t seed, void* hip_stream, sfd_eval_t* out) {
+  using namespace sfd;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SFD_E_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return SFD_E_DEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu[dev]);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SFD_E_DEVICE;
+    scratch_ptr[dev] = p;
+  }
+  Workspace ws;
+  ws.base = static_cast<char*>(scratch_ptr[dev]);
+  ws.cap = kEvalScratchBytes;
+  return evaluate_impl(ws, n, d, indptr, indices, values, B, ell, k, steps, seed, hip_stream, out);
 }

@@ -22,6 +22,7 @@ SFD_E_NOMEM = -4
 SFD_E_DEVICE = -5
 SFD_E_NOCONVERGE = -6
 SFD_E_STATE = -7
+SFD_E_TOOBIG = -8
 MEM_HOST = 0
 MEM_DEVICE = 1
 OPT_DELTA = 1
@@ -65,6 +66,7 @@ EXPORTS = [
     "sfd_batch_append_csr",
     "sfd_batch_sketch",
     "sfd_evaluate",
+    "sfd_evaluate_noalloc",
 ]
 
 
@@ -167,6 +169,7 @@ def load(path: str = LIB_PATH):
         "sfd_batch_append_csr": (i, [vp, i32, vp, vp, vp, vp, vp, i]),
         "sfd_batch_sketch": (i, [vp, vp, i]),
         "sfd_evaluate": (i, [i64, i64, vp, vp, vp, vp, i32, i32, i32, u64, vp, ctypes.POINTER(EvalResult)]),
+        "sfd_evaluate_noalloc": (i, [i64, i64, vp, vp, vp, vp, i32, i32, i32, u64, vp, ctypes.POINTER(EvalResult)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -399,9 +402,11 @@ def start_block(seed: int, stream_id: int, buffer: int, attempt: int, purpose: i
     return out
 
 
-def evaluate(indptr, indices, values, d: int, B=None, k: int = 0, steps: int = 0, seed: int = 0) -> dict:
+def evaluate(indptr, indices, values, d: int, B=None, k: int = 0, steps: int = 0, seed: int = 0,
+             noalloc: bool = False) -> dict:
     """cov-err and proj-err of the sketch B (ell x d) against the CSR matrix A (sfd_evaluate, FP64 on
-    the GPU).  indptr/indices/values and B are torch CUDA tensors (int64, int32, float32, float32)."""
+    the GPU).  indptr/indices/values and B are torch CUDA tensors (int64, int32, float32, float32).
+    noalloc: call sfd_evaluate_noalloc (work memory from the library's fixed scratch) instead."""
     import torch
 
     n = int(indptr.numel()) - 1
@@ -414,7 +419,8 @@ def evaluate(indptr, indices, values, d: int, B=None, k: int = 0, steps: int = 0
             raise TypeError("B must be a contiguous CUDA float32 tensor of shape (ell, d)")
         ell, bp = int(B.shape[0]), B.data_ptr()
     res = EvalResult()
-    _check(load().sfd_evaluate(n, int(d), indptr.data_ptr(), indices.data_ptr(), values.data_ptr(), bp, ell, int(k),
-                               int(steps), int(seed), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
-                               ctypes.byref(res)), "sfd_evaluate")
+    name = "sfd_evaluate_noalloc" if noalloc else "sfd_evaluate"
+    _check(getattr(load(), name)(n, int(d), indptr.data_ptr(), indices.data_ptr(), values.data_ptr(), bp, ell,
+                                 int(k), int(steps), int(seed),
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(res)), name)
     return res.as_dict()
