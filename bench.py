@@ -171,57 +171,61 @@ def run_batch_full(args) -> int:
 
 
 def run_paper_sweep(args) -> int:
-    """The paper's own synthetic workload (Sec. 4: n = 10,000 rows of z distinct +-1 entries,
-    90% of them in the first 1.5 z columns, ell = 50) swept over z (d = 1,000) and over d
-    (z = 100), with three algorithms on the GPU: SFD (Alg 2 with BoostedSparseShrink), SFD with
-    SparseShrink alone (VerifySpectral off, as in the paper's experiments) and FrequentDirections
-    (Sec. 2.1, DenseShrink of ell-row batches).  Reports ms per pass and cov-err (Sec. 4) of each;
-    the paper reports SFD faster than FD on sparse inputs and not on dense ones."""
-    import numpy as np
+    """The paper's own synthetic workload (Sec. 4: rows of z distinct +-1 entries, 90% of them in the
+    first 1.5 z columns) swept as in its Table 1: one parameter at a time over its range, the others
+    at their defaults (n = 10,000, d = 1,000, ell = 50, z = 100): z in 5..500, d in 1e3..6e3, n in
+    1e4..6e4, ell in 5..100.  Three algorithms on the GPU: SFD (Alg 2 with BoostedSparseShrink),
+    SFD with SparseShrink alone (VerifySpectral off, as in the paper's experiments) and
+    FrequentDirections (Sec. 2.1, DenseShrink of ell-row batches).  Reports ms per pass and the
+    cov-err (Sec. 4, k = 10 for proj-err) of each sketch from the GPU evaluator; the paper reports
+    SFD faster than FD on sparse inputs and not on dense ones."""
     import torch
 
-    from oracle import evaluate
     from paper_1602_00412_amd import sfd
     from workloads import paper_head_tail
 
-    n, ell = 10_000, 50
-    points = [(1000, z) for z in (5, 10, 20, 50, 100, 200, 500)] + [(d, 100) for d in (2000, 4000, 6000)]
+    defaults = {"n": 10_000, "d": 1000, "z": 100, "ell": 50}
+    sweeps = {"z": (5, 10, 20, 50, 100, 200, 500), "d": (1000, 2000, 4000, 6000),
+              "n": (10_000, 20_000, 40_000, 60_000), "ell": (5, 10, 20, 50, 100)}
     algos = (("sfd", {}), ("sfd_noverify", {"verify": 0}), ("fd", {"algorithm": "fd"}))
     rows = []
-    for d, z in points:
-        st = paper_head_tail(n=n, d=d, z=z)
-        A = st.to_scipy()
-        ptr = torch.from_numpy(st.indptr).cuda()
-        idx = torch.from_numpy(st.indices).cuda()
-        val = torch.from_numpy(st.values).cuda()
-        out = torch.empty((ell, d), dtype=torch.float32, device="cuda")
-        rec = {"d": d, "z": z, "nnz": st.nnz}
-        for name, opts in algos:
-            sk = sfd.Sketch(d, ell, 0.25, 0, **opts)
+    for param, values in sweeps.items():
+        for v in values:
+            p = dict(defaults, **{param: v})
+            n, d, z, ell = p["n"], p["d"], p["z"], p["ell"]
+            st = paper_head_tail(n=n, d=d, z=z)
+            ptr = torch.from_numpy(st.indptr).cuda()
+            idx = torch.from_numpy(st.indices).cuda()
+            val = torch.from_numpy(st.values).cuda()
+            out = torch.empty((ell, d), dtype=torch.float32, device="cuda")
+            rec = {"sweep": param, "n": n, "d": d, "z": z, "ell": ell, "nnz": st.nnz}
+            for name, opts in algos:
+                sk = sfd.Sketch(d, ell, 0.25, 0, **opts)
 
-            def step():
-                sk.reset()
-                sk.append_csr(ptr, idx, val)
-                sk.sketch(out=out)
+                def step():
+                    sk.reset()
+                    sk.append_csr(ptr, idx, val)
+                    sk.sketch(out=out)
 
-            for _ in range(args.warmup):
-                step()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(args.steps):
-                step()
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t) / args.steps
-            rec[name] = {"ms": ms, "cov_err": evaluate.cov_err(A, out.cpu().numpy().astype(np.float64)),
-                         "buffers": sk.stats()["flushes"]}
-            sk.close()
-        rec["fd_over_sfd_time"] = rec["fd"]["ms"] / rec["sfd_noverify"]["ms"]
-        rows.append(rec)
-        log(f"d={d} z={z}: sfd {rec['sfd']['ms']:.1f} ms, sfd w/o verify {rec['sfd_noverify']['ms']:.1f} ms, "
-            f"fd {rec['fd']['ms']:.1f} ms; cov-err {rec['sfd']['cov_err']:.4f} / {rec['sfd_noverify']['cov_err']:.4f} "
-            f"/ {rec['fd']['cov_err']:.4f}")
-    print(json.dumps({"workload": f"paper head/tail generator, n={n}, ell={ell}, eps=1/4", "steps": args.steps,
-                      "warmup": args.warmup, "points": rows}), flush=True)
+                for _ in range(args.warmup):
+                    step()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.steps):
+                    step()
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t) / args.steps
+                ev = sfd.evaluate(ptr, idx, val, d, out, k=min(10, ell), steps=min(d, 300))
+                rec[name] = {"ms": ms, "cov_err": ev["cov_err"], "proj_err": ev["proj_err"],
+                             "buffers": sk.stats()["flushes"]}
+                sk.close()
+            rec["fd_over_sfd_time"] = rec["fd"]["ms"] / rec["sfd_noverify"]["ms"]
+            rows.append(rec)
+            log(f"{param} sweep n={n} d={d} z={z} ell={ell}: sfd {rec['sfd']['ms']:.1f} ms, sfd w/o verify "
+                f"{rec['sfd_noverify']['ms']:.1f} ms, fd {rec['fd']['ms']:.1f} ms; cov-err "
+                f"{rec['sfd']['cov_err']:.4f} / {rec['sfd_noverify']['cov_err']:.4f} / {rec['fd']['cov_err']:.4f}")
+    print(json.dumps({"workload": "paper head/tail generator (Sec. 4), Table 1 sweeps, eps=1/4",
+                      "defaults": defaults, "steps": args.steps, "warmup": args.warmup, "points": rows}), flush=True)
     return 0
 
 
