@@ -78,12 +78,17 @@ enum {
                                and panels: about 28 (ell d + d) + 20 d L bytes, L the panel
                                width 32/64/128/256, e.g. 0.35 GB at d = 1e5, ell = 50) when first
                                asked for, after the work in flight.  Results do not depend on it. */
-  SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: panels of the
-                               SimultaneousIteration (Alg 1) stored in BF16 with FP32 accumulation;
-                               the last product P^T = A'^T Y (Alg 3) reads the stored BF16 Y,
-                               takes its transform from that Y's own Gram and writes FP32, so
-                               B'^T B' <= A'^T A' (Property 1) still holds for the FP32 values.
-                               Only the subspace quality changes (cov-err, Sec. 4). */
+  SFD_OPT_PRECISION = 9,    /* SFD_PRECISION_FP32 (default) or SFD_PRECISION_BF16: the products
+                               1 .. 2q+1 of SimultaneousIteration (Alg 1) read BF16 copies of the
+                               buffer's values and BF16 panels and write BF16 panels (FP32
+                               accumulation), and the panel transforms and Grams of its
+                               CholeskyQR run on BF16 MFMA (FP32 accumulation; the Cholesky
+                               stays FP64).  The last product P^T = A'^T Y (Alg 3) reads the
+                               FP32 values and the stored BF16 Y, takes its transform from that
+                               Y's own Gram and writes FP32, so B'^T B' <= A'^T A' (Property 1)
+                               still holds for the FP32 values.  Only the subspace quality
+                               changes (cov-err, Sec. 4).  A batch handle runs such buffers on
+                               its lanes rather than in lockstep groups. */
   SFD_OPT_ALGORITHM = 10,   /* SFD_ALGO_SFD (default): Alg 2's flush rule (rows(A') = d or
                                nnz(A') >= ell*d) and BoostedSparseShrink; SFD_ALGO_FD: the
                                paper's comparator FrequentDirections (Sec. 2.1) in batches of
@@ -101,9 +106,17 @@ enum {
                                       buffer whose dominant direction is e_j gets a SparseShrink
                                       that VerifySpectral (Alg 6) rejects: this runs the retry
                                       loop of BoostedSparseShrink (Alg 4) on purpose. */
-  SFD_OPT_TEST_ZERO_ATTEMPTS = 13  /* attempts a < value that SFD_OPT_TEST_ZERO_ROW applies to,
+  SFD_OPT_TEST_ZERO_ATTEMPTS = 13, /* attempts a < value that SFD_OPT_TEST_ZERO_ROW applies to,
                                       >= 0; default 1 (the first attempt of each buffer). */
+  SFD_OPT_CQR2 = 14                /* precision form only: CholeskyQR2 -- a second panel transform,
+                                      Gram and Cholesky after the first, so a panel stored in BF16
+                                      is orthonormal to BF16 precision rather than to that times
+                                      its condition number.  SFD_CQR2_OFF, SFD_CQR2_FINAL
+                                      (default: the final basis Y of Alg 1, whose span defines
+                                      B'), SFD_CQR2_ALL (every product's panel). */
 };
+
+enum { SFD_CQR2_OFF = 0, SFD_CQR2_FINAL = 1, SFD_CQR2_ALL = 2 };
 
 /* Kernel classes of the per-phase profile (sfd_get_profile). */
 enum {

@@ -34,6 +34,7 @@ SOURCES = [
     "sfd_ingest.hip",
     "sfd_spmm.hip",
     "sfd_dense.hip",
+    "sfd_bf16.hip",
     "sfd_small.hip",
     "sfd_eig_tri.hip",
     "sfd_vs.hip",

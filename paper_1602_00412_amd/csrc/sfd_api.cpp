@@ -77,6 +77,7 @@ struct Lane {
   // panels and small work
   float *X = nullptr, *Y = nullptr, *Pt = nullptr;
   uint16_t *Xb = nullptr, *Yb = nullptr;  // BF16 panels of the precision form
+  uint16_t *valb = nullptr, *cscvalb = nullptr;  // BF16 copies of the buffer's CSR / CSC values
   float* gram_part = nullptr;
   double *W = nullptr, *W2 = nullptr;
   double *evals = nullptr, *evecs = nullptr, *SS = nullptr, *M64 = nullptr;
@@ -145,6 +146,7 @@ struct sfd_s {
   int lanes_alloc = kLanesSingle;  // lanes with workspaces
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
+  int cqr2 = SFD_CQR2_FINAL;           // SFD_OPT_CQR2 (precision form)
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
   int test_zero_row = -1;              // SFD_OPT_TEST_ZERO_ROW
   int test_zero_attempts = 1;          // SFD_OPT_TEST_ZERO_ATTEMPTS
@@ -355,6 +357,7 @@ int alloc_lane(sfd_t* h, Lane& ln) {
   ln.scs.transposed = true;
   ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
   ok = ok && dalloc(h, &ln.Xb, d * L) && dalloc(h, &ln.Yb, d * L);
+  ok = ok && dalloc(h, &ln.valb, cap) && dalloc(h, &ln.cscvalb, cap);
   ok = ok && dalloc(h, &ln.gram_part, (int64_t)gram_max_blocks() * 4 * L * L) && dalloc(h, &ln.W, L * L) &&
        dalloc(h, &ln.W2, 4 * L * L);
   ok = ok && dalloc(h, &ln.evals, 2 * L) && dalloc(h, &ln.evecs, 4 * L * L) && dalloc(h, &ln.SS, 4 * L * L);
@@ -434,11 +437,11 @@ int vs_steps(const sfd_t* h, int64_t i) {
 
 // algorithmic bytes of one sparse product over the buffer: the stored entries (id + value)
 // and row pointers once, the input panel read once, the output panel written once (bx, by:
-// bytes per panel element)
-double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed, double bx, double by) {
+// bytes per panel element; bv: bytes per stored value)
+double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed, double bx, double by, double bv) {
   const double N = ln.nnz, m = ln.m, d = (double)h->d, ell = h->ell;
   const double in_rows = transposed ? m : d, out_rows = transposed ? d : m;
-  return 8.0 * N + 4.0 * (out_rows + 1) + ell * (bx * in_rows + by * out_rows);
+  return (4.0 + bv) * N + 4.0 * (out_rows + 1) + ell * (bx * in_rows + by * out_rows);
 }
 
 inline double pbytes(PanelType t) { return t == PanelType::BF16 ? 2.0 : 4.0; }
@@ -461,24 +464,26 @@ int orth_out(sfd_t* h, Lane& ln, void* panel, PanelType pt, int64_t rows) {
   return SFD_OK;
 }
 
-// Y = A' X (the input's transform is applied to Y by orth_out)
-int spmm_csr(sfd_t* h, Lane& ln, const void* X, PanelType xt, void* Y, PanelType yt) {
+// Y = A' X (the input's transform is applied to Y by orth_out); vb: BF16 values
+int spmm_csr(sfd_t* h, Lane& ln, const void* X, PanelType xt, void* Y, PanelType yt, bool vb = false) {
   {
-    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false, pbytes(xt), pbytes(yt)),
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false, pbytes(xt), pbytes(yt), vb ? 2.0 : 4.0),
                  2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 1);
-    CK(spmm(ln.sr, ln.colidx, ln.val, X, xt, h->L, Y, yt, h->L, h->L, ln.partial, ln.st));
+    CK(spmm(ln.sr, ln.colidx, vb ? static_cast<const void*>(ln.valb) : static_cast<const void*>(ln.val), vb, X, xt,
+            h->L, Y, yt, h->L, h->L, ln.partial, ln.st));
   }
   ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
   CK(spmm_finish(ln.sr, ln.partial, Y, yt, h->L, h->L, ln.st));
   return SFD_OK;
 }
 
-// X = A'^T Y
-int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType xt) {
+// X = A'^T Y; vb: BF16 values
+int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType xt, bool vb = false) {
   {
-    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true, pbytes(yt), pbytes(xt)),
+    ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true, pbytes(yt), pbytes(xt), vb ? 2.0 : 4.0),
                  2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 1);
-    CK(spmm(ln.scs, ln.cscrow, ln.cscval, Y, yt, h->L, X, xt, h->L, h->L, ln.partial, ln.st));
+    CK(spmm(ln.scs, ln.cscrow, vb ? static_cast<const void*>(ln.cscvalb) : static_cast<const void*>(ln.cscval), vb,
+            Y, yt, h->L, X, xt, h->L, h->L, ln.partial, ln.st));
   }
   ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
   CK(spmm_finish(ln.scs, ln.partial, X, xt, h->L, h->L, ln.st));
@@ -508,6 +513,11 @@ int prepare(sfd_t* h, Lane& ln) {
   }
   if (ln.m > h->ell) {
     ProfScope ps(h, ln.st, SFD_PROF_OTHER, 0.0, 0.0, 2);
+    if (h->precision == SFD_PRECISION_BF16) {
+      // the precision form's products 1 .. 2q+1 read BF16 copies of the values
+      CK(to_bf16(ln.val, ln.nnz, ln.valb, ln.st));
+      CK(to_bf16(ln.cscval, ln.nnz, ln.cscvalb, ln.st));
+    }
     ln.sr.max_chunks = (int64_t)ln.m + (int64_t)ln.nnz / kSpmmChunk + 2;
     CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
     if (csc_hot(h, ln.m, ln.nnz)) {
@@ -540,25 +550,33 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
       CK(fill_f32(ln.X + (int64_t)h->test_zero_row * L, L, 0.f, ln.st));
   }
   // panels of the iteration: FP32, or BF16 in the precision form, where the products 1 .. 2q+1
-  // read and write BF16 panels (FP32 accumulation) and the last one, P^T = A'^T Y T_y, reads
-  // the stored BF16 Y with T_y from that Y's own Gram and writes FP32: P P^T is then the
-  // compression of A'^T A' onto span(Y), so B'^T B' <= A'^T A' still holds for the FP32 values
+  // read BF16 values and BF16 panels and write BF16 panels (FP32 accumulation; transforms and
+  // Grams on BF16 MFMA), and the last one, P^T = A'^T Y T_y, reads the FP32 values and the stored
+  // BF16 Y with T_y from that Y's own Gram and writes FP32: P P^T is then the compression of
+  // A'^T A' onto span(Y), so B'^T B' <= A'^T A' still holds for the FP32 values.  CholeskyQR2
+  // (SFD_OPT_CQR2): a second transform + Gram + Cholesky of a stored panel, so the panel kept in
+  // BF16 is orthonormal to BF16 precision, not only to that times its condition number
   const bool bf = h->precision == SFD_PRECISION_BF16;
   const PanelType pt = bf ? PanelType::BF16 : PanelType::F32;
   void* X = bf ? static_cast<void*>(ln.Xb) : static_cast<void*>(ln.X);
   void* Y = bf ? static_cast<void*>(ln.Yb) : static_cast<void*>(ln.Y);
+  const bool cqr2_all = bf && h->cqr2 == SFD_CQR2_ALL;
+  const bool cqr2_final = bf && h->cqr2 != SFD_CQR2_OFF;
   if (bf) CK(to_bf16(ln.X, d * L, ln.Xb, ln.st));
   // the first transform from the Gram of G itself (G T = G with T = I)
   CK(set_identity(ln.T, L, 1, ln.st));
   if ((rc = orth_out(h, ln, X, pt, d))) return rc;
   for (int it = 0; it < ln.q; ++it) {
-    if ((rc = spmm_csr(h, ln, X, pt, Y, pt))) return rc;
+    if ((rc = spmm_csr(h, ln, X, pt, Y, pt, bf))) return rc;
     if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
-    if ((rc = spmm_csc(h, ln, Y, pt, X, pt))) return rc;
+    if (cqr2_all && (rc = orth_out(h, ln, Y, pt, m))) return rc;
+    if ((rc = spmm_csc(h, ln, Y, pt, X, pt, bf))) return rc;
     if ((rc = orth_out(h, ln, X, pt, d))) return rc;
+    if (cqr2_all && (rc = orth_out(h, ln, X, pt, d))) return rc;
   }
-  if ((rc = spmm_csr(h, ln, X, pt, Y, pt))) return rc;
+  if ((rc = spmm_csr(h, ln, X, pt, Y, pt, bf))) return rc;
   if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
+  if (cqr2_final && (rc = orth_out(h, ln, Y, pt, m))) return rc;
   if ((rc = spmm_csc(h, ln, Y, pt, ln.Pt, PanelType::F32))) return rc;
   {
     // P^T <- P^T T_y and W = P P^T
@@ -906,11 +924,11 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
   CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
   CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
   for (int iter = 0; iter <= qmax; ++iter) {
-    CK(spmm(g.sr, g.colidx, g.val, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, st));
+    CK(spmm(g.sr, g.colidx, g.val, false, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, st));
     CK(spmm_finish(g.sr, g.partial, g.Y, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.Y, PanelType::F32, L, 0, 0, nby, g.segs_y, K, L, g.T, g.gram_part, g.W, st));
     CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
-    CK(spmm(g.scs, g.cscrow, g.cscval, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, st));
+    CK(spmm(g.scs, g.cscrow, g.cscval, false, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, st));
     CK(spmm_finish(g.scs, g.partial, g.X, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
     // buffers at their final product: P^T = A'^T Y T_y and W = P P^T
@@ -1025,7 +1043,9 @@ int run_batched(sfd_t* h, const std::vector<BufferView>& views) {
     std::vector<BufferView> small;
     std::vector<GroupItem> items;
     for (auto& e : round) {
-      if (e.first.m <= h->ell || h->grp.kmax == 0 || csc_hot(h, e.first.m, e.first.nnz)) {
+      // lockstep groups run FP32 panels; the precision form's buffers take the lanes
+      if (e.first.m <= h->ell || h->grp.kmax == 0 || h->precision == SFD_PRECISION_BF16 ||
+          csc_hot(h, e.first.m, e.first.nnz)) {
         small.push_back(e.first);
         continue;
       }
@@ -1477,6 +1497,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_PRECISION:
       if (value != SFD_PRECISION_FP32 && value != SFD_PRECISION_BF16) return SFD_E_ARG;
       h->precision = (int)value;
+      return SFD_OK;
+    case SFD_OPT_CQR2:
+      if (value != SFD_CQR2_OFF && value != SFD_CQR2_FINAL && value != SFD_CQR2_ALL) return SFD_E_ARG;
+      h->cqr2 = (int)value;
       return SFD_OK;
     case SFD_OPT_LANES: {
       if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;

@@ -48,20 +48,9 @@ struct UpperTiles {
 template <int S>
 constexpr UpperTiles<S> kUpper{};
 
-// element e of a panel row stored as FP32 or as BF16 (the upper half of an FP32)
-template <bool BF>
-__device__ inline float panel_elem(const void* row, int e) {
-  if constexpr (BF)
-    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(row)[e] << 16);
-  else
-    return reinterpret_cast<const float*>(row)[e];
-}
-
 // TWO: the panel is [P | P2] side by side, each W/2 wide (strips of the right half from P2).
-// BF: P is a BF16 panel (products of BF16 values are exact in FP32, so its Gram is the exact
-// Gram of the stored values up to FP32 accumulation).
-template <int W, bool TWO, bool BF>
-__global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __restrict__ P, int ld,
+template <int W, bool TWO>
+__global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __restrict__ P, int ld,
                                                                const float* __restrict__ P2, int ld2, int64_t rows,
                                                                int rpb, float* __restrict__ partials) {
   constexpr int S = W / 16;            // strips
@@ -85,10 +74,10 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __res
   do {                                                                                              \
     const int64_t row_ = (k) + lrow;                                                                \
     const bool ok_ = row_ < r1;                                                                     \
-    const char* pr_ = reinterpret_cast<const char*>(P) + (size_t)(ok_ ? row_ : 0) * ld * (BF ? 2 : 4); \
+    const float* pr_ = P + (ok_ ? row_ : 0) * ld;                                                    \
     const float* pr2_ = P2 + (ok_ ? row_ : 0) * ld2 + lcol;                                         \
     _Pragma("unroll") for (int s = 0; s < S; ++s) f[dd][s] =                                        \
-        ok_ ? (s < SPLIT ? panel_elem<BF>(pr_, 16 * s + lcol) : pr2_[16 * (s - SPLIT)]) : 0.f;      \
+        ok_ ? (s < SPLIT ? pr_[16 * s + lcol] : pr2_[16 * (s - SPLIT)]) : 0.f;                      \
   } while (0)
   int64_t k0 = r0 + 4 * kg;
 #pragma unroll
@@ -126,9 +115,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __res
   }
 }
 
-// P <- P T in place (rows x L panel, FP32 or BF16 elements, pitch ld; T: L x L FP32) and the
-// per-block partial Gram of the result as stored (BF16-rounded in the BF16 form), for
-// k_gram_reduce.  This applies the inverse Cholesky factor of a product's input panel to the
+// P <- P T in place (rows x L FP32 panel, pitch ld; T: L x L FP32) and the per-block partial
+// Gram of the result, for k_gram_reduce (BF16 panels: sfd_bf16.hip).  This applies the inverse Cholesky factor of a product's input panel to the
 // product's output (A'(X T) = (A' X) T), so the sparse products need no per-row epilogue.
 // Both the transform and the Gram run on MFMA (v_mfma_f32_16x16x4f32), 16 rows at a time per
 // wave (wave w of a block: tiles w, w + 8, ...):
@@ -144,15 +132,15 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const void* __res
 // Groups (segs != nullptr): buffer k = blockIdx.y owns rows [segs[k].row0, + segs[k].rows) of P
 // with its own T (T + k L L) and partials (partials + k pstride), and the block geometry a
 // single-buffer launch over that many rows has (segs[k].rpb, .nb), so its result is the same.
-template <int L, bool BF>
-__global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ P, int ld, int64_t rows, int rpb,
+template <int L>
+__global__ __launch_bounds__(kGramThreads) void k_xform_gram(float* __restrict__ P, int ld, int64_t rows, int rpb,
                                                              const float* __restrict__ T,
                                                              float* __restrict__ partials, const GroupSeg* segs,
                                                              int64_t pstride) {
   if (segs) {
     const GroupSeg g = segs[blockIdx.y];
     if ((int)blockIdx.x >= g.nb) return;
-    P = reinterpret_cast<char*>(P) + (size_t)g.row0 * ld * (BF ? 2 : 4);
+    P += (size_t)g.row0 * ld;
     rows = g.rows;
     rpb = g.rpb;
     T += (int64_t)blockIdx.y * L * L;
@@ -164,7 +152,7 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   constexpr int NU = S * (S + 1) / 2;  // upper tiles of the Gram
   constexpr int NW = kGramWaves;
   constexpr int LP = L + 4;            // LDS row pitch (floats)
-  constexpr int EPL = BF ? 8 : 4;      // elements per lane per load (16 bytes)
+  constexpr int EPL = 4;               // elements per lane per load (16 bytes)
   constexpr int LPRW = L / EPL;        // lanes per row in a load pass
   constexpr int RPP = 64 / LPRW;       // rows per load pass
   constexpr int NP = 16 / RPP;         // load passes per 16-row tile
@@ -184,17 +172,17 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = min(rows, r0 + rpb);
   char* base = reinterpret_cast<char*>(P);
-  const size_t pitch = (size_t)ld * (BF ? 2 : 4);
+  const size_t pitch = (size_t)ld * 4;
   const int prow = lane / LPRW, pcol = (lane % LPRW) * EPL;  // this lane's part of a load pass
   float* my = tile[wave];
-  using raw = typename std::conditional<BF, uint4, float4>::type;
+  using raw = float4;
   raw nxt[NP];
   auto load_tile = [&](int64_t t0) {
 #pragma unroll
     for (int ip = 0; ip < NP; ++ip) {
       const int64_t row = t0 + ip * RPP + prow;
       if (row < r1)
-        nxt[ip] = *reinterpret_cast<const raw*>(base + row * pitch + (size_t)pcol * (BF ? 2 : 4));
+        nxt[ip] = *reinterpret_cast<const raw*>(base + row * pitch + (size_t)pcol * 4);
       else
         nxt[ip] = raw{0, 0, 0, 0};
     }
@@ -202,20 +190,9 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   int64_t t0 = r0 + 16 * wave;
   load_tile(t0);
   for (; t0 < r1; t0 += 16 * NW) {
-    // stage the tile (as FP32) and start loading the next one
+    // stage the tile and start loading the next one
 #pragma unroll
-    for (int ip = 0; ip < NP; ++ip) {
-      float* dst = my + (ip * RPP + prow) * LP + pcol;
-      if constexpr (BF) {
-        const uint4 w = nxt[ip];
-        reinterpret_cast<float4*>(dst)[0] = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
-                                                        __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
-        reinterpret_cast<float4*>(dst)[1] = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xFFFF0000u),
-                                                        __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xFFFF0000u));
-      } else {
-        reinterpret_cast<float4*>(dst)[0] = nxt[ip];
-      }
-    }
+    for (int ip = 0; ip < NP; ++ip) reinterpret_cast<float4*>(my + (ip * RPP + prow) * LP + pcol)[0] = nxt[ip];
     load_tile(t0 + 16 * NW);
     __builtin_amdgcn_wave_barrier();
     // out = tile * T
@@ -230,22 +207,14 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
       for (int n = 0; n < S; ++n)
         if (ks < 4 * (n + 1)) o[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tb[ks][n], o[n], 0, 0, 0);
     }
-    // round to the stored precision, store, and add the stored values' Gram
+    // store, and add the stored values' Gram
 #pragma unroll
     for (int n = 0; n < S; ++n) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = t0 + 4 * lk + v;
-        float x = o[n][v];
-        if constexpr (BF) {
-          uint32_t u = __float_as_uint(x);
-          u += 0x7FFFu + ((u >> 16) & 1u);
-          u &= 0xFFFF0000u;
-          x = __uint_as_float(u);
-          if (row < r1) reinterpret_cast<uint16_t*>(base + row * pitch)[16 * n + lm] = (uint16_t)(u >> 16);
-        } else {
-          if (row < r1) reinterpret_cast<float*>(base + row * pitch)[16 * n + lm] = x;
-        }
+        const float x = o[n][v];
+        if (row < r1) reinterpret_cast<float*>(base + row * pitch)[16 * n + lm] = x;
         o[n][v] = row < r1 ? x : 0.f;
       }
     }
@@ -277,8 +246,8 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
   }
 }
 
-// Wide panels (L = 128 or 256): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), FP32 or BF16 panels,
-// and with ACC out <- out + Pin T (FP32 only; used for [P1 | P2] T2 as two passes).  Wave w of a
+// Wide FP32 panels (L = 128 or 256): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), and with
+// ACC out <- out + Pin T (used for [P1 | P2] T2 as two passes).  Wave w of a
 // block computes output strip w (columns 16 w .. 16 w + 15) and keeps its strip of T as MFMA B
 // operands in registers (lane l: T[4 ks + l / 16][16 w + l % 16]); the 16-row input tile is loaded
 // by the whole block (16 bytes per thread), staged in LDS as FP32 (pitch L + 4, two buffers, so
@@ -286,21 +255,20 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(void* __restrict__ 
 // any of it is written, so out may be Pin.  UPPER: T is upper triangular (an inverse Cholesky
 // factor), so strip w needs the k-steps ks < 4 (w + 1) only.
 // Groups: buffer k = blockIdx.z owns rows [segs[k].row0, + segs[k].rows) with T + k L L.
-template <int L, bool BF, bool ACC, bool UPPER>
-__global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi, void* out, int ldo, int64_t rows,
+template <int L, bool ACC, bool UPPER>
+__global__ __launch_bounds__(L * 4) void k_xform_strips(const float* Pin, int ldi, float* out, int ldo, int64_t rows,
                                                         int rpb, const float* __restrict__ T, int ldt,
                                                         const GroupSeg* segs) {
   static_assert(L == 128 || L == 256, "strip-per-wave transform");
-  static_assert(!(BF && ACC), "accumulation is FP32 only");
   constexpr int NT = L * 4;  // threads: one wave per 16-column strip
   constexpr int KS = L / 4;
   constexpr int LP = L + 4;
-  constexpr int EB = BF ? 2 : 4;  // bytes per element
+  constexpr int EB = 4;  // bytes per element
   if (segs) {
     const GroupSeg g = segs[blockIdx.z];
     if ((int)blockIdx.x >= g.nb) return;
-    Pin = reinterpret_cast<const char*>(Pin) + (size_t)g.row0 * ldi * EB;
-    out = reinterpret_cast<char*>(out) + (size_t)g.row0 * ldo * EB;
+    Pin += (size_t)g.row0 * ldi;
+    out += (size_t)g.row0 * ldo;
     rows = g.rows;
     rpb = g.rpb;
     T += (int64_t)blockIdx.z * L * L;
@@ -320,7 +288,7 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi
   const size_t ipitch = (size_t)ldi * EB, opitch = (size_t)ldo * EB;
   // this thread's 4 elements of a tile: row tid / (L / 4), columns 4 (tid % (L / 4)) .. + 3
   const int trow = tid / (L / 4), tcol = 4 * (tid % (L / 4));
-  using raw = typename std::conditional<BF, uint2, float4>::type;
+  using raw = float4;
   auto load = [&](int64_t t0) -> raw {
     const int64_t row = t0 + trow;
     if (row < r1) return *reinterpret_cast<const raw*>(src + row * ipitch + (size_t)tcol * EB);
@@ -329,13 +297,7 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi
   raw nxt = load(r0);
   int buf = 0;
   for (int64_t t0 = r0; t0 < r1; t0 += 16, buf ^= 1) {
-    float* my = tile[buf] + trow * LP + tcol;
-    if constexpr (BF) {
-      reinterpret_cast<float4*>(my)[0] = make_float4(__uint_as_float(nxt.x << 16), __uint_as_float(nxt.x & 0xFFFF0000u),
-                                                     __uint_as_float(nxt.y << 16), __uint_as_float(nxt.y & 0xFFFF0000u));
-    } else {
-      reinterpret_cast<float4*>(my)[0] = nxt;
-    }
+    reinterpret_cast<float4*>(tile[buf] + trow * LP + tcol)[0] = nxt;
     __syncthreads();
     nxt = load(t0 + 16);
     floatx4 o = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -353,15 +315,7 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = t0 + 4 * lk + v;
-      if (row < r1) {
-        if constexpr (BF) {
-          uint32_t u = __float_as_uint(o[v]);
-          u += 0x7FFFu + ((u >> 16) & 1u);
-          reinterpret_cast<uint16_t*>(dst + row * opitch)[16 * w + lm] = (uint16_t)(u >> 16);
-        } else {
-          reinterpret_cast<float*>(dst + row * opitch)[16 * w + lm] = o[v];
-        }
-      }
+      if (row < r1) reinterpret_cast<float*>(dst + row * opitch)[16 * w + lm] = o[v];
     }
   }
 }
@@ -371,16 +325,14 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const void* Pin, int ldi
 // SPLIT = W1 / 64 come from P, the rest from P2) over row block x, for buffer z of a group.
 // Four waves split the rows in 4-row slabs (MFMA operands as in k_gram_partial); their sums are
 // added in wave order and the tile is written at its place in the block's W x W partial.
-template <bool BF>
-__global__ __launch_bounds__(256) void k_gram_tiles(const void* __restrict__ P, int ld, const float* __restrict__ P2,
+__global__ __launch_bounds__(256) void k_gram_tiles(const float* __restrict__ P, int ld, const float* __restrict__ P2,
                                                     int ld2, int W1, int W, int64_t rows, int rpb,
                                                     float* __restrict__ partials, const GroupSeg* segs,
                                                     int64_t pstride) {
-  constexpr int EB = BF ? 2 : 4;
   if (segs) {
     const GroupSeg g = segs[blockIdx.z];
     if ((int)blockIdx.x >= g.nb) return;
-    P = reinterpret_cast<const char*>(P) + (size_t)g.row0 * ld * EB;
+    P += (size_t)g.row0 * ld;
     rows = g.rows;
     rpb = g.rpb;
     partials += (int64_t)blockIdx.z * pstride;
@@ -400,17 +352,10 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const void* __restrict__ P, 
   const int64_t r1 = min(rows, r0 + rpb);
   const int split = W1 / 64;
   // the two slices' column bases and sources
-  const char* baseI = I < split ? reinterpret_cast<const char*>(P) + (size_t)(64 * I) * EB
-                                : reinterpret_cast<const char*>(P2 + 64 * (I - split));
-  const char* baseJ = J < split ? reinterpret_cast<const char*>(P) + (size_t)(64 * J) * EB
-                                : reinterpret_cast<const char*>(P2 + 64 * (J - split));
-  const bool bfI = BF && I < split, bfJ = BF && J < split;
-  const size_t pitchI = I < split ? (size_t)ld * EB : (size_t)ld2 * 4;
-  const size_t pitchJ = J < split ? (size_t)ld * EB : (size_t)ld2 * 4;
-  auto elem = [](const char* rowp, bool bf, int c) -> float {
-    if (bf) return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(rowp)[c] << 16);
-    return reinterpret_cast<const float*>(rowp)[c];
-  };
+  const float* baseI = I < split ? P + 64 * I : P2 + 64 * (I - split);
+  const float* baseJ = J < split ? P + 64 * J : P2 + 64 * (J - split);
+  const int64_t pitchI = I < split ? ld : ld2;
+  const int64_t pitchJ = J < split ? ld : ld2;
   floatx4 acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -422,8 +367,8 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const void* __restrict__ P, 
     const int64_t rr = ok ? row : 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      fi[dd][s] = ok ? elem(baseI + rr * pitchI, bfI, 16 * s + lcol) : 0.f;
-      fj[dd][s] = ok ? elem(baseJ + rr * pitchJ, bfJ, 16 * s + lcol) : 0.f;
+      fi[dd][s] = ok ? baseI[rr * pitchI + 16 * s + lcol] : 0.f;
+      fj[dd][s] = ok ? baseJ[rr * pitchJ + 16 * s + lcol] : 0.f;
     }
   };
   const int64_t step = 16;  // four waves x 4 rows
@@ -686,36 +631,26 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
   const bool bf = pt == PanelType::BF16;
   const int64_t ps = gram_partial_stride(L);
   const dim3 grid((unsigned)nb, (unsigned)K);
-  if (L == 32) {
-    if (bf)
-      k_xform_gram<32, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
-    else
-      k_xform_gram<32, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
+  if (bf) {
+    // BF16 panels: transform and Gram on BF16 MFMA (sfd_bf16.hip)
+    hipError_t e = xform_gram_bf16_partials(static_cast<uint16_t*>(P), ld, rows, rpb, nb, segs, K, L, T, partials, ps,
+                                            true, st);
+    if (e != hipSuccess) return e;
+  } else if (L == 32) {
+    k_xform_gram<32><<<grid, kGramThreads, 0, st>>>(static_cast<float*>(P), ld, rows, rpb, T, partials, segs, ps);
   } else if (L == 64) {
-    if (bf)
-      k_xform_gram<64, true><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
-    else
-      k_xform_gram<64, false><<<grid, kGramThreads, 0, st>>>(P, ld, rows, rpb, T, partials, segs, ps);
+    k_xform_gram<64><<<grid, kGramThreads, 0, st>>>(static_cast<float*>(P), ld, rows, rpb, T, partials, segs, ps);
   } else if (L == 128 || L == 256) {
     // transform in place, then the Gram of the stored result by 64 x 64 tiles
+    float* Pf = static_cast<float*>(P);
     const dim3 gx((unsigned)nb, 1, (unsigned)K);
     const int ns = L / 64;
     const dim3 gg((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), (unsigned)K);
-    if (L == 128) {
-      if (bf)
-        k_xform_strips<128, true, false, true><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-      else
-        k_xform_strips<128, false, false, true><<<gx, 512, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-    } else {
-      if (bf)
-        k_xform_strips<256, true, false, true><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-      else
-        k_xform_strips<256, false, false, true><<<gx, 1024, 0, st>>>(P, ld, P, ld, rows, rpb, T, L, segs);
-    }
-    if (bf)
-      k_gram_tiles<true><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+    if (L == 128)
+      k_xform_strips<128, false, true><<<gx, 512, 0, st>>>(Pf, ld, Pf, ld, rows, rpb, T, L, segs);
     else
-      k_gram_tiles<false><<<gg, 256, 0, st>>>(P, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
+      k_xform_strips<256, false, true><<<gx, 1024, 0, st>>>(Pf, ld, Pf, ld, rows, rpb, T, L, segs);
+    k_gram_tiles<<<gg, 256, 0, st>>>(Pf, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
   } else {
     return hipErrorInvalidValue;
   }
@@ -730,16 +665,16 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
   gram_grid(rows, nb, rpb);
   switch (L) {
     case 32:
-      k_gram_partial<64, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
+      k_gram_partial<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
       break;
     case 64:
-      k_gram_partial<128, true, false><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
+      k_gram_partial<128, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
       break;
     case 128:
     case 256: {
       // [P1 | P2] is 2L wide: 2L / 64 slices and their upper tile pairs
       const int ns = 2 * L / 64;
-      k_gram_tiles<false><<<dim3((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), 1), 256, 0, st>>>(
+      k_gram_tiles<<<dim3((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), 1), 256, 0, st>>>(
           P1, ld1, P2, ld2, L, 2 * L, rows, rpb, partials, nullptr, 0);
       break;
     }
@@ -765,12 +700,12 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
     rpb = (rpb + 15) & ~15;
     nb = (rows + rpb - 1) / rpb;
     if (L == 128) {
-      k_xform_strips<128, false, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<128, false, true, false><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+      k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<128, true, false><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
                                                                      nullptr);
     } else {
-      k_xform_strips<256, false, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<256, false, true, false><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
+      k_xform_strips<256, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
+      k_xform_strips<256, true, false><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
                                                                       nullptr);
     }
   } else {

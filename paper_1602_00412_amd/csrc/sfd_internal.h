@@ -124,10 +124,11 @@ hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const
                               int hot_min, Schedule& s, int* scan_tmp, hipStream_t st);
 // Y[r, :] = sum_k val[k] X[idx[k], :] over the structure of schedule s (its entries idx, val);
 // rows of width L (32, 64, 128 or 256) with pitches ldx / ldy in elements; FP32 accumulation.
-// Panel types: F32 -> F32, BF16 -> BF16 and BF16 -> F32.  This launches the main kernel only;
-// spmm_finish completes the product.
-hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
-                PanelType yt, int ldy, int L, float* partial, hipStream_t st);
+// (values, panel in -> panel out): (FP32, F32 -> F32), (BF16, BF16 -> BF16), (FP32, BF16 -> F32);
+// val_bf16: val holds BF16 values (uint16).  This launches the main kernel only; spmm_finish
+// completes the product.
+hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf16, const void* X, PanelType xt, int ldx,
+                void* Y, PanelType yt, int ldy, int L, float* partial, hipStream_t st);
 // the long rows' fix-up of a product
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1); for a group's stacked
@@ -151,6 +152,11 @@ hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const 
 hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,
                             int L, const float* T, float* partials, double* W, hipStream_t st);
 void gram_geometry(int64_t rows, int* nb, int* rpb);
+// BF16 panels (sfd_bf16.hip): P <- P T on BF16 MFMA (T split into two BF16 parts when split) and
+// the per-block partial Grams of the stored result (upper tiles, FP32), for the Gram reduction
+hipError_t xform_gram_bf16_partials(uint16_t* P, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,
+                                    int L, const float* T, float* partials, int64_t pstride, bool split,
+                                    hipStream_t st);
 int64_t gram_partial_stride(int L);
 // Gram of the side-by-side panel [P1 | P2] (rows x 2L, each half L wide) into FP64 (2L x 2L)
 hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t rows, int L, float* partials, double* W,

@@ -265,11 +265,20 @@ __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::ra
 // descriptor, are loaded before the current block's gathers, so one memory latency per block is
 // exposed instead of three.
 // Output: a whole row goes to out[r], the chunks of a long row to their FP32 partial slots (the
-// fix-up adds them in slot order).
-template <int L, int U, bool BIN, bool BOUT>
+// fix-up adds them in slot order).  VB: the stored values are BF16 (the precision form's products
+// 1 .. 2q+1), widened to FP32 exactly.
+template <bool VB>
+__device__ inline float load_val(const void* __restrict__ val, int q) {
+  if constexpr (VB)
+    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(val)[q] << 16);
+  else
+    return reinterpret_cast<const float*>(val)[q];
+}
+
+template <int L, int U, bool BIN, bool BOUT, bool VB>
 __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_t c0, int64_t c1, int64_t first,
                                            int64_t stride, const int* __restrict__ idx,
-                                           const float* __restrict__ val, const void* __restrict__ X, int ldx,
+                                           const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                            void* __restrict__ out, int ldo, float* __restrict__ partial) {
   using S = Seg<BIN>;
   constexpr int VEC = S::VEC;
@@ -287,7 +296,7 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
   float vi = 0.f;
   if (cc < c1 && p + sub < dc.z) {
     ci = idx[p + sub];
-    vi = val[p + sub];
+    vi = load_val<VB>(val, p + sub);
   }
   float acc[VEC];
 #pragma unroll
@@ -301,7 +310,7 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
     float vi2 = 0.f;
     if ((same || ncc < c1) && np + sub < nend) {
       ci2 = idx[np + sub];
-      vi2 = val[np + sub];
+      vi2 = load_val<VB>(val, np + sub);
     }
     // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
     const int cnt = min(LPR, dc.z - p);
@@ -339,10 +348,10 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
 // regions[1]).  nlocal = kXcdBands: a block first walks the pieces of its XCD's row band
 // (range blockIdx % nlocal, shared with the other blocks of that XCD), then its share of the
 // short columns' range (range nlocal, shared with all blocks); gridDim.x is a multiple of nlocal.
-template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT>
+template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT, bool VB>
 __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ regions,
                                               int nlocal, const int* __restrict__ idx,
-                                              const float* __restrict__ val, const void* __restrict__ X, int ldx,
+                                              const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                               void* __restrict__ out, int ldo, float* __restrict__ partial) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);  // groups per wave
   const int lane = threadIdx.x & 63;
@@ -351,10 +360,10 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
   if (nlocal > 0) {
     const int band = blockIdx.x % nlocal;
     const int64_t slot = blockIdx.x / nlocal;
-    spmm_range<L, U, BIN, BOUT>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
+    spmm_range<L, U, BIN, BOUT, VB>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
                                 (int64_t)(gridDim.x / nlocal) * 4 * G, idx, val, X, ldx, out, ldo, partial);
   }
-  spmm_range<L, U, BIN, BOUT>(desc, regions[nlocal], regions[nlocal + 1], ((int64_t)blockIdx.x * 4 + wave) * G + grp,
+  spmm_range<L, U, BIN, BOUT, VB>(desc, regions[nlocal], regions[nlocal + 1], ((int64_t)blockIdx.x * 4 + wave) * G + grp,
                               (int64_t)gridDim.x * 4 * G, idx, val, X, ldx, out, ldo, partial);
 }
 
@@ -482,8 +491,8 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ slot
   }
 }
 
-template <int L, int U, bool BIN, bool BOUT>
-void launch_spmm(const Schedule& s, const int* idx, const float* val, const void* X, int ldx, void* out, int ldo,
+template <int L, int U, bool BIN, bool BOUT, bool VB>
+void launch_spmm(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
                  float* partial, hipStream_t st) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);
   // about four chunks per group; the grid is not persistent (finished blocks make room for
@@ -493,23 +502,25 @@ void launch_spmm(const Schedule& s, const int* idx, const float* val, const void
   if (s.nlocal > 0) grid = (grid + s.nlocal - 1) / s.nlocal * s.nlocal;
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
-    k_spmm<L, U, true, BIN, BOUT><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx, out,
-                                                                  ldo, partial);
+    k_spmm<L, U, true, BIN, BOUT, VB><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx,
+                                                                      out, ldo, partial);
   else
-    k_spmm<L, U, false, BIN, BOUT><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx, out,
-                                                                   ldo, partial);
+    k_spmm<L, U, false, BIN, BOUT, VB><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx,
+                                                                       out, ldo, partial);
 }
 
 template <int L>
-hipError_t spmm_l(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
-                  PanelType yt, int ldy, float* partial, hipStream_t st) {
+hipError_t spmm_l(const Schedule& s, const int* idx, const void* val, bool vb, const void* X, PanelType xt, int ldx,
+                  void* Y, PanelType yt, int ldy, float* partial, hipStream_t st) {
   const bool xb = xt == PanelType::BF16, yb = yt == PanelType::BF16;
-  if (!xb && !yb) {
-    launch_spmm<L, 8, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
-  } else if (xb && yb) {
-    launch_spmm<L, 4, true, true>(s, idx, val, X, ldx, Y, ldy, partial, st);
-  } else if (xb && !yb) {
-    launch_spmm<L, 4, true, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  // FP32 form: FP32 values and panels.  Precision form: BF16 values and panels in the products
+  // 1 .. 2q+1, FP32 values and output in the last (P^T = A'^T Y)
+  if (!xb && !yb && !vb) {
+    launch_spmm<L, 8, false, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  } else if (xb && yb && vb) {
+    launch_spmm<L, 4, true, true, true>(s, idx, val, X, ldx, Y, ldy, partial, st);
+  } else if (xb && !yb && !vb) {
+    launch_spmm<L, 4, true, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
   } else {
     return hipErrorInvalidValue;
   }
@@ -561,12 +572,12 @@ hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const
   return hipGetLastError();
 }
 
-hipError_t spmm(const Schedule& s, const int* idx, const float* val, const void* X, PanelType xt, int ldx, void* Y,
-                PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
-  if (L == 32) return spmm_l<32>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 64) return spmm_l<64>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 128) return spmm_l<128>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 256) return spmm_l<256>(s, idx, val, X, xt, ldx, Y, yt, ldy, partial, st);
+hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf16, const void* X, PanelType xt, int ldx,
+                void* Y, PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
+  if (L == 32) return spmm_l<32>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 64) return spmm_l<64>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 128) return spmm_l<128>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
+  if (L == 256) return spmm_l<256>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
   return hipErrorInvalidValue;
 }
 

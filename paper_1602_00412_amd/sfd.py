@@ -40,6 +40,10 @@ OPT_ALGORITHM = 10
 OPT_CSC_HOT_MIN = 11
 OPT_TEST_ZERO_ROW = 12
 OPT_TEST_ZERO_ATTEMPTS = 13
+OPT_CQR2 = 14
+CQR2_OFF = 0
+CQR2_FINAL = 1
+CQR2_ALL = 2
 ALGO_SFD = 0
 ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
@@ -238,7 +242,7 @@ class Sketch:
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
                  max_attempts=None, verify=None, stream_id=None, csc_bands=None, csc_hot_min=None,
-                 precision=None, algorithm=None, use_torch_stream: bool = True):
+                 precision=None, algorithm=None, cqr2=None, use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
@@ -250,7 +254,9 @@ class Sketch:
                          (OPT_PRECISION, None if precision is None else
                           {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision)),
                          (OPT_ALGORITHM, None if algorithm is None else
-                          {"sfd": ALGO_SFD, "fd": ALGO_FD}.get(algorithm, algorithm))):
+                          {"sfd": ALGO_SFD, "fd": ALGO_FD}.get(algorithm, algorithm)),
+                         (OPT_CQR2, None if cqr2 is None else
+                          {"off": CQR2_OFF, "final": CQR2_FINAL, "all": CQR2_ALL}.get(cqr2, cqr2))):
             if val is not None:
                 self.set_option(key, val)
         if use_torch_stream:
