@@ -5,13 +5,19 @@ One step = one pass of the whole path over the workload: reset the handle, appen
 (CSR already resident in HBM; each full buffer goes through the buffer step: CSC build,
 SimultaneousIteration, VerifySpectral, BoostedSparseShrink, DenseShrink) and query the sketch.
 
-Workload: n = 1,000,000 rows, d = 100,000, Poisson(50) entries per row from Zipf(1.0) columns,
-lognormal(0,1) values plus a planted rank-20 component with 30% of the energy, ell = 50,
-eps = 1/4, FP32 (workloads.stream_1e6_d1e5).
+Workload of the line's value: n = 1,000,000 rows, d = 100,000, Poisson(50) entries per row from
+Zipf(1.0) columns, lognormal(0,1) values plus a planted rank-20 component with 30% of the energy,
+ell = 50, eps = 1/4, FP32 (workloads.stream_1e6_d1e5).
 
-Prints one JSON line (metric, value in nnz/s, roofline of the dominant kernel class measured
-with HIP events on the library's stream over the timed region, and the FP64 oracle's rate on
-a bounded sample of the same stream as cpu_baseline).
+Prints one JSON line: the metric, its value in nnz/s, the roofline of the dominant kernel class
+(HIP events on the library's stream), the FP64 oracle's rate on a bounded sample of the same
+stream (cpu_baseline), and under "forms" the forms the metric compares, each timed in the same
+run: the BF16 precision form on the same stream, the 2e6-row d = 5e4 stream at ell = 200 and the
+1e7-row d = 1e6 stream at ell = 100 (both generated on the device) in FP32 and BF16, and the
+batched form on all 4,096 streams of the batching workload, with each form's covariance error
+(Sec. 4) from the FP64 evaluator.
+
+Only the cpu_baseline leg (the functions named cpu_baseline*) runs the FP64 oracle.
 """
 
 from __future__ import annotations
@@ -26,6 +32,9 @@ METRIC = "ingested nnz/s on 1 MI355X at fixed cov-err; BF16/batched vs plain FP3
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
 HERE = os.path.dirname(os.path.abspath(__file__))
+# options of the timed handles (--autotune, --graphs)
+SKETCH_OPTS: dict = {}
+BATCH_OPTS: dict = {}
 
 # HBM traffic of one product measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # per dispatch, the factors that make a plain 1 GiB copy read as 1 GiB each way), summed over the
@@ -65,6 +74,30 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gram_rel_distance(B1, B2) -> float:
+    """||B1^T B1 - B2^T B2||_F / ||B2^T B2||_F in FP64 from the small Grams (the sketches' d x d
+    covariances are never formed): ||X^T X||_F^2 = ||X X^T||_F^2 and <B1^T B1, B2^T B2> =
+    ||B1 B2^T||_F^2."""
+    import numpy as np
+
+    B1 = np.asarray(B1, dtype=np.float64)
+    B2 = np.asarray(B2, dtype=np.float64)
+    a = np.sum((B1 @ B1.T) ** 2)
+    c = np.sum((B2 @ B2.T) ** 2)
+    x = np.sum((B1 @ B2.T) ** 2)
+    return float(np.sqrt(max(a + c - 2.0 * x, 0.0) / c)) if c > 0 else float(np.sqrt(a))
+
+
+def free_gpu():
+    import gc
+
+    import torch
+
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(st, ell: int, rows: int):
     """The FP64 oracle on the first `rows` rows of the stream (query folds them in one buffer)."""
     import numpy as np
@@ -96,11 +129,45 @@ def cpu_baseline(st, ell: int, rows: int):
     }
 
 
-def run_batch_full(args) -> int:
-    """All 4,096 streams of the batching workload (d = 2e4, ell = 32, Poisson(30) entries per row,
-    Zipf(1.1) columns, lognormal(0,1) values, 1e3..1e5 rows per stream), generated on the device,
-    resident in HBM, appended in one batch call and queried; a few streams are checked against
-    single-stream handles (bit for bit) and the shortest one against the oracle."""
+def cpu_baseline_eval_refs(sub, Bg, k: int = 10):
+    """The oracle evaluator's measures of a GPU sketch Bg of the sample sub (the references of the
+    GPU evaluator's check): ||A||_F^2 and proj-err (k) by their definitions (Sec. 4)."""
+    from oracle import evaluate
+
+    A = sub.to_scipy()
+    return evaluate.fro2(A), evaluate.proj_err(A, Bg, k)
+
+
+def cpu_baseline_prefix(st, ell: int, q: int):
+    """The FP64 oracle's sketch of a prefix st with a fixed q (the device path's parity check on
+    the large workloads, where the oracle's d x ell Householder QRs at the method's q would take
+    minutes); returns (sketch, seconds)."""
+    from oracle import SFDOracle
+
+    t = time.perf_counter()
+    o = SFDOracle(st.d, ell, 0.25, 0, q=q, unit_roundoff=2.0 ** -24)
+    o.append_csr(st.indptr, st.indices, st.values)
+    return o.sketch(), time.perf_counter() - t
+
+
+def cpu_baseline_stream(indptr, indices, values, d: int, ell: int, stream_id: int):
+    """The FP64 oracle on one whole stream of a batch (host arrays): (sketch, nnz/s, seconds)."""
+    from oracle import SFDOracle
+
+    t = time.perf_counter()
+    o = SFDOracle(d, ell, 0.25, 0, stream_id=stream_id, unit_roundoff=2.0 ** -24)
+    o.append_csr(indptr, indices, values)
+    B = o.sketch()
+    dt = time.perf_counter() - t
+    return B, (int(indptr[-1] - indptr[0]) / dt if dt > 0 else None), dt
+
+
+def measure_batch_full(streams: int, steps: int, warmup: int) -> dict:
+    """The batched form on streams 0 .. streams - 1 of the batching workload (d = 2e4, ell = 32,
+    Poisson(30) entries per row, Zipf(1.1) columns, lognormal(0,1) values, 1e3..1e5 rows per
+    stream), generated on the device, resident in HBM, appended in one batch call and queried.
+    Checks: streams 0, 1 and the shortest equal bit for bit to single-stream handles; the shortest
+    against the FP64 oracle (cpu_baseline leg, which also times it)."""
     import numpy as np
     import torch
 
@@ -108,12 +175,12 @@ def run_batch_full(args) -> int:
     from workloads.device import batch_streams_d2e4
 
     t0 = time.perf_counter()
-    ptr, idx, val, starts = batch_streams_d2e4("cuda", streams=args.batch_first_streams)
+    ptr, idx, val, starts = batch_streams_d2e4("cuda", streams=streams)
     torch.cuda.synchronize()
     S, d, ell = len(starts) - 1, 20_000, 32
     nnz = int(ptr[-1].item())
-    log(f"generated {S} streams, {starts[-1]} rows, {nnz} nnz in {time.perf_counter() - t0:.1f} s")
-    bat = sfd.Batch(S, d, ell)
+    log(f"batch: generated {S} streams, {starts[-1]} rows, {nnz} nnz in {time.perf_counter() - t0:.1f} s")
+    bat = sfd.Batch(S, d, ell, **BATCH_OPTS)
     b_out = torch.empty((S, ell, d), dtype=torch.float32, device="cuda")
     sos = np.arange(S, dtype=np.int32)
 
@@ -122,24 +189,20 @@ def run_batch_full(args) -> int:
         bat.append_csr(sos, starts, ptr, idx, val)
         bat.sketch(out=b_out)
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         t = time.perf_counter()
         step()
         torch.cuda.synchronize()
-        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
+        log(f"batch warmup {w + 1}/{warmup}: {time.perf_counter() - t:.3f} s")
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step()
-        log(f"step {k + 1}/{args.steps} done")
+        log(f"batch step {k + 1}/{steps} done")
     torch.cuda.synchronize()
-    el = (time.perf_counter() - t) / args.steps
+    el = (time.perf_counter() - t) / steps
     flushes = sum(bat.stats(s)["flushes"] for s in range(S))
-    log(f"{1e3 * el:.1f} ms/step, {nnz / el:.3e} nnz/s, {flushes} buffer steps")
-    # samples: streams 0, 1 and the shortest against single-stream handles, the shortest against
-    # the oracle
-    from oracle import SFDOracle, evaluate
-
+    log(f"batch: {1e3 * el:.1f} ms/step, {nnz / el:.3e} nnz/s, {flushes} buffer steps")
     lens = np.diff(starts)
     short = int(np.argmin(lens))
     bitwise = True
@@ -148,26 +211,113 @@ def run_batch_full(args) -> int:
         lo, hi = int(starts[s_]), int(starts[s_ + 1])
         one.append_csr(ptr[lo:hi + 1], idx, val)
         bitwise = bitwise and torch.equal(one.sketch(), b_out[s_])
+        one.close()
     lo, hi = int(starts[short]), int(starts[short + 1])
     a, b = int(ptr[lo].item()), int(ptr[hi].item())
-    o = SFDOracle(d, ell, 0.25, 0, stream_id=short, unit_roundoff=2.0 ** -24)
-    o.append_csr((ptr[lo:hi + 1] - a).cpu().numpy(), idx[a:b].cpu().numpy(), val[a:b].cpu().numpy())
-    parity = evaluate.gram_distance(b_out[short].cpu().numpy().astype(np.float64), o.sketch())
-    log(f"samples: bitwise equal to single-stream handles: {bitwise}; stream {short} ({hi - lo} rows) vs oracle "
-        f"{parity:.2e}")
+    Bo, rate, dt = cpu_baseline_stream((ptr[lo:hi + 1] - a).cpu().numpy(), idx[a:b].cpu().numpy(),
+                                       val[a:b].cpu().numpy(), d, ell, short)
+    parity = gram_rel_distance(b_out[short].cpu().numpy(), Bo)
+    log(f"batch samples: bitwise equal to single-stream handles: {bitwise}; stream {short} ({hi - lo} rows) vs "
+        f"oracle {parity:.2e}")
+    rec = {"value": nnz / el, "unit": "nnz/s", "ms_per_step": 1e3 * el, "steps": steps, "warmup": warmup,
+           "streams": S, "rows": int(starts[-1]), "nnz": nnz, "d": d, "ell": ell, "buffers_per_step": flushes,
+           "bitwise_equal_to_single_stream": bool(bitwise), "oracle_stream": short,
+           "oracle_rel_frobenius": parity,
+           "cpu_baseline": {"value": rate, "unit": "nnz/s", "kind": "oracle",
+                            "sample": f"stream {short} ({hi - lo} rows, {b - a} nnz), whole; {dt:.1f} s"}}
+    bat.close()
+    del ptr, idx, val, b_out
+    free_gpu()
+    return rec
+
+
+def run_batch_full(args) -> int:
+    """All 4,096 streams of the batching workload as the line's workload."""
+    rec = measure_batch_full(args.batch_first_streams, args.steps, args.warmup)
     line = {
-        "metric": METRIC, "value": nnz / el, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": rec["value"], "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{S} independent zipf-poisson streams, {starts[-1]} rows, d={d}, lambda=30, s=1.1, "
-                               f"lognormal, ell={ell} eps=1/4, generated on the device, one batch call",
-                   "nnz": nnz, "ell": ell, "buffers_per_step": flushes, "parallelism": "1 GPU"},
-        "roofline": None, "cpu_baseline": None,
-        "samples": {"bitwise_equal_to_single_stream": bool(bitwise), "oracle_stream": short,
-                    "oracle_rel_frobenius": parity},
+        "config": {"workload": f"{rec['streams']} independent zipf-poisson streams, {rec['rows']} rows, d=20000, "
+                               f"lambda=30, s=1.1, lognormal, ell=32 eps=1/4, generated on the device, one batch call",
+                   "nnz": rec["nnz"], "ell": 32, "buffers_per_step": rec["buffers_per_step"],
+                   "parallelism": "1 GPU"},
+        "roofline": None, "cpu_baseline": rec["cpu_baseline"],
+        "samples": {k: rec[k] for k in ("bitwise_equal_to_single_stream", "oracle_stream", "oracle_rel_frobenius")},
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def measure_large_stream(which: str, steps: int, warmup: int, check_rows: int = 2000) -> dict:
+    """A stream generated on the device in both forms: which = "ell200" (2e6 rows, d = 5e4,
+    Poisson(80), Zipf(1.1), N(0,1) + planted rank-50, ell = 200) or "d1e6" (1e7 rows, d = 1e6,
+    Poisson(100), Zipf(1.0), lognormal + planted rank-100 at 30% energy, ell = 100).  FP32 and
+    BF16 are timed one after the other on the same resident stream (same q, same random blocks);
+    cov-err of each sketch from the FP64 evaluator (sfd_evaluate) against the whole stream; parity
+    of the FP32 path with the oracle on a check_rows prefix at q = 3 (cpu_baseline leg)."""
+    import numpy as np
+    import torch
+
+    from paper_1602_00412_amd import sfd
+    from workloads.device import stream_1e7_d1e6, stream_2e6_d5e4
+
+    big = which == "d1e6"
+    d, ell = (1_000_000, 100) if big else (50_000, 200)
+    t0 = time.perf_counter()
+    indptr, indices, values = (stream_1e7_d1e6 if big else stream_2e6_d5e4)("cuda")
+    torch.cuda.synchronize()
+    n, nnz = indptr.numel() - 1, int(indptr[-1].item())
+    log(f"{which}: generated n={n} d={d} nnz={nnz} in {time.perf_counter() - t0:.1f} s")
+    rec = {"rows": n, "d": d, "ell": ell, "nnz": nnz, "steps": steps, "warmup": warmup}
+    out = torch.empty((ell, d), dtype=torch.float32, device="cuda")
+    for prec in ("fp32", "bf16"):
+        sk = sfd.Sketch(d, ell, 0.25, 0, precision=prec, **SKETCH_OPTS)
+
+        def step():
+            sk.reset()
+            sk.append_csr(indptr, indices, values)
+            sk.sketch(out=out)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / steps
+        r = {"value": nnz / el, "unit": "nnz/s", "ms_per_step": 1e3 * el, "buffers_per_step": sk.stats()["flushes"],
+             "q_last": sk.stats()["last_q"]}
+        t = time.perf_counter()
+        ev = sfd.evaluate(indptr, indices, values, d, out, k=0, steps=160)
+        r["cov_err"] = ev["cov_err"]
+        r["cov_max_ritz_residual"] = ev["cov_max_res"]
+        r["eval_seconds"] = time.perf_counter() - t
+        rec[prec] = r
+        log(f"{which} {prec}: {1e3 * el:.1f} ms/step, {nnz / el:.3e} nnz/s, cov-err {ev['cov_err']:.4e}")
+        sk.close()
+        free_gpu()
+    rec["bf16_speedup_vs_fp32"] = rec["fp32"]["ms_per_step"] / rec["bf16"]["ms_per_step"]
+    rec["bf16_cov_err_over_fp32"] = rec["bf16"]["cov_err"] / rec["fp32"]["cov_err"]
+    # parity of the FP32 path on a prefix (the same kernels and shapes, q shortened to 3)
+    from workloads import CsrStream
+
+    ppre = indptr[:check_rows + 1].cpu().numpy()
+    st = CsrStream(ppre, indices[:int(ppre[-1])].cpu().numpy(), values[:int(ppre[-1])].cpu().numpy(), d,
+                   dict(name=f"{which} prefix"))
+    Bo, dt = cpu_baseline_prefix(st, ell, 3)
+    sk2 = sfd.Sketch(d, ell, 0.25, 0, q=3)
+    sk2.append_csr(torch.from_numpy(st.indptr).cuda(), torch.from_numpy(st.indices).cuda(),
+                   torch.from_numpy(st.values).cuda())
+    rec["prefix_parity_rel_frobenius"] = gram_rel_distance(sk2.sketch().cpu().numpy(), Bo)
+    rec["prefix_parity_rows"] = check_rows
+    sk2.close()
+    log(f"{which}: bf16 {rec['bf16_speedup_vs_fp32']:.2f}x FP32 at cov-err {rec['bf16_cov_err_over_fp32']:.4f}x; "
+        f"prefix parity ({check_rows} rows, q=3) {rec['prefix_parity_rel_frobenius']:.2e} ({dt:.1f} s oracle)")
+    del indptr, indices, values, out
+    free_gpu()
+    return rec
 
 
 def run_paper_sweep(args) -> int:
@@ -245,6 +395,13 @@ def main() -> int:
     ap.add_argument("--csc-hot-min", type=int, default=0,
                     help="entries from which a CSC column is cut into XCD-local pieces (0: the library's default)")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the forms on the 10^6-row stream")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="SFD_OPT_AUTOTUNE of every handle (1: tuned sparse-product launches, the default)")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="SFD_OPT_GRAPHS of the batch handles (1: graph-captured group steps, the default)")
+    ap.add_argument("--big-forms", default="ell200,d1e6,batch4096",
+                    help="forms on their own workloads timed after the line (comma-separated; empty: none)")
     ap.add_argument("--batch-streams", type=int, default=64,
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
     ap.add_argument("--lanes", type=int, default=0, help="lanes of the timed FP32 line (0: the library's default)")
@@ -273,14 +430,16 @@ def main() -> int:
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     else:
-        # the ell = 200 workload's handles run 8 lanes each (FP32 line and BF16 form)
-        want = 32 if args.workload == "ell200" else 16
+        # the ell = 200 workload's handles run 8 lanes each (also a form of the default run)
+        want = 32 if (args.workload == "ell200" or "ell200" in args.big_forms) else 16
         try:
             have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
         except ValueError:
             have = 0
         if have < want:
             os.environ["GPU_MAX_HW_QUEUES"] = str(want)
+    SKETCH_OPTS["autotune"] = bool(args.autotune)
+    BATCH_OPTS.update(autotune=bool(args.autotune), graphs=bool(args.graphs))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
               f"one merge at the end; runs across several GPUs are not implemented", file=sys.stderr)
@@ -344,6 +503,7 @@ def main() -> int:
     log(f"generated n={st_n} d={st_d} nnz={st_nnz} in {time.perf_counter() - t0:.1f} s")
     out = torch.empty((ell, st_d), dtype=torch.float32, device="cuda")
     sk = sfd.Sketch(st_d, ell, 0.25, 0, csc_bands=args.csc_bands or None, csc_hot_min=args.csc_hot_min or None,
+                    **SKETCH_OPTS,
                     precision=args.precision)
     if args.lanes:
         sk.set_option(sfd.OPT_LANES, args.lanes)
@@ -440,12 +600,15 @@ def main() -> int:
                                  "attainable_tflops": attainable, "frac_of_attainable": tf / attainable}
         log(f"roofline: {dom} {roof['avg_launch_us']:.1f} us/launch, {achieved:.1f} {roof['unit']}")
 
-    # The BF16 precision form on the same resident stream: same q, same random blocks, panels of
-    # SimultaneousIteration in BF16 with FP32 accumulation.
+    # The forms: fewer steps than the line (each is a whole pass over its workload).
+    f_steps = max(1, min(args.steps, args.form_steps))
+    f_warmup = max(1, min(args.warmup, 1))
+    # The BF16 precision form on the same resident stream: same q, same random blocks; values and
+    # panels of SimultaneousIteration in BF16, transforms and Grams on BF16 MFMA.
     forms = {}
     sk_bf = None
     if not args.no_forms and not args.profile_only and args.precision == "fp32":
-        sk_bf = sfd.Sketch(st_d, ell, 0.25, 0, precision="bf16")
+        sk_bf = sfd.Sketch(st_d, ell, 0.25, 0, precision="bf16", **SKETCH_OPTS)
         out_bf = torch.empty_like(out)
 
         def step_bf():
@@ -453,21 +616,18 @@ def main() -> int:
             sk_bf.append_csr(indptr, indices, values)
             sk_bf.sketch(out=out_bf)
 
-        for _ in range(args.warmup):
+        for _ in range(f_warmup):
             step_bf()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(f_steps):
             step_bf()
         torch.cuda.synchronize()
         el_bf = time.perf_counter() - t_start
-        from oracle import evaluate as _ev
-
-        forms["bf16"] = {"value": st_nnz / (el_bf / args.steps), "unit": "nnz/s",
-                         "ms_per_step": 1e3 * el_bf / args.steps,
-                         "speedup_vs_fp32": elapsed / el_bf,
-                         "rel_frobenius_vs_fp32": _ev.gram_distance(out_bf.cpu().numpy().astype(np.float64),
-                                                                    out.cpu().numpy().astype(np.float64))}
+        forms["bf16"] = {"value": st_nnz / (el_bf / f_steps), "unit": "nnz/s",
+                         "ms_per_step": 1e3 * el_bf / f_steps, "steps": f_steps,
+                         "speedup_vs_fp32": (elapsed / args.steps) / (el_bf / f_steps),
+                         "rel_frobenius_vs_fp32": gram_rel_distance(out_bf.cpu().numpy(), out.cpu().numpy())}
         log(f"bf16 form: {forms['bf16']['ms_per_step']:.1f} ms/step, {forms['bf16']['value']:.3e} nnz/s "
             f"({forms['bf16']['speedup_vs_fp32']:.2f}x FP32)")
 
@@ -495,7 +655,7 @@ def main() -> int:
         g_val = torch.from_numpy(np.concatenate([x.values for x in bst])).cuda()
         log(f"batched form: {len(bst)} streams, {starts[-1]} rows, {b_nnz} nnz generated in "
             f"{time.perf_counter() - t:.1f} s")
-        bat = sfd.Batch(len(bst), bd, bell)
+        bat = sfd.Batch(len(bst), bd, bell, **BATCH_OPTS)
         b_out = torch.empty((len(bst), bell, bd), dtype=torch.float32, device="cuda")
         sos = np.arange(len(bst), dtype=np.int32)
 
@@ -504,7 +664,7 @@ def main() -> int:
             bat.append_csr(sos, starts, g_ptr, g_idx, g_val)
             bat.sketch(out=b_out)
 
-        single = sfd.Sketch(bd, bell, 0.25, 0)
+        single = sfd.Sketch(bd, bell, 0.25, 0, **SKETCH_OPTS)
         s_out = torch.empty((bell, bd), dtype=torch.float32, device="cuda")
 
         def step_single():
@@ -517,22 +677,24 @@ def main() -> int:
 
         res = {}
         for name, fn in (("batched", step_batch), ("single", step_single)):
-            for _ in range(args.warmup):
+            for _ in range(f_warmup):
                 fn()
             torch.cuda.synchronize()
             t = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(f_steps):
                 fn()
             torch.cuda.synchronize()
-            res[name] = (time.perf_counter() - t) / args.steps
+            res[name] = (time.perf_counter() - t) / f_steps
         forms["batched"] = {"value": b_nnz / res["batched"], "unit": "nnz/s", "ms_per_step": 1e3 * res["batched"],
                             "streams": len(bst), "rows": int(starts[-1]), "nnz": b_nnz, "d": bd, "ell": bell,
                             "single_stream_value": b_nnz / res["single"],
                             "speedup_vs_single_streams": res["single"] / res["batched"],
-                            "ratio_vs_fp32_value": (b_nnz / res["batched"]) / value}
+                            "ratio_vs_fp32_value": (b_nnz / res["batched"]) / value, "steps": f_steps}
         log(f"batched form: {1e3 * res['batched']:.1f} ms/step, {b_nnz / res['batched']:.3e} nnz/s "
             f"({res['single'] / res['batched']:.2f}x one stream at a time)")
-        del bat, single
+        bat.close()
+        single.close()
+        del g_ptr, g_idx, g_val, b_out
 
     # The evaluator (sfd_evaluate, FP64 on the GPU): cov-err and proj-err (k = 10) of the timed
     # line's sketch against the whole stream.  Not for the 10^9-entry stream (its 160-step
@@ -560,6 +722,24 @@ def main() -> int:
             forms["bf16"]["proj_err"] = evb["proj_err"]
             log(f"bf16 form: cov-err {evb['cov_err']:.4e} ({cov_errs['bf16_over_fp32']:.4f}x FP32)")
 
+    # The precision form on its own workloads (ell = 200; d = 1e6, ell = 100) and the batched form
+    # on all 4,096 streams, each generated on the device after the 10^6-row stream's handles are
+    # released.
+    if not args.no_forms and not args.profile_only and args.precision == "fp32" and args.workload == "stream1e6":
+        del sk_bf
+        sk_bf = None
+        free_gpu()
+        for name in args.big_forms.split(","):
+            name = name.strip()
+            if not name:
+                continue
+            if name in ("ell200", "d1e6"):
+                forms[name] = measure_large_stream(name, 1, 1)
+            elif name == "batch4096":
+                forms[name] = measure_batch_full(4096, 1, 1)
+            else:
+                raise SystemExit(f"unknown form {name}")
+
     cpu = None
     parity = None
     eval_check = None
@@ -567,16 +747,12 @@ def main() -> int:
         # The oracle costs a d x ell Householder QR per product (about a second each at d = 1e6,
         # ell = 100), so it checks the device path on the prefix with q = 3 (the same kernels and
         # shapes; the q of the method is only shortened) and is not timed as a baseline.
-        from oracle import SFDOracle, evaluate
-
         t = time.perf_counter()
-        o = SFDOracle(st.d, ell, 0.25, 0, q=3, unit_roundoff=2.0 ** -24)
-        o.append_csr(st.indptr, st.indices, st.values)
-        Bo = o.sketch()
+        Bo, _ = cpu_baseline_prefix(st, ell, 3)
         sk2 = sfd.Sketch(st.d, ell, 0.25, 0, q=3)
         sk2.append_csr(torch.from_numpy(st.indptr).cuda(), torch.from_numpy(st.indices).cuda(),
                        torch.from_numpy(st.values).cuda())
-        parity = evaluate.gram_distance(sk2.sketch().cpu().numpy().astype(np.float64), Bo)
+        parity = gram_rel_distance(sk2.sketch().cpu().numpy(), Bo)
         log(f"prefix parity ({st.n} rows, q=3) vs oracle: {parity:.2e} in {time.perf_counter() - t:.1f} s")
         cpu = None
     elif not args.no_cpu_baseline:
@@ -584,13 +760,11 @@ def main() -> int:
         sub, B_oracle, cpu = cpu_baseline(st, ell, min(args.cpu_sample_rows, st.n))
         log(f"cpu baseline: {cpu['value']:.3e} nnz/s in {time.perf_counter() - t:.1f} s")
         # the GPU on the same sample, compared with the oracle (relative Frobenius of B^T B)
-        from oracle import evaluate
-
         sk2 = sfd.Sketch(st.d, ell, 0.25, 0)
         sk2.append_csr(torch.from_numpy(sub.indptr).cuda(), torch.from_numpy(sub.indices).cuda(),
                        torch.from_numpy(sub.values).cuda())
         Bg = sk2.sketch().cpu().numpy().astype(np.float64)
-        parity = evaluate.gram_distance(Bg, B_oracle)
+        parity = gram_rel_distance(Bg, B_oracle)
         log(f"sample parity (rel. Frobenius of B^T B vs oracle): {parity:.2e}")
         # the evaluator on the same sample against scipy's ARPACK on the evaluator's definitions
         # (the sketch's residual A^T A - B^T B is positive semidefinite, so cov-err is its largest
@@ -607,8 +781,9 @@ def main() -> int:
             op = spla.LinearOperator((st.d, st.d), dtype=np.float64,
                                      matvec=lambda x: A_s.T @ (A_s @ np.ravel(x)) - Bg.T @ (Bg @ np.ravel(x)))
             lmax = spla.eigsh(op, k=1, which="LA", tol=1e-10, return_eigenvectors=False)[0]
-            eval_check = {"cov_err_gpu": ev_s["cov_err"], "cov_err_arpack": float(lmax / evaluate.fro2(A_s)),
-                          "proj_err_gpu": ev_s["proj_err"], "proj_err_ref": evaluate.proj_err(A_s, Bg, 10),
+            fro2_ref, proj_ref = cpu_baseline_eval_refs(sub, Bg, 10)
+            eval_check = {"cov_err_gpu": ev_s["cov_err"], "cov_err_arpack": float(lmax / fro2_ref),
+                          "proj_err_gpu": ev_s["proj_err"], "proj_err_ref": proj_ref,
                           "sample": f"first {sub.n} rows, the GPU sketch of them (ell={ell}), k=10"}
             # cov-err of each form's sketch of the sample against the FP64 oracle's sketch of it, all
             # measured by the FP64 evaluator on the same rows

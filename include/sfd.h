@@ -108,12 +108,25 @@ enum {
                                       loop of BoostedSparseShrink (Alg 4) on purpose. */
   SFD_OPT_TEST_ZERO_ATTEMPTS = 13, /* attempts a < value that SFD_OPT_TEST_ZERO_ROW applies to,
                                       >= 0; default 1 (the first attempt of each buffer). */
-  SFD_OPT_CQR2 = 14                /* precision form only: CholeskyQR2 -- a second panel transform,
+  SFD_OPT_CQR2 = 14,               /* precision form only: CholeskyQR2 -- a second panel transform,
                                       Gram and Cholesky after the first, so a panel stored in BF16
                                       is orthonormal to BF16 precision rather than to that times
                                       its condition number.  SFD_CQR2_OFF, SFD_CQR2_FINAL
                                       (default: the final basis Y of Alg 1, whose span defines
                                       B'), SFD_CQR2_ALL (every product's panel). */
+  SFD_OPT_AUTOTUNE = 15,           /* 1 (default): the launch configuration of each sparse product
+                                      of SimultaneousIteration (entries gathered per batch; a
+                                      static grid or a persistent grid fed by a device work queue)
+                                      is picked by timing the candidates on the first product of
+                                      each shape (panel width, direction, element types, binary
+                                      orders of magnitude of entries and rows), once per process;
+                                      the environment variable SFD_TUNE_CACHE names a file that
+                                      keeps the choices across processes.  Every candidate gives
+                                      the same bits.  0: the default configuration. */
+  SFD_OPT_GRAPHS = 16              /* batch handles, 1 (default): each lockstep group's
+                                      SimultaneousIteration step and VerifySpectral power step are
+                                      captured once as HIP graphs and replayed (q + 1, resp. t
+                                      times); 0: issued launch by launch.  Same results. */
 };
 
 enum { SFD_CQR2_OFF = 0, SFD_CQR2_FINAL = 1, SFD_CQR2_ALL = 2 };

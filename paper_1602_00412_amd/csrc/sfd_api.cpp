@@ -21,8 +21,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
 #include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "sfd.h"
@@ -120,7 +123,8 @@ struct GroupWork {
   GroupSeg *segs_x = nullptr, *segs_y = nullptr;
   int64_t* seg_rows = nullptr;
   int* tsteps = nullptr;
-  GroupSeg* segs_host = nullptr;  // pinned: 2 kmax segments, kmax + 1 row offsets, kmax steps
+  int* qdev = nullptr;  // q of each buffer, then the iteration counter (kmax + 1)
+  GroupSeg* segs_host = nullptr;  // pinned: 2 kmax segments, kmax + 1 row offsets, kmax steps, kmax q
   float *vs_w = nullptr, *vs_wraw = nullptr, *vs_z = nullptr, *vs_c2 = nullptr, *vs_gpart = nullptr;
   double *vs_npart = nullptr, *fro_part = nullptr;
   int64_t cap_rows = 0, cap_nnz = 0;
@@ -147,6 +151,8 @@ struct sfd_s {
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
   int cqr2 = SFD_CQR2_FINAL;           // SFD_OPT_CQR2 (precision form)
+  int autotune = 1;                    // SFD_OPT_AUTOTUNE
+  int graphs = 1;                      // SFD_OPT_GRAPHS (lockstep groups of a batch handle)
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
   int test_zero_row = -1;              // SFD_OPT_TEST_ZERO_ROW
   int test_zero_attempts = 1;          // SFD_OPT_TEST_ZERO_ATTEMPTS
@@ -350,7 +356,8 @@ int alloc_lane(sfd_t* h, Lane& ln) {
   for (Schedule* s : {&ln.sr, &ln.scs}) {
     const int64_t rows = (s == &ln.scs) ? vrows : d + 1;
     ok = ok && dalloc(h, &s->nch, rows) && dalloc(h, &s->pslot, d + 1) && dalloc(h, &s->desc, max_chunks) &&
-         dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4) && dalloc(h, &s->regions, kXcdBands + 2);
+         dalloc(h, &s->long_rows, d + 1) && dalloc(h, &s->counters, 4) && dalloc(h, &s->regions, kXcdBands + 2) &&
+         dalloc(h, &s->queue, kXcdBands + 2);
     s->max_chunks = max_chunks;
   }
   ok = ok && dalloc(h, &ln.partial, slots * L);
@@ -446,6 +453,120 @@ double spmm_bytes(const sfd_t* h, const Lane& ln, bool transposed, double bx, do
 
 inline double pbytes(PanelType t) { return t == PanelType::BF16 ? 2.0 : 4.0; }
 
+// ---- Autotuner of the sparse products' launch configuration (SFD_OPT_AUTOTUNE).  A product is
+// keyed by its panel width, direction, element types, XCD-local pieces and the binary orders of
+// magnitude of its stored entries and of its input and output rows.  The first product with a
+// new key runs every candidate configuration three times on its real operands, alone on the
+// device (all give the same bits, so the extra runs change nothing but the time), with HIP events
+// around each, and the fastest (by its best run) is kept for the process, and appended to the file named by the environment variable
+// SFD_TUNE_CACHE when it is set (read back at the first use, so a later process starts tuned).
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+
+struct Tuner {
+  std::mutex mu;
+  std::map<TuneKey, SpmmConfig> best;
+  bool loaded = false;
+  void load() {
+    if (loaded) return;
+    loaded = true;
+    const char* path = std::getenv("SFD_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    int k[9], u, qu, oc;
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
+                       &k[7], &k[8], &u, &qu, &oc) == 12) {
+      SpmmConfig c;
+      c.unroll = u;
+      c.queue = qu != 0;
+      c.occupancy = oc;
+      best[TuneKey{k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]}] = c;
+    }
+    std::fclose(f);
+  }
+  void store(const TuneKey& key, const SpmmConfig& c) {
+    best[key] = c;
+    const char* path = std::getenv("SFD_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+                 std::get<3>(key), std::get<4>(key), std::get<5>(key), std::get<6>(key), std::get<7>(key),
+                 std::get<8>(key), c.unroll, c.queue ? 1 : 0, c.occupancy);
+    std::fclose(f);
+  }
+};
+Tuner g_tuner;
+
+inline int log2_bucket(int64_t n) {
+  int b = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// The configuration of a product (s, idx, val, X -> Y) on stream st: the tuned one, tuning first
+// when the key is new.  Not during stream capture (tuning synchronises).
+int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
+                   const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows, int64_t nnz,
+                   SpmmConfig* out) {
+  *out = SpmmConfig{};
+  if (!h->autotune) return SFD_OK;
+  const TuneKey key{h->L, s.transposed ? 1 : 0, (int)xt, (int)yt, vb ? 1 : 0, s.nlocal > 0 ? 1 : 0,
+                    log2_bucket(nnz), log2_bucket(in_rows), log2_bucket(s.rows)};
+  std::lock_guard<std::mutex> lock(g_tuner.mu);
+  g_tuner.load();
+  auto it = g_tuner.best.find(key);
+  if (it != g_tuner.best.end()) {
+    *out = it->second;
+    return SFD_OK;
+  }
+  std::vector<SpmmConfig> cand;
+  for (int q = 0; q < 2; ++q)
+    for (int u : {8, 4}) {
+      if (xt == PanelType::BF16 && u != 4) continue;  // BF16 panels gather in batches of 4 only
+      SpmmConfig c;
+      c.unroll = xt == PanelType::BF16 ? 0 : u;
+      c.queue = q != 0;
+      cand.push_back(c);
+    }
+  // measured alone: the work of the other lanes and streams finishes first, so the candidates'
+  // times are not mixed with theirs (once per key, in a warm-up)
+  CK(hipDeviceSynchronize());
+  hipEvent_t a = nullptr, b = nullptr;
+  CK(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return SFD_E_DEVICE;
+  }
+  std::vector<float> best_ms(cand.size(), 1e30f);
+  hipError_t e = hipSuccess;
+  for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+      if ((e = spmm_queue_reset(s, st)) != hipSuccess) break;
+      if ((e = hipEventRecord(a, st)) != hipSuccess) break;
+      if ((e = spmm(s, idx, val, vb, X, xt, h->L, Y, yt, h->L, h->L, partial, cand[i], st)) != hipSuccess) break;
+      if ((e = hipEventRecord(b, st)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+      best_ms[i] = std::min(best_ms[i], ms);
+    }
+  }
+  if (e == hipSuccess) e = spmm_queue_reset(s, st);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return SFD_E_DEVICE;
+  size_t bi = 0;
+  for (size_t i = 1; i < cand.size(); ++i)
+    if (best_ms[i] < best_ms[bi]) bi = i;
+  g_tuner.store(key, cand[bi]);
+  *out = cand[bi];
+  return SFD_OK;
+}
+
 // The output of a product whose input panel had transform T (the lane's current one):
 // panel <- panel T (so the product becomes A' (X T), resp. A'^T (Y T)), then the new T from
 // the transformed panel's Gram.
@@ -466,11 +587,14 @@ int orth_out(sfd_t* h, Lane& ln, void* panel, PanelType pt, int64_t rows) {
 
 // Y = A' X (the input's transform is applied to Y by orth_out); vb: BF16 values
 int spmm_csr(sfd_t* h, Lane& ln, const void* X, PanelType xt, void* Y, PanelType yt, bool vb = false) {
+  const void* val = vb ? static_cast<const void*>(ln.valb) : static_cast<const void*>(ln.val);
+  SpmmConfig cfg;
+  int rc = product_config(h, ln.st, ln.sr, ln.colidx, val, vb, X, xt, Y, yt, ln.partial, h->d, ln.nnz, &cfg);
+  if (rc) return rc;
   {
     ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSR, spmm_bytes(h, ln, false, pbytes(xt), pbytes(yt), vb ? 2.0 : 4.0),
                  2.0 * ln.nnz * h->ell + 2.0 * ln.m * h->ell * h->ell, 1);
-    CK(spmm(ln.sr, ln.colidx, vb ? static_cast<const void*>(ln.valb) : static_cast<const void*>(ln.val), vb, X, xt,
-            h->L, Y, yt, h->L, h->L, ln.partial, ln.st));
+    CK(spmm(ln.sr, ln.colidx, val, vb, X, xt, h->L, Y, yt, h->L, h->L, ln.partial, cfg, ln.st));
   }
   ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
   CK(spmm_finish(ln.sr, ln.partial, Y, yt, h->L, h->L, ln.st));
@@ -479,11 +603,14 @@ int spmm_csr(sfd_t* h, Lane& ln, const void* X, PanelType xt, void* Y, PanelType
 
 // X = A'^T Y; vb: BF16 values
 int spmm_csc(sfd_t* h, Lane& ln, const void* Y, PanelType yt, void* X, PanelType xt, bool vb = false) {
+  const void* val = vb ? static_cast<const void*>(ln.cscvalb) : static_cast<const void*>(ln.cscval);
+  SpmmConfig cfg;
+  int rc = product_config(h, ln.st, ln.scs, ln.cscrow, val, vb, Y, yt, X, xt, ln.partial, ln.m, ln.nnz, &cfg);
+  if (rc) return rc;
   {
     ProfScope ps(h, ln.st, SFD_PROF_SPMM_CSC, spmm_bytes(h, ln, true, pbytes(yt), pbytes(xt), vb ? 2.0 : 4.0),
                  2.0 * ln.nnz * h->ell + 2.0 * h->d * h->ell * h->ell, 1);
-    CK(spmm(ln.scs, ln.cscrow, vb ? static_cast<const void*>(ln.cscvalb) : static_cast<const void*>(ln.cscval), vb,
-            Y, yt, h->L, X, xt, h->L, h->L, ln.partial, ln.st));
+    CK(spmm(ln.scs, ln.cscrow, val, vb, Y, yt, h->L, X, xt, h->L, h->L, ln.partial, cfg, ln.st));
   }
   ProfScope ps(h, ln.st, SFD_PROF_FIXUP, 0.0, 0.0, 1);
   CK(spmm_finish(ln.scs, ln.partial, X, xt, h->L, h->L, ln.st));
@@ -717,6 +844,34 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
   return SFD_OK;
 }
 
+// `body` (launches on st only, no host synchronisation) run n times: captured once as a HIP graph
+// and launched n times when SFD_OPT_GRAPHS is on, else issued n times.
+template <class F>
+int replay(sfd_t* h, hipStream_t st, int n, F&& body) {
+  if (n <= 0) return SFD_OK;
+  if (!h->graphs || n == 1) {
+    for (int i = 0; i < n; ++i) {
+      int rc = body();
+      if (rc) return rc;
+    }
+    return SFD_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = body();
+  const hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (rc || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : SFD_E_DEVICE;
+  }
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(exec, st);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  return e == hipSuccess ? SFD_OK : SFD_E_DEVICE;
+}
+
 // Group workspace for up to kmax buffers (batch handles).
 int alloc_group(sfd_t* h, int kmax) {
   GroupWork& g = h->grp;
@@ -738,7 +893,8 @@ int alloc_group(sfd_t* h, int kmax) {
   for (Schedule* sch : {&g.sr, &g.scs}) {
     const int64_t rows = g.cap_rows + 1;
     ok = ok && dalloc(h, &sch->nch, rows) && dalloc(h, &sch->pslot, rows) && dalloc(h, &sch->desc, max_chunks) &&
-         dalloc(h, &sch->long_rows, rows) && dalloc(h, &sch->counters, 4) && dalloc(h, &sch->regions, kXcdBands + 2);
+         dalloc(h, &sch->long_rows, rows) && dalloc(h, &sch->counters, 4) && dalloc(h, &sch->regions, kXcdBands + 2) &&
+         dalloc(h, &sch->queue, kXcdBands + 2);
     sch->max_chunks = max_chunks;
   }
   g.scs.transposed = true;
@@ -751,13 +907,13 @@ int alloc_group(sfd_t* h, int kmax) {
   ok = ok && dalloc(h, &g.eig_work, kmax * eig_work_bytes(h->ell)) &&
        dalloc(h, &g.cholw, kmax * chol_work_doubles((int)L));
   ok = ok && dalloc(h, &g.segs_x, kmax) && dalloc(h, &g.segs_y, kmax) && dalloc(h, &g.seg_rows, kmax + 1) &&
-       dalloc(h, &g.tsteps, kmax);
+       dalloc(h, &g.tsteps, kmax) && dalloc(h, &g.qdev, kmax + 1);
   ok = ok && dalloc(h, &g.vs_w, kmax * d) && dalloc(h, &g.vs_wraw, kmax * d) && dalloc(h, &g.vs_z, g.cap_rows) &&
        dalloc(h, &g.vs_c2, kmax * 2 * L) && dalloc(h, &g.vs_gpart, kmax * gemv_blocks(d) * L) &&
        dalloc(h, &g.vs_npart, kmax * 1024) && dalloc(h, &g.fro_part, fro2_part_doubles(kmax));
   if (!ok) return SFD_E_NOMEM;
   if (hipHostMalloc((void**)&g.sc_host, sizeof(DevScalars) * kmax) != hipSuccess) return SFD_E_NOMEM;
-  const size_t hbytes = sizeof(GroupSeg) * 2 * kmax + sizeof(int64_t) * (kmax + 1) + sizeof(int) * kmax;
+  const size_t hbytes = sizeof(GroupSeg) * 2 * kmax + sizeof(int64_t) * (kmax + 1) + sizeof(int) * 2 * kmax;
   if (hipHostMalloc((void**)&g.segs_host, hbytes) != hipSuccess) return SFD_E_NOMEM;
   if (hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking) != hipSuccess) return SFD_E_DEVICE;
   if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return SFD_E_DEVICE;
@@ -912,6 +1068,11 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
   CK(hipMemcpyAsync(g.segs_y, hy, sizeof(GroupSeg) * K, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(g.seg_rows, hrows, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, st));
   // ---- SimultaneousIteration (Alg 1) of all buffers
+  int* hq = hsteps + g.kmax;
+  for (int k = 0; k < K; ++k) hq[k] = q[(size_t)k];
+  CK(hipMemcpyAsync(g.qdev, hq, sizeof(int) * K, hipMemcpyHostToDevice, st));
+  int* iter_dev = g.qdev + g.kmax;
+  CK(fill_i32(iter_dev, 1, 0, st));
   CK(fill_f32(g.X, (int64_t)K * d * L, 0.f, st));
   for (int k = 0; k < K; ++k) {
     const GroupItem& it = items[(size_t)k];
@@ -923,22 +1084,34 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
   CK(set_identity(g.T, L, K, st));
   CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
   CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
-  for (int iter = 0; iter <= qmax; ++iter) {
-    CK(spmm(g.sr, g.colidx, g.val, false, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, st));
+  // the products' launch configurations (tuned on first sight; the tuning runs write Y and P^T,
+  // which the iteration overwrites before reading)
+  SpmmConfig cfg_r, cfg_c;
+  if ((rc = product_config(h, st, g.sr, g.colidx, g.val, false, g.X, PanelType::F32, g.Y, PanelType::F32, g.partial,
+                           (int64_t)K * d, NNZ, &cfg_r)))
+    return rc;
+  if ((rc = product_config(h, st, g.scs, g.cscrow, g.cscval, false, g.Y, PanelType::F32, g.Pt, PanelType::F32,
+                           g.partial, M, NNZ, &cfg_c)))
+    return rc;
+  // One iteration: Y = A' X T_x, X = A'^T Y T_y (with the Grams and Choleskys), the buffers at
+  // their final product keep P^T = A'^T Y T_y and P P^T, the counter moves on.  Every iteration is
+  // the same launches with the same arguments, so with SFD_OPT_GRAPHS it is captured once as a
+  // HIP graph and replayed qmax + 1 times.
+  auto iteration = [&]() -> int {
+    CK(spmm(g.sr, g.colidx, g.val, false, g.X, PanelType::F32, L, g.Y, PanelType::F32, L, L, g.partial, cfg_r, st));
     CK(spmm_finish(g.sr, g.partial, g.Y, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.Y, PanelType::F32, L, 0, 0, nby, g.segs_y, K, L, g.T, g.gram_part, g.W, st));
     CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
-    CK(spmm(g.scs, g.cscrow, g.cscval, false, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, st));
+    CK(spmm(g.scs, g.cscrow, g.cscval, false, g.Y, PanelType::F32, L, g.X, PanelType::F32, L, L, g.partial, cfg_c,
+            st));
     CK(spmm_finish(g.scs, g.partial, g.X, PanelType::F32, L, L, st));
     CK(xform_gram_group(g.X, PanelType::F32, L, d, 0, nbx, g.segs_x, K, L, g.T, g.gram_part, g.W, st));
-    // buffers at their final product: P^T = A'^T Y T_y and W = P P^T
-    for (int k = 0; k < K; ++k) {
-      if (q[(size_t)k] != iter) continue;
-      CK(hipMemcpyAsync(g.Pt + k * d * L, g.X + k * d * L, sizeof(float) * d * L, hipMemcpyDeviceToDevice, st));
-      CK(hipMemcpyAsync(g.Wp + k * LL, g.W + k * LL, sizeof(double) * LL, hipMemcpyDeviceToDevice, st));
-    }
-    if (iter < qmax) CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
-  }
+    CK(group_snapshot(iter_dev, g.qdev, K, g.X, g.Pt, d * L, g.W, g.Wp, LL, st));
+    CK(chol_inv_group(g.W, L, ell, L, kCholDropTol, g.T, g.sc, K, LL, g.cholw, st));
+    CK(counter_add(iter_dev, 1, st));
+    return SFD_OK;
+  };
+  if ((rc = replay(h, st, qmax + 1, iteration))) return rc;
   // ---- SparseShrink (Alg 3): eig of P P^T, M = H D, the scalars of Alg 4
   CK(eig_sym_group(g.Wp, L, ell, ell, g.evals, g.evecs, K, LL, 2 * L, 4 * LL, g.eig_work, eig_work_bytes(ell), st));
   CK(ssh_post_group(g.evals, g.evecs, ell, L, kAlpha, g.M64, g.M32, g.sc, K, 2 * L, 4 * LL, st));
@@ -975,15 +1148,19 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     }
     constexpr int kScStride = (int)(sizeof(DevScalars) / sizeof(double));
     CK(vs_init(g.vs_w, d, g.vs_npart, g.sc, st, K));
-    for (int s2 = 0; s2 < tmax; ++s2) {
+    // one power step for every buffer (a buffer past its own t is left as it is): the same
+    // launches every step, captured once and replayed with SFD_OPT_GRAPHS
+    auto power_step = [&]() -> int {
       CK(spmv(g.rowptr, g.colidx, g.val, g.sr, g.vs_w, &g.sc->inv_norm, g.vs_z, g.partial, st, g.seg_rows, K,
               kScStride));
       CK(panel_gemv_t(g.Pt, L, L, d, g.vs_w, &g.sc->inv_norm, g.vs_gpart, st, K, kScStride));
       CK(spmv(g.cscptr, g.cscrow, g.cscval, g.scs, g.vs_z, nullptr, g.vs_wraw, g.partial, st));
       CK(vs_small(g.vs_gpart, gemv_blocks(d), g.M64, ell, L, g.vs_c2, st, K));
       CK(vs_finish(g.vs_wraw, g.Pt, L, L, ell, g.vs_c2, d, g.vs_w, g.vs_npart, st, K));
-      CK(vs_norm(g.vs_npart, vs_finish_blocks(d), g.sc, st, K, s2, g.tsteps));
-    }
+      CK(vs_norm(g.vs_npart, vs_finish_blocks(d), g.sc, st, K, g.tsteps));
+      return SFD_OK;
+    };
+    if ((rc = replay(h, st, tmax, power_step))) return rc;
     CK(hipMemcpyAsync(g.sc_host, g.sc, sizeof(DevScalars) * K, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     for (int k = 0; k < K; ++k) {
@@ -1501,6 +1678,14 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_CQR2:
       if (value != SFD_CQR2_OFF && value != SFD_CQR2_FINAL && value != SFD_CQR2_ALL) return SFD_E_ARG;
       h->cqr2 = (int)value;
+      return SFD_OK;
+    case SFD_OPT_AUTOTUNE:
+      if (value != 0 && value != 1) return SFD_E_ARG;
+      h->autotune = (int)value;
+      return SFD_OK;
+    case SFD_OPT_GRAPHS:
+      if (value != 0 && value != 1) return SFD_E_ARG;
+      h->graphs = (int)value;
       return SFD_OK;
     case SFD_OPT_LANES: {
       if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;

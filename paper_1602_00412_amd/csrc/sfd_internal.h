@@ -57,6 +57,12 @@ hipError_t set_identity(float* T, int L, int K, hipStream_t st);
 hipError_t to_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t st);
 // out (ell x d, row-major) = panel^T restricted to the first ell columns
 hipError_t transpose_out(const float* panel, int ld, int64_t d, int ell, float* out, hipStream_t st);
+// lockstep groups: for the K buffers with q[k] == *iter, Pt + k n <- X + k n (n floats) and
+// Wp + k m <- W + k m (m doubles); iter and q in device memory
+hipError_t group_snapshot(const int* iter, const int* q, int K, const float* X, float* Pt, int64_t n, const double* W,
+                          double* Wp, int64_t m, hipStream_t st);
+// *c += v (device counter, one thread)
+hipError_t counter_add(int* c, int v, hipStream_t st);
 
 // ---------------------------------------------------------------- ingest / CSC (sfd_ingest.hip)
 // validation of a device CSR block: err |= 1 for a decreasing or over-long row, 2 for a bad index
@@ -110,6 +116,15 @@ struct Schedule {
   // the other columns, walked by every block.
   int nlocal = 0;
   bool transposed = false;  // the CSC of a buffer (A'^T products); only names the kernels apart
+  int* queue = nullptr;     // kXcdBands + 2 work-queue counters of the ranges (persistent products)
+};
+
+// Launch configuration of a sparse product.  Every configuration sums each output row's entries
+// in the same order, so the choice changes the time, never the bits.
+struct SpmmConfig {
+  int unroll = 0;     // FP32 panels: entries gathered per batch, 8 (0: default) or 4
+  bool queue = false; // persistent grid fed by the schedule's work queues
+  int occupancy = 4;  // persistent grid: blocks per CU
 };
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
@@ -128,7 +143,10 @@ hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const
 // val_bf16: val holds BF16 values (uint16).  This launches the main kernel only; spmm_finish
 // completes the product.
 hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf16, const void* X, PanelType xt, int ldx,
-                void* Y, PanelType yt, int ldy, int L, float* partial, hipStream_t st);
+                void* Y, PanelType yt, int ldy, int L, float* partial, const SpmmConfig& cfg, hipStream_t st);
+// clears the schedule's work queues (the fix-up does this after every product; needed only
+// between products launched back to back without one)
+hipError_t spmm_queue_reset(const Schedule& s, hipStream_t st);
 // the long rows' fix-up of a product
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st);
 // z[r] = scale * sum_k val[k] y[idx[k]], scale = *scale_ptr (nullptr: 1); for a group's stacked
@@ -231,9 +249,9 @@ hipError_t vs_small(const float* part, int nb, const double* M64, int ell, int L
 int vs_finish_blocks(int64_t d);
 hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell, const float* c2, int64_t d,
                      float* w, double* part, hipStream_t st, int K = 1);
-// reduce ||w||^2, ln_norm += ln||w|| - ln(Delta/2), inv_norm = 1/||w||; in a group a buffer
-// whose step count tsteps[k] is reached (step >= tsteps[k]) is left as it is
-hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K = 1, int step = 0,
-                   const int* tsteps = nullptr);
+// reduce ||w||^2, ln_norm += ln||w|| - ln(Delta/2), inv_norm = 1/||w||; in a group, tsteps[k]
+// counts buffer k's remaining steps down (a buffer at 0 is left as it is), so every step is the
+// same launch
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K = 1, int* tsteps = nullptr);
 
 }  // namespace sfd

@@ -62,10 +62,12 @@ __global__ void k_sched_desc(const int* ptr, int rows, const int* chunk_start, c
   }
 }
 
-// regions[k] = chunk_start[k * span], k = 0 .. nreg (the chunk ranges of a schedule)
-__global__ void k_sched_regions(const int* chunk_start, int64_t span, int nreg, int* regions) {
+// regions[k] = chunk_start[k * span], k = 0 .. nreg (the chunk ranges of a schedule); the work
+// queue counters of the ranges start at 0
+__global__ void k_sched_regions(const int* chunk_start, int64_t span, int nreg, int* regions, int* queue) {
   const int k = threadIdx.x;
   if (k <= nreg) regions[k] = chunk_start[(int64_t)k * span];
+  if (queue && k < kXcdBands + 2) queue[k] = 0;
 }
 
 // rb[b] = first row of row band b (b = 0 .. kXcdBands; rb[kXcdBands] = m); row r is in band
@@ -275,9 +277,13 @@ __device__ inline float load_val(const void* __restrict__ val, int q) {
     return reinterpret_cast<const float*>(val)[q];
 }
 
-template <int L, int U, bool BIN, bool BOUT, bool VB>
+// QUEUE: the group takes its chunks from a work queue (the counter *queue of the range, one
+// atomic per chunk by the group's first lane) instead of first, first + stride, ...; the group
+// holds one chunk ahead, so the descriptor of the next chunk is loaded before the current one's
+// gathers either way.
+template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE>
 __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_t c0, int64_t c1, int64_t first,
-                                           int64_t stride, const int* __restrict__ idx,
+                                           int64_t stride, int* __restrict__ queue, const int* __restrict__ idx,
                                            const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                            void* __restrict__ out, int ldo, float* __restrict__ partial) {
   using S = Seg<BIN>;
@@ -287,9 +293,20 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
   const typename S::raw* Xs = reinterpret_cast<const typename S::raw*>(X);
   const int lds = ldx / VEC;  // row pitch in segments
   const size_t out_row_bytes = (size_t)ldo * (BOUT ? 2 : 4);
-  int64_t cc = c0 + first;
+  // the group's next chunk: from the queue (the first lane takes a ticket, the group shares it)
+  // or the next of the static sequence
+  auto next_chunk = [&](int64_t cur) -> int64_t {
+    if constexpr (QUEUE) {
+      int t = 0;
+      if (sub == 0) t = atomicAdd(queue, 1);
+      return c0 + bcast_i<LPR, 0>(t);
+    } else {
+      return cur + stride;
+    }
+  };
+  int64_t cc = QUEUE ? next_chunk(0) : c0 + first;
   int4 dc = cc < c1 ? desc[cc] : make_int4(0, 0, 0, -1);
-  int64_t ncc = cc + stride;
+  int64_t ncc = cc < c1 ? next_chunk(cc) : c1;
   int4 dn = ncc < c1 ? desc[ncc] : make_int4(0, 0, 0, -1);
   int p = dc.y;
   int ci = 0;
@@ -335,7 +352,7 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
       for (int q = 0; q < VEC; ++q) acc[q] = 0.f;
       cc = ncc;
       dc = dn;
-      ncc += stride;
+      ncc = cc < c1 ? next_chunk(cc) : c1;
       dn = ncc < c1 ? desc[ncc] : make_int4(0, 0, 0, -1);
     }
     p = np;
@@ -348,9 +365,12 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
 // regions[1]).  nlocal = kXcdBands: a block first walks the pieces of its XCD's row band
 // (range blockIdx % nlocal, shared with the other blocks of that XCD), then its share of the
 // short columns' range (range nlocal, shared with all blocks); gridDim.x is a multiple of nlocal.
-template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT, bool VB>
+// QUEUE: a persistent grid (a few blocks per CU) whose groups take chunks from the ranges' work
+// queues (queue[range]); otherwise a grid of about four chunks per group walked statically.
+// Either way each chunk is summed by one group in entry order, so the results are the same bits.
+template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT, bool VB, bool QUEUE>
 __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ regions,
-                                              int nlocal, const int* __restrict__ idx,
+                                              int nlocal, int* __restrict__ queue, const int* __restrict__ idx,
                                               const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                               void* __restrict__ out, int ldo, float* __restrict__ partial) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);  // groups per wave
@@ -360,24 +380,29 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
   if (nlocal > 0) {
     const int band = blockIdx.x % nlocal;
     const int64_t slot = blockIdx.x / nlocal;
-    spmm_range<L, U, BIN, BOUT, VB>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
-                                (int64_t)(gridDim.x / nlocal) * 4 * G, idx, val, X, ldx, out, ldo, partial);
+    spmm_range<L, U, BIN, BOUT, VB, QUEUE>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
+                                           (int64_t)(gridDim.x / nlocal) * 4 * G, queue + band, idx, val, X, ldx, out,
+                                           ldo, partial);
   }
-  spmm_range<L, U, BIN, BOUT, VB>(desc, regions[nlocal], regions[nlocal + 1], ((int64_t)blockIdx.x * 4 + wave) * G + grp,
-                              (int64_t)gridDim.x * 4 * G, idx, val, X, ldx, out, ldo, partial);
+  spmm_range<L, U, BIN, BOUT, VB, QUEUE>(desc, regions[nlocal], regions[nlocal + 1],
+                                         ((int64_t)blockIdx.x * 4 + wave) * G + grp, (int64_t)gridDim.x * 4 * G,
+                                         queue + nlocal, idx, val, X, ldx, out, ldo, partial);
 }
 
 // One block per long row: wave w adds the row's partials w, w + 4, ... (in slot order), then
 // the four wave sums are added in wave order.
+// The product's work queues are cleared here for the next product over the schedule (the
+// product has completed: the fix-up runs after it on the same stream).
 template <int L, bool BOUT>
 __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ slot_start,
                                                     const int* __restrict__ long_rows, const int* __restrict__ nlong_ptr,
                                                     const float* __restrict__ partial, void* __restrict__ Y,
-                                                    int ldy) {
+                                                    int ldy, int* __restrict__ queue) {
   constexpr int CPL = (L + 63) / 64;  // columns per lane
   __shared__ float red[4][L];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  if (queue && blockIdx.x == 0 && threadIdx.x < kXcdBands + 2) queue[threadIdx.x] = 0;
   const int nlong = *nlong_ptr;
   for (int li = blockIdx.x; li < nlong; li += gridDim.x) {
   const int r = long_rows[li];
@@ -491,36 +516,63 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ slot
   }
 }
 
-template <int L, int U, bool BIN, bool BOUT, bool VB>
+int device_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE>
 void launch_spmm(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
-                 float* partial, hipStream_t st) {
+                 float* partial, int occupancy, hipStream_t st) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);
-  // about four chunks per group; the grid is not persistent (finished blocks make room for
-  // waiting ones, which balances uneven chunks), and a multiple of the XCD count for pieces
+  // static: about four chunks per group (finished blocks make room for waiting ones, which
+  // balances uneven chunks); queue: `occupancy` blocks per CU at most.  A multiple of the XCD
+  // count when the schedule has XCD-local pieces.
   int64_t grid = ((int64_t)s.max_chunks + 16 * G - 1) / (16 * G);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, kSpmmMaxBlocks));
+  if (QUEUE) grid = std::min<int64_t>(grid, (int64_t)device_cus() * std::max(occupancy, 1));
   if (s.nlocal > 0) grid = (grid + s.nlocal - 1) / s.nlocal * s.nlocal;
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
-    k_spmm<L, U, true, BIN, BOUT, VB><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx,
-                                                                      out, ldo, partial);
+    k_spmm<L, U, true, BIN, BOUT, VB, QUEUE><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, s.queue, idx,
+                                                                             val, X, ldx, out, ldo, partial);
   else
-    k_spmm<L, U, false, BIN, BOUT, VB><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, idx, val, X, ldx,
-                                                                       out, ldo, partial);
+    k_spmm<L, U, false, BIN, BOUT, VB, QUEUE><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, s.queue,
+                                                                              idx, val, X, ldx, out, ldo, partial);
+}
+
+template <int L, int U, bool BIN, bool BOUT, bool VB>
+void launch_spmm_cfg(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
+                     float* partial, const SpmmConfig& cfg, hipStream_t st) {
+  if (cfg.queue)
+    launch_spmm<L, U, BIN, BOUT, VB, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, st);
+  else
+    launch_spmm<L, U, BIN, BOUT, VB, false>(s, idx, val, X, ldx, out, ldo, partial, 0, st);
 }
 
 template <int L>
 hipError_t spmm_l(const Schedule& s, const int* idx, const void* val, bool vb, const void* X, PanelType xt, int ldx,
-                  void* Y, PanelType yt, int ldy, float* partial, hipStream_t st) {
+                  void* Y, PanelType yt, int ldy, float* partial, const SpmmConfig& cfg, hipStream_t st) {
   const bool xb = xt == PanelType::BF16, yb = yt == PanelType::BF16;
-  // FP32 form: FP32 values and panels.  Precision form: BF16 values and panels in the products
-  // 1 .. 2q+1, FP32 values and output in the last (P^T = A'^T Y)
+  // FP32 form: FP32 values and panels (entries gathered in batches of 8, or 4).  Precision form:
+  // BF16 values and panels in the products 1 .. 2q+1, FP32 values and output in the last
+  // (P^T = A'^T Y); batches of 4
   if (!xb && !yb && !vb) {
-    launch_spmm<L, 8, false, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+    if (cfg.unroll == 4)
+      launch_spmm_cfg<L, 4, false, false, false>(s, idx, val, X, ldx, Y, ldy, partial, cfg, st);
+    else
+      launch_spmm_cfg<L, 8, false, false, false>(s, idx, val, X, ldx, Y, ldy, partial, cfg, st);
   } else if (xb && yb && vb) {
-    launch_spmm<L, 4, true, true, true>(s, idx, val, X, ldx, Y, ldy, partial, st);
+    launch_spmm_cfg<L, 4, true, true, true>(s, idx, val, X, ldx, Y, ldy, partial, cfg, st);
   } else if (xb && !yb && !vb) {
-    launch_spmm<L, 4, true, false, false>(s, idx, val, X, ldx, Y, ldy, partial, st);
+    launch_spmm_cfg<L, 4, true, false, false>(s, idx, val, X, ldx, Y, ldy, partial, cfg, st);
   } else {
     return hipErrorInvalidValue;
   }
@@ -530,9 +582,9 @@ hipError_t spmm_l(const Schedule& s, const int* idx, const void* val, bool vb, c
 template <int L>
 void launch_fixup(const Schedule& s, float* partial, void* Y, bool yb, int ldy, hipStream_t st) {
   if (yb)
-    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy, s.queue);
   else
-    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy);
+    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy, s.queue);
 }
 
 }  // namespace
@@ -546,7 +598,7 @@ hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, 
   if (rows > 0)
     k_sched_desc<<<grid_for(rows, 256, 8192), 256, 0, st>>>(ptr, rows, s.nch, s.pslot, s.desc, s.long_rows,
                                                              s.counters);
-  k_sched_regions<<<1, 64, 0, st>>>(s.nch, rows, 1, s.regions);
+  k_sched_regions<<<1, 64, 0, st>>>(s.nch, rows, 1, s.regions, s.queue);
   s.rows = rows;
   s.nlocal = 0;
   return hipGetLastError();
@@ -566,19 +618,25 @@ hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const
   if ((e = fill_i32(s.counters, 1, 0, st)) != hipSuccess) return e;
   k_hot_desc<<<grid_for(d, 256, 8192), 256, 0, st>>>(cscptr, cscrow, d, hot_min, rb, s.nch, s.pslot, s.desc,
                                                       s.long_rows, s.counters);
-  k_sched_regions<<<1, 64, 0, st>>>(s.nch, d, kXcdBands + 1, s.regions);
+  k_sched_regions<<<1, 64, 0, st>>>(s.nch, d, kXcdBands + 1, s.regions, s.queue);
   s.rows = d;
   s.nlocal = kXcdBands;
   return hipGetLastError();
 }
 
 hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf16, const void* X, PanelType xt, int ldx,
-                void* Y, PanelType yt, int ldy, int L, float* partial, hipStream_t st) {
-  if (L == 32) return spmm_l<32>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 64) return spmm_l<64>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 128) return spmm_l<128>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
-  if (L == 256) return spmm_l<256>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, st);
+                void* Y, PanelType yt, int ldy, int L, float* partial, const SpmmConfig& cfg, hipStream_t st) {
+  if (cfg.queue && !s.queue) return hipErrorInvalidValue;
+  if (L == 32) return spmm_l<32>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
+  if (L == 64) return spmm_l<64>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
+  if (L == 128) return spmm_l<128>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
+  if (L == 256) return spmm_l<256>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t spmm_queue_reset(const Schedule& s, hipStream_t st) {
+  if (!s.queue) return hipSuccess;
+  return fill_i32(s.queue, kXcdBands + 2, 0, st);
 }
 
 hipError_t spmm_finish(const Schedule& s, float* partial, void* Y, PanelType yt, int ldy, int L, hipStream_t st) {

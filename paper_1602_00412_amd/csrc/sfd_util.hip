@@ -166,7 +166,40 @@ __global__ void k_set_identity(float* __restrict__ T, int L, int K) {
   }
 }
 
+// Buffers k of a lockstep group whose SimultaneousIteration ends at the current iteration
+// (q[k] == *iter) keep their panel and Gram: Pt_k <- X_k (n floats), Wp_k <- W_k (m doubles).
+// Block (x, k) copies its share of buffer k.
+__global__ __launch_bounds__(256) void k_group_snapshot(const int* __restrict__ iter, const int* __restrict__ q,
+                                                        const float* __restrict__ X, float* __restrict__ Pt,
+                                                        const double* __restrict__ W, double* __restrict__ Wp,
+                                                        int64_t n, int64_t m) {
+  const int k = blockIdx.y;
+  if (q[k] != *iter) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < n; i += stride) Pt[k * n + i] = X[k * n + i];
+  for (int64_t i = i0; i < m; i += stride) Wp[k * m + i] = W[k * m + i];
+}
+
+__global__ void k_counter_add(int* c, int v) {
+  if (threadIdx.x == 0) *c += v;
+}
+
 }  // namespace
+
+hipError_t group_snapshot(const int* iter, const int* q, int K, const float* X, float* Pt, int64_t n, const double* W,
+                          double* Wp, int64_t m, hipStream_t st) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  k_group_snapshot<<<dim3((unsigned)nb, (unsigned)K), 256, 0, st>>>(iter, q, X, Pt, W, Wp, n, m);
+  return hipGetLastError();
+}
+
+hipError_t counter_add(int* c, int v, hipStream_t st) {
+  k_counter_add<<<1, 64, 0, st>>>(c, v);
+  return hipGetLastError();
+}
 
 hipError_t set_identity(float* T, int L, int K, hipStream_t st) {
   const int64_t n = (int64_t)K * L * L;

@@ -175,14 +175,15 @@ __global__ __launch_bounds__(256) void k_vs_finish(const float* __restrict__ w_r
 
 // steps: the step being taken and, for a group, each buffer's step count (a buffer past its
 // count keeps its norm)
-__global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part, int nb, DevScalars* sc, int step,
-                                                 const int* __restrict__ tsteps) {
+__global__ __launch_bounds__(256) void k_vs_norm(const double* __restrict__ part, int nb, DevScalars* sc,
+                                                 int* __restrict__ tsteps) {
   __shared__ double s[256];
   part += (int64_t)blockIdx.x * nb;
   sc += blockIdx.x;
-  if (tsteps && step >= tsteps[blockIdx.x]) return;
-  double tot = block_sum(part, nb, s);
+  if (tsteps && tsteps[blockIdx.x] <= 0) return;
+  double tot = block_sum(part, nb, s);  // (its barriers order every thread's read of tsteps above)
   if (threadIdx.x == 0) {
+    if (tsteps) tsteps[blockIdx.x] -= 1;
     double nrm = sqrt(tot);
     if (sc->zero_flag || !(nrm > 0.0)) {
       sc->zero_flag = 1;
@@ -234,8 +235,8 @@ hipError_t vs_finish(const float* w_raw, const float* P, int ld, int L, int ell,
   return hipGetLastError();
 }
 
-hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K, int step, const int* tsteps) {
-  k_vs_norm<<<K, 256, 0, st>>>(part, nb, sc, step, tsteps);
+hipError_t vs_norm(const double* part, int nb, DevScalars* sc, hipStream_t st, int K, int* tsteps) {
+  k_vs_norm<<<K, 256, 0, st>>>(part, nb, sc, tsteps);
   return hipGetLastError();
 }
 

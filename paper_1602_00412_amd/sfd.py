@@ -44,6 +44,8 @@ OPT_CQR2 = 14
 CQR2_OFF = 0
 CQR2_FINAL = 1
 CQR2_ALL = 2
+OPT_AUTOTUNE = 15
+OPT_GRAPHS = 16
 ALGO_SFD = 0
 ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
@@ -242,7 +244,8 @@ class Sketch:
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
                  max_attempts=None, verify=None, stream_id=None, csc_bands=None, csc_hot_min=None,
-                 precision=None, algorithm=None, cqr2=None, use_torch_stream: bool = True):
+                 precision=None, algorithm=None, cqr2=None, autotune=None, graphs=None,
+                 use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_create(int(d), int(ell), float(eps), int(seed), ctypes.byref(h)), "sfd_create")
@@ -256,7 +259,9 @@ class Sketch:
                          (OPT_ALGORITHM, None if algorithm is None else
                           {"sfd": ALGO_SFD, "fd": ALGO_FD}.get(algorithm, algorithm)),
                          (OPT_CQR2, None if cqr2 is None else
-                          {"off": CQR2_OFF, "final": CQR2_FINAL, "all": CQR2_ALL}.get(cqr2, cqr2))):
+                          {"off": CQR2_OFF, "final": CQR2_FINAL, "all": CQR2_ALL}.get(cqr2, cqr2)),
+                         (OPT_AUTOTUNE, None if autotune is None else float(bool(autotune))),
+                         (OPT_GRAPHS, None if graphs is None else float(bool(graphs)))):
             if val is not None:
                 self.set_option(key, val)
         if use_torch_stream:
@@ -329,7 +334,7 @@ class Batch:
     Sketch with stream_id = s."""
 
     def __init__(self, nstreams: int, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, precision=None,
-                 lanes=None, use_torch_stream: bool = True):
+                 lanes=None, autotune=None, graphs=None, use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
         _check(lib.sfd_batch_create(int(nstreams), int(d), int(ell), float(eps), int(seed), ctypes.byref(h)),
@@ -340,6 +345,10 @@ class Batch:
             self.set_option(OPT_PRECISION, {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16}.get(precision, precision))
         if lanes is not None:
             self.set_option(OPT_LANES, lanes)
+        if autotune is not None:
+            self.set_option(OPT_AUTOTUNE, float(bool(autotune)))
+        if graphs is not None:
+            self.set_option(OPT_GRAPHS, float(bool(graphs)))
         if use_torch_stream:
             s = _torch_stream_handle()
             if s is not None:

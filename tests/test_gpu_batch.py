@@ -116,3 +116,54 @@ def test_batch_rejects_repeated_stream_and_bad_index(gpu_lib):
         b.append_csr([0, 2], starts, indptr, bad, val)
     assert e.value.code == gpu_lib.SFD_E_INDEX
     assert all(b.stats(s)["rows_seen"] == 0 for s in range(3))
+
+
+@pytest.mark.parametrize("ell", [12, 32])
+def test_graph_replay_and_autotune_keep_the_bits(gpu_lib, ell):
+    # The lockstep groups' iteration and power step are captured once as HIP graphs and replayed
+    # q + 1 (t) times; the products' launch configuration is tuned on first sight.  Three appends
+    # (each runs several groups, so several graphs, each replayed many times), with eager work and
+    # synchronisations in between: after every append each stream's sketch equals, bit for bit,
+    # that of a batch run launch by launch with the default configuration, and that of a
+    # single-stream handle.
+    import torch
+
+    d = 400
+    lens = [900, 2600, 1300, 3100, 450, 1900]
+    streams = [small_random_csr(n, d, 9, 300 + s, dist="lognormal") for s, n in enumerate(lens)]
+    thirds = [[(st.n * j) // 3 for j in range(4)] for st in streams]
+    fast = gpu_lib.Batch(len(streams), d, ell, graphs=True, autotune=True)
+    plain = gpu_lib.Batch(len(streams), d, ell, graphs=False, autotune=False)
+    singles = [gpu_lib.Sketch(d, ell, 0.25, 0, stream_id=s) for s in range(len(streams))]
+    for j in range(3):
+        parts = [st.rows(thirds[s][j], thirds[s][j + 1]) for s, st in enumerate(streams)]
+        indptr, idx, val, starts = _cat(parts)
+        g = [torch.from_numpy(a).cuda() for a in (indptr, idx, val)]
+        sos = np.arange(len(streams), dtype=np.int32)
+        for b in (fast, plain):
+            b.append_csr(sos, starts, *g)
+            torch.cuda.synchronize()
+        for s, p in enumerate(parts):
+            if p.n:
+                singles[s].append_csr(*[torch.from_numpy(a).cuda() for a in (p.indptr, p.indices, p.values)])
+        out_f = fast.sketch().cpu().numpy()
+        out_p = plain.sketch().cpu().numpy()
+        np.testing.assert_array_equal(out_f, out_p)
+        for s in range(len(streams)):
+            np.testing.assert_array_equal(out_f[s], singles[s].sketch().cpu().numpy())
+
+
+def test_autotune_keeps_the_bits_single_stream(gpu_lib):
+    # tuned configurations (static or persistent work-queue grid, gather batch) against the default
+    # one, with XCD-local pieces forced so the band queues are exercised too
+    import torch
+
+    st = small_random_csr(6000, 3000, 30, 41, dist="lognormal")
+    dev = [torch.from_numpy(a).cuda() for a in (st.indptr, st.indices, st.values)]
+    outs = []
+    for tune in (False, True, True):
+        sk = gpu_lib.Sketch(st.d, 40, 0.25, 0, autotune=tune, csc_bands=8, csc_hot_min=8)
+        sk.append_csr(*dev)
+        outs.append(sk.sketch().cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])

@@ -63,3 +63,23 @@ def test_native_sources_include_nothing_from_the_oracle():
             with open(os.path.join(csrc, n)) as f:
                 for inc in re.findall(r'#include\s+"([^"]+)"', f.read()):
                     assert "oracle" not in inc, (n, inc)
+
+
+def test_bench_runs_the_oracle_only_in_its_cpu_baseline_leg():
+    # bench.py may run the oracle only to time it (and to check the device path against what it
+    # computes): every import of oracle/ sits inside a function named cpu_baseline*
+    path = os.path.join(ROOT, "bench.py")
+    with open(path) as f:
+        tree = ast.parse(f.read(), filename=path)
+
+    def visit(node, owner):
+        for child in ast.iter_child_nodes(node):
+            name = child.name if isinstance(child, (ast.FunctionDef, ast.AsyncFunctionDef)) else owner
+            if isinstance(child, ast.Import):
+                assert all(a.name.split(".")[0] != "oracle" for a in child.names) or \
+                    (owner or "").startswith("cpu_baseline"), (owner, child.lineno)
+            elif isinstance(child, ast.ImportFrom) and child.module and child.module.split(".")[0] == "oracle":
+                assert (owner or "").startswith("cpu_baseline"), (owner, child.lineno)
+            visit(child, name)
+
+    visit(tree, None)
