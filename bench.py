@@ -231,6 +231,37 @@ def measure_batch_full(streams: int, steps: int, warmup: int) -> dict:
     return rec
 
 
+FORM_QUEUES = {"ell200": 32, "d1e6": 16, "batch4096": 16}  # hardware queues of each form's process
+
+
+def run_form_child(name: str, args) -> dict:
+    """One form measured by a child process (bench.py --form-child name), its record parsed from
+    the JSON line it prints."""
+    import subprocess
+
+    if name not in FORM_QUEUES:
+        raise SystemExit(f"unknown form {name}")
+    env = dict(os.environ)
+    env["GPU_MAX_HW_QUEUES"] = str(FORM_QUEUES[name])
+    cmd = [sys.executable, os.path.abspath(__file__), "--form-child", name, "--autotune", str(args.autotune),
+           "--graphs", str(args.graphs)]
+    log(f"form {name}: child process, {FORM_QUEUES[name]} hardware queues")
+    res = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True)
+    if res.returncode != 0:
+        raise SystemExit(f"form {name} failed (exit {res.returncode})")
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def form_child(name: str) -> int:
+    """The child side of run_form_child: measures one form and prints its record."""
+    if name in ("ell200", "d1e6"):
+        rec = measure_large_stream(name, 1, 1)
+    else:
+        rec = measure_batch_full(4096, 1, 1)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def run_batch_full(args) -> int:
     """All 4,096 streams of the batching workload as the line's workload."""
     rec = measure_batch_full(args.batch_first_streams, args.steps, args.warmup)
@@ -401,7 +432,9 @@ def main() -> int:
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="SFD_OPT_GRAPHS of the batch handles (1: graph-captured group steps, the default)")
     ap.add_argument("--big-forms", default="ell200,d1e6,batch4096",
-                    help="forms on their own workloads timed after the line (comma-separated; empty: none)")
+                    help="forms on their own workloads timed after the line, each in a child process "
+                         "(comma-separated; empty: none)")
+    ap.add_argument("--form-child", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch-streams", type=int, default=64,
                     help="streams of the batched form (4,096-stream recipe: d=2e4, ell=32, Poisson(30)); 0 skips it")
     ap.add_argument("--lanes", type=int, default=0, help="lanes of the timed FP32 line (0: the library's default)")
@@ -430,8 +463,9 @@ def main() -> int:
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     else:
-        # the ell = 200 workload's handles run 8 lanes each (also a form of the default run)
-        want = 32 if (args.workload == "ell200" or "ell200" in args.big_forms) else 16
+        # the ell = 200 workload's handles run 8 lanes each (the forms run in child processes with
+        # their own setting)
+        want = 32 if args.workload == "ell200" else 16
         try:
             have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
         except ValueError:
@@ -444,6 +478,18 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
               f"one merge at the end; runs across several GPUs are not implemented", file=sys.stderr)
         return 2
+
+    # The forms on their own workloads (ell = 200; d = 1e6, ell = 100; all 4,096 batch streams):
+    # each in a child process of its own with its own hardware-queue count, one after another,
+    # before this process starts on the GPU (so no idle queues of this process compete with
+    # theirs); the records join the line's "forms".
+    big_forms = {}
+    if (not args.form_child and not args.no_forms and not args.profile_only and args.precision == "fp32"
+            and args.workload == "stream1e6"):
+        for name in args.big_forms.split(","):
+            name = name.strip()
+            if name:
+                big_forms[name] = run_form_child(name, args)
 
     import numpy as np
     import torch
@@ -465,6 +511,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
         return 0
+    if args.form_child:
+        return form_child(args.form_child)
     if args.workload == "batch4096":
         return run_batch_full(args)
     if args.workload == "paper":
@@ -725,20 +773,8 @@ def main() -> int:
     # The precision form on its own workloads (ell = 200; d = 1e6, ell = 100) and the batched form
     # on all 4,096 streams, each generated on the device after the 10^6-row stream's handles are
     # released.
-    if not args.no_forms and not args.profile_only and args.precision == "fp32" and args.workload == "stream1e6":
-        del sk_bf
-        sk_bf = None
-        free_gpu()
-        for name in args.big_forms.split(","):
-            name = name.strip()
-            if not name:
-                continue
-            if name in ("ell200", "d1e6"):
-                forms[name] = measure_large_stream(name, 1, 1)
-            elif name == "batch4096":
-                forms[name] = measure_batch_full(4096, 1, 1)
-            else:
-                raise SystemExit(f"unknown form {name}")
+    # (measured by child processes before this process started on the GPU, see main's start)
+    forms.update(big_forms)
 
     cpu = None
     parity = None

@@ -123,10 +123,16 @@ enum {
                                       the environment variable SFD_TUNE_CACHE names a file that
                                       keeps the choices across processes.  Every candidate gives
                                       the same bits.  0: the default configuration. */
-  SFD_OPT_GRAPHS = 16              /* batch handles, 1 (default): each lockstep group's
-                                      SimultaneousIteration step and VerifySpectral power step are
-                                      captured once as HIP graphs and replayed (q + 1, resp. t
-                                      times); 0: issued launch by launch.  Same results. */
+  SFD_OPT_GRAPHS = 16,             /* 1 (default): the SimultaneousIteration step of each buffer
+                                      step (of a lane, or of a batch handle's lockstep group) and
+                                      its VerifySpectral power step are captured once as HIP graphs
+                                      and replayed (q, resp. t times); 0 (and while SFD_OPT_PROFILE
+                                      is on): issued launch by launch.  Same results. */
+  SFD_OPT_PRODUCT_LAUNCH = 17     /* 0 (default): the sparse products' launches as SFD_OPT_AUTOTUNE
+                                      decides; 1: static grid; 2: persistent grid fed by device
+                                      work queues; 3: as 2, and the products Y = A' X of a lane
+                                      stage the input rows of the buffer's most popular columns
+                                      (up to 32 KB) in LDS.  Same results in every mode. */
 };
 
 enum { SFD_CQR2_OFF = 0, SFD_CQR2_FINAL = 1, SFD_CQR2_ALL = 2 };

@@ -152,6 +152,7 @@ struct sfd_s {
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
   int cqr2 = SFD_CQR2_FINAL;           // SFD_OPT_CQR2 (precision form)
   int autotune = 1;                    // SFD_OPT_AUTOTUNE
+  int launch = 0;                      // SFD_OPT_PRODUCT_LAUNCH
   int graphs = 1;                      // SFD_OPT_GRAPHS (lockstep groups of a batch handle)
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
   int test_zero_row = -1;              // SFD_OPT_TEST_ZERO_ROW
@@ -360,6 +361,8 @@ int alloc_lane(sfd_t* h, Lane& ln) {
          dalloc(h, &s->queue, kXcdBands + 2);
     s->max_chunks = max_chunks;
   }
+  ok = ok && dalloc(h, &ln.sr.stage_idx, cap) && dalloc(h, &ln.sr.hot_cols, 512) && dalloc(h, &ln.sr.hot_n, 34) &&
+       dalloc(h, &ln.sr.slot_of, d);
   ok = ok && dalloc(h, &ln.partial, slots * L);
   ln.scs.transposed = true;
   ok = ok && dalloc(h, &ln.X, d * L) && dalloc(h, &ln.Y, d * L) && dalloc(h, &ln.Pt, d * L);
@@ -473,13 +476,14 @@ struct Tuner {
     if (!path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    int k[9], u, qu, oc;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
-                       &k[7], &k[8], &u, &qu, &oc) == 12) {
+    int k[9], u, qu, oc, sg;
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
+                       &k[7], &k[8], &u, &qu, &oc, &sg) == 13) {
       SpmmConfig c;
       c.unroll = u;
       c.queue = qu != 0;
       c.occupancy = oc;
+      c.stage = sg != 0;
       best[TuneKey{k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]}] = c;
     }
     std::fclose(f);
@@ -490,9 +494,9 @@ struct Tuner {
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
                  std::get<3>(key), std::get<4>(key), std::get<5>(key), std::get<6>(key), std::get<7>(key),
-                 std::get<8>(key), c.unroll, c.queue ? 1 : 0, c.occupancy);
+                 std::get<8>(key), c.unroll, c.queue ? 1 : 0, c.occupancy, c.stage ? 1 : 0);
     std::fclose(f);
   }
 };
@@ -513,8 +517,15 @@ int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, 
                    const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows, int64_t nnz,
                    SpmmConfig* out) {
   *out = SpmmConfig{};
+  if (h->launch > 0) {
+    // a fixed launch: static grid, work-queue grid, or work-queue grid staging (where possible)
+    out->queue = h->launch >= 2;
+    out->stage = h->launch == 3 && !s.transposed && s.stage_idx != nullptr;
+    return SFD_OK;
+  }
   if (!h->autotune) return SFD_OK;
-  const TuneKey key{h->L, s.transposed ? 1 : 0, (int)xt, (int)yt, vb ? 1 : 0, s.nlocal > 0 ? 1 : 0,
+  const bool can_stage = !s.transposed && s.stage_idx != nullptr;
+  const TuneKey key{h->L, s.transposed ? 1 : 0, (int)xt, (int)yt, vb ? 1 : 0, (s.nlocal > 0 ? 1 : 0) + (can_stage ? 2 : 0),
                     log2_bucket(nnz), log2_bucket(in_rows), log2_bucket(s.rows)};
   std::lock_guard<std::mutex> lock(g_tuner.mu);
   g_tuner.load();
@@ -524,14 +535,17 @@ int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, 
     return SFD_OK;
   }
   std::vector<SpmmConfig> cand;
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 3; ++q) {
+    if (q == 2 && !can_stage) continue;
     for (int u : {8, 4}) {
       if (xt == PanelType::BF16 && u != 4) continue;  // BF16 panels gather in batches of 4 only
       SpmmConfig c;
       c.unroll = xt == PanelType::BF16 ? 0 : u;
-      c.queue = q != 0;
+      c.queue = q != 0;    // 1: work-queue grid
+      c.stage = q == 2;    // 2: work-queue grid with the popular rows of X staged in LDS
       cand.push_back(c);
     }
+  }
   // measured alone: the work of the other lanes and streams finishes first, so the candidates'
   // times are not mixed with theirs (once per key, in a warm-up)
   CK(hipDeviceSynchronize());
@@ -565,6 +579,35 @@ int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, 
   g_tuner.store(key, cand[bi]);
   *out = cand[bi];
   return SFD_OK;
+}
+
+// `body` (launches on st only, no host synchronisation) run n times: captured once as a HIP graph
+// and launched n times when SFD_OPT_GRAPHS is on, else issued n times (also while the per-class
+// profile is on: its events bracket each launch).
+template <class F>
+int replay(sfd_t* h, hipStream_t st, int n, F&& body) {
+  if (n <= 0) return SFD_OK;
+  if (!h->graphs || h->prof || n == 1) {
+    for (int i = 0; i < n; ++i) {
+      int rc = body();
+      if (rc) return rc;
+    }
+    return SFD_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = body();
+  const hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (rc || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : SFD_E_DEVICE;
+  }
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(exec, st);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  return e == hipSuccess ? SFD_OK : SFD_E_DEVICE;
 }
 
 // The output of a product whose input panel had transform T (the lane's current one):
@@ -647,6 +690,9 @@ int prepare(sfd_t* h, Lane& ln) {
     }
     ln.sr.max_chunks = (int64_t)ln.m + (int64_t)ln.nnz / kSpmmChunk + 2;
     CK(schedule_build(ln.rowptr, ln.m, ln.sr, ln.scan_tmp, ln.st));
+    // the rows a product Y = A' X may stage in LDS (a launch candidate of the autotuner)
+    if (h->autotune || h->launch == 3)
+      CK(stage_build(ln.cscptr, (int)d, ln.colidx, ln.nnz, h->L, h->precision == SFD_PRECISION_BF16, ln.sr, ln.st));
     if (csc_hot(h, ln.m, ln.nnz)) {
       // at most nnz / hot columns reach `hot`, so at most hot_cap
       const int64_t hot = std::max<int64_t>(h->hot_min, (ln.nnz + h->hot_cap - 1) / h->hot_cap);
@@ -693,14 +739,29 @@ int sparse_shrink(sfd_t* h, Lane& ln, int attempt) {
   // the first transform from the Gram of G itself (G T = G with T = I)
   CK(set_identity(ln.T, L, 1, ln.st));
   if ((rc = orth_out(h, ln, X, pt, d))) return rc;
-  for (int it = 0; it < ln.q; ++it) {
-    if ((rc = spmm_csr(h, ln, X, pt, Y, pt, bf))) return rc;
-    if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
-    if (cqr2_all && (rc = orth_out(h, ln, Y, pt, m))) return rc;
-    if ((rc = spmm_csc(h, ln, Y, pt, X, pt, bf))) return rc;
-    if ((rc = orth_out(h, ln, X, pt, d))) return rc;
-    if (cqr2_all && (rc = orth_out(h, ln, X, pt, d))) return rc;
+  // the products' launch configurations before any capture (tuning synchronises); the transposed
+  // product's candidates write P^T, which the last product overwrites
+  if (ln.q > 0) {
+    SpmmConfig c;
+    const void* vr = bf ? static_cast<const void*>(ln.valb) : static_cast<const void*>(ln.val);
+    const void* vc = bf ? static_cast<const void*>(ln.cscvalb) : static_cast<const void*>(ln.cscval);
+    if ((rc = product_config(h, ln.st, ln.sr, ln.colidx, vr, bf, X, pt, Y, pt, ln.partial, d, ln.nnz, &c))) return rc;
+    if ((rc = product_config(h, ln.st, ln.scs, ln.cscrow, vc, bf, Y, pt, ln.Pt, pt, ln.partial, m, ln.nnz, &c)))
+      return rc;
   }
+  // one iteration: Y = A' X T_x, X = A'^T Y T_y with their CholeskyQR steps -- the same launches
+  // with the same arguments every time, so with SFD_OPT_GRAPHS it is captured once and replayed
+  auto iteration = [&]() -> int {
+    int r;
+    if ((r = spmm_csr(h, ln, X, pt, Y, pt, bf))) return r;
+    if ((r = orth_out(h, ln, Y, pt, m))) return r;
+    if (cqr2_all && (r = orth_out(h, ln, Y, pt, m))) return r;
+    if ((r = spmm_csc(h, ln, Y, pt, X, pt, bf))) return r;
+    if ((r = orth_out(h, ln, X, pt, d))) return r;
+    if (cqr2_all && (r = orth_out(h, ln, X, pt, d))) return r;
+    return SFD_OK;
+  };
+  if ((rc = replay(h, ln.st, ln.q, iteration))) return rc;
   if ((rc = spmm_csr(h, ln, X, pt, Y, pt, bf))) return rc;
   if ((rc = orth_out(h, ln, Y, pt, m))) return rc;
   if (cqr2_final && (rc = orth_out(h, ln, Y, pt, m))) return rc;
@@ -732,15 +793,17 @@ int verify_spectral(sfd_t* h, Lane& ln, int attempt, int t) {
   CK(start_block(h->seed, ln.ss->stream_id, (uint64_t)ln.buffer, (uint64_t)attempt, (uint64_t)ln.px, d, 1, ln.vs_w,
                  1, ln.st));
   CK(vs_init(ln.vs_w, d, ln.vs_npart, ln.sc, ln.st));
-  for (int s = 0; s < t; ++s) {
+  // one power step (the same launches every step: captured once and replayed with SFD_OPT_GRAPHS)
+  auto power_step = [&]() -> int {
     CK(spmv(ln.rowptr, ln.colidx, ln.val, ln.sr, ln.vs_w, &ln.sc->inv_norm, ln.vs_z, ln.partial, ln.st));
     CK(panel_gemv_t(ln.Pt, L, L, d, ln.vs_w, &ln.sc->inv_norm, ln.vs_gpart, ln.st));
     CK(spmv(ln.cscptr, ln.cscrow, ln.cscval, ln.scs, ln.vs_z, nullptr, ln.vs_wraw, ln.partial, ln.st));
     CK(vs_small(ln.vs_gpart, gemv_blocks(d), ln.M64, ell, L, ln.vs_c2, ln.st));
     CK(vs_finish(ln.vs_wraw, ln.Pt, L, L, ell, ln.vs_c2, d, ln.vs_w, ln.vs_npart, ln.st));
     CK(vs_norm(ln.vs_npart, vs_finish_blocks(d), ln.sc, ln.st));
-  }
-  return SFD_OK;
+    return SFD_OK;
+  };
+  return replay(h, ln.st, t, power_step);
 }
 
 // Issue everything of a buffer step that does not depend on B or on the VerifySpectral counter.
@@ -842,34 +905,6 @@ int finish_step(sfd_t* h, Lane& ln, int64_t vs_base, int live_in, const float* B
   if ((rc = dense_shrink(h, ln, Bin, ln.Pt, lossless, out))) return rc;
   *live = lossless ? live_in + r_add : ell - 1;
   return SFD_OK;
-}
-
-// `body` (launches on st only, no host synchronisation) run n times: captured once as a HIP graph
-// and launched n times when SFD_OPT_GRAPHS is on, else issued n times.
-template <class F>
-int replay(sfd_t* h, hipStream_t st, int n, F&& body) {
-  if (n <= 0) return SFD_OK;
-  if (!h->graphs || n == 1) {
-    for (int i = 0; i < n; ++i) {
-      int rc = body();
-      if (rc) return rc;
-    }
-    return SFD_OK;
-  }
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  const int rc = body();
-  const hipError_t ce = hipStreamEndCapture(st, &graph);
-  if (rc || ce != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc ? rc : SFD_E_DEVICE;
-  }
-  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(exec, st);
-  if (exec) (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  return e == hipSuccess ? SFD_OK : SFD_E_DEVICE;
 }
 
 // Group workspace for up to kmax buffers (batch handles).
@@ -1686,6 +1721,10 @@ int sfd_set_option(sfd_t* h, int key, double value) {
     case SFD_OPT_GRAPHS:
       if (value != 0 && value != 1) return SFD_E_ARG;
       h->graphs = (int)value;
+      return SFD_OK;
+    case SFD_OPT_PRODUCT_LAUNCH:
+      if (!(value >= 0 && value <= 3) || value != std::floor(value)) return SFD_E_ARG;
+      h->launch = (int)value;
       return SFD_OK;
     case SFD_OPT_LANES: {
       if (!(value >= 1 && value <= kLanes) || value != std::floor(value)) return SFD_E_ARG;

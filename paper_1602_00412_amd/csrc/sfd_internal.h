@@ -117,6 +117,13 @@ struct Schedule {
   int nlocal = 0;
   bool transposed = false;  // the CSC of a buffer (A'^T products); only names the kernels apart
   int* queue = nullptr;     // kXcdBands + 2 work-queue counters of the ranges (persistent products)
+  // rows staged in LDS (CSR schedules of the products Y = A' X; stage_build): the column ids
+  // with the staged ones encoded (nnz), the staged columns, {count, threshold, histogram[32]},
+  // and the slot of every column (d)
+  int* stage_idx = nullptr;
+  int* hot_cols = nullptr;
+  int* hot_n = nullptr;
+  int* slot_of = nullptr;
 };
 
 // Launch configuration of a sparse product.  Every configuration sums each output row's entries
@@ -125,9 +132,15 @@ struct SpmmConfig {
   int unroll = 0;     // FP32 panels: entries gathered per batch, 8 (0: default) or 4
   bool queue = false; // persistent grid fed by the schedule's work queues
   int occupancy = 4;  // persistent grid: blocks per CU
+  bool stage = false; // Y = A' X with a queue grid: the most popular columns' rows of X in LDS
 };
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
+// staging of a buffer's CSR schedule s: the columns whose entry counts (from its CSC colptr) reach
+// the largest power of two that keeps them within 32 KB of LDS rows (L wide, FP32 or BF16), and
+// the column ids of colidx (nnz) with those encoded as -1 - slot, into s's staging arrays
+hipError_t stage_build(const int* cscptr, int d, const int* colidx, int64_t nnz, int L, bool bf16, Schedule& s,
+                       hipStream_t st);
 // The schedule of a buffer's CSC (d columns, rows ascending in every column) with XCD-local
 // pieces: the rows of the buffer (CSR rowptr, m rows, nnz entries) are cut into kXcdBands
 // contiguous bands of about nnz / kXcdBands entries (row r in band floor(rowptr[r] kXcdBands /

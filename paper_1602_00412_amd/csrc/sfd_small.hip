@@ -175,67 +175,6 @@ __global__ __launch_bounds__(64 * NW) void k_chol_inv(const double* __restrict__
   }
 }
 
-// The same factorization for n <= 64 in one wave, with no barriers: Gaussian elimination on the
-// augmented matrix [W | I].  Step k scales row k by 1 / sqrt(pivot) (giving row k of R in the W
-// part) and subtracts R[k][i] times it from every row i > k; the W part then holds R, and the
-// identity part holds the accumulated row operations E = R^{-T} (lower triangular), so
-// T = R^{-1} = E^T with no separate back substitution.  Lane j keeps column j of both parts in
-// one register array: c[i] = W part (i <= j, the upper triangle) or E part (i > j), and E's
-// diagonal entry E[j][j] apart.  Row k is published in LDS (lane j writes its c[k]); a lane then
-// updates its rows i > k with the multiplier of the part row i belongs to: R[k][j] for the W
-// part (nonzero for j > k), E[k][j] for the E part (nonzero for j <= k).  A dropped pivot (see
-// k_chol_inv) zeroes row k of R and of E, so row and column k of T are zero.
-// (a group launch runs one workgroup per buffer k = blockIdx.x on W + k wstride, T + k L L, sc + k)
-__global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__ W, int ldw, int n, int L, double tau,
-                                                      float* __restrict__ T, DevScalars* sc, int64_t wstride) {
-  W += blockIdx.x * wstride;
-  T += (int64_t)blockIdx.x * L * L;
-  sc += blockIdx.x;
-  __shared__ double row[2][64];
-  const int j = threadIdx.x;
-  const bool cn = j < n;
-  double c[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const double x = W[(i < n ? i : 0) * ldw + (cn ? j : 0)];  // unconditional loads, then masked
-    c[i] = (i < n && cn && i <= j) ? x : 0.0;                   // W part above the diagonal, E part 0
-  }
-  const double d0 = cn ? W[j * ldw + j] : 0.0;  // W_jj, the reference of the drop test
-  double ed = 1.0;                              // E[j][j]
-  int drops = 0;
-  // fully unrolled (static register indices); steps k >= n skip their work (a uniform branch)
-#pragma clang loop unroll(full)
-  for (int k = 0; k < 64; ++k) {
-    if (k >= n) continue;
-    const double p = readlane_d(c[k], k);
-    const double dk = readlane_d(d0, k);
-    const bool keep = (dk > 0.0) && (p > tau * dk);
-    const double is = keep ? rsqrt_nr(p) : 0.0;
-    drops += keep ? 0 : 1;
-    // row k of R (lanes j >= k) and of E (lanes j < k), scaled in place
-    c[k] *= is;
-    if (j == k) ed = is;
-    row[k & 1][j] = c[k];
-    __syncthreads();
-    const double mu = j > k ? c[k] : 0.0;                    // R[k][j]: rows k < i <= j
-    const double ml = j < k ? c[k] : (j == k ? ed : 0.0);    // E[k][j]: rows i > j
-#pragma clang loop unroll(full)
-    for (int i = k + 1; i < 64; ++i) {
-      const double r = row[k & 1][i];  // R[k][i]
-      c[i] = fma(-r, i <= j ? mu : ml, c[i]);
-    }
-  }
-  // T = E^T: row j of T is column j of E
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    if (j < L && i < L) {
-      const double t = (i > j) ? c[i] : (i == j ? ed : 0.0);
-      T[j * L + i] = (cn && i < n) ? (float)t : 0.f;
-    }
-  }
-  if (j == 0) sc->dropped = drops;
-}
-
 // The same Cholesky for 128 < n <= 256 in two passes, because the factor and its inverse no
 // longer fit the registers together.  Thread (w, j) of NW waves holds columns c = j + 64 u
 // (u < 4) and, of rows i = NW s + w, only the slots that can be on or above the diagonal of
@@ -733,7 +672,7 @@ hipError_t chol_inv_group(const double* W, int ldw, int ell, int L, double tau, 
                           int64_t wstride, double* Rw, hipStream_t st) {
   if (ell > kCholMaxWide || L > kCholMaxWide) return hipErrorInvalidValue;
   if (ell <= 64 && L <= 64) {
-    k_chol_inv_wave<<<K, 64, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
+    k_chol_inv<4, 1><<<K, 256, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
   } else if (ell <= kCholMax && L <= kCholMax) {
     k_chol_inv<16, 2><<<K, 1024, 0, st>>>(W, ldw, ell, L, tau, T, sc, wstride);
   } else {

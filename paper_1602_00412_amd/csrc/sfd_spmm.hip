@@ -25,6 +25,7 @@ namespace sfd {
 namespace {
 
 constexpr int64_t kSpmmMaxBlocks = 16384;  // 64 four-wave blocks per CU at most
+constexpr int kQueueTicket = 8;            // chunks a group takes from a work queue per atomic
 
 inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
   int64_t g = (n + threads - 1) / threads;
@@ -244,9 +245,10 @@ __device__ inline void store_seg(void* row, int sub, const float* o) {
 
 // U entries of the group's current block, starting at entry T0 of the block: broadcast their
 // ids and values from the lanes that loaded them, gather the U dense row segments, accumulate.
-template <int LPR, int U, int T0, bool BF>
+// STAGE: an id c < 0 names row -1 - c of the rows staged in LDS (hot, pitch LPR segments).
+template <int LPR, int U, int T0, bool BF, bool STAGE>
 __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::raw* __restrict__ Xs, int lds, int sub,
-                                    float* acc) {
+                                    const typename Seg<BF>::raw* hot, float* acc) {
   int c[U];
   float v[U];
   typename Seg<BF>::raw x[U];
@@ -254,7 +256,12 @@ __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::ra
     ((c[u] = bcast_i<LPR, T0 + u>(ci), v[u] = bcast_f<LPR, T0 + u>(vi)), ...);
   }(std::make_integer_sequence<int, U>{});
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = Xs[(int64_t)c[u] * lds + sub];
+  for (int u = 0; u < U; ++u) {
+    if constexpr (STAGE)
+      x[u] = c[u] < 0 ? hot[(-1 - c[u]) * LPR + sub] : Xs[(int64_t)c[u] * lds + sub];
+    else
+      x[u] = Xs[(int64_t)c[u] * lds + sub];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) Seg<BF>::fma(v[u], x[u], acc);
 }
@@ -277,15 +284,17 @@ __device__ inline float load_val(const void* __restrict__ val, int q) {
     return reinterpret_cast<const float*>(val)[q];
 }
 
-// QUEUE: the group takes its chunks from a work queue (the counter *queue of the range, one
-// atomic per chunk by the group's first lane) instead of first, first + stride, ...; the group
-// holds one chunk ahead, so the descriptor of the next chunk is loaded before the current one's
-// gathers either way.
-template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE>
+// QUEUE: the group takes its chunks from a work queue (the counter *queue of the range; the
+// group's first lane takes a ticket of kQueueTicket consecutive chunks per atomic, since one
+// counter serves every group of the grid) instead of first, first + stride, ...; the group holds
+// one chunk ahead, so the descriptor of the next chunk is loaded before the current one's gathers
+// either way.
+template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE, bool STAGE>
 __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_t c0, int64_t c1, int64_t first,
                                            int64_t stride, int* __restrict__ queue, const int* __restrict__ idx,
                                            const void* __restrict__ val, const void* __restrict__ X, int ldx,
-                                           void* __restrict__ out, int ldo, float* __restrict__ partial) {
+                                           void* __restrict__ out, int ldo, float* __restrict__ partial,
+                                           const typename Seg<BIN>::raw* hot) {
   using S = Seg<BIN>;
   constexpr int VEC = S::VEC;
   constexpr int LPR = L / VEC;  // lanes per group
@@ -293,13 +302,18 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
   const typename S::raw* Xs = reinterpret_cast<const typename S::raw*>(X);
   const int lds = ldx / VEC;  // row pitch in segments
   const size_t out_row_bytes = (size_t)ldo * (BOUT ? 2 : 4);
-  // the group's next chunk: from the queue (the first lane takes a ticket, the group shares it)
-  // or the next of the static sequence
+  // the group's next chunk: from its current ticket or a new one (the first lane takes it, the
+  // group shares it), or the next of the static sequence
+  int64_t tk_next = 0, tk_end = 0;
   auto next_chunk = [&](int64_t cur) -> int64_t {
     if constexpr (QUEUE) {
-      int t = 0;
-      if (sub == 0) t = atomicAdd(queue, 1);
-      return c0 + bcast_i<LPR, 0>(t);
+      if (tk_next >= tk_end) {
+        int t = 0;
+        if (sub == 0) t = atomicAdd(queue, kQueueTicket);
+        tk_next = c0 + bcast_i<LPR, 0>(t);
+        tk_end = tk_next + kQueueTicket;
+      }
+      return tk_next++;
     } else {
       return cur + stride;
     }
@@ -332,7 +346,7 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
     // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
     const int cnt = min(LPR, dc.z - p);
     [&]<int... b>(std::integer_sequence<int, b...>) {
-      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN>(ci, vi, Xs, lds, sub, acc) : void()), ...);
+      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN, STAGE>(ci, vi, Xs, lds, sub, hot, acc) : void()), ...);
     }(std::make_integer_sequence<int, LPR / U>{});
     if (!same) {
       float o[VEC];
@@ -368,25 +382,46 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
 // QUEUE: a persistent grid (a few blocks per CU) whose groups take chunks from the ranges' work
 // queues (queue[range]); otherwise a grid of about four chunks per group walked statically.
 // Either way each chunk is summed by one group in entry order, so the results are the same bits.
-template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT, bool VB, bool QUEUE>
+// STAGE (products Y = A' X with a queue grid): each block first copies the input rows of the
+// buffer's most popular columns (hot_cols[0 .. *hot_n), at most kStageBytes of them) to LDS; idx
+// then holds -1 - slot for the entries of those columns (the staged encoding of the column ids).
+constexpr int kStageBytes = 32768;
+
+template <int L, bool BIN>
+constexpr int stage_rows() {
+  return kStageBytes / (L * (BIN ? 2 : 4));
+}
+
+template <int L, int U, bool TRANSPOSED, bool BIN, bool BOUT, bool VB, bool QUEUE, bool STAGE>
 __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, const int* __restrict__ regions,
                                               int nlocal, int* __restrict__ queue, const int* __restrict__ idx,
                                               const void* __restrict__ val, const void* __restrict__ X, int ldx,
-                                              void* __restrict__ out, int ldo, float* __restrict__ partial) {
-  constexpr int G = 64 / (L / Seg<BIN>::VEC);  // groups per wave
+                                              void* __restrict__ out, int ldo, float* __restrict__ partial,
+                                              const int* __restrict__ hot_cols, const int* __restrict__ hot_n) {
+  using raw = typename Seg<BIN>::raw;
+  constexpr int LPR = L / Seg<BIN>::VEC;
+  constexpr int G = 64 / LPR;  // groups per wave
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int grp = lane / (L / Seg<BIN>::VEC);
+  const int grp = lane / LPR;
+  __shared__ raw hot[STAGE ? stage_rows<L, BIN>() * LPR : 1];
+  if constexpr (STAGE) {
+    const int nh = min(*hot_n, stage_rows<L, BIN>());
+    const raw* Xs = reinterpret_cast<const raw*>(X);
+    const int lds = ldx / Seg<BIN>::VEC;
+    for (int i = threadIdx.x; i < nh * LPR; i += 256) hot[i] = Xs[(int64_t)hot_cols[i / LPR] * lds + i % LPR];
+    __syncthreads();
+  }
   if (nlocal > 0) {
     const int band = blockIdx.x % nlocal;
     const int64_t slot = blockIdx.x / nlocal;
-    spmm_range<L, U, BIN, BOUT, VB, QUEUE>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
-                                           (int64_t)(gridDim.x / nlocal) * 4 * G, queue + band, idx, val, X, ldx, out,
-                                           ldo, partial);
+    spmm_range<L, U, BIN, BOUT, VB, QUEUE, STAGE>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
+                                                  (int64_t)(gridDim.x / nlocal) * 4 * G, queue + band, idx, val, X,
+                                                  ldx, out, ldo, partial, hot);
   }
-  spmm_range<L, U, BIN, BOUT, VB, QUEUE>(desc, regions[nlocal], regions[nlocal + 1],
-                                         ((int64_t)blockIdx.x * 4 + wave) * G + grp, (int64_t)gridDim.x * 4 * G,
-                                         queue + nlocal, idx, val, X, ldx, out, ldo, partial);
+  spmm_range<L, U, BIN, BOUT, VB, QUEUE, STAGE>(desc, regions[nlocal], regions[nlocal + 1],
+                                                ((int64_t)blockIdx.x * 4 + wave) * G + grp, (int64_t)gridDim.x * 4 * G,
+                                                queue + nlocal, idx, val, X, ldx, out, ldo, partial, hot);
 }
 
 // One block per long row: wave w adds the row's partials w, w + 4, ... (in slot order), then
@@ -516,6 +551,55 @@ __global__ __launch_bounds__(256) void k_spmv_fixup(const int* __restrict__ slot
   }
 }
 
+// ---- rows staged in LDS for the products Y = A' X: the buffer's most popular columns
+// hist[b] = columns whose entry count lies in [2^b, 2^(b+1))
+__global__ void k_stage_hist(const int* __restrict__ cscptr, int d, int* __restrict__ hist) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) {
+    const int len = cscptr[c + 1] - cscptr[c];
+    if (len >= 2) atomicAdd(&hist[31 - __clz(len)], 1);
+  }
+}
+
+// the count threshold 2^b: the columns from the top bin down whose total stays within cap;
+// hot_n[0] = 0 (filled by k_stage_slots), hot_n[1] = threshold (INT_MAX: none)
+__global__ void k_stage_threshold(const int* __restrict__ hist, int cap, int* __restrict__ hot_n) {
+  if (threadIdx.x != 0) return;
+  int cum = 0, tau = 0x7FFFFFFF;
+  for (int b = 31; b >= 1; --b) {
+    if (cum + hist[b] > cap) break;
+    cum += hist[b];
+    if (hist[b] > 0) tau = 1 << b;
+  }
+  hot_n[0] = 0;
+  hot_n[1] = tau;
+}
+
+// slot_of[c] = the LDS slot of column c (-1: not staged), hot_cols[slot] = c (slot order is that
+// of the atomics; it only places rows in LDS, the products' sums do not depend on it)
+__global__ void k_stage_slots(const int* __restrict__ cscptr, int d, int* __restrict__ hot_n,
+                              int* __restrict__ hot_cols, int* __restrict__ slot_of) {
+  const int tau = hot_n[1];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) {
+    const int len = cscptr[c + 1] - cscptr[c];
+    int slot = -1;
+    if (len >= tau) {
+      slot = atomicAdd(&hot_n[0], 1);
+      hot_cols[slot] = c;
+    }
+    slot_of[c] = slot;
+  }
+}
+
+// enc[k] = -1 - slot of a staged column, else the column id
+__global__ void k_stage_encode(const int* __restrict__ colidx, int64_t nnz, const int* __restrict__ slot_of,
+                               int* __restrict__ enc) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+    const int c = colidx[k];
+    const int s = slot_of[c];
+    enc[k] = s >= 0 ? -1 - s : c;
+  }
+}
+
 int device_cus() {
   static int cus[64] = {};
   int dev = 0;
@@ -528,7 +612,7 @@ int device_cus() {
   return cus[dev];
 }
 
-template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE>
+template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE, bool STAGE = false>
 void launch_spmm(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
                  float* partial, int occupancy, hipStream_t st) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);
@@ -541,17 +625,20 @@ void launch_spmm(const Schedule& s, const int* idx, const void* val, const void*
   if (s.nlocal > 0) grid = (grid + s.nlocal - 1) / s.nlocal * s.nlocal;
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
-    k_spmm<L, U, true, BIN, BOUT, VB, QUEUE><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, s.queue, idx,
-                                                                             val, X, ldx, out, ldo, partial);
+    k_spmm<L, U, true, BIN, BOUT, VB, QUEUE, false><<<(unsigned)grid, 256, 0, st>>>(
+        s.desc, s.regions, s.nlocal, s.queue, idx, val, X, ldx, out, ldo, partial, nullptr, nullptr);
   else
-    k_spmm<L, U, false, BIN, BOUT, VB, QUEUE><<<(unsigned)grid, 256, 0, st>>>(s.desc, s.regions, s.nlocal, s.queue,
-                                                                              idx, val, X, ldx, out, ldo, partial);
+    k_spmm<L, U, false, BIN, BOUT, VB, QUEUE, STAGE><<<(unsigned)grid, 256, 0, st>>>(
+        s.desc, s.regions, s.nlocal, s.queue, STAGE ? s.stage_idx : idx, val, X, ldx, out, ldo, partial, s.hot_cols,
+        s.hot_n);
 }
 
 template <int L, int U, bool BIN, bool BOUT, bool VB>
 void launch_spmm_cfg(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
                      float* partial, const SpmmConfig& cfg, hipStream_t st) {
-  if (cfg.queue)
+  if (cfg.queue && cfg.stage)
+    launch_spmm<L, U, BIN, BOUT, VB, true, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, st);
+  else if (cfg.queue)
     launch_spmm<L, U, BIN, BOUT, VB, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, st);
   else
     launch_spmm<L, U, BIN, BOUT, VB, false>(s, idx, val, X, ldx, out, ldo, partial, 0, st);
@@ -604,6 +691,19 @@ hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, 
   return hipGetLastError();
 }
 
+hipError_t stage_build(const int* cscptr, int d, const int* colidx, int64_t nnz, int L, bool bf16, Schedule& s,
+                       hipStream_t st) {
+  if (!s.stage_idx || !s.hot_cols || !s.hot_n || !s.slot_of) return hipErrorInvalidValue;
+  const int cap = kStageBytes / (L * (bf16 ? 2 : 4));
+  hipError_t e;
+  if ((e = fill_i32(s.hot_n + 2, 32, 0, st)) != hipSuccess) return e;
+  k_stage_hist<<<grid_for(d, 256, 4096), 256, 0, st>>>(cscptr, d, s.hot_n + 2);
+  k_stage_threshold<<<1, 64, 0, st>>>(s.hot_n + 2, cap, s.hot_n);
+  k_stage_slots<<<grid_for(d, 256, 4096), 256, 0, st>>>(cscptr, d, s.hot_n, s.hot_cols, s.slot_of);
+  k_stage_encode<<<grid_for(nnz, 256, 16384), 256, 0, st>>>(colidx, nnz, s.slot_of, s.stage_idx);
+  return hipGetLastError();
+}
+
 hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const int* rowptr, int m, int nnz,
                               int hot_min, Schedule& s, int* scan_tmp, hipStream_t st) {
   if (d <= 0 || m <= 0 || nnz <= 0 || hot_min < 1) return hipErrorInvalidValue;
@@ -627,6 +727,7 @@ hipError_t schedule_build_hot(const int* cscptr, const int* cscrow, int d, const
 hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf16, const void* X, PanelType xt, int ldx,
                 void* Y, PanelType yt, int ldy, int L, float* partial, const SpmmConfig& cfg, hipStream_t st) {
   if (cfg.queue && !s.queue) return hipErrorInvalidValue;
+  if (cfg.stage && (!cfg.queue || s.transposed || !s.stage_idx || !s.hot_cols || !s.hot_n)) return hipErrorInvalidValue;
   if (L == 32) return spmm_l<32>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
   if (L == 64) return spmm_l<64>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
   if (L == 128) return spmm_l<128>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);

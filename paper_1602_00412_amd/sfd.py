@@ -46,6 +46,7 @@ CQR2_FINAL = 1
 CQR2_ALL = 2
 OPT_AUTOTUNE = 15
 OPT_GRAPHS = 16
+OPT_PRODUCT_LAUNCH = 17
 ALGO_SFD = 0
 ALGO_FD = 1
 PROF_CLASSES = ["csc_build", "spmm_csr", "spmm_csc", "gram", "chol", "xform", "eig", "vs", "other", "fixup"]
@@ -244,7 +245,7 @@ class Sketch:
 
     def __init__(self, d: int, ell: int, eps: float = 0.25, seed: int = 0, *, delta=None, q=None,
                  max_attempts=None, verify=None, stream_id=None, csc_bands=None, csc_hot_min=None,
-                 precision=None, algorithm=None, cqr2=None, autotune=None, graphs=None,
+                 precision=None, algorithm=None, cqr2=None, autotune=None, graphs=None, launch=None,
                  use_torch_stream: bool = True):
         lib = load()
         h = ctypes.c_void_p()
@@ -261,7 +262,9 @@ class Sketch:
                          (OPT_CQR2, None if cqr2 is None else
                           {"off": CQR2_OFF, "final": CQR2_FINAL, "all": CQR2_ALL}.get(cqr2, cqr2)),
                          (OPT_AUTOTUNE, None if autotune is None else float(bool(autotune))),
-                         (OPT_GRAPHS, None if graphs is None else float(bool(graphs)))):
+                         (OPT_GRAPHS, None if graphs is None else float(bool(graphs))),
+                         (OPT_PRODUCT_LAUNCH, None if launch is None else
+                          {"auto": 0, "static": 1, "queue": 2, "stage": 3}.get(launch, launch))):
             if val is not None:
                 self.set_option(key, val)
         if use_torch_stream:
