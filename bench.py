@@ -244,7 +244,7 @@ def run_form_child(name: str, args) -> dict:
     env = dict(os.environ)
     env["GPU_MAX_HW_QUEUES"] = str(FORM_QUEUES[name])
     cmd = [sys.executable, os.path.abspath(__file__), "--form-child", name, "--autotune", str(args.autotune),
-           "--graphs", str(args.graphs)]
+           "--graphs", str(args.graphs), "--launch", args.launch]
     log(f"form {name}: child process, {FORM_QUEUES[name]} hardware queues")
     res = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True)
     if res.returncode != 0:
@@ -427,8 +427,10 @@ def main() -> int:
                     help="entries from which a CSC column is cut into XCD-local pieces (0: the library's default)")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched forms' timing")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the forms on the 10^6-row stream")
-    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
-                    help="SFD_OPT_AUTOTUNE of every handle (1: tuned sparse-product launches, the default)")
+    ap.add_argument("--autotune", type=int, default=0, choices=[0, 1],
+                    help="SFD_OPT_AUTOTUNE of every handle (0, the default: static product launches)")
+    ap.add_argument("--launch", default="auto", choices=["auto", "static", "queue", "stage"],
+                    help="SFD_OPT_PRODUCT_LAUNCH of the single-stream handles (auto: as the autotuner decides)")
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="SFD_OPT_GRAPHS of the batch handles (1: graph-captured group steps, the default)")
     ap.add_argument("--big-forms", default="ell200,d1e6,batch4096",
@@ -472,7 +474,7 @@ def main() -> int:
             have = 0
         if have < want:
             os.environ["GPU_MAX_HW_QUEUES"] = str(want)
-    SKETCH_OPTS["autotune"] = bool(args.autotune)
+    SKETCH_OPTS.update(autotune=bool(args.autotune), graphs=bool(args.graphs), launch=args.launch)
     BATCH_OPTS.update(autotune=bool(args.autotune), graphs=bool(args.graphs))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sketch shards by rows with "
@@ -617,10 +619,17 @@ def main() -> int:
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if (args.csc_bands or args.csc_hot_min) else measured_traffic(dom, args.workload, args.precision)}
         bfk = args.precision == "bf16"
         Lw = 32 if ell <= 32 else 64 if ell <= 64 else 128 if ell <= 128 else 256
-        roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {str(bfk).lower()}, "
-                                      f"{str(bfk).lower()}> (X = A'^T Y, CSC)",
-                          "spmm_csr": f"k_spmm<{Lw}, {4 if bfk else 8}, false, {str(bfk).lower()}, "
-                                      f"{str(bfk).lower()}> (Y = A' X, CSR)"}.get(dom, dom)
+        # template arguments <L, U, transposed, BF16 input panel, BF16 output panel, BF16 values,
+        # work queue, LDS staging>: the static grid unless the launch was forced or tuned (the
+        # BF16 form's bulk of products; its last product, P^T = A'^T Y, writes FP32 from FP32 values)
+        b = str(bfk).lower()
+        qu = str(args.launch in ("queue", "stage")).lower()
+        stg = str(args.launch == "stage").lower()
+        tail = ", or a tuned variant" if args.autotune and args.launch == "auto" else ""
+        roof["kernel"] = {"spmm_csc": f"k_spmm<{Lw}, {4 if bfk else 8}, true, {b}, {b}, {b}, {qu}, false> "
+                                      f"(X = A'^T Y, CSC{tail})",
+                          "spmm_csr": f"k_spmm<{Lw}, {4 if bfk else 8}, false, {b}, {b}, {b}, {qu}, {stg}> "
+                                      f"(Y = A' X, CSR{tail})"}.get(dom, dom)
         roof["algorithmic_bytes_per_launch"] = p["bytes"] / p["calls"]
         roof["avg_launch_us"] = avg_s * 1e6
         roof["launches"] = p["calls"]

@@ -114,7 +114,7 @@ enum {
                                       its condition number.  SFD_CQR2_OFF, SFD_CQR2_FINAL
                                       (default: the final basis Y of Alg 1, whose span defines
                                       B'), SFD_CQR2_ALL (every product's panel). */
-  SFD_OPT_AUTOTUNE = 15,           /* 1 (default): the launch configuration of each sparse product
+  SFD_OPT_AUTOTUNE = 15,           /* 1: the launch configuration of each sparse product
                                       of SimultaneousIteration (entries gathered per batch; a
                                       static grid or a persistent grid fed by a device work queue)
                                       is picked by timing the candidates on the first product of
@@ -122,7 +122,8 @@ enum {
                                       orders of magnitude of entries and rows), once per process;
                                       the environment variable SFD_TUNE_CACHE names a file that
                                       keeps the choices across processes.  Every candidate gives
-                                      the same bits.  0: the default configuration. */
+                                      the same bits.  0 (default): the static grid, gathering 8
+                                      entries per batch (4 for BF16 panels). */
   SFD_OPT_GRAPHS = 16,             /* 1 (default): the SimultaneousIteration step of each buffer
                                       step (of a lane, or of a batch handle's lockstep group) and
                                       its VerifySpectral power step are captured once as HIP graphs

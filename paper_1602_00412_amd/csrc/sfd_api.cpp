@@ -151,7 +151,7 @@ struct sfd_s {
   int nlanes = kLanesSingle;       // SFD_OPT_LANES: lanes used for successive buffers
   int precision = SFD_PRECISION_FP32;  // SFD_OPT_PRECISION
   int cqr2 = SFD_CQR2_FINAL;           // SFD_OPT_CQR2 (precision form)
-  int autotune = 1;                    // SFD_OPT_AUTOTUNE
+  int autotune = 0;                    // SFD_OPT_AUTOTUNE
   int launch = 0;                      // SFD_OPT_PRODUCT_LAUNCH
   int graphs = 1;                      // SFD_OPT_GRAPHS (lockstep groups of a batch handle)
   int algorithm = SFD_ALGO_SFD;        // SFD_OPT_ALGORITHM
