@@ -513,9 +513,9 @@ inline int log2_bucket(int64_t n) {
 
 // The configuration of a product (s, idx, val, X -> Y) on stream st: the tuned one, tuning first
 // when the key is new.  Not during stream capture (tuning synchronises).
-int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
-                   const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows, int64_t nnz,
-                   SpmmConfig* out) {
+int product_config_tuned(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
+                         const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows,
+                         int64_t nnz, SpmmConfig* out) {
   *out = SpmmConfig{};
   if (h->launch > 0) {
     // a fixed launch: static grid, work-queue grid, or work-queue grid staging (where possible)
@@ -579,6 +579,16 @@ int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, 
   g_tuner.store(key, cand[bi]);
   *out = cand[bi];
   return SFD_OK;
+}
+
+// ... and every configuration gathers only the panel-row segments that reach column ell - 1
+// (the rest are zero in every panel)
+int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
+                   const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows, int64_t nnz,
+                   SpmmConfig* out) {
+  const int rc = product_config_tuned(h, st, s, idx, val, vb, X, xt, Y, yt, partial, in_rows, nnz, out);
+  out->live = live_segments(h->ell, (int)pbytes(xt));
+  return rc;
 }
 
 // `body` (launches on st only, no host synchronisation) run n times: captured once as a HIP graph
@@ -1089,11 +1099,11 @@ int run_group(sfd_t* h, std::vector<GroupItem>& items) {
     GroupSeg& sx = hx[k];
     sx.row0 = k * d;
     sx.rows = d;
-    gram_geometry(d, &sx.nb, &sx.rpb);
+    gram_geometry(d, (int)L, &sx.nb, &sx.rpb);
     GroupSeg& sy = hy[k];
     sy.row0 = R[(size_t)k];
     sy.rows = items[(size_t)k].v.m;
-    gram_geometry(sy.rows, &sy.nb, &sy.rpb);
+    gram_geometry(sy.rows, (int)L, &sy.nb, &sy.rpb);
     nbx = std::max(nbx, sx.nb);
     nby = std::max(nby, sy.nb);
     hrows[k] = R[(size_t)k];

@@ -5,6 +5,7 @@
 //
 // Panels are row-major and tall (d x L or m x L, L = 32, 64, 128 or 256 >= ell, zero-padded), so
 // every Gram has its contraction along the tall axis.
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -17,6 +18,12 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGramMaxBlocks = 256;
+
+// word 3 of a raw buffer resource on gfx9-family GPUs (stride 0: offsets are bytes, checked
+// against the record count; loads past it return 0 and stores past it are dropped)
+constexpr int kBufferRsrcWord3 = 0x00020000;
+// (the raw buffer builtins move 32-bit integers: floats go through __float_as_uint, never a value
+// conversion)
 
 // Gram partial of a row block.  MFMA v_mfma_f32_16x16x4f32: A (16 x 4) and B (4 x 16) come one
 // float per lane, lane l holding row-of-A / column-of-B (l % 16) at k = l / 16; the 16 x 16
@@ -116,10 +123,14 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __re
 }
 
 // P <- P T in place (rows x L FP32 panel, pitch ld; T: L x L FP32) and the per-block partial
-// Gram of the result, for k_gram_reduce (BF16 panels: sfd_bf16.hip).  This applies the inverse Cholesky factor of a product's input panel to the
-// product's output (A'(X T) = (A' X) T), so the sparse products need no per-row epilogue.
-// Both the transform and the Gram run on MFMA (v_mfma_f32_16x16x4f32), 16 rows at a time per
-// wave (wave w of a block: tiles w, w + 8, ...):
+// Gram of the result, for k_gram_reduce (BF16 panels: sfd_bf16.hip).  This applies the inverse
+// Cholesky factor of a product's input panel to the product's output (A'(X T) = (A' X) T), so the
+// sparse products need no per-row epilogue.  Both the transform and the Gram run on MFMA
+// (v_mfma_f32_16x16x4f32), 16 rows at a time per wave (wave w of a block: tiles w, w + 8, ...):
+//  * the block's rows are addressed through a buffer resource that covers exactly them, so a
+//    tile's rows past the block's end load as zeros and their stores are dropped by the hardware:
+//    no branches around the memory operations, and the loop's wait for the next tile's loads does
+//    not also wait for the current tile's stores;
 //  * the tile is loaded coalesced and staged in LDS (row pitch L + 4 floats: the A-operand reads
 //    below hit 64 distinct banks);
 //  * out (16 x L) = tile (16 x L) * T: k-step ks, strip n: A[m][k] = tile[m][4 ks + k] (lane l:
@@ -128,7 +139,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_partial(const float* __re
 //    strip n needs the k-steps ks < 4 (n + 1) only;
 //  * the accumulator of strip n at fixed v is itself an A / B operand over the four rows
 //    4 k + v (k = l / 16), so Gram += out^T out is formed from the registers directly: for
-//    v = 0..3 and each upper tile (si, sj), MFMA(C_si[v], C_sj[v]).
+//    v = 0..3 and each upper tile (si, sj), MFMA(C_si[v], C_sj[v]).  Rows past the end are zero
+//    and add nothing.
 // Groups (segs != nullptr): buffer k = blockIdx.y owns rows [segs[k].row0, + segs[k].rows) of P
 // with its own T (T + k L L) and partials (partials + k pstride), and the block geometry a
 // single-buffer launch over that many rows has (segs[k].rpb, .nb), so its result is the same.
@@ -166,33 +178,39 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(float* __restrict__
   for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
     for (int n = 0; n < S; ++n) tb[ks][n] = T[(4 * ks + lk) * L + 16 * n + lm];
+  // T is in registers before the tile loop, whose waits then cover only the loop's own loads
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int n = 0; n < S; ++n) asm volatile("" : "+v"(tb[ks][n]));
   floatx4 g[NU];
 #pragma unroll
   for (int t = 0; t < NU; ++t) g[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  const int64_t r1 = min(rows, r0 + rpb);
-  char* base = reinterpret_cast<char*>(P);
-  const size_t pitch = (size_t)ld * 4;
+  const int nr = (int)max((int64_t)0, min(rows, r0 + rpb) - r0);  // this block's rows
+  const int pitch = ld * 4;
+  // rows [r0, r0 + nr) as one buffer: offsets past nr * pitch bytes read 0 and are not written
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(P + (size_t)r0 * ld, (short)0, nr * pitch, kBufferRsrcWord3);
   const int prow = lane / LPRW, pcol = (lane % LPRW) * EPL;  // this lane's part of a load pass
   float* my = tile[wave];
-  using raw = float4;
-  raw nxt[NP];
-  auto load_tile = [&](int64_t t0) {
+  floatx4 nxt[NP];
+  auto load_tile = [&](int t0) {
 #pragma unroll
-    for (int ip = 0; ip < NP; ++ip) {
-      const int64_t row = t0 + ip * RPP + prow;
-      if (row < r1)
-        nxt[ip] = *reinterpret_cast<const raw*>(base + row * pitch + (size_t)pcol * 4);
-      else
-        nxt[ip] = raw{0, 0, 0, 0};
-    }
+    for (int ip = 0; ip < NP; ++ip)
+      nxt[ip] = __builtin_bit_cast(
+          floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, (t0 + ip * RPP + prow) * pitch + pcol * 4, 0, 0));
   };
-  int64_t t0 = r0 + 16 * wave;
-  load_tile(t0);
-  for (; t0 < r1; t0 += 16 * NW) {
-    // stage the tile and start loading the next one
+  auto stage = [&]() {
 #pragma unroll
-    for (int ip = 0; ip < NP; ++ip) reinterpret_cast<float4*>(my + (ip * RPP + prow) * LP + pcol)[0] = nxt[ip];
+    for (int ip = 0; ip < NP; ++ip) *reinterpret_cast<floatx4*>(my + (ip * RPP + prow) * LP + pcol) = nxt[ip];
+  };
+  int t0 = 16 * wave;
+  load_tile(t0);
+  stage();
+  for (; t0 < nr; t0 += 16 * NW) {
+    // start loading the next tile; it is staged at the end of this pass, where the wait for
+    // its loads does not cover the stores issued in between
     load_tile(t0 + 16 * NW);
     __builtin_amdgcn_wave_barrier();
     // out = tile * T
@@ -207,23 +225,19 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(float* __restrict__
       for (int n = 0; n < S; ++n)
         if (ks < 4 * (n + 1)) o[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tb[ks][n], o[n], 0, 0, 0);
     }
-    // store, and add the stored values' Gram
+    // store (rows past the block's end are dropped), and add the Gram of the tile
 #pragma unroll
-    for (int n = 0; n < S; ++n) {
+    for (int n = 0; n < S; ++n)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = t0 + 4 * lk + v;
-        const float x = o[n][v];
-        if (row < r1) reinterpret_cast<float*>(base + row * pitch)[16 * n + lm] = x;
-        o[n][v] = row < r1 ? x : 0.f;
-      }
-    }
+      for (int v = 0; v < 4; ++v)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[n][v]), rs, (t0 + 4 * lk + v) * pitch + (16 * n + lm) * 4, 0, 0);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int t = 0; t < NU; ++t)
         g[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o[kUpper<S>.ti[t]][v], o[kUpper<S>.tj[t]][v], g[t], 0, 0, 0);
     __builtin_amdgcn_wave_barrier();
+    stage();
   }
   // the waves add their sums into one LDS copy in wave order, then the block writes it
   for (int g2 = 0; g2 < NW; ++g2) {
@@ -247,76 +261,105 @@ __global__ __launch_bounds__(kGramThreads) void k_xform_gram(float* __restrict__
 }
 
 // Wide FP32 panels (L = 128 or 256): out <- Pin T (rows x L, T: L x L FP32, pitch ldt), and with
-// ACC out <- out + Pin T (used for [P1 | P2] T2 as two passes).  Wave w of a
-// block computes output strip w (columns 16 w .. 16 w + 15) and keeps its strip of T as MFMA B
-// operands in registers (lane l: T[4 ks + l / 16][16 w + l % 16]); the 16-row input tile is loaded
-// by the whole block (16 bytes per thread), staged in LDS as FP32 (pitch L + 4, two buffers, so
-// one barrier per tile), and read as A operands by every wave.  A tile is read completely before
-// any of it is written, so out may be Pin.  UPPER: T is upper triangular (an inverse Cholesky
-// factor), so strip w needs the k-steps ks < 4 (w + 1) only.
+// ACC out <- out + Pin T (used for [P1 | P2] T2 as two passes).  The blocks stride over the
+// 16-row tiles (block b takes tiles b, b + gridDim.x, ...), so a block loads its part of T once.
+// Wave w computes output strip sw = strip_of_wave(w) (columns 16 sw .. 16 sw + 15) and keeps that
+// strip of T as MFMA B operands in registers (lane l: T[4 ks + l / 16][16 sw + l % 16]); the
+// 16-row input tile is loaded by the whole block (16 bytes per thread), staged in LDS as FP32
+// (pitch L + 4, two buffers, so one barrier per tile), and read as A operands by every wave.  A
+// tile is read completely before any of it is written, so out may be Pin.  UPPER: T is upper
+// triangular (an inverse Cholesky factor), so strip sw needs the k-steps ks < 4 (sw + 1) only.
+// Each wave runs two MFMA chains (even and odd k-steps) and adds them at the end.  The memory
+// operations go through a buffer resource covering the tile's rows, so a tile's rows past the end
+// load as zeros and are not written, with no branches.
 // Groups: buffer k = blockIdx.z owns rows [segs[k].row0, + segs[k].rows) with T + k L L.
+template <int L>
+__device__ __forceinline__ int strip_of_wave(int w) {
+  // waves w, w + 4, w + 8, ... run on one SIMD; strips {s, 7 - s, 8 + s, 15 - s, ...} give every
+  // SIMD the same number of k-steps when T is triangular
+  const int s = w & 3, j = w >> 2;
+  return (j & 1) ? 4 * (j + 1) - 1 - s : 4 * j + s;
+}
+
 template <int L, bool ACC, bool UPPER>
 __global__ __launch_bounds__(L * 4) void k_xform_strips(const float* Pin, int ldi, float* out, int ldo, int64_t rows,
-                                                        int rpb, const float* __restrict__ T, int ldt,
+                                                        const float* __restrict__ T, int ldt,
                                                         const GroupSeg* segs) {
   static_assert(L == 128 || L == 256, "strip-per-wave transform");
-  constexpr int NT = L * 4;  // threads: one wave per 16-column strip
   constexpr int KS = L / 4;
   constexpr int LP = L + 4;
-  constexpr int EB = 4;  // bytes per element
   if (segs) {
     const GroupSeg g = segs[blockIdx.z];
-    if ((int)blockIdx.x >= g.nb) return;
     Pin += (size_t)g.row0 * ldi;
     out += (size_t)g.row0 * ldo;
     rows = g.rows;
-    rpb = g.rpb;
     T += (int64_t)blockIdx.z * L * L;
   }
+  const int64_t ntiles = (rows + 15) / 16;
+  if ((int64_t)blockIdx.x >= ntiles) return;
   __shared__ float tile[2][16 * LP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int w = tid >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
   const int lm = lane & 15, lk = lane >> 4;
+  const int sw = strip_of_wave<L>(w);
+  const int kmax = UPPER ? 4 * (sw + 1) : KS;
   float tb[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) tb[ks] = T[(4 * ks + lk) * ldt + 16 * w + lm];
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  const int64_t r1 = min(rows, r0 + rpb);
-  const char* src = reinterpret_cast<const char*>(Pin);
-  char* dst = reinterpret_cast<char*>(out);
-  const size_t ipitch = (size_t)ldi * EB, opitch = (size_t)ldo * EB;
+  for (int ks = 0; ks < KS; ++ks) tb[ks] = ks < kmax ? T[(4 * ks + lk) * ldt + 16 * sw + lm] : 0.f;
+  // T is in registers before the tile loop, whose waits then cover only the loop's own loads
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(tb[ks]));
+  const int ipitch = ldi * 4, opitch = ldo * 4;
   // this thread's 4 elements of a tile: row tid / (L / 4), columns 4 (tid % (L / 4)) .. + 3
   const int trow = tid / (L / 4), tcol = 4 * (tid % (L / 4));
-  using raw = float4;
-  auto load = [&](int64_t t0) -> raw {
-    const int64_t row = t0 + trow;
-    if (row < r1) return *reinterpret_cast<const raw*>(src + row * ipitch + (size_t)tcol * EB);
-    return raw{};
+  auto rows_of = [&](int64_t t) -> int { return (int)max((int64_t)0, min((int64_t)16, rows - 16 * t)); };
+  auto load = [&](int64_t t) -> floatx4 {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Pin) + (size_t)min(t, ntiles) * 16 * ldi, (short)0, rows_of(t) * ipitch, kBufferRsrcWord3);
+    return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, trow * ipitch + tcol * 4, 0, 0));
   };
-  raw nxt = load(r0);
+  int64_t t = blockIdx.x;
+  floatx4 nxt = load(t);
   int buf = 0;
-  for (int64_t t0 = r0; t0 < r1; t0 += 16, buf ^= 1) {
-    reinterpret_cast<float4*>(tile[buf] + trow * LP + tcol)[0] = nxt;
-    __syncthreads();
-    nxt = load(t0 + 16);
-    floatx4 o = floatx4{0.f, 0.f, 0.f, 0.f};
+  *reinterpret_cast<floatx4*>(tile[0] + trow * LP + tcol) = nxt;
+  for (; t < ntiles; t += gridDim.x, buf ^= 1) {
+    __syncthreads();  // tile[buf] staged; every wave is done with tile[buf ^ 1]
+    nxt = load(t + gridDim.x);
+    const __amdgpu_buffer_rsrc_t ro =
+        __builtin_amdgcn_make_buffer_rsrc(out + (size_t)t * 16 * ldo, (short)0, rows_of(t) * opitch, kBufferRsrcWord3);
+    floatx4 o0 = floatx4{0.f, 0.f, 0.f, 0.f}, o1 = o0;
     if constexpr (ACC) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = t0 + 4 * lk + v;
-        o[v] = row < r1 ? reinterpret_cast<const float*>(dst + row * opitch)[16 * w + lm] : 0.f;
+      for (int v = 0; v < 4; ++v)
+        o0[v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                              ro, (4 * lk + v) * opitch + (16 * sw + lm) * 4, 0, 0));
+    }
+    // k-steps in groups of four (kmax is a multiple of 4); the A operands of the next group are
+    // read from LDS before the current group's MFMAs are issued
+    const float* tl = tile[buf] + lm * LP + lk;
+    float a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = tl[4 * j];
+#pragma unroll
+    for (int kg = 0; kg < KS / 4; ++kg) {
+      if (4 * kg < kmax) {
+        float an[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) an[j] = kg + 1 < KS / 4 ? tl[16 * (kg + 1) + 4 * j] : 0.f;
+        o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], tb[4 * kg], o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], tb[4 * kg + 1], o1, 0, 0, 0);
+        o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], tb[4 * kg + 2], o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], tb[4 * kg + 3], o1, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = an[j];
       }
     }
-    const float* tl = tile[buf];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      if (!UPPER || ks < 4 * (w + 1)) o = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[lm * LP + 4 * ks + lk], tb[ks], o, 0, 0, 0);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = t0 + 4 * lk + v;
-      if (row < r1) reinterpret_cast<float*>(dst + row * opitch)[16 * w + lm] = o[v];
-    }
+    for (int v = 0; v < 4; ++v)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o0[v] + o1[v]), ro, (4 * lk + v) * opitch + (16 * sw + lm) * 4, 0, 0);
+    // the next tile into the other buffer (its last readers were before this pass's barrier)
+    *reinterpret_cast<floatx4*>(tile[buf ^ 1] + trow * LP + tcol) = nxt;
   }
 }
 
@@ -601,8 +644,21 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
 
 int gram_max_blocks() { return kGramMaxBlocks; }
 
-static void gram_grid(int64_t rows, int64_t& nb, int& rpb) {
-  nb = (rows + 511) / 512;
+// Blocks of a strip transform (k_xform_strips) over `tiles` 16-row tiles per buffer for K buffers:
+// one 1024-thread block per compute unit for L = 256, two 512-thread blocks for L = 128, shared
+// out among the buffers; each block strides over its buffer's tiles.
+static int64_t strip_blocks(int L, int64_t tiles, int K) {
+  const int64_t cap = L == 256 ? 256 : 512;
+  int64_t g = std::min(tiles, std::max<int64_t>(1, cap / std::max(1, K)));
+  return std::max<int64_t>(g, 1);
+}
+
+// Row blocks of a Gram (and of the L <= 64 transform + Gram): about 128 rows per block for
+// L <= 64, so that a 10^5-row panel fills the 256 compute units, and 512 for wider panels, whose
+// per-block partials (L x L each) the reduction reads back.
+static void gram_grid(int64_t rows, int L, int64_t& nb, int& rpb) {
+  const int64_t per = L <= 64 ? 128 : 512;
+  nb = (rows + per - 1) / per;
   if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
   if (nb < 1) nb = 1;
   rpb = (int)((rows + nb - 1) / nb);
@@ -614,13 +670,13 @@ hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const 
                       hipStream_t st) {
   int64_t nb;
   int rpb;
-  gram_grid(rows, nb, rpb);
+  gram_grid(rows, L, nb, rpb);
   return xform_gram_group(P, pt, ld, rows, rpb, (int)nb, nullptr, 1, L, T, partials, W, st);
 }
 
-void gram_geometry(int64_t rows, int* nb, int* rpb) {
+void gram_geometry(int64_t rows, int L, int* nb, int* rpb) {
   int64_t n;
-  gram_grid(rows, n, *rpb);
+  gram_grid(rows, L, n, *rpb);
   *nb = (int)n;
 }
 
@@ -643,13 +699,13 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
   } else if (L == 128 || L == 256) {
     // transform in place, then the Gram of the stored result by 64 x 64 tiles
     float* Pf = static_cast<float*>(P);
-    const dim3 gx((unsigned)nb, 1, (unsigned)K);
+    const dim3 gx((unsigned)strip_blocks(L, (int64_t)nb * 32, K), 1, (unsigned)K);
     const int ns = L / 64;
     const dim3 gg((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), (unsigned)K);
     if (L == 128)
-      k_xform_strips<128, false, true><<<gx, 512, 0, st>>>(Pf, ld, Pf, ld, rows, rpb, T, L, segs);
+      k_xform_strips<128, false, true><<<gx, 512, 0, st>>>(Pf, ld, Pf, ld, rows, T, L, segs);
     else
-      k_xform_strips<256, false, true><<<gx, 1024, 0, st>>>(Pf, ld, Pf, ld, rows, rpb, T, L, segs);
+      k_xform_strips<256, false, true><<<gx, 1024, 0, st>>>(Pf, ld, Pf, ld, rows, T, L, segs);
     k_gram_tiles<<<gg, 256, 0, st>>>(Pf, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
   } else {
     return hipErrorInvalidValue;
@@ -662,7 +718,7 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
                  hipStream_t st) {
   int64_t nb;
   int rpb;
-  gram_grid(rows, nb, rpb);
+  gram_grid(rows, 2 * L, nb, rpb);
   switch (L) {
     case 32:
       k_gram_partial<64, true><<<(unsigned)nb, kGramThreads, 0, st>>>(P1, ld1, P2, ld2, rows, rpb, partials);
@@ -694,19 +750,13 @@ hipError_t panel_xform2(const float* P1, int ld1, const float* P2, int ld2, int 
     k_panel_xform2<64><<<grid, 256, 0, st>>>(P1, ld1, P2, ld2, T2, out, ldo, rows);
   } else if (L == 128 || L == 256) {
     // out = P1 T2[0:L] (out may be P1), then out += P2 T2[L:2L]
-    int64_t nb;
-    int rpb;
-    gram_grid(rows, nb, rpb);
-    rpb = (rpb + 15) & ~15;
-    nb = (rows + rpb - 1) / rpb;
+    const unsigned nb = (unsigned)strip_blocks(L, (rows + 15) / 16, 1);
     if (L == 128) {
-      k_xform_strips<128, false, false><<<(unsigned)nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<128, true, false><<<(unsigned)nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
-                                                                     nullptr);
+      k_xform_strips<128, false, false><<<nb, 512, 0, st>>>(P1, ld1, out, ldo, rows, T2, L, nullptr);
+      k_xform_strips<128, true, false><<<nb, 512, 0, st>>>(P2, ld2, out, ldo, rows, T2 + L * L, L, nullptr);
     } else {
-      k_xform_strips<256, false, false><<<(unsigned)nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, rpb, T2, L, nullptr);
-      k_xform_strips<256, true, false><<<(unsigned)nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, rpb, T2 + L * L, L,
-                                                                      nullptr);
+      k_xform_strips<256, false, false><<<nb, 1024, 0, st>>>(P1, ld1, out, ldo, rows, T2, L, nullptr);
+      k_xform_strips<256, true, false><<<nb, 1024, 0, st>>>(P2, ld2, out, ldo, rows, T2 + L * L, L, nullptr);
     }
   } else {
     return hipErrorInvalidValue;

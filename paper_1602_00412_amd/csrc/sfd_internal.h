@@ -133,7 +133,13 @@ struct SpmmConfig {
   bool queue = false; // persistent grid fed by the schedule's work queues
   int occupancy = 4;  // persistent grid: blocks per CU
   bool stage = false; // Y = A' X with a queue grid: the most popular columns' rows of X in LDS
+  int live = 0;       // 16-byte segments of each panel row to gather (0: all).  The columns past
+                      // the sketch's ell are zero in every panel, so the segments wholly past the
+                      // last 64-byte sector that holds a live column need not be fetched
 };
+// the segments of a panel row (elem_bytes per element) that reach the 64-byte sector holding
+// column ell - 1: what SpmmConfig::live needs to gather
+int live_segments(int ell, int elem_bytes);
 // builds the chunk schedule of a CSR/CSC structure on the device (no host synchronisation)
 hipError_t schedule_build(const int* ptr, int rows, Schedule& s, int* scan_tmp, hipStream_t st);
 // staging of a buffer's CSR schedule s: the columns whose entry counts (from its CSC colptr) reach
@@ -182,7 +188,7 @@ hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const 
 // With segs = nullptr and K = 1 it is the single-buffer launch over (rows, rpb, nb).
 hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,
                             int L, const float* T, float* partials, double* W, hipStream_t st);
-void gram_geometry(int64_t rows, int* nb, int* rpb);
+void gram_geometry(int64_t rows, int L, int* nb, int* rpb);
 // BF16 panels (sfd_bf16.hip): P <- P T on BF16 MFMA (T split into two BF16 parts when split) and
 // the per-block partial Grams of the stored result (upper tiles, FP32), for the Gram reduction
 hipError_t xform_gram_bf16_partials(uint16_t* P, int ld, int64_t rows, int rpb, int nb, const GroupSeg* segs, int K,

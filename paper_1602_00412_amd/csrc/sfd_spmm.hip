@@ -248,7 +248,7 @@ __device__ inline void store_seg(void* row, int sub, const float* o) {
 // STAGE: an id c < 0 names row -1 - c of the rows staged in LDS (hot, pitch LPR segments).
 template <int LPR, int U, int T0, bool BF, bool STAGE>
 __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::raw* __restrict__ Xs, int lds, int sub,
-                                    const typename Seg<BF>::raw* hot, float* acc) {
+                                    bool live, const typename Seg<BF>::raw* hot, float* acc) {
   int c[U];
   float v[U];
   typename Seg<BF>::raw x[U];
@@ -257,7 +257,11 @@ __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::ra
   }(std::make_integer_sequence<int, U>{});
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if constexpr (STAGE)
+    // a lane whose columns are all past the sketch's ell holds zeros in every panel row: its
+    // gather is skipped (the row's tail sectors are never fetched) and it adds zeros
+    if (!live)
+      x[u] = typename Seg<BF>::raw{};
+    else if constexpr (STAGE)
       x[u] = c[u] < 0 ? hot[(-1 - c[u]) * LPR + sub] : Xs[(int64_t)c[u] * lds + sub];
     else
       x[u] = Xs[(int64_t)c[u] * lds + sub];
@@ -294,11 +298,12 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
                                            int64_t stride, int* __restrict__ queue, const int* __restrict__ idx,
                                            const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                            void* __restrict__ out, int ldo, float* __restrict__ partial,
-                                           const typename Seg<BIN>::raw* hot) {
+                                           const typename Seg<BIN>::raw* hot, int nlive) {
   using S = Seg<BIN>;
   constexpr int VEC = S::VEC;
   constexpr int LPR = L / VEC;  // lanes per group
   const int sub = (threadIdx.x & 63) % LPR;
+  const bool live = sub < nlive;  // this lane's columns reach below ell
   const typename S::raw* Xs = reinterpret_cast<const typename S::raw*>(X);
   const int lds = ldx / VEC;  // row pitch in segments
   const size_t out_row_bytes = (size_t)ldo * (BOUT ? 2 : 4);
@@ -346,7 +351,7 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
     // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
     const int cnt = min(LPR, dc.z - p);
     [&]<int... b>(std::integer_sequence<int, b...>) {
-      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN, STAGE>(ci, vi, Xs, lds, sub, hot, acc) : void()), ...);
+      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN, STAGE>(ci, vi, Xs, lds, sub, live, hot, acc) : void()), ...);
     }(std::make_integer_sequence<int, LPR / U>{});
     if (!same) {
       float o[VEC];
@@ -397,7 +402,8 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
                                               int nlocal, int* __restrict__ queue, const int* __restrict__ idx,
                                               const void* __restrict__ val, const void* __restrict__ X, int ldx,
                                               void* __restrict__ out, int ldo, float* __restrict__ partial,
-                                              const int* __restrict__ hot_cols, const int* __restrict__ hot_n) {
+                                              const int* __restrict__ hot_cols, const int* __restrict__ hot_n,
+                                              int nlive) {
   using raw = typename Seg<BIN>::raw;
   constexpr int LPR = L / Seg<BIN>::VEC;
   constexpr int G = 64 / LPR;  // groups per wave
@@ -417,11 +423,11 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
     const int64_t slot = blockIdx.x / nlocal;
     spmm_range<L, U, BIN, BOUT, VB, QUEUE, STAGE>(desc, regions[band], regions[band + 1], (slot * 4 + wave) * G + grp,
                                                   (int64_t)(gridDim.x / nlocal) * 4 * G, queue + band, idx, val, X,
-                                                  ldx, out, ldo, partial, hot);
+                                                  ldx, out, ldo, partial, hot, nlive);
   }
   spmm_range<L, U, BIN, BOUT, VB, QUEUE, STAGE>(desc, regions[nlocal], regions[nlocal + 1],
                                                 ((int64_t)blockIdx.x * 4 + wave) * G + grp, (int64_t)gridDim.x * 4 * G,
-                                                queue + nlocal, idx, val, X, ldx, out, ldo, partial, hot);
+                                                queue + nlocal, idx, val, X, ldx, out, ldo, partial, hot, nlive);
 }
 
 // One block per long row: wave w adds the row's partials w, w + 4, ... (in slot order), then
@@ -614,7 +620,7 @@ int device_cus() {
 
 template <int L, int U, bool BIN, bool BOUT, bool VB, bool QUEUE, bool STAGE = false>
 void launch_spmm(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
-                 float* partial, int occupancy, hipStream_t st) {
+                 float* partial, int occupancy, int nlive, hipStream_t st) {
   constexpr int G = 64 / (L / Seg<BIN>::VEC);
   // static: about four chunks per group (finished blocks make room for waiting ones, which
   // balances uneven chunks); queue: `occupancy` blocks per CU at most.  A multiple of the XCD
@@ -626,22 +632,24 @@ void launch_spmm(const Schedule& s, const int* idx, const void* val, const void*
   // TRANSPOSED (CSC products) only gives the two products different kernel names
   if (s.transposed)
     k_spmm<L, U, true, BIN, BOUT, VB, QUEUE, false><<<(unsigned)grid, 256, 0, st>>>(
-        s.desc, s.regions, s.nlocal, s.queue, idx, val, X, ldx, out, ldo, partial, nullptr, nullptr);
+        s.desc, s.regions, s.nlocal, s.queue, idx, val, X, ldx, out, ldo, partial, nullptr, nullptr, nlive);
   else
     k_spmm<L, U, false, BIN, BOUT, VB, QUEUE, STAGE><<<(unsigned)grid, 256, 0, st>>>(
         s.desc, s.regions, s.nlocal, s.queue, STAGE ? s.stage_idx : idx, val, X, ldx, out, ldo, partial, s.hot_cols,
-        s.hot_n);
+        s.hot_n, nlive);
 }
 
 template <int L, int U, bool BIN, bool BOUT, bool VB>
 void launch_spmm_cfg(const Schedule& s, const int* idx, const void* val, const void* X, int ldx, void* out, int ldo,
                      float* partial, const SpmmConfig& cfg, hipStream_t st) {
+  constexpr int LPR = L / Seg<BIN>::VEC;
+  const int nlive = cfg.live > 0 && cfg.live < LPR ? cfg.live : LPR;
   if (cfg.queue && cfg.stage)
-    launch_spmm<L, U, BIN, BOUT, VB, true, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, st);
+    launch_spmm<L, U, BIN, BOUT, VB, true, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, nlive, st);
   else if (cfg.queue)
-    launch_spmm<L, U, BIN, BOUT, VB, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, st);
+    launch_spmm<L, U, BIN, BOUT, VB, true>(s, idx, val, X, ldx, out, ldo, partial, cfg.occupancy, nlive, st);
   else
-    launch_spmm<L, U, BIN, BOUT, VB, false>(s, idx, val, X, ldx, out, ldo, partial, 0, st);
+    launch_spmm<L, U, BIN, BOUT, VB, false>(s, idx, val, X, ldx, out, ldo, partial, 0, nlive, st);
 }
 
 template <int L>
@@ -733,6 +741,11 @@ hipError_t spmm(const Schedule& s, const int* idx, const void* val, bool val_bf1
   if (L == 128) return spmm_l<128>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
   if (L == 256) return spmm_l<256>(s, idx, val, val_bf16, X, xt, ldx, Y, yt, ldy, partial, cfg, st);
   return hipErrorInvalidValue;
+}
+
+int live_segments(int ell, int elem_bytes) {
+  const int bytes = (ell * elem_bytes + 63) / 64 * 64;
+  return bytes / 16;
 }
 
 hipError_t spmm_queue_reset(const Schedule& s, hipStream_t st) {
