@@ -430,8 +430,11 @@ __global__ __launch_bounds__(256) void k_spmm(const int4* __restrict__ desc, con
                                                 queue + nlocal, idx, val, X, ldx, out, ldo, partial, hot, nlive);
 }
 
-// One block per long row: wave w adds the row's partials w, w + 4, ... (in slot order), then
-// the four wave sums are added in wave order.
+// One block per long row (rows whose chunks went to partial slots: long rows and XCD-local
+// pieces; a Zipf-hot column of a 5 * 10^6-entry buffer has over a thousand): wave w adds the
+// slots w, w + 4, w + 8, ... of each column, eight of them in flight at once (slot w + 4 i into
+// sum i % 8); the eight sums are added as a fixed tree, then the four wave sums in wave order.
+// The order is fixed, so results do not depend on scheduling.
 // The product's work queues are cleared here for the next product over the schedule (the
 // product has completed: the fix-up runs after it on the same stream).
 template <int L, bool BOUT>
@@ -440,56 +443,49 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(const int* __restrict__ slot
                                                     const float* __restrict__ partial, void* __restrict__ Y,
                                                     int ldy, int* __restrict__ queue) {
   constexpr int CPL = (L + 63) / 64;  // columns per lane
+  constexpr int ILP = 8;              // slots in flight per wave
   __shared__ float red[4][L];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   if (queue && blockIdx.x == 0 && threadIdx.x < kXcdBands + 2) queue[threadIdx.x] = 0;
   const int nlong = *nlong_ptr;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   for (int li = blockIdx.x; li < nlong; li += gridDim.x) {
-  const int r = long_rows[li];
-  const int n = slot_start[r + 1] - slot_start[r];
-  const float* base = partial + (int64_t)slot_start[r] * L;
-  float acc[CPL];
-#pragma unroll
-  for (int u = 0; u < CPL; ++u) acc[u] = 0.f;
-  int j = wave;
-  for (; j + 4 < n; j += 8) {
+    const int r = long_rows[li];
+    const int s0 = slot_start[r];
+    const int n = slot_start[r + 1] - s0;
+    const float* base = partial + (int64_t)s0 * L;
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
       const int col = lane + 64 * u;
-      if (col < L) {
-        const float a = base[(int64_t)j * L + col], b = base[(int64_t)(j + 4) * L + col];
-        acc[u] += a;
-        acc[u] += b;
+      if (col >= L) continue;
+      const float* pc = base + col;
+      float a[ILP];
+#pragma unroll
+      for (int k = 0; k < ILP; ++k) a[k] = 0.f;
+      int j = wave;
+      for (; j + 4 * (ILP - 1) < n; j += 4 * ILP) {
+#pragma unroll
+        for (int k = 0; k < ILP; ++k) a[k] += pc[(int64_t)(j + 4 * k) * L];
       }
-    }
-  }
-  for (; j < n; j += 4) {
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int col = lane + 64 * u;
-      if (col < L) acc[u] += base[(int64_t)j * L + col];
+      for (int k = 0; k < ILP - 1; ++k)
+        if (j + 4 * k < n) a[k] += pc[(int64_t)(j + 4 * k) * L];
+      red[wave][col] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
-  }
-#pragma unroll
-  for (int u = 0; u < CPL; ++u) {
-    const int col = lane + 64 * u;
-    if (col < L) red[wave][col] = acc[u];
-  }
-  __syncthreads();
-  for (int col = threadIdx.x; col < L; col += 256) {
-    const float v = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
-    if constexpr (BOUT)
-      reinterpret_cast<uint16_t*>(Y)[(int64_t)r * ldy + col] = (uint16_t)f32_to_bf16(v);
-    else
-      reinterpret_cast<float*>(Y)[(int64_t)r * ldy + col] = v;
-  }
-  __syncthreads();
+    __syncthreads();
+    for (int col = threadIdx.x; col < L; col += 256) {
+      const float v = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+      if constexpr (BOUT)
+        reinterpret_cast<uint16_t*>(Y)[(int64_t)r * ldy + col] = (uint16_t)f32_to_bf16(v);
+      else
+        reinterpret_cast<float*>(Y)[(int64_t)r * ldy + col] = v;
+    }
+    __syncthreads();
   }
 }
 
-// Four chunks per wave, one per 16-lane group; a group strides its chunk's entries and
-// reduces with a 16-lane xor tree.
+// Four chunks per wave, one per 16-lane group; a group strides its chunk's entries (lane s takes
+// s, s + 16, ...) and reduces with a 16-lane xor tree.
 // In a group (seg_rows != nullptr) row r belongs to the buffer k with seg_rows[k] <= r <
 // seg_rows[k + 1] and is scaled by scale_ptr[k sstride].
 __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, const int* __restrict__ nchunks_ptr,
@@ -503,22 +499,46 @@ __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, con
   const int grp = lane >> 4;
   const float scale1 = (scale_ptr && !seg_rows) ? (float)(*scale_ptr) : 1.f;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
-  for (int64_t base = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 4; base < nchunks; base += nwaves * 4) {
-    const int64_t cc = base + grp;
-    const bool active = cc < nchunks;
-    const int4 dc = active ? desc[cc] : make_int4(0, 0, 0, -1);
-    float acc = 0.f;
-    int p = dc.y + sub;
-    for (; p + 16 < dc.z; p += 32) {
-      const int c0 = idx[p], c1 = idx[p + 16];
-      const float v0 = val[p], v1 = val[p + 16];
-      acc = fmaf(v0, y[c0], acc);
-      acc = fmaf(v1, y[c1], acc);
+  // the lane's entries p, p + 16, ... of a chunk in rounds of four: a round's ids and values are
+  // loaded together, then its four gathers, then the products are added in entry order.  A wave
+  // takes four chunks at a time (one per group) and loads the descriptors and the first round of
+  // its next four before the current ones are reduced and stored.
+  auto load_round = [&](int p, int end, int* c, float* v) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool in = p + 16 * k < end;
+      c[k] = in ? idx[p + 16 * k] : 0;
+      v[k] = in ? val[p + 16 * k] : 0.f;
     }
-    if (p < dc.z) acc = fmaf(val[p], y[idx[p]], acc);
+  };
+  auto add_round = [&](int p, int end, const int* c, const float* v, float& acc) {
+    float yv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) yv[k] = p + 16 * k < end ? y[c[k]] : 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (p + 16 * k < end) acc = fmaf(v[k], yv[k], acc);
+  };
+  int64_t base = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 4;
+  int4 dc = base + grp < nchunks ? desc[base + grp] : make_int4(0, 0, 0, -1);
+  int c[4];
+  float v[4];
+  load_round(dc.y + sub, dc.z, c, v);
+  for (; base < nchunks; base += nwaves * 4) {
+    const int64_t nb = base + nwaves * 4;
+    const int4 dn = nb + grp < nchunks ? desc[nb + grp] : make_int4(0, 0, 0, -1);
+    float acc = 0.f;
+    add_round(dc.y + sub, dc.z, c, v, acc);
+    for (int p = dc.y + sub + 64; p < dc.z; p += 64) {
+      int c2[4];
+      float v2[4];
+      load_round(p, dc.z, c2, v2);
+      add_round(p, dc.z, c2, v2, acc);
+    }
+    load_round(dn.y + sub, dn.z, c, v);
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    if (active && sub == 0) {
+    if (base + grp < nchunks && sub == 0) {
       float scale = scale1;
       if (scale_ptr && seg_rows) {
         int lo = 0, hi = K;  // last k with seg_rows[k] <= row
@@ -528,12 +548,13 @@ __global__ __launch_bounds__(256) void k_spmv(const int4* __restrict__ desc, con
         }
         scale = (float)scale_ptr[(int64_t)lo * sstride];
       }
-      const float v = acc * scale;
+      const float val_out = acc * scale;
       if (dc.w < 0)
-        z[dc.x] = v;
+        z[dc.x] = val_out;
       else
-        partial[dc.w] = v;
+        partial[dc.w] = val_out;
     }
+    dc = dn;
   }
 }
 
@@ -674,12 +695,16 @@ hipError_t spmm_l(const Schedule& s, const int* idx, const void* val, bool vb, c
   return hipGetLastError();
 }
 
+// blocks of the fix-up: a block per long row, striding over the rows
+constexpr unsigned kFixupBlocks = 1024;
+
 template <int L>
 void launch_fixup(const Schedule& s, float* partial, void* Y, bool yb, int ldy, hipStream_t st) {
   if (yb)
-    k_spmm_fixup<L, true><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy, s.queue);
+    k_spmm_fixup<L, true><<<kFixupBlocks, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy, s.queue);
   else
-    k_spmm_fixup<L, false><<<256, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy, s.queue);
+    k_spmm_fixup<L, false><<<kFixupBlocks, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, Y, ldy,
+                                                         s.queue);
 }
 
 }  // namespace
@@ -775,8 +800,9 @@ hipError_t spmv(const int* ptr, const int* idx, const float* val, const Schedule
   (void)ptr;
   // every chunk of the schedule, in descriptor order: [regions[0], regions[nlocal + 1])
   const int* nchunks = s.regions + s.nlocal + 1;
-  int64_t g = ((int64_t)s.max_chunks + 15) / 16;
-  if (g > kSpmmMaxBlocks) g = kSpmmMaxBlocks;
+  // about eight chunks per group of 16 lanes (16 groups per block)
+  int64_t g = ((int64_t)s.max_chunks + 127) / 128;
+  if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   k_spmv<<<(unsigned)g, 256, 0, st>>>(s.desc, nchunks, idx, val, y, scale_ptr, z, partial, seg_rows, K, sstride);
   k_spmv_fixup<<<64, 256, 0, st>>>(s.pslot, s.long_rows, s.counters, partial, z);
