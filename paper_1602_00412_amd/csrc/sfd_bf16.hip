@@ -74,14 +74,21 @@ __device__ inline int strip_of(int w, int e) {
   return e == 0 ? w : Bf16Geom<L>::S - 1 - w;
 }
 
-// pair j of wave w's (strip, k-step) list: with two strips, strip w's k-steps 0 .. w / 2 come
-// first, then those of strip S - 1 - w; with one, k-step j of strip w (needed when j <= w / 2)
+// pair j of wave w's (strip, k-step) list: with two strips (w needs k-steps 0 .. w / 2, S - 1 - w
+// needs 0 .. (S - 1 - w) / 2), the pairs of the two strips alternate while both have k-steps left,
+// so consecutive MFMAs go to different accumulators; with one strip, k-step j of strip w
 template <int L>
 __device__ inline void pair_of(int w, int j, int& e, int& ks) {
   if constexpr (Bf16Geom<L>::SPW == 2) {
-    const int n0 = w / 2 + 1;
-    e = j < n0 ? 0 : 1;
-    ks = j < n0 ? j : j - n0;
+    const int n0 = w / 2 + 1, n1 = Bf16Geom<L>::NKS - n0;
+    const int m = n0 < n1 ? n0 : n1;
+    if (j < 2 * m) {
+      e = j & 1;
+      ks = j >> 1;
+    } else {
+      e = n0 > n1 ? 0 : 1;
+      ks = m + (j - 2 * m);
+    }
   } else {
     e = 0;
     ks = j;
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(Bf16Geom<L>::NT) void k_xform_gram_bf16(uint16_t* _
   __shared__ u32x4 sop[SPI][S][64];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int w = tid >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
   const int lm = lane & 15, lk = lane >> 4;
   // B operands: column slices of T (rows 32 ks + 8 lk .. + 7 of column 16 n + lm) for this wave's
   // (strip, k-step) pairs, split into BF16 parts
@@ -172,9 +179,11 @@ __global__ __launch_bounds__(Bf16Geom<L>::NT) void k_xform_gram_bf16(uint16_t* _
     for (int s = 0; s < SPI; ++s) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        floatx4 acc[SPW];
+        // the T_hi and T_lo products go to separate accumulators (independent MFMA chains),
+        // added once the k-steps are done
+        floatx4 acc[SPW], accl[SPW];
 #pragma unroll
-        for (int e = 0; e < SPW; ++e) acc[e] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int e = 0; e < SPW; ++e) acc[e] = accl[e] = floatx4{0.f, 0.f, 0.f, 0.f};
         const uint16_t* arow = sin_ + (32 * s + 16 * h + lm) * LP + 8 * lk;
 #pragma unroll
         for (int j = 0; j < NKS; ++j) {
@@ -186,8 +195,12 @@ __global__ __launch_bounds__(Bf16Geom<L>::NT) void k_xform_gram_bf16(uint16_t* _
           for (int ee = 0; ee < SPW; ++ee) {
             if (ee != e) continue;
             acc[ee] = mfma_bf16(a, th[j], acc[ee]);
-            if constexpr (SPLIT) acc[ee] = mfma_bf16(a, tl[j], acc[ee]);
+            if constexpr (SPLIT) accl[ee] = mfma_bf16(a, tl[j], accl[ee]);
           }
+        }
+        if constexpr (SPLIT) {
+#pragma unroll
+          for (int e = 0; e < SPW; ++e) acc[e] += accl[e];
         }
 #pragma unroll
         for (int e = 0; e < SPW; ++e) {

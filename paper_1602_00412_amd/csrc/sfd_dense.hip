@@ -451,42 +451,52 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const float* __restrict__ P,
   }
 }
 
-// W64[i][j] = sum over blocks of the upper-triangle partial (i <= j), mirrored, so W64 is exactly
-// symmetric.  A block owns 16 entries; sixteen thread groups sum interleaved sixteenths of the
-// partials (fixed order) and the group sums are added in group order.
+// W64[i][j] = W64[j][i] = sum over blocks of the partials' entry (i, j), i <= j (the partials hold
+// the tiles on and above the diagonal), so W64 is exactly symmetric and each upper entry is read
+// once per partial.  Block (x, i) owns row i, columns 16 x .. 16 x + 15 (blocks wholly below the
+// diagonal return); sixteen thread groups sum interleaved sixteenths of the partials, four loads
+// in flight each, in a fixed order, and the group sums are added in group order.  Groups: buffer
+// k = blockIdx.z with segs[k].nb partials at partials + k pstride.
 __global__ __launch_bounds__(256) void k_gram_reduce(const float* __restrict__ partials, int nb, int W,
                                                      double* __restrict__ Wout, const GroupSeg* segs,
                                                      int64_t pstride) {
   __shared__ double red[16][16];
-  if (segs) {  // buffer k = blockIdx.y of a group
-    nb = segs[blockIdx.y].nb;
-    partials += (int64_t)blockIdx.y * pstride;
-    Wout += (int64_t)blockIdx.y * W * W;
+  const int i = blockIdx.y;
+  const int j0 = blockIdx.x * 16;
+  if (j0 + 15 < i) return;
+  if (segs) {
+    nb = segs[blockIdx.z].nb;
+    partials += (int64_t)blockIdx.z * pstride;
+    Wout += (int64_t)blockIdx.z * W * W;
   }
   const int q = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
-  const int e = blockIdx.x * 16 + q;
-  const int WW = W * W;
+  const int j = j0 + q;
+  const bool mine = j >= i && j < W;
+  const int64_t WW = (int64_t)W * W;
   double s = 0.0;
-  if (e < WW) {
-    const int i = e / W, j = e % W;
-    const int src = i <= j ? e : j * W + i;
-    const float* p = partials + src;
+  if (mine) {
+    const float* p = partials + (int64_t)i * W + j;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int b = grp;
-    for (; b + 16 < nb; b += 32) {
-      const float v0 = p[(int64_t)b * WW], v1 = p[(int64_t)(b + 16) * WW];
-      s += (double)v0;
-      s += (double)v1;
+    for (; b + 48 < nb; b += 64) {
+      const float v0 = p[b * WW], v1 = p[(b + 16) * WW], v2 = p[(b + 32) * WW], v3 = p[(b + 48) * WW];
+      s0 += (double)v0;
+      s1 += (double)v1;
+      s2 += (double)v2;
+      s3 += (double)v3;
     }
-    for (; b < nb; b += 16) s += (double)p[(int64_t)b * WW];
+    for (; b < nb; b += 16) s0 += (double)p[b * WW];
+    s = (s0 + s1) + (s2 + s3);
   }
   red[grp][q] = s;
   __syncthreads();
-  if (threadIdx.x < 16 && e < WW) {
+  if (threadIdx.x < 16 && mine) {
     double t = 0.0;
 #pragma unroll
     for (int g2 = 0; g2 < 16; ++g2) t += red[g2][q];
-    Wout[e] = t;
+    Wout[(int64_t)i * W + j] = t;
+    Wout[(int64_t)j * W + i] = t;
   }
 }
 
@@ -653,11 +663,12 @@ static int64_t strip_blocks(int L, int64_t tiles, int K) {
   return std::max<int64_t>(g, 1);
 }
 
-// Row blocks of a Gram (and of the L <= 64 transform + Gram): about 128 rows per block for
-// L <= 64, so that a 10^5-row panel fills the 256 compute units, and 512 for wider panels, whose
-// per-block partials (L x L each) the reduction reads back.
-static void gram_grid(int64_t rows, int L, int64_t& nb, int& rpb) {
-  const int64_t per = L <= 64 ? 128 : 512;
+// Row blocks of a Gram (and of the fused transform + Gram): about 128 rows per block for L <= 64,
+// so that a 10^5-row panel fills the 256 compute units, and 512 for wider FP32 panels, whose
+// per-block partials (L x L each) the reduction reads back (at most kGramMaxBlocks blocks).
+static void gram_grid(int64_t rows, int L, int64_t& nb, int& rpb, bool bf16 = false) {
+  // (BF16 panels of 128 or 256 columns: the fused BF16 transform + Gram takes ~200-row blocks)
+  const int64_t per = L <= 64 ? 128 : bf16 ? 192 : 512;
   nb = (rows + per - 1) / per;
   if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
   if (nb < 1) nb = 1;
@@ -670,7 +681,7 @@ hipError_t xform_gram(void* P, PanelType pt, int ld, int64_t rows, int L, const 
                       hipStream_t st) {
   int64_t nb;
   int rpb;
-  gram_grid(rows, L, nb, rpb);
+  gram_grid(rows, L, nb, rpb, pt == PanelType::BF16);
   return xform_gram_group(P, pt, ld, rows, rpb, (int)nb, nullptr, 1, L, T, partials, W, st);
 }
 
@@ -710,7 +721,8 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
   } else {
     return hipErrorInvalidValue;
   }
-  k_gram_reduce<<<dim3((unsigned)((L * L + 15) / 16), (unsigned)K), 256, 0, st>>>(partials, nb, L, W, segs, ps);
+  k_gram_reduce<<<dim3((unsigned)((L + 15) / 16), (unsigned)L, (unsigned)K), 256, 0, st>>>(partials, nb, L, W, segs,
+                                                                                           ps);
   return hipGetLastError();
 }
 
@@ -736,7 +748,8 @@ hipError_t gram2(const float* P1, int ld1, const float* P2, int ld2, int64_t row
     }
     default: return hipErrorInvalidValue;
   }
-  k_gram_reduce<<<(unsigned)((4 * L * L + 15) / 16), 256, 0, st>>>(partials, (int)nb, 2 * L, W, nullptr, 0);
+  k_gram_reduce<<<dim3((unsigned)((2 * L + 15) / 16), (unsigned)(2 * L), 1), 256, 0, st>>>(partials, (int)nb, 2 * L, W,
+                                                                                         nullptr, 0);
   return hipGetLastError();
 }
 
