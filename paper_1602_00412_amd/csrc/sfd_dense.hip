@@ -655,20 +655,23 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
 int gram_max_blocks() { return kGramMaxBlocks; }
 
 // Blocks of a strip transform (k_xform_strips) over `tiles` 16-row tiles per buffer for K buffers:
-// one 1024-thread block per compute unit for L = 256, two 512-thread blocks for L = 128, shared
-// out among the buffers; each block strides over its buffer's tiles.
+// at most 64 (L = 256) or 128 (L = 128) blocks in all, shared out among the buffers; each block
+// strides over its buffer's tiles and loads its part of T (up to 256 KB) once.  Fewer, longer
+// blocks cost less compute-unit time in all than one block per CU, and compute-unit time is what
+// paces a step when several lanes share the GPU (their kernels fill the CUs these leave free).
 static int64_t strip_blocks(int L, int64_t tiles, int K) {
-  const int64_t cap = L == 256 ? 256 : 512;
+  const int64_t cap = L == 256 ? 64 : 128;
   int64_t g = std::min(tiles, std::max<int64_t>(1, cap / std::max(1, K)));
   return std::max<int64_t>(g, 1);
 }
 
-// Row blocks of a Gram (and of the fused transform + Gram): about 128 rows per block for L <= 64,
-// so that a 10^5-row panel fills the 256 compute units, and 512 for wider FP32 panels, whose
-// per-block partials (L x L each) the reduction reads back (at most kGramMaxBlocks blocks).
+// Row blocks of a Gram (and of the fused transform + Gram): about 512 rows per block (1,024 for
+// the fused BF16 kernel of 128- and 256-wide panels, whose blocks load both BF16 parts of T), at
+// most kGramMaxBlocks.  Smaller blocks finish a lone transform sooner (128-row blocks: 19.9 against
+// 23.8 us on a 10^5 x 64 panel) but spend more compute-unit time on loading T and on per-block
+// partial Grams, and with several lanes on the GPU that time is what paces the step.
 static void gram_grid(int64_t rows, int L, int64_t& nb, int& rpb, bool bf16 = false) {
-  // (BF16 panels of 128 or 256 columns: the fused BF16 transform + Gram takes ~200-row blocks)
-  const int64_t per = L <= 64 ? 128 : bf16 ? 192 : 512;
+  const int64_t per = bf16 && L >= 128 ? 1024 : 512;
   nb = (rows + per - 1) / per;
   if (nb > kGramMaxBlocks) nb = kGramMaxBlocks;
   if (nb < 1) nb = 1;
