@@ -430,7 +430,7 @@ def main() -> int:
     ap.add_argument("--autotune", type=int, default=0, choices=[0, 1],
                     help="SFD_OPT_AUTOTUNE of every handle (0, the default: static product launches)")
     ap.add_argument("--launch", default="auto", choices=["auto", "static", "queue", "stage"],
-                    help="SFD_OPT_PRODUCT_LAUNCH of the single-stream handles (auto: as the autotuner decides)")
+                    help="SFD_OPT_PRODUCT_LAUNCH of the single-stream handles (auto: the tuned launch with --autotune 1, else the static grid)")
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="SFD_OPT_GRAPHS of the batch handles (1: graph-captured group steps, the default)")
     ap.add_argument("--big-forms", default="ell200,d1e6,batch4096",

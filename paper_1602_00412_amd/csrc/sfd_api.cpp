@@ -511,8 +511,9 @@ inline int log2_bucket(int64_t n) {
   return b;
 }
 
-// The configuration of a product (s, idx, val, X -> Y) on stream st: the tuned one, tuning first
-// when the key is new.  Not during stream capture (tuning synchronises).
+// The launch of a product (s, idx, val, X -> Y) on stream st: the one SFD_OPT_PRODUCT_LAUNCH forces,
+// else the tuned one with SFD_OPT_AUTOTUNE (tuning first when the key is new), else the static
+// grid.  Not during stream capture (tuning synchronises).
 int product_config_tuned(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
                          const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows,
                          int64_t nnz, SpmmConfig* out) {
@@ -581,8 +582,9 @@ int product_config_tuned(sfd_t* h, hipStream_t st, const Schedule& s, const int*
   return SFD_OK;
 }
 
-// ... and every configuration gathers only the panel-row segments that reach column ell - 1
-// (the rest are zero in every panel)
+// The configuration of a product: its launch (above), gathering only the 16-byte segments of a
+// panel row that reach the 64-byte sector holding column ell - 1 (the columns past ell are zero in
+// every panel, so the results are the same bits).
 int product_config(sfd_t* h, hipStream_t st, const Schedule& s, const int* idx, const void* val, bool vb,
                    const void* X, PanelType xt, void* Y, PanelType yt, float* partial, int64_t in_rows, int64_t nnz,
                    SpmmConfig* out) {
