@@ -1921,11 +1921,12 @@ int sfd_batch_create(int32_t nstreams, int64_t d, int32_t ell, double eps, uint6
     return rc;
   }
   if (nstreams > 1) {
-    // lockstep groups of up to 64 buffers, within about 4 GiB of workspace
+    // lockstep groups of up to 128 buffers, within about 8 GiB of workspace (128 rather than 64:
+    // 7.33 against 7.55 s for 4,096 streams at d = 2e4, ell = 32; fewer host round trips)
     sfd_t* h = b->core;
     const int64_t L = h->L;
     const int64_t per = h->cap * 40 + h->d * L * 4 * 3 + gram_partial_stride((int)L) * 4 + h->d * 64;
-    int kmax = (int)std::min<int64_t>({(int64_t)nstreams, 64, std::max<int64_t>(1, ((int64_t)4 << 30) / per)});
+    int kmax = (int)std::min<int64_t>({(int64_t)nstreams, 128, std::max<int64_t>(1, ((int64_t)8 << 30) / per)});
     DeviceGuard g(h->device);
     if (kmax >= 2 && (rc = alloc_group(h, kmax)) != SFD_OK) {
       sfd_destroy(h);
