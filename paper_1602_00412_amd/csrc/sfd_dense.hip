@@ -363,168 +363,6 @@ __global__ __launch_bounds__(L * 4) void k_xform_strips(const float* Pin, int ld
   }
 }
 
-// The CholeskyQR step of wide FP32 panels (L = 128, 256): P <- P T in place (T upper triangular)
-// and the per-block partial Gram of the result, in one pass over the panel.  Eight waves; wave w
-// computes output strips n(w, e), e < SPW (one strip at L = 128, dealt as in k_xform_strips; two at
-// L = 256, w and S - 1 - w, equal work under a triangular T), two MFMA chains per strip, with T's
-// strips held as B operands in registers.  Each 16-row output tile goes from the accumulators to
-// LDS, and the block forms the tile's contribution to the Gram from there: the S (S + 1) / 2 upper
-// 16 x 16 tiles of the L x L Gram are dealt to the waves round-robin (wave w: tiles w, w + 8, ...),
-// each an MFMA chain over the tile's rows (4 rows per v_mfma_f32_16x16x4f32).  The Gram tiles a
-// wave owns never change, so a block's partial needs no reduction across waves: each wave writes
-// its tiles of the block's L x L partial at the end.  A block with no tiles writes zeros, so every
-// one of the gridDim.x partials of a buffer is defined.  Blocks stride over the 16-row tiles.
-// Groups: buffer k = blockIdx.z owns rows [segs[k].row0, + segs[k].rows) with T + k L L and
-// partials + k pstride.
-constexpr int kStripGramWaves = 8;
-
-template <int L>
-__global__ __launch_bounds__(64 * kStripGramWaves) void k_xform_gram_strips(float* P, int ld, int64_t rows,
-                                                                            const float* __restrict__ T,
-                                                                            float* __restrict__ partials,
-                                                                            const GroupSeg* segs, int64_t pstride) {
-  static_assert(L == 128 || L == 256, "strip transform + Gram");
-  constexpr int NW = kStripGramWaves;
-  constexpr int NT = 64 * NW;
-  constexpr int KS = L / 4;
-  constexpr int LP = L + 4;
-  constexpr int S = L / 16;
-  constexpr int SPW = S / NW;               // strips per wave
-  constexpr int NU = S * (S + 1) / 2;       // upper Gram tiles
-  constexpr int TPW = (NU + NW - 1) / NW;   // Gram tiles per wave
-  constexpr int NLD = 16 * L / 4 / NT;      // 16-byte loads per thread per tile
-  if (segs) {
-    const GroupSeg g = segs[blockIdx.z];
-    P += (size_t)g.row0 * ld;
-    rows = g.rows;
-    T += (int64_t)blockIdx.z * L * L;
-    partials += (int64_t)blockIdx.z * pstride;
-  }
-  const int64_t ntiles = (rows + 15) / 16;
-  __shared__ float tile[2][16 * LP];
-  __shared__ float outt[16 * LP];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
-  const int lm = lane & 15, lk = lane >> 4;
-  int sn[SPW], kmax[SPW];
-#pragma unroll
-  for (int e = 0; e < SPW; ++e) {
-    sn[e] = SPW == 1 ? strip_of_wave<L>(w) : (e == 0 ? w : S - 1 - w);
-    kmax[e] = 4 * (sn[e] + 1);
-  }
-  float tb[SPW][KS];
-#pragma unroll
-  for (int e = 0; e < SPW; ++e)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) tb[e][ks] = ks < kmax[e] ? T[(4 * ks + lk) * L + 16 * sn[e] + lm] : 0.f;
-  // T is in registers before the tile loop, whose waits then cover only the loop's own loads
-#pragma unroll
-  for (int e = 0; e < SPW; ++e)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(tb[e][ks]));
-  floatx4 g[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) g[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int pitch = ld * 4;
-  auto rows_of = [&](int64_t t) -> int { return (int)max((int64_t)0, min((int64_t)16, rows - 16 * t)); };
-  auto rsrc = [&](int64_t t) {
-    return __builtin_amdgcn_make_buffer_rsrc(P + (size_t)min(t, ntiles) * 16 * ld, (short)0, rows_of(t) * pitch,
-                                             kBufferRsrcWord3);
-  };
-  // this thread's 16-byte pieces of a tile: piece c = j NT + tid, row c / (L / 4), column 4 (c % (L / 4))
-  auto load = [&](int64_t t, floatx4* x) {
-    const __amdgpu_buffer_rsrc_t r = rsrc(t);
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int c = j * NT + tid;
-      x[j] = __builtin_bit_cast(
-          floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, (c / (L / 4)) * pitch + 4 * (c % (L / 4)) * 4, 0, 0));
-    }
-  };
-  auto stage = [&](float* dst, const floatx4* x) {
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int c = j * NT + tid;
-      *reinterpret_cast<floatx4*>(dst + (c / (L / 4)) * LP + 4 * (c % (L / 4))) = x[j];
-    }
-  };
-  int64_t t = blockIdx.x;
-  floatx4 nxt[NLD];
-  load(t, nxt);
-  int buf = 0;
-  stage(tile[0], nxt);
-  for (; t < ntiles; t += gridDim.x, buf ^= 1) {
-    __syncthreads();  // tile[buf] staged; every wave is done with tile[buf ^ 1] and with outt
-    load(t + gridDim.x, nxt);
-    const __amdgpu_buffer_rsrc_t ro = rsrc(t);
-    const float* tl = tile[buf] + lm * LP + lk;
-#pragma unroll
-    for (int e = 0; e < SPW; ++e) {
-      floatx4 o0 = floatx4{0.f, 0.f, 0.f, 0.f}, o1 = o0;
-      float a[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = tl[4 * j];
-#pragma unroll
-      for (int kg = 0; kg < KS / 4; ++kg) {
-        if (4 * kg < kmax[e]) {
-          float an[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) an[j] = kg + 1 < KS / 4 ? tl[16 * (kg + 1) + 4 * j] : 0.f;
-          o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], tb[e][4 * kg], o0, 0, 0, 0);
-          o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], tb[e][4 * kg + 1], o1, 0, 0, 0);
-          o0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], tb[e][4 * kg + 2], o0, 0, 0, 0);
-          o1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], tb[e][4 * kg + 3], o1, 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[j] = an[j];
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float x = o0[v] + o1[v];
-        outt[(4 * lk + v) * LP + 16 * sn[e] + lm] = x;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), ro, (4 * lk + v) * pitch + (16 * sn[e] + lm) * 4, 0,
-                                              0);
-      }
-    }
-    __syncthreads();  // the output tile is complete in LDS
-    // Gram += out^T out over the tile's 16 rows: tile u = (si, sj), k-step ks: A lane l =
-    // out[4 ks + l / 16][16 si + l % 16], B lane l = out[4 ks + l / 16][16 sj + l % 16]
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      int u = w + NW * q;
-      if (u < NU) {
-        int si = 0;
-        while (u >= S - si) {
-          u -= S - si;
-          ++si;
-        }
-        const float* ai = outt + lk * LP + 16 * si + lm;
-        const float* bj = outt + lk * LP + 16 * (si + u) + lm;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          g[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[4 * ks * LP], bj[4 * ks * LP], g[q], 0, 0, 0);
-      }
-    }
-    // the next tile into the other buffer (its last readers were before this pass's first barrier)
-    stage(tile[buf ^ 1], nxt);
-  }
-  float* out = partials + (int64_t)blockIdx.x * L * L;
-#pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    int u = w + NW * q;
-    if (u < NU) {
-      int si = 0;
-      while (u >= S - si) {
-        u -= S - si;
-        ++si;
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[(16 * si + 4 * lk + v) * L + 16 * (si + u) + lm] = g[q][v];
-    }
-  }
-}
-
 // Gram partials of wide panels by 64 x 64 output tiles: block (x, y, z) forms tile pair
 // y = (I, J), I <= J, of the W x W Gram of the panel [P | P2] (64-column slices; slices below
 // SPLIT = W1 / 64 come from P, the rest from P2) over row block x, for buffer z of a group.
@@ -626,11 +464,11 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const float* __restrict__ p
   const int i = blockIdx.y;
   const int j0 = blockIdx.x * 16;
   if (j0 + 15 < i) return;
-  // buffer k = blockIdx.z of a group: its partials and W; segs (if given) holds its block count,
-  // else every buffer has nb
-  partials += (int64_t)blockIdx.z * pstride;
-  Wout += (int64_t)blockIdx.z * W * W;
-  if (segs) nb = segs[blockIdx.z].nb;
+  if (segs) {
+    nb = segs[blockIdx.z].nb;
+    partials += (int64_t)blockIdx.z * pstride;
+    Wout += (int64_t)blockIdx.z * W * W;
+  }
   const int q = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
   const int j = j0 + q;
@@ -873,18 +711,16 @@ hipError_t xform_gram_group(void* P, PanelType pt, int ld, int64_t rows, int rpb
   } else if (L == 64) {
     k_xform_gram<64><<<grid, kGramThreads, 0, st>>>(static_cast<float*>(P), ld, rows, rpb, T, partials, segs, ps);
   } else if (L == 128 || L == 256) {
-    // transform in place and the partial Grams of the result in one pass (one partial per block
-    // of the launch, whatever the buffer's rows)
+    // transform in place, then the Gram of the stored result by 64 x 64 tiles
     float* Pf = static_cast<float*>(P);
-    const int gb = (int)strip_blocks(L, (int64_t)nb * 32, K);
-    const dim3 gx((unsigned)gb, 1, (unsigned)K);
+    const dim3 gx((unsigned)strip_blocks(L, (int64_t)nb * 32, K), 1, (unsigned)K);
+    const int ns = L / 64;
+    const dim3 gg((unsigned)nb, (unsigned)(ns * (ns + 1) / 2), (unsigned)K);
     if (L == 128)
-      k_xform_gram_strips<128><<<gx, 64 * kStripGramWaves, 0, st>>>(Pf, ld, rows, T, partials, segs, ps);
+      k_xform_strips<128, false, true><<<gx, 512, 0, st>>>(Pf, ld, Pf, ld, rows, T, L, segs);
     else
-      k_xform_gram_strips<256><<<gx, 64 * kStripGramWaves, 0, st>>>(Pf, ld, rows, T, partials, segs, ps);
-    k_gram_reduce<<<dim3((unsigned)((L + 15) / 16), (unsigned)L, (unsigned)K), 256, 0, st>>>(partials, gb, L, W,
-                                                                                           nullptr, ps);
-    return hipGetLastError();
+      k_xform_strips<256, false, true><<<gx, 1024, 0, st>>>(Pf, ld, Pf, ld, rows, T, L, segs);
+    k_gram_tiles<<<gg, 256, 0, st>>>(Pf, ld, nullptr, 0, L, L, rows, rpb, partials, segs, ps);
   } else {
     return hipErrorInvalidValue;
   }
