@@ -167,3 +167,22 @@ def test_autotune_keeps_the_bits_single_stream(gpu_lib):
         outs.append(sk.sketch().cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_batch_past_one_lockstep_group_equals_single_streams(gpu_lib):
+    """130 streams with one full buffer each: a round of 130 buffers runs as two lockstep groups
+    (a batch handle groups up to 128), and every stream's sketch still equals its single-stream
+    handle's bit for bit, on both sides of the group boundary."""
+    import torch
+
+    d, ell, n = 300, 12, 320
+    streams = [small_random_csr(n, d, 6, 700 + s, dist="lognormal") for s in range(130)]
+    indptr, idx, val, starts = _cat(streams)
+    b = gpu_lib.Batch(len(streams), d, ell)
+    b.append_csr(np.arange(len(streams), dtype=np.int32), starts, torch.from_numpy(indptr).cuda(),
+                 torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda())
+    B = b.sketch().cpu().numpy()
+    for s in (0, 1, 127, 128, 129):
+        sk, Bs = _single(gpu_lib, streams[s], d, ell, s)
+        assert b.stats(s)["flushes"] == sk.stats()["flushes"] >= 1
+        assert np.array_equal(B[s], Bs), s
