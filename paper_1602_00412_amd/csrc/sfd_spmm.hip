@@ -244,30 +244,46 @@ __device__ inline void store_seg(void* row, int sub, const float* o) {
 }
 
 // U entries of the group's current block, starting at entry T0 of the block: broadcast their
-// ids and values from the lanes that loaded them, gather the U dense row segments, accumulate.
+// ids from the lanes that loaded them and gather their dense row segments.  A lane whose columns
+// are all past the sketch's ell (live == false) holds zeros in every panel row: it reads segment 0
+// of the row instead (a sector the group's first lane fetches anyway), so the row's tail sectors
+// are never fetched and no load sits behind a branch; what it sums is discarded when its output
+// is stored (zeros in its place).
 // STAGE: an id c < 0 names row -1 - c of the rows staged in LDS (hot, pitch LPR segments).
+template <int LPR, int U, int T0, bool BF, bool STAGE>
+__device__ inline void gather_load(int ci, const typename Seg<BF>::raw* __restrict__ Xs, int lds, int sub, bool live,
+                                   const typename Seg<BF>::raw* hot, typename Seg<BF>::raw* x) {
+  int c[U];
+  [&]<int... u>(std::integer_sequence<int, u...>) {
+    ((c[u] = bcast_i<LPR, T0 + u>(ci)), ...);
+  }(std::make_integer_sequence<int, U>{});
+  const int s = live ? sub : 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if constexpr (STAGE)
+      x[u] = c[u] < 0 ? hot[(-1 - c[u]) * LPR + sub] : Xs[(int64_t)c[u] * lds + s];
+    else
+      x[u] = Xs[(int64_t)c[u] * lds + s];
+  }
+}
+
+// ... and add them: acc += value * segment, in entry order
+template <int LPR, int U, int T0, bool BF>
+__device__ inline void gather_add(float vi, const typename Seg<BF>::raw* x, float* acc) {
+  float v[U];
+  [&]<int... u>(std::integer_sequence<int, u...>) {
+    ((v[u] = bcast_f<LPR, T0 + u>(vi)), ...);
+  }(std::make_integer_sequence<int, U>{});
+#pragma unroll
+  for (int u = 0; u < U; ++u) Seg<BF>::fma(v[u], x[u], acc);
+}
+
 template <int LPR, int U, int T0, bool BF, bool STAGE>
 __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::raw* __restrict__ Xs, int lds, int sub,
                                     bool live, const typename Seg<BF>::raw* hot, float* acc) {
-  int c[U];
-  float v[U];
   typename Seg<BF>::raw x[U];
-  [&]<int... u>(std::integer_sequence<int, u...>) {
-    ((c[u] = bcast_i<LPR, T0 + u>(ci), v[u] = bcast_f<LPR, T0 + u>(vi)), ...);
-  }(std::make_integer_sequence<int, U>{});
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    // a lane whose columns are all past the sketch's ell holds zeros in every panel row: its
-    // gather is skipped (the row's tail sectors are never fetched) and it adds zeros
-    if (!live)
-      x[u] = typename Seg<BF>::raw{};
-    else if constexpr (STAGE)
-      x[u] = c[u] < 0 ? hot[(-1 - c[u]) * LPR + sub] : Xs[(int64_t)c[u] * lds + sub];
-    else
-      x[u] = Xs[(int64_t)c[u] * lds + sub];
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) Seg<BF>::fma(v[u], x[u], acc);
+  gather_load<LPR, U, T0, BF, STAGE>(ci, Xs, lds, sub, live, hot, x);
+  gather_add<LPR, U, T0, BF>(vi, x, acc);
 }
 
 // Y[r, :] = sum_k val[k] X[idx[k], :] over the chunk descriptors [c0, c1): this lane's group
@@ -342,21 +358,33 @@ __device__ __forceinline__ void spmm_range(const int4* __restrict__ desc, int64_
     const bool same = p + LPR < dc.z;
     const int np = same ? p + LPR : dn.y;
     const int nend = same ? dc.z : dn.z;
-    int ci2 = 0;
-    float vi2 = 0.f;
-    if ((same || ncc < c1) && np + sub < nend) {
-      ci2 = idx[np + sub];
-      vi2 = load_val<VB>(val, np + sub);
-    }
-    // entries beyond the chunk have id 0 and value 0: whole U-blocks past the end are skipped
+    // entries beyond the chunk have id 0 and value 0.  The block's first U entries are gathered
+    // whatever its length (an empty row's chunk adds zeros: 0 times a row of X); then the next
+    // block's ids and values are loaded, after those gathers, so the wait for the gathers does
+    // not also wait for these loads; they load unconditionally, from the descriptors for an
+    // entry past the end (then taken as id 0, value 0), so the waits count them exactly.
+    typename Seg<BIN>::raw x0[U];
+    gather_load<LPR, U, 0, BIN, STAGE>(ci, Xs, lds, sub, live, hot, x0);
+    const bool nok = (same || ncc < c1) && np + sub < nend;
+    const char* const ip = nok ? reinterpret_cast<const char*>(idx + (np + sub)) : reinterpret_cast<const char*>(desc);
+    const char* const vp = nok ? reinterpret_cast<const char*>(val) + (size_t)(np + sub) * (VB ? 2 : 4)
+                               : reinterpret_cast<const char*>(desc);
+    int ci2 = *reinterpret_cast<const int*>(ip);
+    float vi2 = load_val<VB>(vp, 0);
+    ci2 = nok ? ci2 : 0;
+    vi2 = nok ? vi2 : 0.f;
+    gather_add<LPR, U, 0, BIN>(vi, x0, acc);
+    // the block's other U-blocks: whole U-blocks past the chunk's end are skipped
     const int cnt = min(LPR, dc.z - p);
     [&]<int... b>(std::integer_sequence<int, b...>) {
-      ((cnt > b * U ? gather_block<LPR, U, b * U, BIN, STAGE>(ci, vi, Xs, lds, sub, live, hot, acc) : void()), ...);
-    }(std::make_integer_sequence<int, LPR / U>{});
+      ((cnt > (b + 1) * U ? gather_block<LPR, U, (b + 1) * U, BIN, STAGE>(ci, vi, Xs, lds, sub, live, hot, acc)
+                          : void()),
+       ...);
+    }(std::make_integer_sequence<int, LPR / U - 1>{});
     if (!same) {
       float o[VEC];
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) o[q] = acc[q];
+      for (int q = 0; q < VEC; ++q) o[q] = live ? acc[q] : 0.f;
       if constexpr (BOUT) {
         if (dc.w < 0)
           store_seg<VEC, true>(reinterpret_cast<char*>(out) + (size_t)dc.x * out_row_bytes, sub, o);
