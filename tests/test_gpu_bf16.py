@@ -69,6 +69,15 @@ def test_bf16_form_cqr2_modes(gpu_lib, cqr2, n, d, ell, lam, seed):
     _check_form(gpu_lib, st, ell, cqr2=cqr2)
 
 
+@pytest.mark.parametrize("n,d,ell,lam,seed", [(1500, 2000, 50, 20, 12), (2500, 3000, 100, 25, 13)])
+def test_bf16_form_with_empty_rows_and_columns(gpu_lib, n, d, ell, lam, seed):
+    # a third of the rows empty and many columns never entered (L = 64 and 128): the BF16
+    # products' empty chunks write zero rows, and the form keeps Property 1 and the cov-err bar
+    st = small_random_csr(n, d, lam, seed, empty_rate=0.3, dist="lognormal")
+    assert (np.diff(st.indptr) == 0).any() and len(np.unique(st.indices)) < d
+    _check_form(gpu_lib, st, ell)
+
+
 def test_bf16_form_is_deterministic(gpu_lib):
     # no atomics and fixed reduction orders: a second run gives the same bits
     st = small_random_csr(3000, 1200, 15, 4, dist="lognormal")

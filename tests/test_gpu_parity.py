@@ -190,6 +190,18 @@ def test_empty_stream_and_empty_rows(gpu_lib):
     _parity(B, o.sketch())
 
 
+@pytest.mark.parametrize("n,d,ell,lam,seed", [(1500, 2000, 50, 20, 12), (2500, 3000, 100, 25, 13)])
+def test_empty_rows_and_columns_on_wide_panels(gpu_lib, n, d, ell, lam, seed):
+    # 64- and 128-wide panels, a third of the rows empty and many columns never entered: the
+    # products write zero rows for the empty chunks of both directions (their first gather block
+    # runs whatever the chunk's length and adds zeros)
+    st = small_random_csr(n, d, lam, seed, empty_rate=0.3)
+    assert (np.diff(st.indptr) == 0).any() and len(np.unique(st.indices)) < d
+    o = _oracle(st, ell)
+    _, B = _gpu_sketch(gpu_lib, st, ell)
+    _parity(B, o.sketch())
+
+
 def test_duplicate_column_ids(gpu_lib):
     st = small_random_csr(400, 50, 5, 9, dup_rate=0.25)
     o = _oracle(st, 7)
