@@ -43,7 +43,7 @@ BATCH_OPTS: dict = {}
 TRAFFIC_SOURCES = ("paper_1602_00412_amd/csrc/sfd_spmm.hip", "paper_1602_00412_amd/csrc/sfd_internal.h")
 MEASURED_TRAFFIC = {
     # (class, workload, precision): (bytes per call, sha256 prefix of TRAFFIC_SOURCES, summary)
-    ("spmm_csc", "stream1e6", "fp32"): (6.4540e+08, "60efe2083974b6d7",
+    ("spmm_csc", "stream1e6", "fp32"): (6.4540e+08, "f20bfb611243cd82",
                                       "profiles/sfd_spmm_csc_ell50_1e5row_buffers_hbm_traffic.txt"),
 }
 

@@ -290,9 +290,9 @@ __device__ inline void gather_block(int ci, float vi, const typename Seg<BF>::ra
 // takes chunks c0 + first, + stride, ...  A group of L/VEC lanes owns a chunk at a time (lane s
 // holds columns VEC s .. VEC s + VEC - 1) and walks it in blocks of L/VEC entries: lane s of the
 // group loads entry s of the block (coalesced), then the entries are broadcast inside the group
-// and their dense row segments gathered.  The next block's ids and values, and the next chunk's
-// descriptor, are loaded before the current block's gathers, so one memory latency per block is
-// exposed instead of three.
+// and their dense row segments gathered.  The next chunk's descriptor is loaded a chunk ahead and
+// the next block's ids and values right after the current block's first gathers, so their
+// latency overlaps the gathers instead of adding to them.
 // Output: a whole row goes to out[r], the chunks of a long row to their FP32 partial slots (the
 // fix-up adds them in slot order).  VB: the stored values are BF16 (the precision form's products
 // 1 .. 2q+1), widened to FP32 exactly.
